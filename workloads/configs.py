@@ -1,0 +1,107 @@
+"""Seeded synthetic workloads (input generation only; no multigrid arithmetic).
+
+Each workload bundles a mesh, its DG matrix in BSR form, right-hand side(s),
+the initial adaptive candidates B^1 and the method parameters.  Seeds: mesh 0,
+right-hand side 1, B^1 2.  Sizes follow the benchmark configurations:
+
+* ``poisson2d_p1_16``  : 16x16 split squares, SIPG p=1 (512 triangles, 1,536 dofs)
+* ``poisson2d_p3_256`` : Delaunay of 256^2 jittered points, SIPG p=3
+                         (130,050 triangles, 1,300,500 dofs)
+* ``convdiff2d_p2_363``: Delaunay of 363^2 jittered points, LDG + upwind p=2
+                         (262,088 triangles, 1,572,528 dofs)
+* ``poisson3d_p2_64``  : 64^3 jittered Kuhn cube, SIPG p=2
+                         (1,572,864 tetrahedra, 15,728,640 dofs)
+
+Scaled-down variants (same recipe, fewer elements) are used by the tests.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import dg, mesh as meshes
+
+
+@dataclass
+class Params:
+    n_levels: int                 # levels L_0..L_{n_levels-1}
+    bisections: int               # binary splits per level (2^b-way aggregation)
+    r: int                        # adaptive candidates
+    t_pre: int = 3
+    t_post: int = 3
+    omega_fixed: float = 0.0      # 0 -> adaptive omega from the power iteration
+    gamma: float = 0.03
+    q_power: int = 3
+    relax_max: int = 100
+    n_cut: float = 3.0
+    pow_seed: int = 3
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: object
+    p: int
+    A: dg.BSR
+    b: np.ndarray
+    B1: np.ndarray
+    params: Params
+    krylov: str                   # "pcg" | "gmres"
+    tol: float = 1e-8
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def centroids(self):
+        return np.ascontiguousarray(self.mesh.centroids())
+
+    @property
+    def adjacency(self):
+        return self.mesh.adjacency()
+
+
+def n_cut_default(dim):
+    """n_cut = 2^d - (d - 1) (Section 4.3)."""
+    return float(2 ** dim - (dim - 1))
+
+
+def _finish(name, m, p, A, params, krylov, rhs_kind="normal", n_rhs=1, extra=None):
+    n = A.n
+    rng_b = np.random.default_rng(1)
+    if rhs_kind == "normal":
+        b = rng_b.standard_normal((n, n_rhs))
+    else:
+        b = rng_b.uniform(-1.0, 1.0, (n, n_rhs))
+    if n_rhs == 1:
+        b = b[:, 0]
+    B1 = np.random.default_rng(2).standard_normal((n, params.r))
+    return Workload(name, m, p, A, np.ascontiguousarray(b), np.ascontiguousarray(B1), params, krylov,
+                    extra=extra or {})
+
+
+def poisson2d_split(nx=16, p=1, n_levels=3, bisections=3, r=1, nu=1, omega=0.7, n_rhs=1):
+    m = meshes.split_square(nx)
+    A = dg.assemble_sipg(m, p)
+    prm = Params(n_levels, bisections, r, nu, nu, omega_fixed=omega, n_cut=n_cut_default(2))
+    return _finish(f"poisson2d_p{p}_split{nx}", m, p, A, prm, "pcg", n_rhs=n_rhs)
+
+
+def poisson2d_delaunay(side=256, p=3, n_levels=5, bisections=2, r=3, nu=3, n_rhs=1):
+    m = meshes.jittered_delaunay(side, 0.25, seed=0)
+    A = dg.assemble_sipg(m, p)
+    prm = Params(n_levels, bisections, r, nu, nu, n_cut=n_cut_default(2))
+    return _finish(f"poisson2d_p{p}_delaunay{side}", m, p, A, prm, "pcg", n_rhs=n_rhs)
+
+
+def convdiff2d_delaunay(side=363, p=2, peclet=1e2, n_levels=6, bisections=2, r=4, nu=3, n_rhs=1):
+    m = meshes.jittered_delaunay(side, 0.25, seed=0)
+    beta = np.array([np.cos(0.3), np.sin(0.3)])
+    A = dg.assemble_ldg_upwind(m, p, beta, 1.0 / peclet)
+    prm = Params(n_levels, bisections, r, nu, nu, n_cut=n_cut_default(2))
+    return _finish(f"convdiff2d_p{p}_delaunay{side}_pe{peclet:g}", m, p, A, prm, "gmres",
+                   rhs_kind="uniform", n_rhs=n_rhs, extra={"peclet": peclet})
+
+
+def poisson3d_kuhn(n=64, p=2, n_levels=5, bisections=3, r=4, nu=2, n_rhs=1):
+    m = meshes.kuhn_cube(n, 0.2, seed=0)
+    A = dg.assemble_sipg(m, p)
+    prm = Params(n_levels, bisections, r, nu, nu, n_cut=n_cut_default(3))
+    return _finish(f"poisson3d_p{p}_kuhn{n}", m, p, A, prm, "pcg", n_rhs=n_rhs)
