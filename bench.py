@@ -1,0 +1,249 @@
+#!/usr/bin/env python
+"""Benchmark of the geometric alpha-SA multigrid hot path on one MI355X.
+
+Workload: 2D Poisson, SIPG p=3 (10 dofs per triangle) on the Delaunay
+triangulation of 256^2 seeded jittered points (130,050 triangles, 1,300,500
+dofs), 5-level hierarchy by recursive coordinate bisection, 3 adaptive
+candidates, V(3,3) block Jacobi with adaptive damping; right-hand side(s)
+N(0,1) from seed 1.  The hierarchy is built once (setup time reported
+separately); a step is one solve of the batch of right-hand sides to a true
+relative residual of 1e-8 from x = 0, with the V-cycle as preconditioner:
+
+* mixed : FP32 V-cycle inside FP64 flexible CG (the reported value),
+* fp64  : FP64 V-cycle inside FP64 CG (reported beside it).
+
+Prints one JSON line (see the README section of the design doc for its fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def level_bytes(info, w, m, nu):
+    """Algorithmic bytes of one V(nu,nu) visit of a non-coarsest level: 2nu passes
+    over A_k and D_k^{-1}, (6nu+5) passes over level-k vectors, one over T_k and R_k."""
+    A = info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
+    D = info.n_units * info.nb * info.nb * w
+    TR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_units + 1)
+    RR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_agg + 1)
+    return 2 * nu * (A + D) + (6 * nu + 5) * info.n * m * w + TR + RR
+
+
+def sweep_bytes(info, w, m):
+    """Algorithmic bytes of one block-Jacobi sweep y = x + omega D^-1 (b - A x):
+    A (values and indices), D^-1, and x, b read once, y written once."""
+    return (info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
+            + info.n_units * info.nb * info.nb * w + 3 * info.n * m * w)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rhs", type=int, default=1, help="right-hand sides per solve")
+    ap.add_argument("--side", type=int, default=256, help="grid points per side (256: the full workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2504_13373_amd as am
+    from workloads import configs
+
+    dev = torch.device("cuda:0")
+    log(f"generating workload (side {args.side})")
+    t0 = time.perf_counter()
+    w = configs.poisson2d_delaunay(side=args.side, n_rhs=args.rhs)
+    log(f"workload: {w.mesh.n_elem} elements, {w.A.n} dofs, {w.A.nnzb} blocks ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h, agg = am.setup_from_workload(w, mixed=True)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
+    log(f"setup {setup_s:.2f} s; levels n = {[i.n for i in infos]}, omega = {[round(i.omega, 4) for i in infos[:-1]]}")
+
+    m = args.rhs
+    b = torch.as_tensor(w.b.reshape(w.A.n, m) if m > 1 else w.b).to(dev).contiguous()
+    x = torch.zeros_like(b)
+    maxit = 50000
+
+    def solve(method, prec):
+        x.zero_()
+        rc, st = am.amgdg_solve(h, b, x, method, prec, 1e-8, maxit)
+        return rc, st
+
+    paths = {"mixed": (am.AMGDG_FCG, am.AMGDG_MIXED), "fp64": (am.AMGDG_PCG, am.AMGDG_FP64)}
+    res = {}
+    A = w.A.to_scipy()
+    bh = w.b.reshape(w.A.n, m) if m > 1 else w.b[:, None]
+    for name, (meth, prec) in paths.items():
+        for i in range(args.warmup):
+            rc, st = solve(meth, prec)
+            log(f"warmup {name} {i}: rc {rc}, iterations {st.max_iterations}")
+        torch.cuda.synchronize()
+        times = []
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = solve(meth, prec)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            log(f"step {name} {i}: {times[-1] * 1e3:.1f} ms, iterations {st.max_iterations}, rc {rc}")
+        xh = x.cpu().numpy().reshape(w.A.n, m)
+        true_rel = float(np.max(np.linalg.norm(bh - A @ xh, axis=0) / np.linalg.norm(bh, axis=0)))
+        res[name] = dict(times=times, its=st.max_iterations, rc=rc, true_rel=true_rel)
+
+    # V-cycle HBM rate (algorithmic bytes / measured time), both precisions
+    nu = w.params.t_pre
+    stream = torch.cuda.current_stream()
+    vc = {}
+    for name, (prec, wb, dt) in {"fp64": (am.AMGDG_FP64, 8, torch.float64),
+                                 "fp32": (am.AMGDG_MIXED, 4, torch.float32)}.items():
+        r = torch.randn(w.A.n * m, dtype=dt, device=dev).reshape(b.shape)
+        z = torch.zeros_like(r)
+        for _ in range(3):
+            am.amgdg_vcycle(h, r, z, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            am.amgdg_vcycle(h, r, z, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps * 1e-3
+        nN = infos[-1].n
+        byts = sum(level_bytes(i, wb, m, nu) for i in infos[:-1]) + nN * nN * 8 + 2 * nN * m * 8
+        vc[name] = dict(ms=t * 1e3, gbps=byts / t / 1e9, bytes=byts)
+        log(f"V-cycle {name}: {t * 1e3:.3f} ms, {byts / 1e9:.3f} GB algorithmic, {byts / t / 1e9:.0f} GB/s")
+
+    # dominant kernel: the level-0 block-Jacobi sweep, timed with HIP events on the
+    # stream it is launched on (one kernel launch per call with internal ordering)
+    kern = {}
+    for name, (prec, wb, dt) in {"fp32": (am.AMGDG_MIXED, 4, torch.float32),
+                                 "fp64": (am.AMGDG_FP64, 8, torch.float64)}.items():
+        xx = torch.randn(w.A.n * m, dtype=dt, device=dev).reshape(b.shape)
+        bb = torch.randn_like(xx)
+        yy = torch.zeros_like(xx)
+        for _ in range(5):
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.kernel_reps):
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
+        byts = sweep_bytes(infos[0], wb, m)
+        kern[name] = dict(us=t * 1e6, gbps=byts / t / 1e9, bytes=byts)
+        log(f"level-0 sweep {name}: {t * 1e6:.1f} us, {byts / 1e6:.1f} MB, {byts / t / 1e9:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, res["fp64"]["its"])
+
+    mixed_t = float(np.mean(res["mixed"]["times"]))
+    fp64_t = float(np.mean(res["fp64"]["times"]))
+    k = kern["fp32"]
+    line = {
+        "metric": "solves/sec + HBM GB/s of V-cycle to 1e-8 rel. resid; mixed vs FP64, p99 latency",
+        "value": m / mixed_t,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed_t * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle + f64 Krylov",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2D Poisson SIPG p=3, Delaunay of {args.side}^2 jittered points "
+                        f"({w.mesh.n_elem} triangles, {w.A.n} dofs), 5-level RCB hierarchy, r=3, V(3,3), "
+                        f"tol 1e-8, {m} RHS per solve",
+            "rhs_per_solve": m,
+            "outer": "flexible CG (mixed) / CG (fp64)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "level-0 FP32 block-Jacobi sweep (k_sweep<float,1,SWEEP>)",
+            "achieved": k["gbps"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": k["gbps"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": k["bytes"],
+            "us_per_launch": k["us"],
+        },
+        "fp64": {
+            "solves_per_s": m / fp64_t,
+            "ms_per_solve": fp64_t * 1e3,
+            "iterations": res["fp64"]["its"],
+            "true_rel_residual": res["fp64"]["true_rel"],
+            "sweep_gbps": kern["fp64"]["gbps"],
+            "sweep_us": kern["fp64"]["us"],
+        },
+        "mixed": {
+            "iterations": res["mixed"]["its"],
+            "true_rel_residual": res["mixed"]["true_rel"],
+            "speedup_vs_fp64": fp64_t / mixed_t,
+        },
+        "vcycle": {name: {"ms": v["ms"], "GBps": v["gbps"], "frac": v["gbps"] / HBM_PEAK_GBS} for name, v in vc.items()},
+        "setup_s": setup_s,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(w, gpu_iterations, n_iter=5):
+    """The FP64 oracle on the host cores: its setup, then n_iter PCG iterations
+    at full size, extrapolated to the GPU's iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import amg, krylov, rcb
+    log("cpu baseline: oracle setup")
+    t0 = time.perf_counter()
+    aggs, _ = rcb.rcb_hierarchy(w.centroids, w.params.n_levels, w.params.bisections)
+    A = w.A.to_scipy()
+    H = amg.setup(A, w.A.nb, aggs, w.params, w.B1)
+    t_setup = time.perf_counter() - t0
+    b = w.b if w.b.ndim == 1 else w.b[:, 0]
+    log(f"cpu baseline: oracle setup {t_setup:.1f} s; timing {n_iter} PCG iterations")
+    t0 = time.perf_counter()
+    krylov.pcg(A, b, lambda r: amg.vcycle(H, r), 1e-30, n_iter)
+    t_it = (time.perf_counter() - t0) / n_iter
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {
+        "value": 1.0 / (t_it * gpu_iterations),
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"FP64 oracle (NumPy/SciPy) setup ({t_setup:.1f} s) then {n_iter} PCG iterations on the full "
+                  f"workload ({t_it:.3f} s each), extrapolated to the {gpu_iterations} iterations of one solve; "
+                  f"sparse products single-threaded, dense LAPACK on {threads} threads",
+    }
+
+
+if __name__ == "__main__":
+    main()

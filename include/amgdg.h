@@ -1,0 +1,226 @@
+/*
+ * amgdg -- geometric adaptive smoothed-aggregation multigrid for DG matrices
+ * (Pan, Lindsey & Persson, "Geometric adaptive smoothed aggregation multigrid
+ * for discontinuous Galerkin discretisations", arXiv 2504.13373), on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The problem (Section 4.5): given the n x n DG matrix A with one dense nb x nb
+ * block per element and coupled element pair, the mesh graph of the elements
+ * and a nested hierarchy of element aggregates (Section 4.1), build the
+ * multigrid operators of Algorithm 5 and solve A x = b with the V-cycle of
+ * Algorithm 2, on its own or as a preconditioner of a Krylov method.
+ *
+ * Conventions for every entry point
+ *  - Return value: AMGDG_OK (0) on success, a negative AMGDG_E* code on error,
+ *    AMGDG_ENOCONV (> 0) when a solve stopped at its iteration limit.  No entry
+ *    point throws; amgdg_last_error() gives a message for the calling thread.
+ *  - Host arrays are read during the call only (the library copies what it
+ *    keeps).  Device arrays are caller-owned and must stay valid until the work
+ *    queued on `stream` has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *    device work is queued on it; calls that return host data synchronise it.
+ *  - Block storage is row-major inside each block; multi-column vectors are
+ *    row-major n x m (the m values of one dof are contiguous).
+ *  - Element and dof numbering is the caller's.  The library renumbers elements
+ *    internally so that every aggregate is a contiguous range; this is invisible
+ *    except through the AMGDG_INTERNAL_ORDER flag of amgdg_apply.
+ *  - A handle is not thread-safe; distinct handles are.
+ */
+#ifndef AMGDG_H
+#define AMGDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define AMGDG_OK            0
+#define AMGDG_EINVAL       -1  /* bad argument: null pointer, size, unsorted or duplicate
+                                  column, missing diagonal block, non-nested hierarchy */
+#define AMGDG_ESINGULAR    -2  /* a diagonal block or the coarsest matrix has a pivot
+                                  |u_ii| <= n * eps * max|a| */
+#define AMGDG_ENOMEM       -3  /* device or host allocation failed */
+#define AMGDG_EHIP         -4  /* HIP runtime error */
+#define AMGDG_ENAN         -5  /* NaN or Inf in the data or the iteration */
+#define AMGDG_EBREAKDOWN   -6  /* Krylov breakdown, e.g. p^T A p <= 0 in CG */
+#define AMGDG_EUNSUPPORTED -7  /* valid input outside what this build implements */
+#define AMGDG_ENOCONV       1  /* iteration limit reached; x holds the last iterate */
+
+/* --------------------------------------------------------------- parameters */
+typedef struct {
+    int32_t  n_levels;     /* levels L_0..L_{n_levels-1}; L_{n_levels-1} is solved directly */
+    int32_t  r;            /* adaptive candidates per level (columns of B^k) */
+    int32_t  t_pre;        /* pre-smoothing sweeps (Algorithm 2) */
+    int32_t  t_post;       /* post-smoothing sweeps */
+    int32_t  q_power;      /* power-iteration steps of Algorithm 4 */
+    int32_t  relax_max;    /* cap on the sweeps of the candidate relaxation (eq:bsmooth) */
+    double   omega_fixed;  /* > 0: use this damping on every level instead of eq:omega */
+    double   gamma;        /* stagnation tolerance of eq:bsmooth */
+    double   n_cut;        /* coarsening factor of eq:sik (h-step) */
+    int32_t  b_update;     /* 0: B^{k+1} = R B^k (Algorithm 5); 1: P~^T B^k (eq:SA_Bk) */
+    int32_t  mixed;        /* 1: also keep FP32 copies of all level operators */
+    uint64_t pow_seed;     /* level k's power-iteration start vector: SplitMix64 stream
+                              pow_seed + k, entries 2u-1, in caller dof order */
+    uint64_t b1_seed;      /* B^1 stream when no B^1 is given (Box-Muller normals) */
+} amgdg_params;
+
+/* Fills the paper's defaults: gamma 0.03 (Section 4.2), q 3 (Section 4.4),
+ * t_pre = t_post = 3 (Section 5), n_cut 3 (2D value 2^d - d + 1, Section 4.3),
+ * relax_max 100, r 3, n_levels 2, adaptive omega, B^{k+1} = R B^k, FP64 only. */
+void amgdg_default_params(amgdg_params* p);
+
+/* ------------------------------------------------------------ hierarchy */
+/* Nested element aggregates by recursive coordinate bisection, the stand-in for
+ * the 2^d-way METIS splits of Section 4.1.  A node splits along the axis of
+ * largest centroid extent (ties: lowest axis), elements sorted by (coordinate,
+ * element id), left child = first ceil(m/2).  With D = ceil(log2 n_elem), the
+ * level-k aggregates (k >= 1) are the nodes at depth D - k*bisections (a leaf
+ * above that depth is its own aggregate), numbered depth first.
+ *   centroids : host, n_elem x dim doubles (dim 1..3)
+ *   agg_out   : host, (n_levels-1) x n_elem int32: row k-1 maps element -> level-k aggregate
+ *   leaf_order: host, n_elem int64 or NULL: elements in depth-first leaf order
+ * Host only; never touches the GPU.  EINVAL if D - (n_levels-1)*bisections < 0. */
+int amgdg_partition_rcb(int64_t n_elem, int32_t dim, const double* centroids, int32_t n_levels,
+                        int32_t bisections, int32_t* agg_out, int64_t* leaf_order);
+
+/* ------------------------------------------------- symbolic plan (host only) */
+/* The index construction of the setup, without numbers: element renumbering,
+ * and per level the block patterns of T (eq:TR0: block (e,J) iff J is the
+ * aggregate of e or of a block column of row e of A_k), R = T^T and
+ * A_{k+1} = R A_k T (block (I,J) iff T(a,I), A_k(a,b), T(b,J) all exist).
+ * Inputs as for amgdg_setup.  Host only; never touches the GPU. */
+typedef struct amgdg_plan_s* amgdg_plan;
+int amgdg_plan_create(amgdg_plan* out, int64_t n_elem, const int32_t* row_ptr, const int32_t* col_idx,
+                      int64_t nnzb, int32_t n_levels, const int32_t* agg_of_elem);
+void amgdg_plan_destroy(amgdg_plan p);
+
+/* Items for amgdg_plan_size / amgdg_plan_export and amgdg_export_level.  Level-0
+ * rows (A_0, T_0, D_0^{-1}, B^0, P~_0) are returned in caller element order;
+ * coarse levels are numbered by aggregate id. */
+#define AMGDG_PERM        1   /* int64[n_elem]: internal position -> caller element (level 0 only) */
+#define AMGDG_T_ROWPTR    2   /* int32[n_units_k + 1] */
+#define AMGDG_T_COLIDX    3   /* int32[nnzb_T] (level-(k+1) aggregate ids) */
+#define AMGDG_A_ROWPTR    4   /* int32[n_units_k + 1]: pattern of A_k (k = 0: the caller's) */
+#define AMGDG_A_COLIDX    5
+#define AMGDG_R_ROWPTR    6   /* int32[n_agg + 1] */
+#define AMGDG_R_COLIDX    7
+#define AMGDG_A_VALS     10   /* double[nnzb_A * nb * nb] (A_k) */
+#define AMGDG_T_VALS     11   /* double[nnzb_T * nb * s] */
+#define AMGDG_R_VALS     12   /* double[nnzb_T * s * nb] */
+#define AMGDG_DINV       13   /* double[n_units * nb * nb] */
+#define AMGDG_B_RELAXED  14   /* double[n * r]: candidates after relaxation */
+#define AMGDG_B_INPUT    15   /* double[n * r]: candidates before relaxation */
+#define AMGDG_PTILDE     16   /* double[n_units * nb * s]: the P~ rows of each unit */
+#define AMGDG_SVALS      17   /* double[n_agg * r]: singular values, descending */
+
+/* Number of elements of `what` (in its own type) at level k. */
+int amgdg_plan_size(amgdg_plan p, int32_t k, int32_t what, int64_t* count);
+int amgdg_plan_export(amgdg_plan p, int32_t k, int32_t what, void* host_buf, int64_t bytes);
+
+/* ------------------------------------------------------------------ setup */
+typedef struct amgdg_ctx* amgdg_handle;
+
+/* Algorithm 5 on the GPU: per level k = 0..n_levels-2 the block-Jacobi diagonal
+ * inverses (Section 4.4), the damping (Algorithm 4, eq:omega), the relaxation of
+ * the candidates (eq:bsmooth), the tentative prolongator by per-aggregate SVD
+ * (eq:splitB_dg, eq:sik), T = (I - omega D^{-1} A) P~ and R = T^T (eq:TR0),
+ * A_{k+1} = R A_k T and B^{k+1} = R B^k; then the inverse of the coarsest
+ * matrix.  Every arithmetic step runs in the library's HIP kernels.
+ *   n_elem, nb       : element count and dofs per element (1..64)
+ *   row_ptr, col_idx : host BSR pattern, int32, columns sorted, diagonal present
+ *   vals             : host, nnzb * nb * nb doubles
+ *   adj_ptr, adj_idx : host face graph of the elements (CSR) or NULL; only checked
+ *   agg_of_elem      : host, (n_levels-1) x n_elem, element -> level-k aggregate;
+ *                      ids dense per level, nested, and ordered so that the
+ *                      children of each coarser aggregate have consecutive ids
+ *   B1               : host, n x r row-major in caller order, or NULL
+ *   p                : parameters (NULL: defaults)
+ * The coarse block size s = min(ceil(|A_J| / n_cut), |A_J|, r) must be the same
+ * for every aggregate of a level (EUNSUPPORTED otherwise). */
+int amgdg_setup(amgdg_handle* out, int64_t n_elem, int32_t nb, const int32_t* row_ptr,
+                const int32_t* col_idx, const double* vals, int64_t nnzb, const int32_t* adj_ptr,
+                const int32_t* adj_idx, const int32_t* agg_of_elem, const amgdg_params* p,
+                const double* B1, void* stream);
+int amgdg_destroy(amgdg_handle h);
+
+typedef struct {
+    int64_t n_units;     /* block rows of A_k */
+    int32_t nb;          /* block size of level k */
+    int32_t s;           /* block size of level k+1 (0 on the coarsest level) */
+    int64_t n;           /* dofs of level k */
+    int64_t nnzb;        /* blocks of A_k */
+    int64_t nnzb_T;      /* blocks of T_k (0 on the coarsest level) */
+    int64_t n_agg;       /* block rows of A_{k+1} */
+    double  omega;       /* damping omega_k */
+    double  rho;         /* power-iteration estimate (NaN if omega was fixed) */
+    int32_t r;           /* candidates relaxed on this level */
+    int32_t sweeps[16];  /* relaxation sweeps per candidate (first 16) */
+    int64_t bytes_A, bytes_Dinv, bytes_T, bytes_R;   /* FP64 bytes held for level k */
+} amgdg_level_info;
+int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out);
+int amgdg_num_levels(amgdg_handle h);
+
+/* Copies an item of level k to host memory (synchronises `stream`). */
+int amgdg_export_level(amgdg_handle h, int32_t k, int32_t what, void* host_buf, int64_t bytes,
+                       void* stream);
+
+/* ------------------------------------------------------------------ solve */
+#define AMGDG_FP64  0   /* FP64 V-cycle */
+#define AMGDG_MIXED 1   /* FP32 V-cycle (FP32 operators and accumulation; coarsest
+                           solve in FP64) inside FP64 outer iterations */
+
+#define AMGDG_STATIONARY 0  /* x <- x + V(b - A x) (Algorithm 2 as a solver) */
+#define AMGDG_PCG        1  /* preconditioned CG (symmetric positive definite A) */
+#define AMGDG_FCG        2  /* flexible CG (Polak-Ribiere beta) */
+#define AMGDG_FGMRES     3  /* restarted right-preconditioned FGMRES(restart), CGS2;
+                               each restart recomputes the FP64 residual */
+
+typedef struct {
+    int32_t iterations[64];   /* per column (first 64) */
+    double  rel_residual[64]; /* true ||b - A x|| / ||b|| per column, FP64 */
+    int32_t max_iterations;
+    int32_t all_converged;
+    double  seconds;
+} amgdg_solve_stats;
+
+/* Solves A X = B for m columns from X = 0 (or the given X if AMGDG_X0 is set in
+ * flags), stopping each column when its true relative residual is <= rtol.
+ *   b_dev, x_dev : device, n x m doubles, caller order
+ *   stats        : host or NULL
+ * The V-cycle precision is AMGDG_FP64 or AMGDG_MIXED (needs params.mixed). */
+#define AMGDG_X0             1
+#define AMGDG_INTERNAL_ORDER 2
+int amgdg_solve(amgdg_handle h, int32_t m, const double* b_dev, double* x_dev, int32_t method,
+                int32_t precision, double rtol, int32_t max_it, int32_t restart, int32_t flags,
+                amgdg_solve_stats* stats, void* stream);
+
+/* One V-cycle z = V(r) from z = 0 (Algorithm 2, one pass), m columns.
+ * precision AMGDG_FP64: r, z are double*; AMGDG_MIXED: float*. */
+int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int32_t precision,
+                 int32_t flags, void* stream);
+
+/* Single steps of the hot path on level k (one kernel launch each, for tests
+ * and timing).  x, b, y: device arrays of the sizes below, double (FP64) or
+ * float (MIXED), m columns.  An argument the operation does not read (b for
+ * SPMV, RESTRICT, COARSE; x for SWEEP0) is ignored and may be NULL.  Level-0
+ * vectors are in caller order unless AMGDG_INTERNAL_ORDER is set (then no
+ * permutation kernel runs).  y must not alias x or b. */
+#define AMGDG_OP_SPMV      0  /* y = A_k x                               (n_k)      */
+#define AMGDG_OP_SWEEP     1  /* y = x + omega D^{-1} (b - A_k x)         (Alg. 1)   */
+#define AMGDG_OP_SWEEP0    2  /* y = omega D^{-1} b (sweep from zero)                */
+#define AMGDG_OP_RESIDUAL  3  /* y = b - A_k x                                       */
+#define AMGDG_OP_RESTRICT  4  /* y = R_k x   (x: n_k, y: n_{k+1})                    */
+#define AMGDG_OP_PROLONG   5  /* y = b + T_k x (x: n_{k+1}, b, y: n_k)               */
+#define AMGDG_OP_COARSE    6  /* y = A_N^{-1} x on the coarsest level (always FP64)  */
+int amgdg_apply(amgdg_handle h, int32_t k, int32_t op, int32_t m, int32_t precision, const void* x,
+                const void* b, void* y, int32_t flags, void* stream);
+
+/* Message for the last non-zero status returned on the calling thread. */
+const char* amgdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMGDG_H */

@@ -1,0 +1,121 @@
+// Launch wrappers of the HIP kernels (gfx950, wave64).  All launches go to the
+// stream given; nothing here allocates or synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace amgdg {
+
+// Sliced, row-interleaved block-sparse matrix with br x bc blocks.
+//
+// Block rows are grouped in slices of G = floor(64 / br) rows; one wavefront
+// owns a slice and each of its first L = G * br lanes owns one scalar row.  A
+// slice stores K (its longest block row) block slots per row, padded with zero
+// blocks whose column is 0.  Value (k, j) of lane l is at
+//     vals[voff[s] + (k * bc + j) * L + l]
+// so that for fixed (k, j) the wavefront reads L consecutive values, and the
+// column of slot k of the slice's block row g is cols[coff[s] + k * G + g].
+template <typename T>
+struct Sell {
+    int32_t n_brow = 0, br = 0, bc = 0, G = 0, L = 0, n_slices = 0;
+    const int64_t* voff = nullptr;
+    const int32_t* coff = nullptr;
+    const int32_t* K = nullptr;
+    const int32_t* cols = nullptr;
+    const T* vals = nullptr;
+};
+
+// sweep modes
+enum SweepMode : int {
+    SWEEP = 0,   // y = x + omega D^{-1} (b - A x)
+    SWEEP0 = 1,  // y = omega D^{-1} b
+    RELAX = 2,   // y = x - omega D^{-1} A x   (columns with mask 0 are copied)
+    DINVA = 3,   // y = D^{-1} A x
+};
+// spmv modes
+enum SpmvMode : int {
+    AX = 0,      // y = A x
+    B_MINUS = 1, // y = b - A x
+    B_PLUS = 2,  // y = b + A x
+};
+
+// Dinv in sliced layout: value (i, j) of block row g of slice s at
+// dinv[s * br * L + j * L + g * br + i].
+template <typename T>
+hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
+                        int m, const int32_t* colmask, hipStream_t st);
+template <typename T>
+hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st);
+
+// ---- setup ----
+hipError_t launch_to_sell_vals(const double* nat, const int64_t* slot_src, int64_t n_slots, int G, int L, int br,
+                               int bc, const int64_t* slot_voff, double* vals, hipStream_t st);
+hipError_t launch_dinv_to_sell(const double* dinv_nat, int64_t n_brow, int br, int G, int L, double* dinv_sell,
+                               hipStream_t st);
+hipError_t launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st);
+hipError_t launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st);
+hipError_t launch_block_inverse(const double* Avals, const int32_t* diag_pos, int64_t n_brow, int nb, double* dinv,
+                                int32_t* flag, hipStream_t st);
+hipError_t launch_svd(const double* B, int r, const int32_t* first_child, int64_t n_agg, int nb, int s,
+                      double* Pu, double* svals, int32_t* flag, hipStream_t st);
+hipError_t launch_T_build(const double* Avals, const int32_t* A_ci, const int32_t* T_row, const int32_t* T_ci,
+                          const int32_t* Tm_ptr, const int32_t* Tm_a, const int32_t* agg, int64_t nT, int nb, int s,
+                          const double* Pu, const double* dinv, double omega, double* W, double* Tvals,
+                          hipStream_t st);
+hipError_t launch_R_from_T(const double* Tvals, const int32_t* R_t, int64_t nR, int nb, int s, double* Rvals,
+                           hipStream_t st);
+hipError_t launch_AT(const double* Avals, const double* Tvals, const int64_t* pp, const int32_t* pa,
+                     const int32_t* pt, int64_t nAT, int nb, int s, double* ATvals, hipStream_t st);
+hipError_t launch_galerkin(const double* Tvals, const double* ATvals, const int64_t* pp, const int32_t* pt,
+                           const int32_t* pu, int64_t nC, int nb, int s, double* Cvals, hipStream_t st);
+hipError_t launch_dense_from_bsr(const double* vals, const int32_t* rp, const int32_t* ci, int64_t n_brow, int nb,
+                                 int64_t nnzb, double* dense, hipStream_t st);
+// in-place inverse of a dense row-major n x n matrix (Gauss-Jordan, row pivoting);
+// flag |= 1 if a pivot is <= tol_scale * amax[0]; rowc, colc: n doubles of scratch
+hipError_t launch_gj_invert(double* a, int64_t n, int32_t* piv, int32_t* flag, const double* amax, double tol_scale,
+                            double* rowc, double* colc, hipStream_t st);
+// out[0] = max |a_i|; out must hold 1 + DOT_PARTS doubles
+hipError_t launch_absmax(const double* a, int64_t n, double* out, hipStream_t st);
+hipError_t launch_uniform(uint64_t seed, const int64_t* perm, int64_t n_units, int nb, double* x, hipStream_t st);
+hipError_t launch_normal(uint64_t seed, const int64_t* perm, int64_t n_units, int nb, int r, double* x,
+                         hipStream_t st);
+
+constexpr int DOT_PARTS = 1024;
+// ---- vectors ----
+// per-column dot products of row-major n x m arrays, accumulated in FP64 in a
+// fixed order: out[c] = sum_i a[i,c] * b[i,c]
+template <typename T>
+hipError_t launch_dot(const T* a, const T* b, int64_t n, int m, double* part, double* out, hipStream_t st);
+// y[i,c] = a*x[i,c] + by*y[i,c] with per-column device scalars (alpha[c] * sa)
+hipError_t launch_axpby_dev(const double* x, double* y, int64_t n, int m, const double* alpha, double sa,
+                            double by, hipStream_t st);
+// CG updates: x += alpha p ; r -= alpha q  (per column alpha)
+hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const double* p, const double* q, int64_t n,
+                        int m, const double* alpha, hipStream_t st);
+// dst[i,c] = src[i,c] for the columns c with mask[c] != 0
+hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, const int32_t* mask, hipStream_t st);
+// p = z + beta p
+hipError_t launch_cg_p(double* p, const double* z, int64_t n, int m, const double* beta, hipStream_t st);
+// alpha[c] = active ? num[c] / den[c] : 0 ; flags breakdown if den <= 0 (CG) or not finite
+hipError_t launch_div_scalars(const double* num, const double* den, const int32_t* active, int m, double* out,
+                              int32_t check_positive, int32_t* flag, hipStream_t st);
+// beta[c] = active ? (rz_new[c] - sub[c]) / rz[c] : 0 ; then rz[c] = rz_new[c]
+hipError_t launch_beta(const double* rz_new, const double* sub, double* rz, const int32_t* active, int m,
+                       double* beta, hipStream_t st);
+// y = Ainv x (dense, row-major n x n, FP64), m columns
+hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n, int m, hipStream_t st);
+// level-0 reorder: out[internal unit u] = in[caller element perm[u]] (gather) or the inverse (scatter)
+template <typename Ti, typename To>
+hipError_t launch_permute(const Ti* in, To* out, const int64_t* perm, int64_t n_units, int nb, int m,
+                          int gather, hipStream_t st);
+template <typename Ti, typename To>
+hipError_t launch_convert(const Ti* in, To* out, int64_t n, hipStream_t st);
+hipError_t launch_scale_by_inv_norm(double* x, int64_t n, const double* nrm2, hipStream_t st);
+// Krylov multi-vector ops (FGMRES): h[j] = V[j] . w for j < nv (V: nv x n); w -= sum_j V[j] h[j]
+hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part,
+                           double* out, hipStream_t st);
+hipError_t launch_multi_axpy(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n,
+                             double sign, hipStream_t st);
+
+}  // namespace amgdg

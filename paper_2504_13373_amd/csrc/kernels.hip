@@ -1,0 +1,1119 @@
+// HIP kernels of the multigrid hot path and setup, for gfx950 (wave64).
+//
+// Memory-bound kernels (BSR SpMV, block-Jacobi sweeps, transfers, vector ops)
+// use the sliced row-interleaved layout described in kernels.h: a wavefront
+// owns floor(64/nb) consecutive block rows, one lane per scalar row, so every
+// load of matrix values by a wavefront is one contiguous run of L values.
+// Workgroups are 4 wavefronts; workgroup ids are remapped so that each of the
+// 8 XCDs (dispatched round-robin) processes one contiguous range of slices,
+// which keeps neighbouring x blocks in that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace amgdg {
+
+constexpr int WG = 256;
+constexpr int WAVES_PER_WG = WG / 64;
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+    const int q = nblk >> 3, rmd = nblk & 7;
+    const int x = bid & 7, j = bid >> 3;
+    return x * q + (x < rmd ? x : rmd) + j;
+}
+
+static inline unsigned grid_for(int64_t n, int per = WG) { return unsigned((n + per - 1) / per); }
+
+// ============================================================ BSR kernels
+
+template <typename T, int M, int MODE>
+__global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
+                                               const T* __restrict__ b, T* __restrict__ y, T omega,
+                                               const int32_t* __restrict__ colmask, int ld) {
+    constexpr bool HAS_B = (MODE == SWEEP || MODE == SWEEP0);
+    constexpr bool HAS_A = (MODE != SWEEP0);
+    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + (threadIdx.x >> 6);
+    if (slice >= A.n_slices) return;
+    const int lane = threadIdx.x & 63;
+    const int L = A.L, br = A.br;
+    const int lc = lane < L ? lane : L - 1;
+    const int g = lc / br;
+    const int i = lc - g * br;
+    const int64_t brow = int64_t(slice) * A.G + g;
+    const bool own = lane < L && brow < A.n_brow;
+    const int64_t row = brow * br + i;
+
+    T r[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) r[c] = T(0);
+    if (HAS_B && own) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) r[c] = b[row * ld + c];
+    }
+    if (HAS_A) {
+        const int K = A.K[slice];
+        const int bc = A.bc;
+        const T* __restrict__ vp = A.vals + A.voff[slice] + lc;
+        const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
+        for (int k = 0; k < K; ++k) {
+            const int64_t cb = int64_t(cp[k * A.G]) * bc;
+            const T* __restrict__ vk = vp + int64_t(k) * bc * L;
+            for (int j = 0; j < bc; ++j) {
+                const T a = vk[int64_t(j) * L];
+#pragma unroll
+                for (int c = 0; c < M; ++c) r[c] -= a * x[(cb + j) * ld + c];
+            }
+        }
+    }
+    T o[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) o[c] = T(0);
+    const T* __restrict__ dp = dinv + int64_t(slice) * br * L + lc;
+    for (int j = 0; j < br; ++j) {
+        const T d = dp[int64_t(j) * L];
+        const int src = g * br + j;
+#pragma unroll
+        for (int c = 0; c < M; ++c) o[c] += d * __shfl(r[c], src);
+    }
+    if (!own) return;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        T v;
+        if (MODE == SWEEP) v = x[row * ld + c] + omega * o[c];
+        else if (MODE == SWEEP0) v = omega * o[c];
+        else if (MODE == RELAX) v = colmask[c] ? x[row * ld + c] + omega * o[c] : x[row * ld + c];
+        else v = -o[c];  // DINVA: r = -A x
+        y[row * ld + c] = v;
+    }
+}
+
+template <typename T, int M, int MODE>
+__global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
+                                              T* __restrict__ y, int ldx, int ldy) {
+    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + (threadIdx.x >> 6);
+    if (slice >= A.n_slices) return;
+    const int lane = threadIdx.x & 63;
+    const int L = A.L, br = A.br;
+    const int lc = lane < L ? lane : L - 1;
+    const int g = lc / br;
+    const int i = lc - g * br;
+    const int64_t brow = int64_t(slice) * A.G + g;
+    const bool own = lane < L && brow < A.n_brow;
+    const int64_t row = brow * br + i;
+    T acc[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc[c] = T(0);
+    const int K = A.K[slice];
+    const int bc = A.bc;
+    const T* __restrict__ vp = A.vals + A.voff[slice] + lc;
+    const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
+    for (int k = 0; k < K; ++k) {
+        const int64_t cb = int64_t(cp[k * A.G]) * bc;
+        const T* __restrict__ vk = vp + int64_t(k) * bc * L;
+        for (int j = 0; j < bc; ++j) {
+            const T a = vk[int64_t(j) * L];
+#pragma unroll
+            for (int c = 0; c < M; ++c) acc[c] += a * x[(cb + j) * ldx + c];
+        }
+    }
+    if (!own) return;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        T v = acc[c];
+        if (MODE == B_MINUS) v = b[row * ldy + c] - v;
+        else if (MODE == B_PLUS) v = b[row * ldy + c] + v;
+        y[row * ldy + c] = v;
+    }
+}
+
+template <typename T, int M>
+static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
+                          const int32_t* mask, int ld, hipStream_t st) {
+    dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
+    if (A.n_slices == 0) return hipSuccess;
+    switch (mode) {
+        case SWEEP: hipLaunchKernelGGL((k_sweep<T, M, SWEEP>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case SWEEP0: hipLaunchKernelGGL((k_sweep<T, M, SWEEP0>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case RELAX: hipLaunchKernelGGL((k_sweep<T, M, RELAX>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case DINVA: hipLaunchKernelGGL((k_sweep<T, M, DINVA>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int ldx, int ldy,
+                         hipStream_t st) {
+    dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
+    if (A.n_slices == 0) return hipSuccess;
+    switch (mode) {
+        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, 0, st, A, x, b, y, ldx, ldy); break;
+        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, 0, st, A, x, b, y, ldx, ldy); break;
+        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, 0, st, A, x, b, y, ldx, ldy); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Columns are processed in chunks of 16, 8, 4, 3, 2, 1 (each a separate launch).
+template <typename T>
+hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
+                        const int32_t* colmask, hipStream_t st) {
+    int c0 = 0;
+    while (c0 < m) {
+        const int rem = m - c0;
+        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const T* xc = x ? x + c0 : nullptr;
+        const T* bc = b ? b + c0 : nullptr;
+        const int32_t* mc = colmask ? colmask + c0 : nullptr;
+        hipError_t e;
+        switch (w) {
+            case 16: e = sweep_m<T, 16>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 8: e = sweep_m<T, 8>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 4: e = sweep_m<T, 4>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 3: e = sweep_m<T, 3>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 2: e = sweep_m<T, 2>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            default: e = sweep_m<T, 1>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+        }
+        if (e != hipSuccess) return e;
+        c0 += w;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st) {
+    int c0 = 0;
+    while (c0 < m) {
+        const int rem = m - c0;
+        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const T* bc = b ? b + c0 : nullptr;
+        hipError_t e;
+        switch (w) {
+            case 16: e = spmv_m<T, 16>(mode, A, x + c0, bc, y + c0, m, m, st); break;
+            case 8: e = spmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, m, st); break;
+            case 4: e = spmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, m, st); break;
+            case 3: e = spmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, m, st); break;
+            case 2: e = spmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, m, st); break;
+            default: e = spmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, m, st); break;
+        }
+        if (e != hipSuccess) return e;
+        c0 += w;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_sweep<double>(int, const Sell<double>&, const double*, const double*, const double*,
+                                         double*, double, int, const int32_t*, hipStream_t);
+template hipError_t launch_sweep<float>(int, const Sell<float>&, const float*, const float*, const float*, float*,
+                                        float, int, const int32_t*, hipStream_t);
+template hipError_t launch_spmv<double>(int, const Sell<double>&, const double*, const double*, double*, int,
+                                        hipStream_t);
+template hipError_t launch_spmv<float>(int, const Sell<float>&, const float*, const float*, float*, int,
+                                       hipStream_t);
+
+// ============================================================ layout conversion
+
+// one thread per (slot, i, j): slot = (slice, k, g); value goes to
+// vals[slot_voff[slot] + (k*bc + j)*L + g*br + i] where slot_voff already
+// includes the slice offset and the k*bc*L term plus g*br.
+__global__ void k_to_sell_vals(const double* __restrict__ nat, const int64_t* __restrict__ slot_src, int64_t n_slots,
+                               int L, int br, int bc, const int64_t* __restrict__ slot_voff, double* __restrict__ vals) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(br) * bc;
+    if (t >= n_slots * per) return;
+    const int64_t slot = t / per;
+    const int rem = int(t - slot * per);
+    const int i = rem / bc, j = rem - (rem / bc) * bc;
+    const int64_t src = slot_src[slot];
+    vals[slot_voff[slot] + int64_t(j) * L + i] = src >= 0 ? nat[src * per + int64_t(i) * bc + j] : 0.0;
+}
+
+hipError_t launch_to_sell_vals(const double* nat, const int64_t* slot_src, int64_t n_slots, int G, int L, int br,
+                               int bc, const int64_t* slot_voff, double* vals, hipStream_t st) {
+    (void)G;
+    const int64_t tot = n_slots * br * bc;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_sell_vals, dim3(grid_for(tot)), dim3(WG), 0, st, nat, slot_src, n_slots, L, br, bc,
+                       slot_voff, vals);
+    return hipGetLastError();
+}
+
+__global__ void k_dinv_to_sell(const double* __restrict__ dn, int64_t n_brow, int br, int G, int L,
+                               double* __restrict__ ds) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(br) * br;
+    if (t >= n_brow * per) return;
+    const int64_t e = t / per;
+    const int rem = int(t - e * per);
+    const int i = rem / br, j = rem - (rem / br) * br;
+    const int64_t s = e / G;
+    const int g = int(e - s * G);
+    ds[s * br * L + int64_t(j) * L + g * br + i] = dn[t];
+}
+
+hipError_t launch_dinv_to_sell(const double* dn, int64_t n_brow, int br, int G, int L, double* ds, hipStream_t st) {
+    const int64_t tot = n_brow * br * br;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dinv_to_sell, dim3(grid_for(tot)), dim3(WG), 0, st, dn, n_brow, br, G, L, ds);
+    return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+__global__ void k_convert(const Ti* __restrict__ a, To* __restrict__ b, int64_t n) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = To(a[t]);  // double -> float rounds to nearest even
+}
+
+template <typename Ti, typename To>
+hipError_t launch_convert(const Ti* in, To* out, int64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_convert<Ti, To>), dim3(grid_for(n)), dim3(WG), 0, st, in, out, n);
+    return hipGetLastError();
+}
+template hipError_t launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template hipError_t launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template hipError_t launch_convert<double, double>(const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_convert<float, float>(const float*, float*, int64_t, hipStream_t);
+
+hipError_t launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st) {
+    return launch_convert<double, float>(a, b, n, st);
+}
+hipError_t launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st) {
+    return launch_convert<float, double>(a, b, n, st);
+}
+
+// ============================================================ block inverse
+// Batched Gauss-Jordan with partial pivoting (LAPACK-style pivot choice: the
+// largest magnitude, the lowest row on ties).  One lane holds one row of the
+// augmented block [D | I]; floor(64/nb) blocks per wavefront; nb <= 16.
+constexpr int MAXB = 16;
+
+__global__ __launch_bounds__(WG) void k_block_inverse(const double* __restrict__ Av, const int32_t* __restrict__ dpos,
+                                                      int64_t n_brow, int nb, double* __restrict__ dinv,
+                                                      int32_t* __restrict__ flag) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int G = 64 / nb;
+    const int L = G * nb;
+    const int lc = lane < L ? lane : L - 1;
+    const int g = lc / nb, i = lc - g * nb;
+    const int64_t blk = (int64_t(blockIdx.x) * WAVES_PER_WG + wave) * G + g;
+    const bool own = lane < L && blk < n_brow;
+    const int base = g * nb;
+    double a[MAXB], v[MAXB];
+    const double* src = own ? Av + int64_t(dpos[blk]) * nb * nb + int64_t(i) * nb : nullptr;
+    double amax = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        a[q] = (own && q < nb) ? src[q] : 0.0;
+        v[q] = (q == i) ? 1.0 : 0.0;
+        amax = fmax(amax, fabs(a[q]));
+    }
+    for (int j = 0; j < nb; ++j) amax = fmax(amax, __shfl(amax, base + j));
+    const double tol = nb * DBL_EPSILON * amax;
+    bool singular = (amax == 0.0);
+    for (int c = 0; c < nb; ++c) {
+        double ac = 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q)
+            if (q == c) ac = a[q];
+        // pivot row p >= c of largest |a[p][c]|
+        int p = c;
+        double best = -1.0;
+        for (int j = c; j < nb; ++j) {
+            const double val = fabs(__shfl(ac, base + j));
+            if (val > best) { best = val; p = j; }
+        }
+        // swap rows c and p
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            const double ap = __shfl(a[q], base + p), acq = __shfl(a[q], base + c);
+            const double vp = __shfl(v[q], base + p), vcq = __shfl(v[q], base + c);
+            if (i == c) { a[q] = ap; v[q] = vp; }
+            else if (i == p) { a[q] = acq; v[q] = vcq; }
+        }
+        double acol = 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q)
+            if (q == c) acol = a[q];
+        const double piv = __shfl(acol, base + c);
+        if (!(fabs(piv) > tol)) singular = true;
+        const double inv = 1.0 / piv;
+        double rc[MAXB], vc[MAXB];
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q) {
+            rc[q] = __shfl(a[q], base + c) * inv;
+            vc[q] = __shfl(v[q], base + c) * inv;
+        }
+        if (i == c) {
+#pragma unroll
+            for (int q = 0; q < MAXB; ++q) { a[q] = rc[q]; v[q] = vc[q]; }
+        } else {
+            const double f = acol;
+#pragma unroll
+            for (int q = 0; q < MAXB; ++q) { a[q] -= f * rc[q]; v[q] -= f * vc[q]; }
+        }
+    }
+    if (!own) return;
+    if (singular) atomicOr(flag, 1);
+    double* dst = dinv + blk * nb * nb + int64_t(i) * nb;
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q)
+        if (q < nb) dst[q] = v[q];
+}
+
+hipError_t launch_block_inverse(const double* Av, const int32_t* dpos, int64_t n_brow, int nb, double* dinv,
+                                int32_t* flag, hipStream_t st) {
+    if (nb < 1 || nb > MAXB) return hipErrorInvalidValue;
+    const int G = 64 / nb;
+    const int64_t waves = (n_brow + G - 1) / G;
+    if (waves == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_inverse, dim3(grid_for(waves, WAVES_PER_WG)), dim3(WG), 0, st, Av, dpos, n_brow, nb,
+                       dinv, flag);
+    return hipGetLastError();
+}
+
+// ============================================================ SVD (one-sided Jacobi)
+// One wavefront per aggregate J.  The rows of J are the contiguous dofs
+// [first_child[J] * nb, first_child[J+1] * nb) of B (row-major, r columns).
+// Lanes hold rows lane and lane + 64 (<= 128 rows), r <= 8 columns.  Hestenes'
+// one-sided Jacobi rotates column pairs until they are orthogonal to working
+// precision; the singular values are the column norms and the left singular
+// vectors the normalised columns.  Output: the leading s columns (descending
+// singular values), each flipped so its largest-magnitude entry (lowest row on
+// ties) is positive, written to Pu (row-major n x s), and all r singular values.
+constexpr int SVD_MAXR = 8;
+constexpr int SVD_MAXROWS = 128;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(WG) void k_svd(const double* __restrict__ B, int r, const int32_t* __restrict__ fc,
+                                            int64_t n_agg, int nb, int s, double* __restrict__ Pu,
+                                            double* __restrict__ sv, int32_t* __restrict__ flag) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t J = int64_t(blockIdx.x) * WAVES_PER_WG + wave;
+    if (J >= n_agg) return;
+    const int64_t r0 = int64_t(fc[J]) * nb;
+    const int nrows = int(int64_t(fc[J + 1]) * nb - r0);
+    if (nrows > SVD_MAXROWS) { if (lane == 0) atomicOr(flag, 2); return; }
+    double m0[SVD_MAXR], m1[SVD_MAXR];
+    const bool h0 = lane < nrows, h1 = lane + 64 < nrows;
+#pragma unroll
+    for (int c = 0; c < SVD_MAXR; ++c) {
+        m0[c] = (h0 && c < r) ? B[(r0 + lane) * r + c] : 0.0;
+        m1[c] = (h1 && c < r) ? B[(r0 + lane + 64) * r + c] : 0.0;
+    }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        bool rotated = false;
+#pragma unroll
+        for (int p = 0; p < SVD_MAXR; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < SVD_MAXR; ++q) {
+                if (q >= r) continue;
+                const double al = wave_sum(m0[p] * m0[p] + m1[p] * m1[p]);
+                const double be = wave_sum(m0[q] * m0[q] + m1[q] * m1[q]);
+                const double ga = wave_sum(m0[p] * m0[q] + m1[p] * m1[q]);
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                rotated = true;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                const double a0 = m0[p], b0 = m0[q], a1 = m1[p], b1 = m1[q];
+                m0[p] = cs * a0 - sn * b0;
+                m0[q] = sn * a0 + cs * b0;
+                m1[p] = cs * a1 - sn * b1;
+                m1[q] = sn * a1 + cs * b1;
+            }
+        }
+        if (!rotated) break;
+    }
+    double sig[SVD_MAXR];
+#pragma unroll
+    for (int c = 0; c < SVD_MAXR; ++c) sig[c] = (c < r) ? sqrt(wave_sum(m0[c] * m0[c] + m1[c] * m1[c])) : -1.0;
+#pragma unroll
+    for (int c = 0; c < SVD_MAXR; ++c) {
+        if (c >= r) continue;
+        int rank = 0;
+#pragma unroll
+        for (int q = 0; q < SVD_MAXR; ++q)
+            if (q < r && (sig[q] > sig[c] || (sig[q] == sig[c] && q < c))) ++rank;
+        if (lane == 0) sv[J * r + rank] = sig[c];
+        if (rank >= s) continue;
+        if (!(sig[c] > 0.0)) { if (lane == 0) atomicOr(flag, 4); }
+        const double inv = sig[c] > 0.0 ? 1.0 / sig[c] : 0.0;
+        const double u0 = m0[c] * inv, u1 = m1[c] * inv;
+        // largest magnitude entry, lowest row on ties
+        double bv = h0 ? fabs(u0) : -1.0;
+        int brw = lane;
+        if (h1 && fabs(u1) > bv) { bv = fabs(u1); brw = lane + 64; }
+        double sgnv = (brw == lane) ? u0 : u1;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int orw = __shfl_xor(brw, o);
+            const double os = __shfl_xor(sgnv, o);
+            if (ov > bv || (ov == bv && orw < brw)) { bv = ov; brw = orw; sgnv = os; }
+        }
+        const double fl = sgnv < 0.0 ? -1.0 : 1.0;
+        if (h0) Pu[(r0 + lane) * s + rank] = fl * u0;
+        if (h1) Pu[(r0 + lane + 64) * s + rank] = fl * u1;
+    }
+}
+
+hipError_t launch_svd(const double* B, int r, const int32_t* fc, int64_t n_agg, int nb, int s, double* Pu,
+                      double* sv, int32_t* flag, hipStream_t st) {
+    if (r < 1 || r > SVD_MAXR || s < 1 || s > r) return hipErrorInvalidValue;
+    if (n_agg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_svd, dim3(grid_for(n_agg, WAVES_PER_WG)), dim3(WG), 0, st, B, r, fc, n_agg, nb, s, Pu, sv,
+                       flag);
+    return hipGetLastError();
+}
+
+// ============================================================ T, R, A T, Galerkin
+// Small dense block products driven by host-built index lists (symbolic phase).
+// One thread per (output block, output row); s <= 16 accumulators per thread.
+
+// W_t = sum_{a in Tm(t)} A_a * P~[col(a)]   (nb x s);  T_t = [J==agg(e)] P~[e] - omega D_e^{-1} W_t
+__global__ void k_T_W(const double* __restrict__ Av, const int32_t* __restrict__ A_ci, const int32_t* __restrict__ Tm_ptr,
+                      const int32_t* __restrict__ Tm_a, int64_t nT, int nb, int s, const double* __restrict__ Pu,
+                      double* __restrict__ W) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= nT * nb) return;
+    const int64_t t = tid / nb;
+    const int i = int(tid - t * nb);
+    double acc[MAXB];
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+    for (int32_t q = Tm_ptr[t]; q < Tm_ptr[t + 1]; ++q) {
+        const int32_t a = Tm_a[q];
+        const double* Ar = Av + int64_t(a) * nb * nb + int64_t(i) * nb;
+        const double* Pc = Pu + int64_t(A_ci[a]) * nb * s;
+        for (int j = 0; j < nb; ++j) {
+            const double av = Ar[j];
+#pragma unroll
+            for (int l = 0; l < MAXB; ++l)
+                if (l < s) acc[l] += av * Pc[j * s + l];
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l)
+        if (l < s) W[(t * nb + i) * s + l] = acc[l];
+}
+
+__global__ void k_T_final(const int32_t* __restrict__ T_row, const int32_t* __restrict__ T_ci,
+                          const int32_t* __restrict__ agg, int64_t nT, int nb, int s, const double* __restrict__ Pu,
+                          const double* __restrict__ dinv, double omega, const double* __restrict__ W,
+                          double* __restrict__ Tv) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= nT * nb) return;
+    const int64_t t = tid / nb;
+    const int i = int(tid - t * nb);
+    const int64_t e = T_row[t];
+    const bool own = T_ci[t] == agg[e];
+    double acc[MAXB];
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+    const double* Dr = dinv + e * nb * nb + int64_t(i) * nb;
+    const double* Wt = W + t * nb * s;
+    for (int j = 0; j < nb; ++j) {
+        const double d = Dr[j];
+#pragma unroll
+        for (int l = 0; l < MAXB; ++l)
+            if (l < s) acc[l] += d * Wt[j * s + l];
+    }
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l)
+        if (l < s) Tv[(t * nb + i) * s + l] = (own ? Pu[(e * nb + i) * s + l] : 0.0) - omega * acc[l];
+}
+
+hipError_t launch_T_build(const double* Av, const int32_t* A_ci, const int32_t* T_row, const int32_t* T_ci,
+                          const int32_t* Tm_ptr, const int32_t* Tm_a, const int32_t* agg, int64_t nT, int nb, int s,
+                          const double* Pu, const double* dinv, double omega, double* W, double* Tv, hipStream_t st) {
+    if (s > MAXB) return hipErrorInvalidValue;
+    if (nT == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_T_W, dim3(grid_for(nT * nb)), dim3(WG), 0, st, Av, A_ci, Tm_ptr, Tm_a, nT, nb, s, Pu, W);
+    hipLaunchKernelGGL(k_T_final, dim3(grid_for(nT * nb)), dim3(WG), 0, st, T_row, T_ci, agg, nT, nb, s, Pu, dinv,
+                       omega, W, Tv);
+    return hipGetLastError();
+}
+
+__global__ void k_R_from_T(const double* __restrict__ Tv, const int32_t* __restrict__ R_t, int64_t nR, int nb, int s,
+                           double* __restrict__ Rv) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(nb) * s;
+    if (tid >= nR * per) return;
+    const int64_t rb = tid / per;
+    const int rem = int(tid - rb * per);
+    const int l = rem / nb, j = rem - (rem / nb) * nb;  // R block is s x nb: (l, j)
+    Rv[tid] = Tv[int64_t(R_t[rb]) * per + int64_t(j) * s + l];
+}
+
+hipError_t launch_R_from_T(const double* Tv, const int32_t* R_t, int64_t nR, int nb, int s, double* Rv,
+                           hipStream_t st) {
+    const int64_t tot = nR * nb * s;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_R_from_T, dim3(grid_for(tot)), dim3(WG), 0, st, Tv, R_t, nR, nb, s, Rv);
+    return hipGetLastError();
+}
+
+// AT_u = sum over pairs (a, t) of A_a (nb x nb) * T_t (nb x s)
+__global__ void k_AT(const double* __restrict__ Av, const double* __restrict__ Tv, const int64_t* __restrict__ pp,
+                     const int32_t* __restrict__ pa, const int32_t* __restrict__ pt, int64_t nAT, int nb, int s,
+                     double* __restrict__ ATv) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= nAT * nb) return;
+    const int64_t u = tid / nb;
+    const int i = int(tid - u * nb);
+    double acc[MAXB];
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+    for (int64_t q = pp[u]; q < pp[u + 1]; ++q) {
+        const double* Ar = Av + int64_t(pa[q]) * nb * nb + int64_t(i) * nb;
+        const double* Tt = Tv + int64_t(pt[q]) * nb * s;
+        for (int j = 0; j < nb; ++j) {
+            const double av = Ar[j];
+#pragma unroll
+            for (int l = 0; l < MAXB; ++l)
+                if (l < s) acc[l] += av * Tt[j * s + l];
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l)
+        if (l < s) ATv[(u * nb + i) * s + l] = acc[l];
+}
+
+hipError_t launch_AT(const double* Av, const double* Tv, const int64_t* pp, const int32_t* pa, const int32_t* pt,
+                     int64_t nAT, int nb, int s, double* ATv, hipStream_t st) {
+    if (s > MAXB) return hipErrorInvalidValue;
+    if (nAT == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_AT, dim3(grid_for(nAT * nb)), dim3(WG), 0, st, Av, Tv, pp, pa, pt, nAT, nb, s, ATv);
+    return hipGetLastError();
+}
+
+// C_v = sum over pairs (t, u) of T_t^T (s x nb) * AT_u (nb x s)
+__global__ void k_galerkin(const double* __restrict__ Tv, const double* __restrict__ ATv,
+                           const int64_t* __restrict__ pp, const int32_t* __restrict__ pt,
+                           const int32_t* __restrict__ pu, int64_t nC, int nb, int s, double* __restrict__ Cv) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= nC * s) return;
+    const int64_t v = tid / s;
+    const int i = int(tid - v * s);
+    double acc[MAXB];
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+    for (int64_t q = pp[v]; q < pp[v + 1]; ++q) {
+        const double* Tt = Tv + int64_t(pt[q]) * nb * s;
+        const double* Au = ATv + int64_t(pu[q]) * nb * s;
+        for (int j = 0; j < nb; ++j) {
+            const double tv = Tt[j * s + i];
+#pragma unroll
+            for (int l = 0; l < MAXB; ++l)
+                if (l < s) acc[l] += tv * Au[j * s + l];
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < MAXB; ++l)
+        if (l < s) Cv[(v * s + i) * s + l] = acc[l];
+}
+
+hipError_t launch_galerkin(const double* Tv, const double* ATv, const int64_t* pp, const int32_t* pt,
+                           const int32_t* pu, int64_t nC, int nb, int s, double* Cv, hipStream_t st) {
+    if (s > MAXB) return hipErrorInvalidValue;
+    if (nC == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_galerkin, dim3(grid_for(nC * s)), dim3(WG), 0, st, Tv, ATv, pp, pt, pu, nC, nb, s, Cv);
+    return hipGetLastError();
+}
+
+// ============================================================ coarsest level
+__global__ void k_dense_from_bsr(const double* __restrict__ vals, const int32_t* __restrict__ rp,
+                                 const int32_t* __restrict__ ci, int64_t n_brow, int nb, double* __restrict__ dense) {
+    const int64_t nnz = rp[n_brow];
+    const int64_t per = int64_t(nb) * nb;
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= nnz * per) return;
+    const int64_t blk = tid / per;
+    const int rem = int(tid - blk * per);
+    const int i = rem / nb, j = rem - (rem / nb) * nb;
+    // block row by binary search
+    int64_t lo = 0, hi = n_brow;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (rp[mid] <= blk) lo = mid; else hi = mid;
+    }
+    const int64_t n = n_brow * nb;
+    dense[(lo * nb + i) * n + int64_t(ci[blk]) * nb + j] = vals[tid];
+}
+
+hipError_t launch_dense_from_bsr(const double* vals, const int32_t* rp, const int32_t* ci, int64_t n_brow, int nb,
+                                 int64_t nnzb, double* dense, hipStream_t st) {
+    const int64_t n = n_brow * nb;
+    hipError_t e = hipMemsetAsync(dense, 0, sizeof(double) * n * n, st);
+    if (e != hipSuccess) return e;
+    const int64_t tot = nnzb * nb * nb;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dense_from_bsr, dim3(grid_for(tot)), dim3(WG), 0, st, vals, rp, ci, n_brow, nb, dense);
+    return hipGetLastError();
+}
+
+__global__ void k_absmax_part(const double* __restrict__ a, int64_t n, double* __restrict__ out) {
+    __shared__ double sh[WG];
+    double m = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) m = fmax(m, fabs(a[i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+__global__ void k_absmax_final(const double* __restrict__ part, int np, double* __restrict__ out) {
+    __shared__ double sh[WG];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < np; i += WG) m = fmax(m, part[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+hipError_t launch_absmax(const double* a, int64_t n, double* out, hipStream_t st) {
+    // out must hold 1 + DOT_PARTS doubles: out[0] result, out[1..] partials
+    const int np = int(std::min<int64_t>(DOT_PARTS, std::max<int64_t>(1, (n + WG - 1) / WG)));
+    hipLaunchKernelGGL(k_absmax_part, dim3(np), dim3(WG), 0, st, a, n, out + 1);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(WG), 0, st, out + 1, np, out);
+    return hipGetLastError();
+}
+
+// In-place Gauss-Jordan inversion with row pivoting, one elimination step per
+// call: (1) one workgroup picks the pivot row (largest |a[i][c]|, i >= c, lowest
+// row on ties), swaps it into row c and saves row c and column c; (2) the rank-1
+// update of every entry.  After all steps the row interchanges are undone as
+// column interchanges in reverse order.
+__global__ void k_gj_pivot(double* __restrict__ a, int64_t n, int64_t c, int32_t* __restrict__ piv,
+                           int32_t* __restrict__ flag, const double* __restrict__ amax, double tol_scale,
+                           double* __restrict__ rowc, double* __restrict__ colc) {
+    __shared__ double bv[1024];
+    __shared__ int64_t bi[1024];
+    const int t = threadIdx.x;
+    double best = -1.0;
+    int64_t bidx = c;
+    for (int64_t i = c + t; i < n; i += blockDim.x) {
+        const double v = fabs(a[i * n + c]);
+        if (v > best) { best = v; bidx = i; }
+    }
+    bv[t] = best;
+    bi[t] = bidx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            if (bv[t + o] > bv[t] || (bv[t + o] == bv[t] && bi[t + o] < bi[t])) { bv[t] = bv[t + o]; bi[t] = bi[t + o]; }
+        }
+        __syncthreads();
+    }
+    const int64_t p = bi[0];
+    if (t == 0) {
+        piv[c] = int32_t(p);
+        if (!(bv[0] > tol_scale * amax[0])) atomicOr(flag, 1);
+    }
+    if (p != c)
+        for (int64_t j = t; j < n; j += blockDim.x) {
+            const double tmp = a[c * n + j];
+            a[c * n + j] = a[p * n + j];
+            a[p * n + j] = tmp;
+        }
+    __syncthreads();
+    for (int64_t j = t; j < n; j += blockDim.x) {
+        rowc[j] = a[c * n + j];
+        colc[j] = a[j * n + c];
+    }
+}
+
+__global__ void k_gj_update(double* __restrict__ a, int64_t n, int64_t c, const double* __restrict__ rowc,
+                            const double* __restrict__ colc) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= n * n) return;
+    const int64_t i = tid / n, j = tid - (tid / n) * n;
+    const double pv = rowc[c];
+    double v;
+    if (i != c && j != c) v = a[tid] - colc[i] * rowc[j] / pv;
+    else if (i == c && j != c) v = rowc[j] / pv;
+    else if (i != c) v = -colc[i] / pv;
+    else v = 1.0 / pv;
+    a[tid] = v;
+}
+
+__global__ void k_gj_unpermute(double* __restrict__ a, int64_t n, const int32_t* __restrict__ piv) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double* row = a + i * n;
+    for (int64_t c = n - 1; c >= 0; --c) {
+        const int64_t p = piv[c];
+        if (p != c) {
+            const double tmp = row[c];
+            row[c] = row[p];
+            row[p] = tmp;
+        }
+    }
+}
+
+hipError_t launch_gj_invert(double* a, int64_t n, int32_t* piv, int32_t* flag, const double* amax, double tol_scale,
+                            double* rowc, double* colc, hipStream_t st) {
+    for (int64_t c = 0; c < n; ++c) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, a, n, c, piv, flag, amax, tol_scale, rowc, colc);
+        hipLaunchKernelGGL(k_gj_update, dim3(grid_for(n * n)), dim3(WG), 0, st, a, n, c, rowc, colc);
+    }
+    hipLaunchKernelGGL(k_gj_unpermute, dim3(grid_for(n)), dim3(WG), 0, st, a, n, piv);
+    return hipGetLastError();
+}
+
+// ============================================================ random streams
+// SplitMix64 (Steele, Lea & Flood 2014): output i of the stream seeded with s is
+// mix(s + (i+1) * 0x9E3779B97F4A7C15); uniform double = (z >> 11) * 2^-53.
+__device__ __forceinline__ uint64_t splitmix(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double u01(uint64_t z) { return double(z >> 11) * 0x1.0p-53; }
+
+// x[u*nb + i] = 2 U(seed, (perm ? perm[u] : u) * nb + i) - 1
+__global__ void k_uniform(uint64_t seed, const int64_t* __restrict__ perm, int64_t n_units, int nb, double* __restrict__ x) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_units * nb) return;
+    const int64_t u = t / nb;
+    const int i = int(t - u * nb);
+    const int64_t e = perm ? perm[u] : u;
+    x[t] = 2.0 * u01(splitmix(seed, uint64_t(e * nb + i))) - 1.0;
+}
+
+hipError_t launch_uniform(uint64_t seed, const int64_t* perm, int64_t n_units, int nb, double* x, hipStream_t st) {
+    if (n_units * nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uniform, dim3(grid_for(n_units * nb)), dim3(WG), 0, st, seed, perm, n_units, nb, x);
+    return hipGetLastError();
+}
+
+// Box-Muller normals: stream index k = (caller dof) * r + c; pair k/2 uses
+// u1 = 1 - U(2*(k/2)), u2 = U(2*(k/2)+1); even k -> R cos(2 pi u2), odd -> R sin.
+__global__ void k_normal(uint64_t seed, const int64_t* __restrict__ perm, int64_t n_units, int nb, int r,
+                         double* __restrict__ x) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_units * nb * r) return;
+    const int64_t row = t / r;
+    const int c = int(t - row * r);
+    const int64_t u = row / nb;
+    const int i = int(row - u * nb);
+    const int64_t e = perm ? perm[u] : u;
+    const uint64_t k = uint64_t((e * nb + i) * r + c);
+    const uint64_t pr = k >> 1;
+    const double u1 = 1.0 - u01(splitmix(seed, 2 * pr));
+    const double u2 = u01(splitmix(seed, 2 * pr + 1));
+    const double R = sqrt(-2.0 * log(u1));
+    x[t] = (k & 1) ? R * sin(2.0 * M_PI * u2) : R * cos(2.0 * M_PI * u2);
+}
+
+hipError_t launch_normal(uint64_t seed, const int64_t* perm, int64_t n_units, int nb, int r, double* x, hipStream_t st) {
+    const int64_t tot = n_units * nb * r;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_normal, dim3(grid_for(tot)), dim3(WG), 0, st, seed, perm, n_units, nb, r, x);
+    return hipGetLastError();
+}
+
+// ============================================================ reductions
+// Deterministic two-pass dot products: a fixed grid of partial sums (grid-stride
+// loop, LDS tree), then one workgroup sums the partials in a fixed order.
+template <typename T, int M>
+__global__ __launch_bounds__(WG) void k_dot_part(const T* __restrict__ a, const T* __restrict__ b, int64_t n, int ld,
+                                                 double* __restrict__ part) {
+    __shared__ double sh[WG];
+    double s[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) s[c] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) s[c] += double(a[i * ld + c]) * double(b[i * ld + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        sh[threadIdx.x] = s[c];
+        __syncthreads();
+        for (int o = WG / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[int64_t(c) * gridDim.x + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(WG) void k_sum_parts(const double* __restrict__ part, int np, int m, double* __restrict__ out) {
+    __shared__ double sh[WG];
+    for (int c = 0; c < m; ++c) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < np; i += WG) s += part[int64_t(c) * np + i];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = WG / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = sh[0];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+hipError_t launch_dot(const T* a, const T* b, int64_t n, int m, double* part, double* out, hipStream_t st) {
+    // part must hold DOT_PARTS * m doubles
+    const int np = int(std::min<int64_t>(DOT_PARTS, std::max<int64_t>(1, (n + WG - 1) / WG)));
+    int c0 = 0;
+    while (c0 < m) {
+        const int rem = m - c0;
+        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        double* pc = part + int64_t(c0) * np;
+        switch (w) {
+            case 16: hipLaunchKernelGGL((k_dot_part<T, 16>), dim3(np), dim3(WG), 0, st, a + c0, b + c0, n, m, pc); break;
+            case 8: hipLaunchKernelGGL((k_dot_part<T, 8>), dim3(np), dim3(WG), 0, st, a + c0, b + c0, n, m, pc); break;
+            case 4: hipLaunchKernelGGL((k_dot_part<T, 4>), dim3(np), dim3(WG), 0, st, a + c0, b + c0, n, m, pc); break;
+            case 3: hipLaunchKernelGGL((k_dot_part<T, 3>), dim3(np), dim3(WG), 0, st, a + c0, b + c0, n, m, pc); break;
+            case 2: hipLaunchKernelGGL((k_dot_part<T, 2>), dim3(np), dim3(WG), 0, st, a + c0, b + c0, n, m, pc); break;
+            default: hipLaunchKernelGGL((k_dot_part<T, 1>), dim3(np), dim3(WG), 0, st, a + c0, b + c0, n, m, pc); break;
+        }
+        c0 += w;
+    }
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(WG), 0, st, part, np, m, out);
+    return hipGetLastError();
+}
+template hipError_t launch_dot<double>(const double*, const double*, int64_t, int, double*, double*, hipStream_t);
+template hipError_t launch_dot<float>(const float*, const float*, int64_t, int, double*, double*, hipStream_t);
+
+// ============================================================ Krylov vector ops
+__global__ void k_axpby_dev(const double* __restrict__ x, double* __restrict__ y, int64_t n, int m,
+                            const double* __restrict__ alpha, double sa, double by) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * m) return;
+    const int c = int(t % m);
+    const double a = (alpha ? alpha[c] : 1.0) * sa;
+    y[t] = a * x[t] + by * y[t];
+}
+
+hipError_t launch_axpby_dev(const double* x, double* y, int64_t n, int m, const double* alpha, double sa, double by,
+                            hipStream_t st) {
+    if (n * m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpby_dev, dim3(grid_for(n * m)), dim3(WG), 0, st, x, y, n, m, alpha, sa, by);
+    return hipGetLastError();
+}
+
+__global__ void k_cg_xr(double* __restrict__ x, const double* r_in, double* r_out, const double* __restrict__ p,
+                        const double* __restrict__ q, int64_t n, int m, const double* __restrict__ alpha) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * m) return;
+    const double a = alpha[t % m];
+    x[t] += a * p[t];
+    r_out[t] = r_in[t] - a * q[t];
+}
+
+hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const double* p, const double* q, int64_t n,
+                        int m, const double* alpha, hipStream_t st) {
+    if (n * m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_xr, dim3(grid_for(n * m)), dim3(WG), 0, st, x, r_in, r_out, p, q, n, m, alpha);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_cols(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int m,
+                            const int32_t* __restrict__ mask) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * m) return;
+    if (mask[t % m]) dst[t] = src[t];
+}
+
+hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, const int32_t* mask, hipStream_t st) {
+    if (n * m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(n * m)), dim3(WG), 0, st, src, dst, n, m, mask);
+    return hipGetLastError();
+}
+
+__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, int64_t n, int m,
+                       const double* __restrict__ beta) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n * m) return;
+    p[t] = z[t] + beta[t % m] * p[t];
+}
+
+hipError_t launch_cg_p(double* p, const double* z, int64_t n, int m, const double* beta, hipStream_t st) {
+    if (n * m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * m)), dim3(WG), 0, st, p, z, n, m, beta);
+    return hipGetLastError();
+}
+
+__global__ void k_div_scalars(const double* __restrict__ num, const double* __restrict__ den,
+                              const int32_t* __restrict__ active, int m, double* __restrict__ out, int32_t checkpos,
+                              int32_t* __restrict__ flag) {
+    const int c = threadIdx.x;
+    if (c >= m) return;
+    if (!active[c]) { out[c] = 0.0; return; }
+    const double d = den[c];
+    if (checkpos && !(d > 0.0)) atomicOr(flag, 1);
+    const double v = num[c] / d;
+    if (!isfinite(v)) atomicOr(flag, 2);
+    out[c] = isfinite(v) ? v : 0.0;
+}
+
+hipError_t launch_div_scalars(const double* num, const double* den, const int32_t* active, int m, double* out,
+                              int32_t check_positive, int32_t* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_div_scalars, dim3(1), dim3(64), 0, st, num, den, active, m, out, check_positive, flag);
+    return hipGetLastError();
+}
+
+__global__ void k_beta(const double* __restrict__ rz_new, const double* __restrict__ sub, double* __restrict__ rz,
+                       const int32_t* __restrict__ active, int m, double* __restrict__ beta) {
+    const int c = threadIdx.x;
+    if (c >= m) return;
+    const double nw = rz_new[c];
+    beta[c] = active[c] ? (nw - (sub ? sub[c] : 0.0)) / rz[c] : 0.0;
+    rz[c] = nw;
+}
+
+hipError_t launch_beta(const double* rz_new, const double* sub, double* rz, const int32_t* active, int m,
+                       double* beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_beta, dim3(1), dim3(64), 0, st, rz_new, sub, rz, active, m, beta);
+    return hipGetLastError();
+}
+
+// dense y = A x, one wavefront per row, lanes stride the columns
+template <int M>
+__global__ __launch_bounds__(WG) void k_gemv(const double* __restrict__ A, const double* __restrict__ x,
+                                             double* __restrict__ y, int64_t n, int ld) {
+    const int64_t row = int64_t(blockIdx.x) * WAVES_PER_WG + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int lane = threadIdx.x & 63;
+    double acc[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) acc[c] = 0.0;
+    const double* Ar = A + row * n;
+    for (int64_t j = lane; j < n; j += 64) {
+        const double a = Ar[j];
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[c] += a * x[j * ld + c];
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const double v = wave_sum(acc[c]);
+        if (lane == 0) y[row * ld + c] = v;
+    }
+}
+
+hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n, int m, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    dim3 grid(grid_for(n, WAVES_PER_WG));
+    int c0 = 0;
+    while (c0 < m) {
+        const int rem = m - c0;
+        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        switch (w) {
+            case 16: hipLaunchKernelGGL((k_gemv<16>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 8: hipLaunchKernelGGL((k_gemv<8>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 4: hipLaunchKernelGGL((k_gemv<4>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 3: hipLaunchKernelGGL((k_gemv<3>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 2: hipLaunchKernelGGL((k_gemv<2>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            default: hipLaunchKernelGGL((k_gemv<1>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+        }
+        c0 += w;
+    }
+    return hipGetLastError();
+}
+
+// level-0 reordering between caller element order and internal order
+template <typename Ti, typename To>
+__global__ void k_permute(const Ti* __restrict__ in, To* __restrict__ out, const int64_t* __restrict__ perm,
+                          int64_t n_units, int per_unit, int gather) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_units * per_unit) return;
+    const int64_t u = t / per_unit;
+    const int64_t w = t - u * per_unit;
+    const int64_t ext = perm[u] * per_unit + w;
+    if (gather) out[t] = To(in[ext]);
+    else out[ext] = To(in[t]);
+}
+
+template <typename Ti, typename To>
+hipError_t launch_permute(const Ti* in, To* out, const int64_t* perm, int64_t n_units, int nb, int m, int gather,
+                          hipStream_t st) {
+    const int64_t tot = n_units * nb * m;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_permute<Ti, To>), dim3(grid_for(tot)), dim3(WG), 0, st, in, out, perm, n_units, nb * m,
+                       gather);
+    return hipGetLastError();
+}
+template hipError_t launch_permute<double, double>(const double*, double*, const int64_t*, int64_t, int, int, int, hipStream_t);
+template hipError_t launch_permute<double, float>(const double*, float*, const int64_t*, int64_t, int, int, int, hipStream_t);
+template hipError_t launch_permute<float, double>(const float*, double*, const int64_t*, int64_t, int, int, int, hipStream_t);
+template hipError_t launch_permute<float, float>(const float*, float*, const int64_t*, int64_t, int, int, int, hipStream_t);
+
+__global__ void k_scale_inv_norm(double* __restrict__ x, int64_t n, const double* __restrict__ nrm2) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = x[t] / sqrt(nrm2[0]);
+}
+
+hipError_t launch_scale_by_inv_norm(double* x, int64_t n, const double* nrm2, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_inv_norm, dim3(grid_for(n)), dim3(WG), 0, st, x, n, nrm2);
+    return hipGetLastError();
+}
+
+// h[j] = V[j] . w ; grid (parts, nv), fixed order
+__global__ __launch_bounds__(WG) void k_multidot_part(const double* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ w, int64_t n, double* __restrict__ part) {
+    __shared__ double sh[WG];
+    const int j = blockIdx.y;
+    const double* v = V + int64_t(j) * ldv;
+    double s = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) s += v[i] * w[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[int64_t(j) * gridDim.x + blockIdx.x] = sh[0];
+}
+
+hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* part,
+                           double* out, hipStream_t st) {
+    // part must hold 256 * nv doubles
+    const int np = int(std::min<int64_t>(256, std::max<int64_t>(1, (n + WG - 1) / WG)));
+    hipLaunchKernelGGL(k_multidot_part, dim3(np, nv), dim3(WG), 0, st, V, ldv, w, n, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(WG), 0, st, part, np, nv, out);
+    return hipGetLastError();
+}
+
+__global__ void k_multi_axpy(const double* __restrict__ V, int64_t ldv, int nv, const double* __restrict__ h,
+                             double* __restrict__ w, int64_t n, double sign) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < nv; ++j) s += V[int64_t(j) * ldv + i] * h[j];
+    w[i] += sign * s;
+}
+
+hipError_t launch_multi_axpy(const double* V, int64_t ldv, int nv, const double* h, double* w, int64_t n, double sign,
+                             hipStream_t st) {
+    if (n == 0 || nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n)), dim3(WG), 0, st, V, ldv, nv, h, w, n, sign);
+    return hipGetLastError();
+}
+
+}  // namespace amgdg

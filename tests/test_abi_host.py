@@ -1,0 +1,127 @@
+"""Host-only checks of libamgdg (no GPU): the library loads, exports every
+symbol include/amgdg.h declares, and its index construction (recursive
+coordinate bisection, renumbering, symbolic patterns of T, R and A_{k+1})
+matches the oracle bit for bit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2504_13373_amd as am
+from oracle import amg, rcb
+from workloads import configs, mesh as meshes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "amgdg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(amgdg_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = am.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("side,levels,bis", [(23, 4, 2), (40, 5, 2), (17, 3, 3)])
+def test_rcb_bit_exact_vs_oracle(side, levels, bis):
+    m = meshes.jittered_delaunay(side, seed=side)
+    c = m.centroids()
+    agg_lib, leaf_lib = am.amgdg_partition_rcb(c, levels, bis)
+    aggs, leaf = rcb.rcb_hierarchy(c, levels, bis)
+    elem = rcb.agg_of_elem_levels(aggs)
+    for k in range(levels - 1):
+        assert np.array_equal(agg_lib[k], elem[k])
+    assert np.array_equal(leaf_lib, leaf)
+
+
+def test_rcb_3d_bit_exact_vs_oracle():
+    m = meshes.kuhn_cube(5, seed=1)
+    c = m.centroids()
+    agg_lib, leaf_lib = am.amgdg_partition_rcb(c, 3, 3)
+    aggs, leaf = rcb.rcb_hierarchy(c, 3, 3)
+    elem = rcb.agg_of_elem_levels(aggs)
+    for k in range(2):
+        assert np.array_equal(agg_lib[k], elem[k])
+    assert np.array_equal(leaf_lib, leaf)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: configs.poisson2d_split(nx=8, p=1, n_levels=3, bisections=2, r=2),
+    lambda: configs.poisson2d_delaunay(side=33, p=1, n_levels=4, bisections=2, r=3),
+    lambda: configs.convdiff2d_delaunay(side=17, p=1, n_levels=3, r=2),
+])
+def test_symbolic_patterns_bit_exact_vs_oracle(maker):
+    w = maker()
+    nl = w.params.n_levels
+    agg_lib, _ = am.amgdg_partition_rcb(w.centroids, nl, w.params.bisections)
+    aggs, _ = rcb.rcb_hierarchy(w.centroids, nl, w.params.bisections)
+    pats = amg.block_patterns(w.A.row_ptr, w.A.col_idx, aggs)
+    plan = am.amgdg_plan_create(w.A.n_brow, w.A.row_ptr, w.A.col_idx, nl, agg_lib)
+    # level 0 A pattern is the input
+    assert np.array_equal(plan.export(0, am.AMGDG_A_ROWPTR), w.A.row_ptr)
+    assert np.array_equal(plan.export(0, am.AMGDG_A_COLIDX), w.A.col_idx)
+    for k in range(nl - 1):
+        assert np.array_equal(plan.export(k, am.AMGDG_T_ROWPTR), pats[k]["T_ptr"])
+        assert np.array_equal(plan.export(k, am.AMGDG_T_COLIDX), pats[k]["T_idx"])
+        assert np.array_equal(plan.export(k + 1, am.AMGDG_A_ROWPTR), pats[k]["A_ptr"])
+        assert np.array_equal(plan.export(k + 1, am.AMGDG_A_COLIDX), pats[k]["A_idx"])
+        # R = T^T: its pattern is the transpose
+        import scipy.sparse as sp
+        nun = len(pats[k]["T_ptr"]) - 1
+        Tp = sp.csr_matrix((np.ones(len(pats[k]["T_idx"])), pats[k]["T_idx"], pats[k]["T_ptr"]),
+                           shape=(nun, int(pats[k]["T_idx"].max()) + 1))
+        Rp = Tp.T.tocsr()
+        Rp.sort_indices()
+        assert np.array_equal(plan.export(k, am.AMGDG_R_ROWPTR), Rp.indptr)
+        assert np.array_equal(plan.export(k, am.AMGDG_R_COLIDX), Rp.indices)
+    perm = plan.export(0, am.AMGDG_PERM)
+    assert sorted(perm) == list(range(w.A.n_brow))
+    # every aggregate is a contiguous range of the internal order
+    for a in rcb.agg_of_elem_levels(aggs):
+        assert np.all(np.diff(a[perm]) >= 0)
+    plan.close()
+
+
+def test_plan_rejects_bad_input():
+    w = configs.poisson2d_split(nx=4, p=1, n_levels=2, bisections=2, r=1)
+    agg, _ = am.amgdg_partition_rcb(w.centroids, 2, 2)
+    ci = w.A.col_idx.copy()
+    ci[0], ci[1] = ci[1], ci[0]           # unsorted row
+    with pytest.raises(am.AmgdgError) as e:
+        am.amgdg_plan_create(w.A.n_brow, w.A.row_ptr, ci, 2, agg)
+    assert e.value.code == am.AMGDG_EINVAL
+    bad = agg.copy()
+    bad[0, :] = 0
+    bad[0, -1] = 2                          # id 1 never used: not dense
+    with pytest.raises(am.AmgdgError):
+        am.amgdg_plan_create(w.A.n_brow, w.A.row_ptr, w.A.col_idx, 2, bad)
+    # missing diagonal block
+    rp, ci = w.A.row_ptr.copy(), w.A.col_idx.copy()
+    keep = np.ones(len(ci), bool)
+    keep[np.nonzero(ci[rp[0]:rp[1]] == 0)[0][0] + rp[0]] = False
+    ci2 = ci[keep]
+    rp2 = rp.copy()
+    rp2[1:] -= 1
+    with pytest.raises(am.AmgdgError):
+        am.amgdg_plan_create(w.A.n_brow, rp2, ci2, 2, agg)
+    with pytest.raises(am.AmgdgError):
+        am.amgdg_partition_rcb(w.centroids, 30, 3)   # too many levels
+
+
+def test_non_nested_hierarchy_rejected():
+    w = configs.poisson2d_split(nx=4, p=1, n_levels=3, bisections=2, r=1)
+    agg, _ = am.amgdg_partition_rcb(w.centroids, 3, 2)
+    bad = agg.copy()
+    # move one element to a different level-2 aggregate than its level-1 siblings
+    e = int(np.nonzero(agg[0] == 0)[0][0])
+    bad[1, e] = (bad[1, e] + 1) % (bad[1].max() + 1)
+    with pytest.raises(am.AmgdgError) as ex:
+        am.amgdg_plan_create(w.A.n_brow, w.A.row_ptr, w.A.col_idx, 3, bad)
+    assert "nested" in str(ex.value)
