@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--side", type=int, default=256, help="grid points per side (256: the full workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--max-it", type=int, default=50000,
+                    help="iteration cap per solve (profiling runs cap it; the reported value needs convergence)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -85,7 +87,7 @@ def main():
     m = args.rhs
     b = torch.as_tensor(w.b.reshape(w.A.n, m) if m > 1 else w.b).to(dev).contiguous()
     x = torch.zeros_like(b)
-    maxit = 50000
+    maxit = args.max_it
 
     def solve(method, prec):
         x.zero_()

@@ -85,6 +85,17 @@ struct SellStore {
     int64_t n_vals = 0;
 };
 
+// An operator of the hierarchy in the layout its block shape calls for: the
+// sliced row-interleaved layout for tall blocks (br > 4), block CSR with a lane
+// group per block row for small blocks (coarse levels, restriction).
+struct MatStore {
+    bool vec = false;
+    SellStore s;
+    Bcsr<double> bd;
+    Bcsr<float> bf;
+    int64_t n_vals = 0;
+};
+
 template <typename T>
 struct VBuf {
     T *b = nullptr, *u = nullptr, *w = nullptr, *r = nullptr;
@@ -100,7 +111,8 @@ struct Level {
     double* Dinv_nat = nullptr;
     double* Dinv_sell = nullptr;
     float* Dinv_sell32 = nullptr;
-    SellStore A, T, R;
+    float* Dinv_nat32 = nullptr;
+    MatStore A, T, R;
     double *B_in = nullptr, *B_rel = nullptr, *Pu = nullptr, *sv = nullptr, *T_nat = nullptr, *R_nat = nullptr;
     VBuf<double> v64;
     VBuf<float> v32;
@@ -221,6 +233,75 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
 
 
 // ------------------------------------------------------------ setup
+static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const std::vector<int32_t>& rp,
+                      const std::vector<int32_t>& ci, const double* nat_d, bool f32, hipStream_t st) {
+    if (br <= BCSR_MAXBR) {
+        M.vec = true;
+        const int64_t nnzb = int64_t(ci.size());
+        const double avg = n_brow > 0 ? double(nnzb) / double(n_brow) : 1.0;
+        int P = 4;
+        while (P < avg && P < 64) P *= 2;
+        Bcsr<double> d;
+        d.n_brow = int32_t(n_brow);
+        d.br = br;
+        d.bc = bc;
+        d.P = P;
+        d.rp = upload(C.mem, rp, st);
+        d.ci = upload(C.mem, ci, st);
+        d.vals = nat_d;
+        M.bd = d;
+        M.bf.n_brow = d.n_brow;
+        M.bf.br = br;
+        M.bf.bc = bc;
+        M.bf.P = P;
+        M.bf.rp = d.rp;
+        M.bf.ci = d.ci;
+        M.n_vals = nnzb * br * bc;
+        if (f32) {
+            float* fv = C.mem.alloc<float>(M.n_vals);
+            HIPCHK(launch_f64_to_f32(nat_d, fv, M.n_vals, st));
+            M.bf.vals = fv;
+        }
+    } else {
+        M.vec = false;
+        build_sell(C, M.s, n_brow, br, bc, rp, ci, nat_d, f32, st);
+        M.n_vals = M.s.n_vals;
+    }
+}
+
+template <typename T>
+static const Sell<T>& sel(const SellStore& S);
+template <>
+const Sell<double>& sel<double>(const SellStore& S) { return S.d; }
+template <>
+const Sell<float>& sel<float>(const SellStore& S) { return S.f; }
+template <typename T>
+static const Bcsr<T>& bsel(const MatStore& M);
+template <>
+const Bcsr<double>& bsel<double>(const MatStore& M) { return M.bd; }
+template <>
+const Bcsr<float>& bsel<float>(const MatStore& M) { return M.bf; }
+
+template <typename T>
+static const T* dinv_of(const Level& L);
+template <>
+const double* dinv_of<double>(const Level& L) { return L.A.vec ? L.Dinv_nat : L.Dinv_sell; }
+template <>
+const float* dinv_of<float>(const Level& L) { return L.A.vec ? L.Dinv_nat32 : L.Dinv_sell32; }
+
+template <typename T>
+static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, int m, hipStream_t st) {
+    if (M.vec) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st));
+    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st));
+}
+
+template <typename T>
+static void mat_sweep(int mode, const Level& L, const T* x, const T* b, T* y, T omega, int m, const int32_t* mask,
+                      hipStream_t st) {
+    if (L.A.vec) HIPCHK(launch_bsweep<T>(mode, bsel<T>(L.A), dinv_of<T>(L), x, b, y, omega, m, mask, st));
+    else HIPCHK(launch_sweep<T>(mode, sel<T>(L.A.s), dinv_of<T>(L), x, b, y, omega, m, mask, st));
+}
+
 
 static double dot1(Ctx& C, const double* a, const double* b, int64_t n, hipStream_t st) {
     HIPCHK(launch_dot<double>(a, b, n, 1, C.scratch, C.scal, st));
@@ -247,12 +328,12 @@ static double power_rho(Ctx& C, Level& L, int k, hipStream_t st) {
     HIPCHK(launch_dot<double>(x, x, L.n, 1, C.scratch, C.scal, st));
     HIPCHK(launch_scale_by_inv_norm(x, L.n, C.scal, st));
     for (int it = 0; it < C.prm.q_power; ++it) {
-        HIPCHK(launch_sweep<double>(DINVA, L.A.d, L.Dinv_sell, x, nullptr, y, -1.0, 1, nullptr, st));
+        mat_sweep<double>(DINVA, L, x, nullptr, y, -1.0, 1, nullptr, st);
         HIPCHK(launch_dot<double>(y, y, L.n, 1, C.scratch, C.scal, st));
         HIPCHK(launch_scale_by_inv_norm(y, L.n, C.scal, st));
         std::swap(x, y);
     }
-    HIPCHK(launch_sweep<double>(DINVA, L.A.d, L.Dinv_sell, x, nullptr, y, -1.0, 1, nullptr, st));
+    mat_sweep<double>(DINVA, L, x, nullptr, y, -1.0, 1, nullptr, st);
     return std::sqrt(dot1(C, y, y, L.n, st));
 }
 
@@ -270,7 +351,7 @@ static void relax_candidates(Ctx& C, Level& L, double* B, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(mask, act.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice, st));
     const double thr = 1.0 + C.prm.gamma;
     for (int sweep = 0; sweep < C.prm.relax_max; ++sweep) {
-        HIPCHK(launch_sweep<double>(RELAX, L.A.d, L.Dinv_sell, X, nullptr, Y, L.omega, r, mask, st));
+        mat_sweep<double>(RELAX, L, X, nullptr, Y, L.omega, r, mask, st);
         std::vector<double> ny = dotm(C, Y, Y, L.n, r, st);
         std::swap(X, Y);
         bool any = false;
@@ -389,10 +470,10 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
             if (read_flag(C, st))
                 throw Error(AMGDG_ESINGULAR, "diagonal block singular to working precision on level " + std::to_string(k));
         }
-        build_sell(C, L.A, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.A_nat, C.mixed, st);
-        {
-            const int G = L.A.d.G, Ll = L.A.d.L;
-            const int64_t cnt = int64_t(L.A.d.n_slices) * L.nb * Ll;
+        build_mat(C, L.A, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.A_nat, C.mixed, st);
+        if (!L.A.vec) {
+            const int G = L.A.s.d.G, Ll = L.A.s.d.L;
+            const int64_t cnt = int64_t(L.A.s.d.n_slices) * L.nb * Ll;
             L.Dinv_sell = C.mem.alloc<double>(cnt);
             HIPCHK(hipMemsetAsync(L.Dinv_sell, 0, sizeof(double) * cnt, st));
             HIPCHK(launch_dinv_to_sell(L.Dinv_nat, L.n_units, L.nb, G, Ll, L.Dinv_sell, st));
@@ -400,6 +481,9 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
                 L.Dinv_sell32 = C.mem.alloc<float>(cnt);
                 HIPCHK(launch_f64_to_f32(L.Dinv_sell, L.Dinv_sell32, cnt, st));
             }
+        } else if (C.mixed) {
+            L.Dinv_nat32 = C.mem.alloc<float>(L.n_units * L.nb * L.nb);
+            HIPCHK(launch_f64_to_f32(L.Dinv_nat, L.Dinv_nat32, L.n_units * L.nb * L.nb, st));
         }
         // omega_k
         if (p.omega_fixed > 0) {
@@ -452,8 +536,8 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
             HIPCHK(launch_R_from_T(L.T_nat, R_t, L.nT, L.nb, s, L.R_nat, st));
             HIPCHK(hipStreamSynchronize(st));
         }
-        build_sell(C, L.T, L.n_units, L.nb, s, P.T_rp, P.T_ci, L.T_nat, C.mixed, st);
-        build_sell(C, L.R, P.n_agg, s, L.nb, P.R_rp, P.R_ci, L.R_nat, C.mixed, st);
+        build_mat(C, L.T, L.n_units, L.nb, s, P.T_rp, P.T_ci, L.T_nat, C.mixed, st);
+        build_mat(C, L.R, P.n_agg, s, L.nb, P.R_rp, P.R_ci, L.R_nat, C.mixed, st);
         // A_{k+1} = R (A T)
         Level& Ln = C.lv[k + 1];
         {
@@ -475,7 +559,7 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         // B^{k+1} = R B^k
         if (k + 1 < C.N) {
             double* Bn = C.mem.alloc<double>(P.n_agg * s * r);
-            HIPCHK(launch_spmv<double>(AX, L.R.d, B, nullptr, Bn, r, st));
+            mat_spmv<double>(AX, L.R, B, nullptr, Bn, r, st);
             B = Bn;
         }
         cur_nb = s;
@@ -520,19 +604,6 @@ VBuf<double>& vbuf<double>(Level& L) { return L.v64; }
 template <>
 VBuf<float>& vbuf<float>(Level& L) { return L.v32; }
 
-template <typename T>
-static const Sell<T>& sel(const SellStore& S);
-template <>
-const Sell<double>& sel<double>(const SellStore& S) { return S.d; }
-template <>
-const Sell<float>& sel<float>(const SellStore& S) { return S.f; }
-
-template <typename T>
-static const T* dinv_of(const Level& L);
-template <>
-const double* dinv_of<double>(const Level& L) { return L.Dinv_sell; }
-template <>
-const float* dinv_of<float>(const Level& L) { return L.Dinv_sell32; }
 
 template <typename T>
 static void coarse_solve(Ctx& C, const T* b, T* u, int m, hipStream_t st);
@@ -566,16 +637,16 @@ static void vcycle_impl(Ctx& C, const T* b0, T* z0, int m, hipStream_t st) {
         if (tpre == 0) {
             HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * L.n * m, st));
         } else {
-            HIPCHK(launch_sweep<T>(SWEEP0, sel<T>(L.A), dinv_of<T>(L), nullptr, bk, cur, om, m, nullptr, st));
+            mat_sweep<T>(SWEEP0, L, nullptr, bk, cur, om, m, nullptr, st);
             for (int t = 1; t < tpre; ++t) {
-                HIPCHK(launch_sweep<T>(SWEEP, sel<T>(L.A), dinv_of<T>(L), cur, bk, oth, om, m, nullptr, st));
+                mat_sweep<T>(SWEEP, L, cur, bk, oth, om, m, nullptr, st);
                 std::swap(cur, oth);
             }
         }
         V.cur = cur;
-        HIPCHK(launch_spmv<T>(B_MINUS, sel<T>(L.A), cur, bk, V.r, m, st));
+        mat_spmv<T>(B_MINUS, L.A, cur, bk, V.r, m, st);
         Level& Ln = C.lv[k + 1];
-        HIPCHK(launch_spmv<T>(AX, sel<T>(L.R), V.r, nullptr, vbuf<T>(Ln).b, m, st));
+        mat_spmv<T>(AX, L.R, V.r, nullptr, vbuf<T>(Ln).b, m, st);
     }
     {
         VBuf<T>& V = vbuf<T>(C.lv[N]);
@@ -590,11 +661,11 @@ static void vcycle_impl(Ctx& C, const T* b0, T* z0, int m, hipStream_t st) {
         T* cur = V.cur;
         auto other = [&](T* c) { return c == V.u ? V.w : V.u; };
         T* dst = (k == 0 && tpost == 0) ? z0 : other(cur);
-        HIPCHK(launch_spmv<T>(B_PLUS, sel<T>(L.T), vbuf<T>(C.lv[k + 1]).cur, cur, dst, m, st));
+        mat_spmv<T>(B_PLUS, L.T, vbuf<T>(C.lv[k + 1]).cur, cur, dst, m, st);
         cur = dst;
         for (int t = 0; t < tpost; ++t) {
             dst = (k == 0 && t == tpost - 1) ? z0 : other(cur);
-            HIPCHK(launch_sweep<T>(SWEEP, sel<T>(L.A), dinv_of<T>(L), cur, bk, dst, om, m, nullptr, st));
+            mat_sweep<T>(SWEEP, L, cur, bk, dst, om, m, nullptr, st);
             cur = dst;
         }
         V.cur = cur;
@@ -656,7 +727,7 @@ static std::vector<double> true_res(Ctx& C, const double* b, const double* x, in
         // level 0 is the coarsest level: it has no sliced copy; use the dense inverse path's operator
         throw Error(AMGDG_EUNSUPPORTED, "Krylov solve needs at least two levels");
     }
-    HIPCHK(launch_spmv<double>(B_MINUS, L.A.d, x, b, C.kt, m, st));
+    mat_spmv<double>(B_MINUS, L.A, x, b, C.kt, m, st);
     return dotm(C, C.kt, C.kt, L.n, m, st);
 }
 
@@ -698,7 +769,7 @@ static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool fl
     HIPCHK(launch_dot<double>(r, z, n, m, C.scratch, d_rz, st));
     HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
     for (int it = 1; it <= maxit; ++it) {
-        HIPCHK(launch_spmv<double>(AX, L.A.d, p, nullptr, q, m, st));
+        mat_spmv<double>(AX, L.A, p, nullptr, q, m, st);
         HIPCHK(launch_dot<double>(p, q, n, m, C.scratch, d_dot, st));
         HIPCHK(launch_div_scalars(d_rz, d_dot, C.active_d, m, d_alpha, 1, C.flag, st));
         HIPCHK(launch_cg_xr(x, r, flexible ? rn : r, p, q, n, m, d_alpha, st));
@@ -814,7 +885,7 @@ static int solve_fgmres(Ctx& C, int precision, double tol, int restart, int maxi
             double* zj = C.Z + int64_t(j) * n;
             double* w = C.V + int64_t(j + 1) * n;
             precond(C, vj, zj, 1, precision, st);
-            HIPCHK(launch_spmv<double>(AX, L.A.d, zj, nullptr, w, 1, st));
+            mat_spmv<double>(AX, L.A, zj, nullptr, w, 1, st);
             // CGS2
             std::vector<double> h(j + 2, 0.0);
             for (int pass = 0; pass < 2; ++pass) {
@@ -952,16 +1023,12 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
     const T* xi = !uses_x ? nullptr : (fine_x ? in(x, V.b) : x);
     const T* bi = uses_b ? in(b, V.r) : nullptr;
     switch (op) {
-        case AMGDG_OP_SPMV: HIPCHK(launch_spmv<T>(AX, sel<T>(L.A), xi, nullptr, out, m, st)); break;
-        case AMGDG_OP_RESIDUAL: HIPCHK(launch_spmv<T>(B_MINUS, sel<T>(L.A), xi, bi, out, m, st)); break;
-        case AMGDG_OP_SWEEP:
-            HIPCHK(launch_sweep<T>(SWEEP, sel<T>(L.A), dinv_of<T>(L), xi, bi, out, T(L.omega), m, nullptr, st));
-            break;
-        case AMGDG_OP_SWEEP0:
-            HIPCHK(launch_sweep<T>(SWEEP0, sel<T>(L.A), dinv_of<T>(L), nullptr, bi, out, T(L.omega), m, nullptr, st));
-            break;
-        case AMGDG_OP_RESTRICT: HIPCHK(launch_spmv<T>(AX, sel<T>(L.R), xi, nullptr, out, m, st)); break;
-        case AMGDG_OP_PROLONG: HIPCHK(launch_spmv<T>(B_PLUS, sel<T>(L.T), xi, bi, out, m, st)); break;
+        case AMGDG_OP_SPMV: mat_spmv<T>(AX, L.A, xi, nullptr, out, m, st); break;
+        case AMGDG_OP_RESIDUAL: mat_spmv<T>(B_MINUS, L.A, xi, bi, out, m, st); break;
+        case AMGDG_OP_SWEEP: mat_sweep<T>(SWEEP, L, xi, bi, out, T(L.omega), m, nullptr, st); break;
+        case AMGDG_OP_SWEEP0: mat_sweep<T>(SWEEP0, L, nullptr, bi, out, T(L.omega), m, nullptr, st); break;
+        case AMGDG_OP_RESTRICT: mat_spmv<T>(AX, L.R, xi, nullptr, out, m, st); break;
+        case AMGDG_OP_PROLONG: mat_spmv<T>(B_PLUS, L.T, xi, bi, out, m, st); break;
         case AMGDG_OP_COARSE: coarse_solve<T>(C, xi, out, m, st); break;
         default: throw Error(AMGDG_EINVAL, "bad op");
     }

@@ -26,6 +26,19 @@ struct Sell {
     const T* vals = nullptr;
 };
 
+// Block-CSR matrix with small br x bc blocks (br <= 4), for coarse levels and
+// restriction: a group of P lanes (P a power of two, 4..64) owns one block row,
+// lane p of the group handles blocks rp[row] + p, + P, ...; the partial
+// products are summed across the group with xor-shuffles.
+template <typename T>
+struct Bcsr {
+    int32_t n_brow = 0, br = 0, bc = 0, P = 0;
+    const int32_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    const T* vals = nullptr;  // row-major blocks
+};
+constexpr int BCSR_MAXBR = 4;
+
 // sweep modes
 enum SweepMode : int {
     SWEEP = 0,   // y = x + omega D^{-1} (b - A x)
@@ -47,6 +60,12 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
                         int m, const int32_t* colmask, hipStream_t st);
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st);
+// the same operations on a block-CSR matrix; dinv: natural layout (n_brow x br x br)
+template <typename T>
+hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
+                         const int32_t* colmask, hipStream_t st);
+template <typename T>
+hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st);
 
 // ---- setup ----
 hipError_t launch_to_sell_vals(const double* nat, const int64_t* slot_src, int64_t n_slots, int G, int L, int br,

@@ -216,6 +216,227 @@ template hipError_t launch_spmv<double>(int, const Sell<double>&, const double*,
 template hipError_t launch_spmv<float>(int, const Sell<float>&, const float*, const float*, float*, int,
                                        hipStream_t);
 
+// ============================================================ block-CSR kernels (small blocks)
+
+// acc[i][c] = sum over the blocks of block row `brow` handled by this lane of
+// A_blk[i][j] * x[col*bc + j][c]; then summed over the P lanes of the group.
+template <typename T, int M, int BR>
+__device__ __forceinline__ void bcsr_row(const Bcsr<T>& A, int64_t brow, bool valid, int p, const T* __restrict__ x,
+                                         int ld, T (&acc)[BR][M]) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[i][c] = T(0);
+    if (valid) {
+        const int bc = A.bc;
+        const int e = A.rp[brow + 1];
+        for (int blk = A.rp[brow] + p; blk < e; blk += A.P) {
+            const int64_t cb = int64_t(A.ci[blk]) * bc;
+            const T* __restrict__ a = A.vals + int64_t(blk) * BR * bc;
+            for (int j = 0; j < bc; ++j) {
+                T xv[M];
+#pragma unroll
+                for (int c = 0; c < M; ++c) xv[c] = x[(cb + j) * ld + c];
+#pragma unroll
+                for (int i = 0; i < BR; ++i) {
+                    const T av = a[i * bc + j];
+#pragma unroll
+                    for (int c = 0; c < M; ++c) acc[i][c] += av * xv[c];
+                }
+            }
+        }
+    }
+    for (int off = A.P >> 1; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int c = 0; c < M; ++c) acc[i][c] += __shfl_xor(acc[i][c], off);
+    }
+}
+
+template <typename T, int M, int MODE, int BR>
+__global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
+                                                const T* __restrict__ b, T* __restrict__ y, T omega,
+                                                const int32_t* __restrict__ colmask, int ld) {
+    constexpr bool HAS_B = (MODE == SWEEP || MODE == SWEEP0);
+    constexpr bool HAS_A = (MODE != SWEEP0);
+    const int gpw = 64 / A.P;
+    const int64_t wv = int64_t(xcd_remap(blockIdx.x, gridDim.x)) * WAVES_PER_WG + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int g = lane / A.P, p = lane - (lane / A.P) * A.P;
+    const int64_t brow = wv * gpw + g;
+    const bool valid = brow < A.n_brow;
+    T acc[BR][M];
+    if (HAS_A) {
+        bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
+    } else {
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int c = 0; c < M; ++c) acc[i][c] = T(0);
+    }
+    if (!valid || p >= BR) return;
+    // residual of the whole block row, then row p of D^{-1} applied to it
+    T o[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) o[c] = T(0);
+    const T* __restrict__ dr = dinv + (brow * BR + p) * BR;
+#pragma unroll
+    for (int j = 0; j < BR; ++j) {
+        const T d = dr[j];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const T bj = HAS_B ? b[(brow * BR + j) * ld + c] : T(0);
+            o[c] += d * (bj - acc[j][c]);
+        }
+    }
+    const int64_t row = brow * BR + p;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        T v;
+        if (MODE == SWEEP) v = x[row * ld + c] + omega * o[c];
+        else if (MODE == SWEEP0) v = omega * o[c];
+        else if (MODE == RELAX) v = colmask[c] ? x[row * ld + c] + omega * o[c] : x[row * ld + c];
+        else v = -o[c];
+        y[row * ld + c] = v;
+    }
+}
+
+template <typename T, int M, int MODE, int BR>
+__global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
+                                               T* __restrict__ y, int ld) {
+    const int gpw = 64 / A.P;
+    const int64_t wv = int64_t(xcd_remap(blockIdx.x, gridDim.x)) * WAVES_PER_WG + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int g = lane / A.P, p = lane - (lane / A.P) * A.P;
+    const int64_t brow = wv * gpw + g;
+    const bool valid = brow < A.n_brow;
+    T acc[BR][M];
+    bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
+    if (!valid || p >= BR) return;
+    const int64_t row = brow * BR + p;
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+        if (i != p) continue;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            T v = acc[i][c];
+            if (MODE == B_MINUS) v = b[row * ld + c] - v;
+            else if (MODE == B_PLUS) v = b[row * ld + c] + v;
+            y[row * ld + c] = v;
+        }
+    }
+}
+
+template <typename T, int M, int BR>
+static hipError_t bsweep_mb(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
+                            const int32_t* mask, int ld, hipStream_t st) {
+    const int64_t waves = (A.n_brow + (64 / A.P) - 1) / (64 / A.P);
+    if (waves == 0) return hipSuccess;
+    dim3 grid(grid_for(waves, WAVES_PER_WG)), block(WG);
+    switch (mode) {
+        case SWEEP: hipLaunchKernelGGL((k_bsweep<T, M, SWEEP, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case SWEEP0: hipLaunchKernelGGL((k_bsweep<T, M, SWEEP0, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case RELAX: hipLaunchKernelGGL((k_bsweep<T, M, RELAX, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case DINVA: hipLaunchKernelGGL((k_bsweep<T, M, DINVA, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int M, int BR>
+static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st) {
+    const int64_t waves = (A.n_brow + (64 / A.P) - 1) / (64 / A.P);
+    if (waves == 0) return hipSuccess;
+    dim3 grid(grid_for(waves, WAVES_PER_WG)), block(WG);
+    switch (mode) {
+        case AX: hipLaunchKernelGGL((k_bspmv<T, M, AX, BR>), grid, block, 0, st, A, x, b, y, ld); break;
+        case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld); break;
+        case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+static hipError_t bsweep_m(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
+                           const int32_t* mask, int ld, hipStream_t st) {
+    switch (A.br) {
+        case 1: return bsweep_mb<T, M, 1>(mode, A, dinv, x, b, y, omega, mask, ld, st);
+        case 2: return bsweep_mb<T, M, 2>(mode, A, dinv, x, b, y, omega, mask, ld, st);
+        case 3: return bsweep_mb<T, M, 3>(mode, A, dinv, x, b, y, omega, mask, ld, st);
+        case 4: return bsweep_mb<T, M, 4>(mode, A, dinv, x, b, y, omega, mask, ld, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int M>
+static hipError_t bspmv_m(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st) {
+    switch (A.br) {
+        case 1: return bspmv_mb<T, M, 1>(mode, A, x, b, y, ld, st);
+        case 2: return bspmv_mb<T, M, 2>(mode, A, x, b, y, ld, st);
+        case 3: return bspmv_mb<T, M, 3>(mode, A, x, b, y, ld, st);
+        case 4: return bspmv_mb<T, M, 4>(mode, A, x, b, y, ld, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
+                         const int32_t* colmask, hipStream_t st) {
+    int c0 = 0;
+    while (c0 < m) {
+        const int rem = m - c0;
+        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const T* xc = x ? x + c0 : nullptr;
+        const T* bc = b ? b + c0 : nullptr;
+        const int32_t* mc = colmask ? colmask + c0 : nullptr;
+        hipError_t e;
+        switch (w) {
+            case 16: e = bsweep_m<T, 16>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 8: e = bsweep_m<T, 8>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 4: e = bsweep_m<T, 4>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 3: e = bsweep_m<T, 3>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 2: e = bsweep_m<T, 2>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            default: e = bsweep_m<T, 1>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+        }
+        if (e != hipSuccess) return e;
+        c0 += w;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st) {
+    int c0 = 0;
+    while (c0 < m) {
+        const int rem = m - c0;
+        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const T* bc = b ? b + c0 : nullptr;
+        hipError_t e;
+        switch (w) {
+            case 16: e = bspmv_m<T, 16>(mode, A, x + c0, bc, y + c0, m, st); break;
+            case 8: e = bspmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, st); break;
+            case 4: e = bspmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, st); break;
+            case 3: e = bspmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, st); break;
+            case 2: e = bspmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, st); break;
+            default: e = bspmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, st); break;
+        }
+        if (e != hipSuccess) return e;
+        c0 += w;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_bsweep<double>(int, const Bcsr<double>&, const double*, const double*, const double*,
+                                          double*, double, int, const int32_t*, hipStream_t);
+template hipError_t launch_bsweep<float>(int, const Bcsr<float>&, const float*, const float*, const float*, float*,
+                                         float, int, const int32_t*, hipStream_t);
+template hipError_t launch_bspmv<double>(int, const Bcsr<double>&, const double*, const double*, double*, int,
+                                         hipStream_t);
+template hipError_t launch_bspmv<float>(int, const Bcsr<float>&, const float*, const float*, float*, int,
+                                        hipStream_t);
+
 // ============================================================ layout conversion
 
 // one thread per (slot, i, j): slot = (slice, k, g); value goes to
