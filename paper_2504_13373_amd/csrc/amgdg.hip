@@ -153,6 +153,42 @@ static int32_t read_flag(Ctx& C, hipStream_t st) {
     return f;
 }
 
+// Values of one precision in the sliced layout (the offsets depend on the
+// vector width, so FP64 and FP32 copies each have their own).
+template <typename T>
+static void sell_values(Ctx& C, Sell<T>& d, int64_t ns, const std::vector<int32_t>& K,
+                        const std::vector<int64_t>& slot_src, const std::vector<int32_t>& slot_k,
+                        const std::vector<int32_t>& slot_g, const std::vector<int32_t>& slot_s, const double* nat_d,
+                        hipStream_t st) {
+    constexpr int VW = 16 / int(sizeof(T));
+    std::vector<int64_t> voff(ns + 1), base(slot_s.size());
+    int64_t v = 0;
+    int32_t tpad = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        voff[s] = v;
+        const int32_t tq = (K[s] * d.bc + VW - 1) / VW;
+        tpad = std::max(tpad, tq * VW);
+        v += int64_t(tq) * VW * d.L;
+    }
+    voff[ns] = v;
+    for (size_t q = 0; q < slot_s.size(); ++q) base[q] = voff[slot_s[q]];
+    d.tpad = std::max<int32_t>(tpad, VW);
+    d.brpad = (d.br + VW - 1) / VW * VW;
+    d.voff = upload(C.mem, voff, st);
+    T* vals = C.mem.alloc<T>(v);
+    HIPCHK(hipMemsetAsync(vals, 0, sizeof(T) * size_t(std::max<int64_t>(v, 1)), st));
+    {
+        DevMem tmp;
+        const int64_t* src = upload(tmp, slot_src, st);
+        const int64_t* bs = upload(tmp, base, st);
+        const int32_t* sk = upload(tmp, slot_k, st);
+        const int32_t* sg = upload(tmp, slot_g, st);
+        HIPCHK(launch_to_sell_vals<T>(nat_d, src, bs, sk, sg, int64_t(slot_s.size()), d.L, d.br, d.bc, vals, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    d.vals = vals;
+}
+
 // Builds the sliced layout of a natural BSR matrix (row-major br x bc blocks)
 // whose pattern (rp, ci) is on the host and values nat_d on the device.
 static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, const std::vector<int32_t>& rp,
@@ -160,9 +196,8 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
     if (br < 1 || br > 64) throw Error(AMGDG_EUNSUPPORTED, "block size must be 1..64");
     const int G = 64 / br, L = G * br;
     const int64_t ns = (n_brow + G - 1) / G;
-    std::vector<int64_t> voff(ns + 1), slot_src, slot_voff;
-    std::vector<int32_t> coff(ns + 1), K(ns), cols;
-    int64_t v = 0;
+    std::vector<int32_t> coff(ns + 1), K(ns), cols, slot_k, slot_g, slot_s;
+    std::vector<int64_t> slot_src;
     int32_t c = 0;
     for (int64_t s = 0; s < ns; ++s) {
         int32_t kmax = 0;
@@ -171,26 +206,25 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
             if (row < n_brow) kmax = std::max(kmax, rp[row + 1] - rp[row]);
         }
         K[s] = kmax;
-        voff[s] = v;
         coff[s] = c;
-        for (int k = 0; k < kmax; ++k)
+        for (int kk = 0; kk < kmax; ++kk)
             for (int g = 0; g < G; ++g) {
                 const int64_t row = s * G + g;
                 int64_t blk = -1;
                 int32_t col = 0;
-                if (row < n_brow && k < rp[row + 1] - rp[row]) {
-                    blk = rp[row] + k;
+                if (row < n_brow && kk < rp[row + 1] - rp[row]) {
+                    blk = rp[row] + kk;
                     col = ci[blk];
                 }
                 cols.push_back(col);
                 slot_src.push_back(blk);
-                slot_voff.push_back(v + int64_t(k) * bc * L + int64_t(g) * br);
+                slot_k.push_back(kk);
+                slot_g.push_back(g);
+                slot_s.push_back(int32_t(s));
             }
-        v += int64_t(kmax) * bc * L;
         c += kmax * G;
         if (c < 0) throw Error(AMGDG_EUNSUPPORTED, "matrix too large for int32 slot indexing");
     }
-    voff[ns] = v;
     coff[ns] = c;
     Sell<double> d;
     d.n_brow = int32_t(n_brow);
@@ -199,40 +233,37 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
     d.G = G;
     d.L = L;
     d.n_slices = int32_t(ns);
-    d.voff = upload(C.mem, voff, st);
     d.coff = upload(C.mem, coff, st);
     d.K = upload(C.mem, K, st);
     d.cols = upload(C.mem, cols, st);
-    double* vals = C.mem.alloc<double>(v);
-    {
-        DevMem tmp;
-        const int64_t* ss = upload(tmp, slot_src, st);
-        const int64_t* sv = upload(tmp, slot_voff, st);
-        HIPCHK(launch_to_sell_vals(nat_d, ss, int64_t(slot_src.size()), G, L, br, bc, sv, vals, st));
-        HIPCHK(hipStreamSynchronize(st));
-    }
-    d.vals = vals;
+    Sell<float> f;
+    f.n_brow = d.n_brow;
+    f.br = br;
+    f.bc = bc;
+    f.G = G;
+    f.L = L;
+    f.n_slices = d.n_slices;
+    f.coff = d.coff;
+    f.K = d.K;
+    f.cols = d.cols;
+    sell_values<double>(C, d, ns, K, slot_src, slot_k, slot_g, slot_s, nat_d, st);
+    if (f32) sell_values<float>(C, f, ns, K, slot_src, slot_k, slot_g, slot_s, nat_d, st);
     S.d = d;
-    S.n_vals = v;
-    S.f.n_brow = d.n_brow;
-    S.f.br = br;
-    S.f.bc = bc;
-    S.f.G = G;
-    S.f.L = L;
-    S.f.n_slices = d.n_slices;
-    S.f.voff = d.voff;
-    S.f.coff = d.coff;
-    S.f.K = d.K;
-    S.f.cols = d.cols;
-    if (f32) {
-        float* fv = C.mem.alloc<float>(v);
-        HIPCHK(launch_f64_to_f32(vals, fv, v, st));
-        S.f.vals = fv;
-    }
+    S.f = f;
+    int64_t nv = 0;
+    for (int64_t s = 0; s < ns; ++s) nv += int64_t(K[s]) * bc * L;
+    S.n_vals = nv;
 }
 
+template <typename T>
+static T* sell_dinv(Ctx& C, const Sell<T>& A, const double* dinv_nat, hipStream_t st) {
+    const int64_t cnt = int64_t(A.n_slices) * A.brpad * A.L;
+    T* out = C.mem.alloc<T>(cnt);
+    HIPCHK(hipMemsetAsync(out, 0, sizeof(T) * size_t(std::max<int64_t>(cnt, 1)), st));
+    HIPCHK(launch_dinv_to_sell<T>(dinv_nat, A.n_brow, A.br, A.G, A.L, A.brpad, out, st));
+    return out;
+}
 
-// ------------------------------------------------------------ setup
 static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const std::vector<int32_t>& rp,
                       const std::vector<int32_t>& ci, const double* nat_d, bool f32, hipStream_t st) {
     if (br <= BCSR_MAXBR) {
@@ -472,15 +503,8 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         }
         build_mat(C, L.A, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.A_nat, C.mixed, st);
         if (!L.A.vec) {
-            const int G = L.A.s.d.G, Ll = L.A.s.d.L;
-            const int64_t cnt = int64_t(L.A.s.d.n_slices) * L.nb * Ll;
-            L.Dinv_sell = C.mem.alloc<double>(cnt);
-            HIPCHK(hipMemsetAsync(L.Dinv_sell, 0, sizeof(double) * cnt, st));
-            HIPCHK(launch_dinv_to_sell(L.Dinv_nat, L.n_units, L.nb, G, Ll, L.Dinv_sell, st));
-            if (C.mixed) {
-                L.Dinv_sell32 = C.mem.alloc<float>(cnt);
-                HIPCHK(launch_f64_to_f32(L.Dinv_sell, L.Dinv_sell32, cnt, st));
-            }
+            L.Dinv_sell = sell_dinv<double>(C, L.A.s.d, L.Dinv_nat, st);
+            if (C.mixed) L.Dinv_sell32 = sell_dinv<float>(C, L.A.s.f, L.Dinv_nat, st);
         } else if (C.mixed) {
             L.Dinv_nat32 = C.mem.alloc<float>(L.n_units * L.nb * L.nb);
             HIPCHK(launch_f64_to_f32(L.Dinv_nat, L.Dinv_nat32, L.n_units * L.nb * L.nb, st));

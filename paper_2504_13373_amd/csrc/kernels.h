@@ -7,18 +7,21 @@
 
 namespace amgdg {
 
-// Sliced, row-interleaved block-sparse matrix with br x bc blocks.
+// Sliced, row-interleaved block-sparse matrix with br x bc blocks (br > 4).
 //
 // Block rows are grouped in slices of G = floor(64 / br) rows; one wavefront
 // owns a slice and each of its first L = G * br lanes owns one scalar row.  A
 // slice stores K (its longest block row) block slots per row, padded with zero
-// blocks whose column is 0.  Value (k, j) of lane l is at
-//     vals[voff[s] + (k * bc + j) * L + l]
-// so that for fixed (k, j) the wavefront reads L consecutive values, and the
-// column of slot k of the slice's block row g is cols[coff[s] + k * G + g].
+// blocks whose column is 0.  The K*bc values of a lane's row are flattened as
+// t = k*bc + j and stored in vectors of VW = 16 / sizeof(T) values:
+//     vals[voff[s] + (t / VW) * L * VW + l * VW + t % VW]
+// so that one 16-byte load per lane reads VW values and a wavefront reads one
+// contiguous run of 16 * L bytes.  The column of slot k of block row g of the
+// slice is cols[coff[s] + k * G + g].  tpad is the largest K*bc of any slice
+// rounded up to VW (the per-row length of the x staging buffer in LDS).
 template <typename T>
 struct Sell {
-    int32_t n_brow = 0, br = 0, bc = 0, G = 0, L = 0, n_slices = 0;
+    int32_t n_brow = 0, br = 0, bc = 0, G = 0, L = 0, n_slices = 0, tpad = 0, brpad = 0;
     const int64_t* voff = nullptr;
     const int32_t* coff = nullptr;
     const int32_t* K = nullptr;
@@ -53,8 +56,9 @@ enum SpmvMode : int {
     B_PLUS = 2,  // y = b + A x
 };
 
-// Dinv in sliced layout: value (i, j) of block row g of slice s at
-// dinv[s * br * L + j * L + g * br + i].
+// D^{-1} in sliced layout: the br x br block of block row g is stored like a
+// one-slot slice with its columns padded to brpad (a multiple of VW):
+// value (i, j) at dinv[s * brpad * L + (j / VW) * L * VW + (g * br + i) * VW + j % VW].
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
                         int m, const int32_t* colmask, hipStream_t st);
@@ -68,9 +72,15 @@ template <typename T>
 hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st);
 
 // ---- setup ----
-hipError_t launch_to_sell_vals(const double* nat, const int64_t* slot_src, int64_t n_slots, int G, int L, int br,
-                               int bc, const int64_t* slot_voff, double* vals, hipStream_t st);
-hipError_t launch_dinv_to_sell(const double* dinv_nat, int64_t n_brow, int br, int G, int L, double* dinv_sell,
+// Fill the sliced values of type T from natural FP64 blocks: for slot q (one
+// block slot of one block row), its source block src[q] (-1: zero padding),
+// its slice's value offset base[q], its slot k[q] and row-in-slice g[q].
+template <typename T>
+hipError_t launch_to_sell_vals(const double* nat, const int64_t* slot_src, const int64_t* slot_base,
+                               const int32_t* slot_k, const int32_t* slot_g, int64_t n_slots, int L, int br, int bc,
+                               T* vals, hipStream_t st);
+template <typename T>
+hipError_t launch_dinv_to_sell(const double* dinv_nat, int64_t n_brow, int br, int G, int L, int brpad, T* dinv_sell,
                                hipStream_t st);
 hipError_t launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st);
 hipError_t launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st);

@@ -30,22 +30,84 @@ static inline unsigned grid_for(int64_t n, int per = WG) { return unsigned((n + 
 
 // ============================================================ BSR kernels
 
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    using type = double2;
+};
+template <>
+struct Vec16<float> {
+    using type = float4;
+};
+
+// Makes this wavefront's LDS writes visible to its own later LDS reads.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// r[c] -= sum_t vals[t] * x(t)[c] over the flattened (slot, column) values of
+// this lane's row; the x blocks of the slice are first staged in LDS (xs, one
+// row of tpad * M values per block row of the slice) by the lanes i < bc.
+template <typename T, int M>
+__device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, int lc, int g, int i,
+                                         const T* __restrict__ x, int ld, T* xs, T (&r)[M], T sign) {
+    constexpr int VW = 16 / int(sizeof(T));
+    using V = typename Vec16<T>::type;
+    const int L = A.L, bc = A.bc, G = A.G, TP = A.tpad;
+    const int K = A.K[slice];
+    const int Tn = K * bc;
+    const int TQ = (Tn + VW - 1) / VW;
+    const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
+    T* xr = xs + g * TP * M;
+    if (lane < L) {
+        if (i < bc) {
+            for (int kk = 0; kk < K; ++kk) {
+                const T* __restrict__ src = x + (int64_t(cp[kk * G]) * bc + i) * ld;
+#pragma unroll
+                for (int c = 0; c < M; ++c) xr[(kk * bc + i) * M + c] = src[c];
+            }
+        }
+        for (int t = Tn + i; t < TQ * VW; t += A.br)
+#pragma unroll
+            for (int c = 0; c < M; ++c) xr[t * M + c] = T(0);
+    }
+    wave_lds_sync();
+    const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + lc;
+#pragma unroll 4
+    for (int q = 0; q < TQ; ++q) {
+        T a[VW];
+        *reinterpret_cast<V*>(a) = vp[q * L];
+#pragma unroll
+        for (int u = 0; u < VW; ++u)
+#pragma unroll
+            for (int c = 0; c < M; ++c) r[c] += sign * a[u] * xr[(q * VW + u) * M + c];
+    }
+}
+
 template <typename T, int M, int MODE>
 __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ y, T omega,
                                                const int32_t* __restrict__ colmask, int ld) {
     constexpr bool HAS_B = (MODE == SWEEP || MODE == SWEEP0);
     constexpr bool HAS_A = (MODE != SWEEP0);
-    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + (threadIdx.x >> 6);
+    constexpr int VW = 16 / int(sizeof(T));
+    using V = typename Vec16<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
     if (slice >= A.n_slices) return;
-    const int lane = threadIdx.x & 63;
-    const int L = A.L, br = A.br;
+    const int L = A.L, br = A.br, G = A.G, BP = A.brpad;
     const int lc = lane < L ? lane : L - 1;
     const int g = lc / br;
     const int i = lc - g * br;
-    const int64_t brow = int64_t(slice) * A.G + g;
+    const int64_t brow = int64_t(slice) * G + g;
     const bool own = lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (A.tpad + BP) * M;
+    T* rs = xs + G * A.tpad * M;
 
     T r[M];
 #pragma unroll
@@ -54,30 +116,28 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
 #pragma unroll
         for (int c = 0; c < M; ++c) r[c] = b[row * ld + c];
     }
-    if (HAS_A) {
-        const int K = A.K[slice];
-        const int bc = A.bc;
-        const T* __restrict__ vp = A.vals + A.voff[slice] + lc;
-        const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
-        for (int k = 0; k < K; ++k) {
-            const int64_t cb = int64_t(cp[k * A.G]) * bc;
-            const T* __restrict__ vk = vp + int64_t(k) * bc * L;
-            for (int j = 0; j < bc; ++j) {
-                const T a = vk[int64_t(j) * L];
+    if (HAS_A) sell_row<T, M>(A, slice, lane, lc, g, i, x, ld, xs, r, T(-1));
+    // residual of the block row through LDS, then row i of D^{-1}
+    T* rr = rs + g * BP * M;
+    if (lane < L) {
 #pragma unroll
-                for (int c = 0; c < M; ++c) r[c] -= a * x[(cb + j) * ld + c];
-            }
-        }
+        for (int c = 0; c < M; ++c) rr[i * M + c] = r[c];
+        for (int t = br + i; t < BP; t += br)
+#pragma unroll
+            for (int c = 0; c < M; ++c) rr[t * M + c] = T(0);
     }
+    wave_lds_sync();
     T o[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) o[c] = T(0);
-    const T* __restrict__ dp = dinv + int64_t(slice) * br * L + lc;
-    for (int j = 0; j < br; ++j) {
-        const T d = dp[int64_t(j) * L];
-        const int src = g * br + j;
+    const V* __restrict__ dp = reinterpret_cast<const V*>(dinv + int64_t(slice) * BP * L) + lc;
+    for (int jq = 0; jq < BP / VW; ++jq) {
+        T d[VW];
+        *reinterpret_cast<V*>(d) = dp[jq * L];
 #pragma unroll
-        for (int c = 0; c < M; ++c) o[c] += d * __shfl(r[c], src);
+        for (int u = 0; u < VW; ++u)
+#pragma unroll
+            for (int c = 0; c < M; ++c) o[c] += d[u] * rr[(jq * VW + u) * M + c];
     }
     if (!own) return;
 #pragma unroll
@@ -94,32 +154,22 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
 template <typename T, int M, int MODE>
 __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, int ldx, int ldy) {
-    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + (threadIdx.x >> 6);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
     if (slice >= A.n_slices) return;
-    const int lane = threadIdx.x & 63;
-    const int L = A.L, br = A.br;
+    const int L = A.L, br = A.br, G = A.G;
     const int lc = lane < L ? lane : L - 1;
     const int g = lc / br;
     const int i = lc - g * br;
-    const int64_t brow = int64_t(slice) * A.G + g;
+    const int64_t brow = int64_t(slice) * G + g;
     const bool own = lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * A.tpad * M;
     T acc[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = T(0);
-    const int K = A.K[slice];
-    const int bc = A.bc;
-    const T* __restrict__ vp = A.vals + A.voff[slice] + lc;
-    const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
-    for (int k = 0; k < K; ++k) {
-        const int64_t cb = int64_t(cp[k * A.G]) * bc;
-        const T* __restrict__ vk = vp + int64_t(k) * bc * L;
-        for (int j = 0; j < bc; ++j) {
-            const T a = vk[int64_t(j) * L];
-#pragma unroll
-            for (int c = 0; c < M; ++c) acc[c] += a * x[(cb + j) * ldx + c];
-        }
-    }
+    sell_row<T, M>(A, slice, lane, lc, g, i, x, ldx, xs, acc, T(1));
     if (!own) return;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
@@ -135,11 +185,12 @@ static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x,
                           const int32_t* mask, int ld, hipStream_t st) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
+    const size_t lds = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * M * sizeof(T);
     switch (mode) {
-        case SWEEP: hipLaunchKernelGGL((k_sweep<T, M, SWEEP>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case SWEEP0: hipLaunchKernelGGL((k_sweep<T, M, SWEEP0>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case RELAX: hipLaunchKernelGGL((k_sweep<T, M, RELAX>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case DINVA: hipLaunchKernelGGL((k_sweep<T, M, DINVA>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case SWEEP: hipLaunchKernelGGL((k_sweep<T, M, SWEEP>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case SWEEP0: hipLaunchKernelGGL((k_sweep<T, M, SWEEP0>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case RELAX: hipLaunchKernelGGL((k_sweep<T, M, RELAX>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case DINVA: hipLaunchKernelGGL((k_sweep<T, M, DINVA>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -150,29 +201,40 @@ static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* 
                          hipStream_t st) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
+    const size_t lds = size_t(WAVES_PER_WG) * A.G * A.tpad * M * sizeof(T);
     switch (mode) {
-        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, 0, st, A, x, b, y, ldx, ldy); break;
-        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, 0, st, A, x, b, y, ldx, ldy); break;
-        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, 0, st, A, x, b, y, ldx, ldy); break;
+        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, lds, st, A, x, b, y, ldx, ldy); break;
+        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, lds, st, A, x, b, y, ldx, ldy); break;
+        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, lds, st, A, x, b, y, ldx, ldy); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// Columns are processed in chunks of 16, 8, 4, 3, 2, 1 (each a separate launch).
+// Columns are processed in chunks (each a separate launch): the LDS staging
+// buffers grow with the chunk width, so it is capped at 4 (FP64) / 8 (FP32).
+// and kept within 64 KB of LDS per workgroup.
+template <typename T>
+static int sell_chunk(int rem, const Sell<T>& A, bool with_dinv) {
+    int cap = sizeof(T) == 8 ? 4 : 8;
+    const size_t per_col = size_t(WAVES_PER_WG) * A.G * (A.tpad + (with_dinv ? A.brpad : 0)) * sizeof(T);
+    while (cap > 1 && per_col * cap > 65536) cap = cap == 8 ? 4 : cap - 1;
+    const int w = rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+    return w <= cap ? w : cap;
+}
+
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                         const int32_t* colmask, hipStream_t st) {
     int c0 = 0;
     while (c0 < m) {
-        const int rem = m - c0;
-        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const int w = sell_chunk<T>(m - c0, A, true);
+        if (size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * w * sizeof(T) > 65536) return hipErrorInvalidConfiguration;
         const T* xc = x ? x + c0 : nullptr;
         const T* bc = b ? b + c0 : nullptr;
         const int32_t* mc = colmask ? colmask + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 16: e = sweep_m<T, 16>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
             case 8: e = sweep_m<T, 8>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
             case 4: e = sweep_m<T, 4>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
             case 3: e = sweep_m<T, 3>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
@@ -189,12 +251,11 @@ template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st) {
     int c0 = 0;
     while (c0 < m) {
-        const int rem = m - c0;
-        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const int w = sell_chunk<T>(m - c0, A, false);
+        if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(T) > 65536) return hipErrorInvalidConfiguration;
         const T* bc = b ? b + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 16: e = spmv_m<T, 16>(mode, A, x + c0, bc, y + c0, m, m, st); break;
             case 8: e = spmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, m, st); break;
             case 4: e = spmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, m, st); break;
             case 3: e = spmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, m, st); break;
@@ -439,33 +500,44 @@ template hipError_t launch_bspmv<float>(int, const Bcsr<float>&, const float*, c
 
 // ============================================================ layout conversion
 
-// one thread per (slot, i, j): slot = (slice, k, g); value goes to
-// vals[slot_voff[slot] + (k*bc + j)*L + g*br + i] where slot_voff already
-// includes the slice offset and the k*bc*L term plus g*br.
-__global__ void k_to_sell_vals(const double* __restrict__ nat, const int64_t* __restrict__ slot_src, int64_t n_slots,
-                               int L, int br, int bc, const int64_t* __restrict__ slot_voff, double* __restrict__ vals) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// one thread per (slot q, i, j): t = k*bc + j goes to
+// vals[base + (t / VW) * L * VW + (g*br + i) * VW + t % VW]
+template <typename T>
+__global__ void k_to_sell_vals(const double* __restrict__ nat, const int64_t* __restrict__ src,
+                               const int64_t* __restrict__ base, const int32_t* __restrict__ sk,
+                               const int32_t* __restrict__ sg, int64_t n_slots, int L, int br, int bc,
+                               T* __restrict__ vals) {
+    constexpr int VW = 16 / int(sizeof(T));
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per = int64_t(br) * bc;
-    if (t >= n_slots * per) return;
-    const int64_t slot = t / per;
-    const int rem = int(t - slot * per);
+    if (tid >= n_slots * per) return;
+    const int64_t q = tid / per;
+    const int rem = int(tid - q * per);
     const int i = rem / bc, j = rem - (rem / bc) * bc;
-    const int64_t src = slot_src[slot];
-    vals[slot_voff[slot] + int64_t(j) * L + i] = src >= 0 ? nat[src * per + int64_t(i) * bc + j] : 0.0;
+    const int64_t s = src[q];
+    if (s < 0) return;  // padding slot: the buffer was zeroed
+    const int t = sk[q] * bc + j;
+    vals[base[q] + int64_t(t / VW) * L * VW + int64_t(sg[q] * br + i) * VW + t % VW] = T(nat[s * per + int64_t(i) * bc + j]);
 }
 
-hipError_t launch_to_sell_vals(const double* nat, const int64_t* slot_src, int64_t n_slots, int G, int L, int br,
-                               int bc, const int64_t* slot_voff, double* vals, hipStream_t st) {
-    (void)G;
+template <typename T>
+hipError_t launch_to_sell_vals(const double* nat, const int64_t* src, const int64_t* base, const int32_t* sk,
+                               const int32_t* sg, int64_t n_slots, int L, int br, int bc, T* vals, hipStream_t st) {
     const int64_t tot = n_slots * br * bc;
     if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_to_sell_vals, dim3(grid_for(tot)), dim3(WG), 0, st, nat, slot_src, n_slots, L, br, bc,
-                       slot_voff, vals);
+    hipLaunchKernelGGL((k_to_sell_vals<T>), dim3(grid_for(tot)), dim3(WG), 0, st, nat, src, base, sk, sg, n_slots, L,
+                       br, bc, vals);
     return hipGetLastError();
 }
+template hipError_t launch_to_sell_vals<double>(const double*, const int64_t*, const int64_t*, const int32_t*,
+                                                const int32_t*, int64_t, int, int, int, double*, hipStream_t);
+template hipError_t launch_to_sell_vals<float>(const double*, const int64_t*, const int64_t*, const int32_t*,
+                                               const int32_t*, int64_t, int, int, int, float*, hipStream_t);
 
-__global__ void k_dinv_to_sell(const double* __restrict__ dn, int64_t n_brow, int br, int G, int L,
-                               double* __restrict__ ds) {
+template <typename T>
+__global__ void k_dinv_to_sell(const double* __restrict__ dn, int64_t n_brow, int br, int G, int L, int BP,
+                               T* __restrict__ ds) {
+    constexpr int VW = 16 / int(sizeof(T));
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per = int64_t(br) * br;
     if (t >= n_brow * per) return;
@@ -474,15 +546,18 @@ __global__ void k_dinv_to_sell(const double* __restrict__ dn, int64_t n_brow, in
     const int i = rem / br, j = rem - (rem / br) * br;
     const int64_t s = e / G;
     const int g = int(e - s * G);
-    ds[s * br * L + int64_t(j) * L + g * br + i] = dn[t];
+    ds[s * BP * L + int64_t(j / VW) * L * VW + int64_t(g * br + i) * VW + j % VW] = T(dn[t]);
 }
 
-hipError_t launch_dinv_to_sell(const double* dn, int64_t n_brow, int br, int G, int L, double* ds, hipStream_t st) {
+template <typename T>
+hipError_t launch_dinv_to_sell(const double* dn, int64_t n_brow, int br, int G, int L, int BP, T* ds, hipStream_t st) {
     const int64_t tot = n_brow * br * br;
     if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dinv_to_sell, dim3(grid_for(tot)), dim3(WG), 0, st, dn, n_brow, br, G, L, ds);
+    hipLaunchKernelGGL((k_dinv_to_sell<T>), dim3(grid_for(tot)), dim3(WG), 0, st, dn, n_brow, br, G, L, BP, ds);
     return hipGetLastError();
 }
+template hipError_t launch_dinv_to_sell<double>(const double*, int64_t, int, int, int, int, double*, hipStream_t);
+template hipError_t launch_dinv_to_sell<float>(const double*, int64_t, int, int, int, int, float*, hipStream_t);
 
 template <typename Ti, typename To>
 __global__ void k_convert(const Ti* __restrict__ a, To* __restrict__ b, int64_t n) {
