@@ -143,6 +143,14 @@ struct Ctx {
     float *kr32 = nullptr, *kz32 = nullptr;
     double *V = nullptr, *Z = nullptr;
     int32_t* active_d = nullptr;
+    // fused Krylov steps: partial sums, arrival counter, status record (rr[0..64), flag)
+    double* kpart = nullptr;
+    unsigned* counter = nullptr;
+    double* stat = nullptr;
+    double* stat_h = nullptr;  // pinned host mirror of stat
+    ~Ctx() {
+        if (stat_h) (void)hipHostFree(stat_h);
+    }
 };
 
 static int32_t read_flag(Ctx& C, hipStream_t st) {
@@ -433,6 +441,12 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
     C.scal = C.mem.alloc<double>(2048);
     C.flag = C.mem.alloc<int32_t>(4);
     HIPCHK(hipMemsetAsync(C.flag, 0, 4 * sizeof(int32_t), st));
+    C.kpart = C.mem.alloc<double>(2 * 16 * (KRY_BLOCKS + 1) + 64);
+    C.counter = C.mem.alloc<unsigned>(1);
+    HIPCHK(hipMemsetAsync(C.counter, 0, sizeof(unsigned), st));
+    C.stat = C.mem.alloc<double>(65);
+    HIPCHK(hipMemsetAsync(C.stat, 0, 65 * sizeof(double), st));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&C.stat_h), 65 * sizeof(double), hipHostMallocDefault));
     C.perm_d = upload(C.mem, C.plan.perm, st);
 
     // level-0 values in internal order
@@ -764,22 +778,28 @@ static void check_nan(const std::vector<double>& v, const char* what) {
 // (flexible = true): in the flexible variant, when the recursive residual of a
 // column claims convergence or has dropped by kReplaceDrop since its last
 // replacement and the true FP64 residual does not meet the tolerance, the true
-// residual replaces the recursive one.
+// residual replaces the recursive one.  Per iteration: q = A p, p.q, the fused
+// update of x and r (with ||r||^2 and, for the mixed V-cycle, the FP32 copy of
+// r), the preconditioner, the fused r.z (and z.r_old), the new direction, and
+// one readback of the status record (||r||^2 per column and the error flag).
 static constexpr double kReplaceDrop = 1e-6;
 
 static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool flexible, KrylovState& S,
                     hipStream_t st) {
     Level& L = C.lv[0];
     const int64_t n = L.n;
+    const bool mixed = precision == AMGDG_MIXED;
     double *b = C.kb, *x = C.kx, *r = C.kr, *rn = C.kr2, *z = C.kz, *p = C.kp, *q = C.kq;
-    double* sc = C.scal;  // [0,64) pq/dots, [64,128) rz, [128,192) alpha, [192,256) beta/zr_old
-    double *d_dot = sc, *d_rz = sc + 64, *d_alpha = sc + 128, *d_sub = sc + 192;
+    double* sc = C.scal;
+    double *d_pq = sc, *d_rz = sc + 64, *d_rz2 = sc + 128, *d_zro = sc + 192;
+    int32_t* flag = reinterpret_cast<int32_t*>(C.stat + 64);
+    float* r32 = mixed ? C.kr32 : nullptr;
     std::vector<int32_t> act(m, 1);
+    std::vector<double> anchor(m, 1.0);
     std::vector<double> rr0 = true_res(C, b, x, m, st);
     HIPCHK(hipMemcpyAsync(r, C.kt, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
     S.its.assign(m, 0);
     S.rel.assign(m, 0.0);
-    std::vector<double> anchor(m, 1.0);
     bool any = false;
     for (int c = 0; c < m; ++c) {
         S.rel[c] = std::sqrt(rr0[c]) / S.bnorm[c];
@@ -788,28 +808,40 @@ static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool fl
         any = any || act[c];
     }
     if (!any) return AMGDG_OK;
-    HIPCHK(hipMemcpyAsync(C.active_d, act.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
-    precond(C, r, z, m, precision, st);
-    HIPCHK(launch_dot<double>(r, z, n, m, C.scratch, d_rz, st));
+    auto upload_act = [&]() {
+        HIPCHK(hipMemcpyAsync(C.active_d, act.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    };
+    upload_act();
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
+    auto apply_M = [&](double* rz_out, const double* r_old, double* zro) {
+        if (mixed) vcycle_impl<float>(C, C.kr32, C.kz32, m, st);
+        else vcycle_impl<double>(C, r, z, m, st);
+        HIPCHK(launch_zdots(mixed ? C.kz32 : nullptr, z, r, r_old, n, m, C.kpart, C.counter, rz_out, zro, st));
+    };
+    if (mixed) HIPCHK((launch_convert<double, float>(r, r32, n * m, st)));
+    apply_M(d_rz, nullptr, nullptr);
     HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
     for (int it = 1; it <= maxit; ++it) {
         mat_spmv<double>(AX, L.A, p, nullptr, q, m, st);
-        HIPCHK(launch_dot<double>(p, q, n, m, C.scratch, d_dot, st));
-        HIPCHK(launch_div_scalars(d_rz, d_dot, C.active_d, m, d_alpha, 1, C.flag, st));
-        HIPCHK(launch_cg_xr(x, r, flexible ? rn : r, p, q, n, m, d_alpha, st));
+        HIPCHK(launch_dot_tail(p, q, n, m, C.kpart, C.counter, d_pq, st));
+        HIPCHK(launch_cg_update(x, r, flexible ? rn : r, p, q, r32, n, m, d_rz, d_pq, C.active_d, C.kpart, C.counter,
+                                C.stat, flag, st));
         if (flexible) std::swap(r, rn);  // r: new residual, rn: previous
-        std::vector<double> rr = dotm(C, r, r, n, m, st);
-        if (int32_t f = read_flag(C, st)) {
+        HIPCHK(hipMemcpyAsync(C.stat_h, C.stat, sizeof(double) * 65, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int32_t f = *reinterpret_cast<const int32_t*>(C.stat_h + 64);
+        if (f) {
+            HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
             throw Error(f & 1 ? AMGDG_EBREAKDOWN : AMGDG_ENAN,
                         f & 1 ? "CG breakdown: p^T A p <= 0 (matrix or preconditioner not SPD)" : "NaN in CG");
         }
-        check_nan(rr, "CG residual");
-        bool need_true = false;
+        bool need_true = false, changed = false;
         std::vector<int32_t> check(m, 0), repl(m, 0);
         for (int c = 0; c < m; ++c)
             if (act[c]) {
                 S.its[c] = it;
-                S.rel[c] = std::sqrt(rr[c]) / S.bnorm[c];
+                S.rel[c] = std::sqrt(C.stat_h[c]) / S.bnorm[c];
                 if (S.rel[c] <= tol || (flexible && S.rel[c] <= anchor[c] * kReplaceDrop)) check[c] = 1;
                 need_true = need_true || check[c];
             }
@@ -822,6 +854,7 @@ static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool fl
                     if (t <= tol) {
                         act[c] = 0;
                         S.rel[c] = t;
+                        changed = true;
                     } else if (flexible) {
                         // residual replacement: the true residual takes the place of the recursive one
                         repl[c] = 1;
@@ -832,18 +865,17 @@ static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool fl
             if (any_repl) {
                 HIPCHK(hipMemcpyAsync(C.active_d + 64, repl.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
                 HIPCHK(launch_copy_cols(C.kt, r, n, m, C.active_d + 64, st));
+                if (mixed) HIPCHK((launch_convert<double, float>(r, r32, n * m, st)));
                 HIPCHK(hipStreamSynchronize(st));
             }
         }
         any = false;
         for (int c = 0; c < m; ++c) any = any || act[c];
         if (!any) return AMGDG_OK;
-        HIPCHK(hipMemcpyAsync(C.active_d, act.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
-        precond(C, r, z, m, precision, st);
-        HIPCHK(launch_dot<double>(r, z, n, m, C.scratch, d_dot, st));
-        if (flexible) HIPCHK(launch_dot<double>(z, rn, n, m, C.scratch, d_sub, st));
-        HIPCHK(launch_beta(d_dot, flexible ? d_sub : nullptr, d_rz, C.active_d, m, d_alpha, st));
-        HIPCHK(launch_cg_p(p, z, n, m, d_alpha, st));
+        if (changed) upload_act();
+        apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
+        HIPCHK(launch_cg_dir(p, z, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz, C.active_d, st));
+        std::swap(d_rz, d_rz2);
     }
     return AMGDG_ENOCONV;
 }

@@ -122,6 +122,26 @@ hipError_t launch_axpby_dev(const double* x, double* y, int64_t n, int m, const 
 // CG updates: x += alpha p ; r -= alpha q  (per column alpha)
 hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const double* p, const double* q, int64_t n,
                         int m, const double* alpha, hipStream_t st);
+// ---- fused Krylov steps (deterministic: per-workgroup partial sums, the last
+// workgroup to finish sums them in a fixed order and resets `counter`) ----
+constexpr int KRY_BLOCKS = 512;
+// out[c] = sum_i a[i,c] b[i,c]   (part: KRY_BLOCKS * m doubles, counter: 1 uint)
+hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, unsigned* counter,
+                           double* out, hipStream_t st);
+// CG update of m columns: alpha = active ? rz / pq : 0 (flag |= 1 if an active pq <= 0,
+// 2 if alpha is not finite); x += alpha p; r_out = r_in - alpha q; r32 = float(r_out)
+// if r32 != NULL; rr[c] = ||r_out[:,c]||^2.
+hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const double* p, const double* q,
+                            float* r32, int64_t n, int m, const double* rz, const double* pq,
+                            const int32_t* active, double* part, unsigned* counter, double* rr, int32_t* flag,
+                            hipStream_t st);
+// z = double(z32) if z32 != NULL; rz[c] = r.z ; zro[c] = z.r_old if r_old != NULL
+hipError_t launch_zdots(const float* z32, double* z, const double* r, const double* r_old, int64_t n, int m,
+                        double* part, unsigned* counter, double* rz, double* zro, hipStream_t st);
+// p = z + beta p, beta = active ? (rz_new - zro) / rz_old : 0  (zro may be NULL)
+hipError_t launch_cg_dir(double* p, const double* z, int64_t n, int m, const double* rz_new, const double* zro,
+                         const double* rz_old, const int32_t* active, hipStream_t st);
+
 // dst[i,c] = src[i,c] for the columns c with mask[c] != 0
 hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, const int32_t* mask, hipStream_t st);
 // p = z + beta p

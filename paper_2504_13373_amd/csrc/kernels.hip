@@ -1229,6 +1229,222 @@ hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const doub
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ fused Krylov steps
+
+// Block reduction of s[c] into part[c * gridDim.x + block]; the last block to
+// arrive sums the partials of every block in a fixed order into out[c].
+template <int M>
+__device__ __forceinline__ bool grid_reduce_tail(double (&s)[M], double* __restrict__ part, unsigned* counter,
+                                                 double* __restrict__ out) {
+    __shared__ double sh[WG];
+    __shared__ bool is_last;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        sh[threadIdx.x] = s[c];
+        __syncthreads();
+        for (int o = WG / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[int64_t(c) * gridDim.x + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned t = atomicAdd(counter, 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < int(gridDim.x); i += WG) v += part[int64_t(c) * gridDim.x + i];
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = WG / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = sh[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+    return true;
+}
+
+static inline unsigned kry_grid(int64_t n) {
+    return unsigned(std::min<int64_t>(KRY_BLOCKS, std::max<int64_t>(1, (n + WG - 1) / WG)));
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_dot_tail(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                                 int ld, double* part, unsigned* counter, double* out) {
+    double s[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) s[c] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG)
+#pragma unroll
+        for (int c = 0; c < M; ++c) s[c] += a[i * ld + c] * b[i * ld + c];
+    grid_reduce_tail<M>(s, part, counter, out);
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_cg_update(double* __restrict__ x, const double* r_in, double* r_out,
+                                                  const double* __restrict__ p, const double* __restrict__ q,
+                                                  float* __restrict__ r32, int64_t n, int ld,
+                                                  const double* __restrict__ rz, const double* __restrict__ pq,
+                                                  const int32_t* __restrict__ active, double* part, unsigned* counter,
+                                                  double* rr, int32_t* flag) {
+    double al[M], s[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        s[c] = 0.0;
+        al[c] = 0.0;
+        if (active[c]) {
+            const double d = pq[c];
+            al[c] = rz[c] / d;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                if (!(d > 0.0)) atomicOr(flag, 1);
+                if (!isfinite(al[c])) atomicOr(flag, 2);
+            }
+            if (!isfinite(al[c])) al[c] = 0.0;
+        }
+    }
+    for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const int64_t e = i * ld + c;
+            x[e] += al[c] * p[e];
+            const double v = r_in[e] - al[c] * q[e];
+            r_out[e] = v;
+            if (r32) r32[e] = float(v);
+            s[c] += v * v;
+        }
+    }
+    if (grid_reduce_tail<M>(s, part, counter, rr) && threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            if (!isfinite(rr[c])) atomicOr(flag, 2);
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, double* z, const double* __restrict__ r,
+                                              const double* __restrict__ r_old, int64_t n, int ld, double* part,
+                                              unsigned* counter, double* rz, double* zro) {
+    constexpr int M2 = 2 * M;
+    double s[M2];
+#pragma unroll
+    for (int c = 0; c < M2; ++c) s[c] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const int64_t e = i * ld + c;
+            double zv;
+            if (z32) {
+                zv = double(z32[e]);
+                z[e] = zv;
+            } else {
+                zv = z[e];
+            }
+            s[c] += r[e] * zv;
+            if (r_old) s[M + c] += zv * r_old[e];
+        }
+    }
+    // the 2M sums land in a staging area after the partials; the last block
+    // copies them to rz and zro
+    double* stage = part + int64_t(M2) * gridDim.x;
+    if (grid_reduce_tail<M2>(s, part, counter, stage) && threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            rz[c] = stage[c];
+            if (zro) zro[c] = stage[M + c];
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, int64_t n, int ld,
+                                               const double* __restrict__ rzn, const double* __restrict__ zro,
+                                               const double* __restrict__ rzo, const int32_t* __restrict__ active) {
+    double be[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) be[c] = active[c] ? (rzn[c] - (zro ? zro[c] : 0.0)) / rzo[c] : 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG)
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const int64_t e = i * ld + c;
+            p[e] = z[e] + be[c] * p[e];
+        }
+}
+
+template <typename F>
+static hipError_t for_chunks(int m, F&& f) {
+    int c0 = 0;
+    while (c0 < m) {
+        const int rem = m - c0;
+        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        hipError_t e = f(c0, w);
+        if (e != hipSuccess) return e;
+        c0 += w;
+    }
+    return hipSuccess;
+}
+
+#define KRY_DISPATCH(w, KERNEL, ...)                                                                   \
+    switch (w) {                                                                                     \
+        case 16: hipLaunchKernelGGL((KERNEL<16>), __VA_ARGS__); break;                                \
+        case 8: hipLaunchKernelGGL((KERNEL<8>), __VA_ARGS__); break;                                  \
+        case 4: hipLaunchKernelGGL((KERNEL<4>), __VA_ARGS__); break;                                  \
+        case 3: hipLaunchKernelGGL((KERNEL<3>), __VA_ARGS__); break;                                  \
+        case 2: hipLaunchKernelGGL((KERNEL<2>), __VA_ARGS__); break;                                  \
+        default: hipLaunchKernelGGL((KERNEL<1>), __VA_ARGS__); break;                                 \
+    }
+
+hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, unsigned* counter,
+                           double* out, hipStream_t st) {
+    const unsigned g = kry_grid(n);
+    return for_chunks(m, [&](int c0, int w) {
+        KRY_DISPATCH(w, k_dot_tail, dim3(g), dim3(WG), 0, st, a + c0, b + c0, n, m, part, counter, out + c0);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const double* p, const double* q,
+                            float* r32, int64_t n, int m, const double* rz, const double* pq,
+                            const int32_t* active, double* part, unsigned* counter, double* rr, int32_t* flag,
+                            hipStream_t st) {
+    const unsigned g = kry_grid(n);
+    return for_chunks(m, [&](int c0, int w) {
+        KRY_DISPATCH(w, k_cg_update, dim3(g), dim3(WG), 0, st, x + c0, r_in + c0, r_out + c0, p + c0, q + c0,
+                     r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, counter, rr + c0, flag);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_zdots(const float* z32, double* z, const double* r, const double* r_old, int64_t n, int m,
+                        double* part, unsigned* counter, double* rz, double* zro, hipStream_t st) {
+    // part must hold 2 * 16 * (KRY_BLOCKS + 1) doubles
+    const unsigned g = kry_grid(n);
+    return for_chunks(m, [&](int c0, int w) {
+        KRY_DISPATCH(w, k_zdots, dim3(g), dim3(WG), 0, st, z32 ? z32 + c0 : nullptr, z + c0, r + c0,
+                     r_old ? r_old + c0 : nullptr, n, m, part, counter, rz + c0, zro ? zro + c0 : nullptr);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_cg_dir(double* p, const double* z, int64_t n, int m, const double* rz_new, const double* zro,
+                         const double* rz_old, const int32_t* active, hipStream_t st) {
+    const unsigned g = kry_grid(n);
+    return for_chunks(m, [&](int c0, int w) {
+        KRY_DISPATCH(w, k_cg_dir, dim3(g), dim3(WG), 0, st, p + c0, z + c0, n, m, rz_new + c0,
+                     zro ? zro + c0 : nullptr, rz_old + c0, active + c0);
+        return hipGetLastError();
+    });
+}
+
 __global__ void k_copy_cols(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int m,
                             const int32_t* __restrict__ mask) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
