@@ -192,6 +192,8 @@ typedef struct {
  * The V-cycle precision is AMGDG_FP64 or AMGDG_MIXED (needs params.mixed). */
 #define AMGDG_X0             1
 #define AMGDG_INTERNAL_ORDER 2
+#define AMGDG_EAGER          4  /* launch the V-cycle kernel by kernel instead of replaying
+                                   its captured HIP graph (the default for solve and vcycle) */
 int amgdg_solve(amgdg_handle h, int32_t m, const double* b_dev, double* x_dev, int32_t method,
                 int32_t precision, double rtol, int32_t max_it, int32_t restart, int32_t flags,
                 amgdg_solve_stats* stats, void* stream);

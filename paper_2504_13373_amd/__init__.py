@@ -26,7 +26,7 @@ AMGDG_B_RELAXED, AMGDG_B_INPUT, AMGDG_PTILDE, AMGDG_SVALS = 14, 15, 16, 17
 # precision, methods, flags, ops
 AMGDG_FP64, AMGDG_MIXED = 0, 1
 AMGDG_STATIONARY, AMGDG_PCG, AMGDG_FCG, AMGDG_FGMRES = 0, 1, 2, 3
-AMGDG_X0, AMGDG_INTERNAL_ORDER = 1, 2
+AMGDG_X0, AMGDG_INTERNAL_ORDER, AMGDG_EAGER = 1, 2, 4
 (AMGDG_OP_SPMV, AMGDG_OP_SWEEP, AMGDG_OP_SWEEP0, AMGDG_OP_RESIDUAL, AMGDG_OP_RESTRICT,
  AMGDG_OP_PROLONG, AMGDG_OP_COARSE) = range(7)
 

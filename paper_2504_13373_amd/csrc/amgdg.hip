@@ -141,6 +141,7 @@ struct Ctx {
     double *kb = nullptr, *kx = nullptr, *kr = nullptr, *kr2 = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr,
            *kt = nullptr;
     float *kr32 = nullptr, *kz32 = nullptr;
+    double *kgin = nullptr, *kgout = nullptr;  // fixed input/output of the FP64 V-cycle graph
     double *V = nullptr, *Z = nullptr;
     int32_t* active_d = nullptr;
     // fused Krylov steps: partial sums, arrival counter, status record (rr[0..64), flag)
@@ -148,7 +149,30 @@ struct Ctx {
     unsigned* counter = nullptr;
     double* stat = nullptr;
     double* stat_h = nullptr;  // pinned host mirror of stat
+    // captured V-cycles, keyed by (precision, columns, input, output)
+    struct GraphEntry {
+        int prec, m;
+        const void* in;
+        void* out;
+        hipGraph_t g;
+        hipGraphExec_t e;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap = nullptr;
+    hipEvent_t ev = nullptr;  // status readback of the Krylov loop
+    bool use_graph = true;  // per call: off with AMGDG_EAGER
+    void drop_graphs() {
+        for (auto& e : graphs) {
+            (void)hipGraphExecDestroy(e.e);
+            (void)hipGraphDestroy(e.g);
+        }
+        graphs.clear();
+    }
     ~Ctx() {
+        (void)hipDeviceSynchronize();
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+        if (ev) (void)hipEventDestroy(ev);
         if (stat_h) (void)hipHostFree(stat_h);
     }
 };
@@ -611,6 +635,7 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
 static void ensure_ws(Ctx& C, int m, hipStream_t st) {
     if (m <= C.ws_m) return;
     HIPCHK(hipStreamSynchronize(st));
+    C.drop_graphs();
     C.ws.release();
     for (int k = 0; k <= C.N; ++k) {
         Level& L = C.lv[k];
@@ -710,6 +735,50 @@ static void vcycle_impl(Ctx& C, const T* b0, T* z0, int m, hipStream_t st) {
     }
 }
 
+// The V-cycle as a captured HIP graph: its ~40 launches (most of them small
+// coarse-level kernels) are submitted as one graph launch, so the host no
+// longer paces the coarse levels.  The graph is captured on a private stream
+// the first time a (precision, m, input, output) combination is seen and
+// replayed on the caller's stream; workspace reallocation drops the cache.  It
+// holds only kernel nodes (no memset or copy nodes).
+template <typename T>
+static void vcycle_run(Ctx& C, const T* b0, T* z0, int m, hipStream_t st, bool allow_graph) {
+    if (!allow_graph || C.prm.t_pre == 0 || C.N == 0) {
+        vcycle_impl<T>(C, b0, z0, m, st);
+        return;
+    }
+    const int prec = int(sizeof(T));
+    for (auto& e : C.graphs)
+        if (e.prec == prec && e.m == m && e.in == b0 && e.out == z0) {
+            HIPCHK(hipGraphLaunch(e.e, st));
+            return;
+        }
+    if (C.graphs.size() >= 8) {
+        HIPCHK(hipStreamSynchronize(st));
+        C.drop_graphs();
+    }
+    if (!C.cap) HIPCHK(hipStreamCreateWithFlags(&C.cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(C.cap, hipStreamCaptureModeThreadLocal));
+    try {
+        vcycle_impl<T>(C, b0, z0, m, C.cap);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(C.cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamEndCapture(C.cap, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        HIPCHK(err);
+    }
+    C.graphs.push_back({prec, m, b0, z0, g, ex});
+    HIPCHK(hipGraphLaunch(ex, st));
+}
+
 // ------------------------------------------------------------ Krylov drivers
 
 struct KrylovState {
@@ -722,8 +791,10 @@ static void ensure_krylov(Ctx& C, int m, int restart, int method, hipStream_t st
     const int64_t n = C.lv[0].n;
     if (C.kr_m >= m && (method != AMGDG_FGMRES || C.kr_restart >= restart) && C.kb) return;
     HIPCHK(hipStreamSynchronize(st));
+    C.drop_graphs();
     for (void* p : {(void*)C.kb, (void*)C.kx, (void*)C.kr, (void*)C.kr2, (void*)C.kz, (void*)C.kp, (void*)C.kq,
-                    (void*)C.kt, (void*)C.kr32, (void*)C.kz32, (void*)C.V, (void*)C.Z, (void*)C.active_d})
+                    (void*)C.kt, (void*)C.kr32, (void*)C.kz32, (void*)C.V, (void*)C.Z, (void*)C.active_d,
+                    (void*)C.kgin, (void*)C.kgout})
         if (p) C.ws.free(p);
     C.kb = C.ws.alloc<double>(n * m);
     C.kx = C.ws.alloc<double>(n * m);
@@ -735,6 +806,8 @@ static void ensure_krylov(Ctx& C, int m, int restart, int method, hipStream_t st
     C.kt = C.ws.alloc<double>(n * m);
     C.kr32 = C.mixed ? C.ws.alloc<float>(n * m) : nullptr;
     C.kz32 = C.mixed ? C.ws.alloc<float>(n * m) : nullptr;
+    C.kgin = C.ws.alloc<double>(n * m);
+    C.kgout = C.ws.alloc<double>(n * m);
     C.active_d = C.ws.alloc<int32_t>(128);
     if (method == AMGDG_FGMRES) {
         C.V = C.ws.alloc<double>(n * (restart + 1));
@@ -747,14 +820,26 @@ static void ensure_krylov(Ctx& C, int m, int restart, int method, hipStream_t st
     C.kr_m = m;
 }
 
+// z = V(r) in FP64 for arbitrary r, z: through the graph's fixed buffers.
+static void precond_fp64(Ctx& C, const double* r, double* z, int m, hipStream_t st) {
+    if (!C.use_graph) {
+        vcycle_impl<double>(C, r, z, m, st);
+        return;
+    }
+    const size_t bytes = sizeof(double) * size_t(C.lv[0].n) * m;
+    if (r != C.kgin) HIPCHK(hipMemcpyAsync(C.kgin, r, bytes, hipMemcpyDeviceToDevice, st));
+    vcycle_run<double>(C, C.kgin, C.kgout, m, st, true);
+    if (z != C.kgout) HIPCHK(hipMemcpyAsync(z, C.kgout, bytes, hipMemcpyDeviceToDevice, st));
+}
+
 static void precond(Ctx& C, const double* r, double* z, int m, int precision, hipStream_t st) {
     const int64_t n = C.lv[0].n;
     if (precision == AMGDG_MIXED) {
         HIPCHK((launch_convert<double, float>(r, C.kr32, n * m, st)));
-        vcycle_impl<float>(C, C.kr32, C.kz32, m, st);
+        vcycle_run<float>(C, C.kr32, C.kz32, m, st, C.use_graph);
         HIPCHK((launch_convert<float, double>(C.kz32, z, n * m, st)));
     } else {
-        vcycle_impl<double>(C, r, z, m, st);
+        precond_fp64(C, r, z, m, st);
     }
 }
 
@@ -815,23 +900,32 @@ static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool fl
     upload_act();
     HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
     auto apply_M = [&](double* rz_out, const double* r_old, double* zro) {
-        if (mixed) vcycle_impl<float>(C, C.kr32, C.kz32, m, st);
-        else vcycle_impl<double>(C, r, z, m, st);
+        if (mixed) vcycle_run<float>(C, C.kr32, C.kz32, m, st, C.use_graph);
+        else if (!flexible) vcycle_run<double>(C, r, z, m, st, C.use_graph);  // r, z are fixed buffers here
+        else precond_fp64(C, r, z, m, st);
         HIPCHK(launch_zdots(mixed ? C.kz32 : nullptr, z, r, r_old, n, m, C.kpart, C.counter, rz_out, zro, st));
     };
     if (mixed) HIPCHK((launch_convert<double, float>(r, r32, n * m, st)));
     apply_M(d_rz, nullptr, nullptr);
     HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
+    mat_spmv<double>(AX, L.A, p, nullptr, q, m, st);
+    HIPCHK(launch_dot_tail(p, q, n, m, C.kpart, C.counter, d_pq, st));
+    if (!C.ev) HIPCHK(hipEventCreateWithFlags(&C.ev, hipEventDisableTiming));
     for (int it = 1; it <= maxit; ++it) {
-        mat_spmv<double>(AX, L.A, p, nullptr, q, m, st);
-        HIPCHK(launch_dot_tail(p, q, n, m, C.kpart, C.counter, d_pq, st));
         HIPCHK(launch_cg_update(x, r, flexible ? rn : r, p, q, r32, n, m, d_rz, d_pq, C.active_d, C.kpart, C.counter,
                                 C.stat, flag, st));
         if (flexible) std::swap(r, rn);  // r: new residual, rn: previous
         HIPCHK(hipMemcpyAsync(C.stat_h, C.stat, sizeof(double) * 65, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipEventRecord(C.ev, st));
+        // run ahead: the preconditioner of the new residual is queued before the
+        // host looks at the status, so the GPU does not wait for the host; it
+        // writes only z and the new dot products, so it is simply redone if the
+        // residual gets replaced below
+        apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
+        HIPCHK(hipEventSynchronize(C.ev));
         const int32_t f = *reinterpret_cast<const int32_t*>(C.stat_h + 64);
         if (f) {
+            HIPCHK(hipStreamSynchronize(st));
             HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
             throw Error(f & 1 ? AMGDG_EBREAKDOWN : AMGDG_ENAN,
                         f & 1 ? "CG breakdown: p^T A p <= 0 (matrix or preconditioner not SPD)" : "NaN in CG");
@@ -866,17 +960,23 @@ static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool fl
                 HIPCHK(hipMemcpyAsync(C.active_d + 64, repl.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
                 HIPCHK(launch_copy_cols(C.kt, r, n, m, C.active_d + 64, st));
                 if (mixed) HIPCHK((launch_convert<double, float>(r, r32, n * m, st)));
+                apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
                 HIPCHK(hipStreamSynchronize(st));
             }
         }
         any = false;
         for (int c = 0; c < m; ++c) any = any || act[c];
-        if (!any) return AMGDG_OK;
+        if (!any) {
+            HIPCHK(hipStreamSynchronize(st));
+            return AMGDG_OK;
+        }
         if (changed) upload_act();
-        apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
         HIPCHK(launch_cg_dir(p, z, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz, C.active_d, st));
         std::swap(d_rz, d_rz2);
+        mat_spmv<double>(AX, L.A, p, nullptr, q, m, st);
+        HIPCHK(launch_dot_tail(p, q, n, m, C.kpart, C.counter, d_pq, st));
     }
+    HIPCHK(hipStreamSynchronize(st));
     return AMGDG_ENOCONV;
 }
 
@@ -997,6 +1097,7 @@ static int solve_impl(Ctx& C, int m, const double* b_dev, double* x_dev, int met
         throw Error(AMGDG_EUNSUPPORTED, "FGMRES: m = 1 and 1 <= restart <= 256");
     if (method < AMGDG_STATIONARY || method > AMGDG_FGMRES) throw Error(AMGDG_EINVAL, "bad method");
     const auto t0 = std::chrono::steady_clock::now();
+    C.use_graph = !(flags & AMGDG_EAGER);
     ensure_ws(C, m, st);
     ensure_krylov(C, m, restart, method, st);
     Level& L = C.lv[0];
@@ -1451,14 +1552,15 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
     ensure_krylov(C, m, 0, AMGDG_PCG, st);
     Level& L = C.lv[0];
     const bool internal = flags & AMGDG_INTERNAL_ORDER;
+    const bool graph = !(flags & AMGDG_EAGER);
     if (precision == AMGDG_FP64) {
         const double* r = static_cast<const double*>(r_dev);
         double* z = static_cast<double*>(z_dev);
         if (internal) {
-            vcycle_impl<double>(C, r, z, m, st);
+            vcycle_run<double>(C, r, z, m, st, graph);
         } else {
             HIPCHK((launch_permute<double, double>(r, C.kr, C.perm_d, L.n_units, L.nb, m, 1, st)));
-            vcycle_impl<double>(C, C.kr, C.kz, m, st);
+            vcycle_run<double>(C, C.kr, C.kz, m, st, graph);
             HIPCHK((launch_permute<double, double>(C.kz, z, C.perm_d, L.n_units, L.nb, m, 0, st)));
         }
     } else if (precision == AMGDG_MIXED) {
@@ -1466,10 +1568,10 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
         const float* r = static_cast<const float*>(r_dev);
         float* z = static_cast<float*>(z_dev);
         if (internal) {
-            vcycle_impl<float>(C, r, z, m, st);
+            vcycle_run<float>(C, r, z, m, st, graph);
         } else {
             HIPCHK((launch_permute<float, float>(r, C.kr32, C.perm_d, L.n_units, L.nb, m, 1, st)));
-            vcycle_impl<float>(C, C.kr32, C.kz32, m, st);
+            vcycle_run<float>(C, C.kr32, C.kz32, m, st, graph);
             HIPCHK((launch_permute<float, float>(C.kz32, z, C.perm_d, L.n_units, L.nb, m, 0, st)));
         }
     } else {

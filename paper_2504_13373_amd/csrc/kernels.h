@@ -122,9 +122,10 @@ hipError_t launch_axpby_dev(const double* x, double* y, int64_t n, int m, const 
 // CG updates: x += alpha p ; r -= alpha q  (per column alpha)
 hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const double* p, const double* q, int64_t n,
                         int m, const double* alpha, hipStream_t st);
-// ---- fused Krylov steps (deterministic: per-workgroup partial sums, the last
-// workgroup to finish sums them in a fixed order and resets `counter`) ----
-constexpr int KRY_BLOCKS = 512;
+// ---- fused Krylov steps (deterministic: each workgroup writes partial sums,
+// a one-workgroup finalize kernel adds them in a fixed order; `counter` is
+// unused and kept for the call signature) ----
+constexpr int KRY_BLOCKS = 2048;
 // out[c] = sum_i a[i,c] b[i,c]   (part: KRY_BLOCKS * m doubles, counter: 1 uint)
 hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, unsigned* counter,
                            double* out, hipStream_t st);

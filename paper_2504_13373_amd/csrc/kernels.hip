@@ -1231,13 +1231,12 @@ hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const doub
 
 // ------------------------------------------------------------ fused Krylov steps
 
-// Block reduction of s[c] into part[c * gridDim.x + block]; the last block to
-// arrive sums the partials of every block in a fixed order into out[c].
+// Each workgroup writes its partial sums s[c] to part[c * gridDim.x + block];
+// k_finalize sums them in a fixed order (the kernel boundary orders the two, so
+// no device-scope fence is needed inside the streaming kernels).
 template <int M>
-__device__ __forceinline__ bool grid_reduce_tail(double (&s)[M], double* __restrict__ part, unsigned* counter,
-                                                 double* __restrict__ out) {
+__device__ __forceinline__ void block_partials(double (&s)[M], double* __restrict__ part) {
     __shared__ double sh[WG];
-    __shared__ bool is_last;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         sh[threadIdx.x] = s[c];
@@ -1249,29 +1248,30 @@ __device__ __forceinline__ bool grid_reduce_tail(double (&s)[M], double* __restr
         if (threadIdx.x == 0) part[int64_t(c) * gridDim.x + blockIdx.x] = sh[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
+}
+
+// out1[c] = sum_i part[c*np + i] for c < split, out2[c - split] for c >= split;
+// flag |= 2 if a sum is not finite (flag may be NULL).
+__global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int np, int mt,
+                                                 double* __restrict__ out1, int split, double* __restrict__ out2,
+                                                 int32_t* __restrict__ flag) {
+    __shared__ double sh[WG];
+    for (int c = 0; c < mt; ++c) {
         double v = 0.0;
-        for (int i = threadIdx.x; i < int(gridDim.x); i += WG) v += part[int64_t(c) * gridDim.x + i];
+        for (int i = threadIdx.x; i < np; i += WG) v += part[int64_t(c) * np + i];
         sh[threadIdx.x] = v;
         __syncthreads();
         for (int o = WG / 2; o > 0; o >>= 1) {
             if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
             __syncthreads();
         }
-        if (threadIdx.x == 0) out[c] = sh[0];
+        if (threadIdx.x == 0) {
+            if (c < split) out1[c] = sh[0];
+            else out2[c - split] = sh[0];
+            if (flag && !isfinite(sh[0])) atomicOr(flag, 2);
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-    return true;
 }
 
 static inline unsigned kry_grid(int64_t n) {
@@ -1279,15 +1279,15 @@ static inline unsigned kry_grid(int64_t n) {
 }
 
 template <int M>
-__global__ __launch_bounds__(WG) void k_dot_tail(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
-                                                 int ld, double* part, unsigned* counter, double* out) {
+__global__ __launch_bounds__(WG) void k_dot_part2(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                                  int ld, double* part) {
     double s[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) s[c] = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG)
 #pragma unroll
         for (int c = 0; c < M; ++c) s[c] += a[i * ld + c] * b[i * ld + c];
-    grid_reduce_tail<M>(s, part, counter, out);
+    block_partials<M>(s, part);
 }
 
 template <int M>
@@ -1295,8 +1295,7 @@ __global__ __launch_bounds__(WG) void k_cg_update(double* __restrict__ x, const 
                                                   const double* __restrict__ p, const double* __restrict__ q,
                                                   float* __restrict__ r32, int64_t n, int ld,
                                                   const double* __restrict__ rz, const double* __restrict__ pq,
-                                                  const int32_t* __restrict__ active, double* part, unsigned* counter,
-                                                  double* rr, int32_t* flag) {
+                                                  const int32_t* __restrict__ active, double* part, int32_t* flag) {
     double al[M], s[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
@@ -1323,17 +1322,12 @@ __global__ __launch_bounds__(WG) void k_cg_update(double* __restrict__ x, const 
             s[c] += v * v;
         }
     }
-    if (grid_reduce_tail<M>(s, part, counter, rr) && threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < M; ++c)
-            if (!isfinite(rr[c])) atomicOr(flag, 2);
-    }
+    block_partials<M>(s, part);
 }
 
 template <int M>
 __global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, double* z, const double* __restrict__ r,
-                                              const double* __restrict__ r_old, int64_t n, int ld, double* part,
-                                              unsigned* counter, double* rz, double* zro) {
+                                              const double* __restrict__ r_old, int64_t n, int ld, double* part) {
     constexpr int M2 = 2 * M;
     double s[M2];
 #pragma unroll
@@ -1353,16 +1347,7 @@ __global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, dou
             if (r_old) s[M + c] += zv * r_old[e];
         }
     }
-    // the 2M sums land in a staging area after the partials; the last block
-    // copies them to rz and zro
-    double* stage = part + int64_t(M2) * gridDim.x;
-    if (grid_reduce_tail<M2>(s, part, counter, stage) && threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            rz[c] = stage[c];
-            if (zro) zro[c] = stage[M + c];
-        }
-    }
+    block_partials<M2>(s, part);
 }
 
 template <int M>
@@ -1405,9 +1390,12 @@ static hipError_t for_chunks(int m, F&& f) {
 
 hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, unsigned* counter,
                            double* out, hipStream_t st) {
+    (void)counter;
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
-        KRY_DISPATCH(w, k_dot_tail, dim3(g), dim3(WG), 0, st, a + c0, b + c0, n, m, part, counter, out + c0);
+        KRY_DISPATCH(w, k_dot_part2, dim3(g), dim3(WG), 0, st, a + c0, b + c0, n, m, part);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), w, out + c0, w,
+                           static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr));
         return hipGetLastError();
     });
 }
@@ -1416,21 +1404,26 @@ hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const 
                             float* r32, int64_t n, int m, const double* rz, const double* pq,
                             const int32_t* active, double* part, unsigned* counter, double* rr, int32_t* flag,
                             hipStream_t st) {
+    (void)counter;
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
         KRY_DISPATCH(w, k_cg_update, dim3(g), dim3(WG), 0, st, x + c0, r_in + c0, r_out + c0, p + c0, q + c0,
-                     r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, counter, rr + c0, flag);
+                     r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), w, rr + c0, w,
+                           static_cast<double*>(nullptr), flag);
         return hipGetLastError();
     });
 }
 
 hipError_t launch_zdots(const float* z32, double* z, const double* r, const double* r_old, int64_t n, int m,
                         double* part, unsigned* counter, double* rz, double* zro, hipStream_t st) {
-    // part must hold 2 * 16 * (KRY_BLOCKS + 1) doubles
+    (void)counter;
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
         KRY_DISPATCH(w, k_zdots, dim3(g), dim3(WG), 0, st, z32 ? z32 + c0 : nullptr, z + c0, r + c0,
-                     r_old ? r_old + c0 : nullptr, n, m, part, counter, rz + c0, zro ? zro + c0 : nullptr);
+                     r_old ? r_old + c0 : nullptr, n, m, part);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), r_old ? 2 * w : w, rz + c0, w,
+                           zro ? zro + c0 : static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr));
         return hipGetLastError();
     });
 }

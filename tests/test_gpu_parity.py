@@ -341,3 +341,42 @@ def test_error_paths():
         am.amgdg_solve(h, bn, x, am.AMGDG_PCG)
     assert e.value.code == am.AMGDG_ENAN
     h.close()
+
+
+# ------------------------------------------------------------------ captured V-cycle
+
+@pytest.mark.parametrize("prec", [am.AMGDG_FP64, am.AMGDG_MIXED])
+@pytest.mark.parametrize("m", [1, 3])
+def test_graph_replays_match_eager(prec, m):
+    """The V-cycle replayed from its captured graph equals the kernel-by-kernel
+    V-cycle bit for bit, on every replay, with eager work and synchronisations
+    between the replays."""
+    w, H, h = case("sipg3")
+    dt = torch.float64 if prec == am.AMGDG_FP64 else torch.float32
+    g = np.random.default_rng(31)
+    for rep in range(4):
+        r = to_dev(g.standard_normal((w.A.n, m)) if m > 1 else g.standard_normal(w.A.n), dt)
+        z_eager = torch.zeros_like(r)
+        am.amgdg_vcycle(h, r, z_eager, precision=prec, flags=am.AMGDG_EAGER)
+        torch.cuda.synchronize()
+        z_graph = torch.full_like(r, float("nan"))
+        am.amgdg_vcycle(h, r, z_graph, precision=prec)
+        # eager work in between: a single step on another level and a torch op
+        y = torch.zeros(am.amgdg_level_info_get(h, 1).n, dtype=dt, device=DEV)
+        am.amgdg_apply(h, 1, am.AMGDG_OP_SPMV, torch.ones_like(y), None, y, precision=prec)
+        _ = (r * 2).sum()
+        torch.cuda.synchronize()
+        assert torch.equal(z_graph, z_eager), rep
+
+
+def test_graph_solve_equals_eager_solve():
+    w, H, h = case("sipg3")
+    b = to_dev(w.b)
+    for meth, prec in ((am.AMGDG_PCG, am.AMGDG_FP64), (am.AMGDG_FCG, am.AMGDG_MIXED), (am.AMGDG_FCG, am.AMGDG_FP64)):
+        x1 = torch.zeros_like(b)
+        rc1, st1 = am.amgdg_solve(h, b, x1, meth, prec, 1e-8, 5000, flags=am.AMGDG_EAGER)
+        x2 = torch.zeros_like(b)
+        rc2, st2 = am.amgdg_solve(h, b, x2, meth, prec, 1e-8, 5000)
+        assert rc1 == rc2 == am.AMGDG_OK
+        assert st1.iterations[0] == st2.iterations[0]
+        assert torch.equal(x1, x2)
