@@ -48,6 +48,22 @@ def sweep_bytes(info, w, m):
             + info.n_units * info.nb * info.nb * w + 3 * info.n * m * w)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernels.hip (else None)."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "sweep_level0_poisson2d_p3_256_traffic.txt")
+    src = os.path.join(ROOT, "paper_2504_13373_amd", "csrc", "kernels.hip")
+    if not os.path.exists(f):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(f) if "=" in l)
+    if kv.get("kernel") != kernel:
+        return None
+    if kv.get("kernels_hip_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return float(kv["hbm_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +73,9 @@ def main():
     ap.add_argument("--side", type=int, default=256, help="grid points per side (256: the full workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="also run a plain elementwise copy of MB megabytes (reads and writes MB each), "
+                         "the reference for the HBM traffic counters")
     ap.add_argument("--max-it", type=int, default=50000,
                     help="iteration cap per solve (profiling runs cap it; the reported value needs convergence)")
     args = ap.parse_args()
@@ -159,6 +178,15 @@ def main():
         kern[name] = dict(us=t * 1e6, gbps=byts / t / 1e9, bytes=byts)
         log(f"level-0 sweep {name}: {t * 1e6:.1f} us, {byts / 1e6:.1f} MB, {byts / t / 1e9:.0f} GB/s")
 
+    if args.copy_calibration:
+        nbytes = args.copy_calibration * 1000 * 1000
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x elementwise copy of {nbytes} bytes")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, res["fp64"]["its"])
@@ -193,7 +221,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": k["gbps"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("k_sweep<float, 1, 0>"),
             "bytes_per_launch": k["bytes"],
             "us_per_launch": k["us"],
         },
