@@ -187,9 +187,19 @@ typedef struct {
 
 /* Solves A X = B for m columns from X = 0 (or the given X if AMGDG_X0 is set in
  * flags), stopping each column when its true relative residual is <= rtol.
- *   b_dev, x_dev : device, n x m doubles, caller order
+ *   b_dev, x_dev : device, n x m doubles (row-major: column c of row i at
+ *                  i * m + c), caller order
  *   stats        : host or NULL
- * The V-cycle precision is AMGDG_FP64 or AMGDG_MIXED (needs params.mixed). */
+ * The V-cycle precision is AMGDG_FP64 or AMGDG_MIXED (needs params.mixed).
+ * PCG and FCG (section 5 runs CG with the V-cycle of Algorithm 2 as its
+ * preconditioner) treat the columns as independent solves: every kernel
+ * computes column c from column c alone and reductions add in an order fixed
+ * by n, so a column's iterates, iteration count and result are bit-identical
+ * whatever m is and whatever the other columns hold.  In FCG a column whose
+ * recursive residual has dropped by 1e-6 since its last check, or meets rtol,
+ * is checked against its true residual, which replaces the recursive one when
+ * it is above rtol.  Returns AMGDG_ENOCONV if a column did not converge within
+ * max_it iterations; a breakdown (p^T A p <= 0) or a NaN fails the call. */
 #define AMGDG_X0             1
 #define AMGDG_INTERNAL_ORDER 2
 #define AMGDG_EAGER          4  /* launch the V-cycle kernel by kernel instead of replaying
@@ -218,6 +228,54 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
 #define AMGDG_OP_COARSE    6  /* y = A_N^{-1} x on the coarsest level (always FP64)  */
 int amgdg_apply(amgdg_handle h, int32_t k, int32_t op, int32_t m, int32_t precision, const void* x,
                 const void* b, void* y, int32_t flags, void* stream);
+
+/* Device bytes of the solve state of one batch of `width` right-hand sides on
+ * this hierarchy (what a server counts against its budget per batch). */
+int amgdg_batch_bytes(amgdg_handle h, int32_t width, int64_t* bytes);
+
+/* Serving: continuous batching of the PCG / FCG solves of amgdg_solve
+ * (section 5), submitted one right-hand side at a time.
+ * Requests on the same (handle, method, precision) share a batch of `width`
+ * columns: a request takes a free column between two iterations and leaves it
+ * when it converges, fails or reaches max_it, so every level operator is read
+ * once per iteration for all requests of the batch (the multi-RHS kernels).
+ * Each request's iterates, iteration count and x are bit-identical to
+ * amgdg_solve of that right-hand side alone (m = 1).  Each batch runs on a
+ * stream of its own.  A new batch is created only while the device bytes of
+ * all batches (amgdg_batch_bytes) stay within hbm_budget_bytes; an idle batch
+ * of another key is released to make room; otherwise the request waits.
+ * Requests are admitted in submission order; one that cannot be placed does
+ * not hold back those that can.  The server does not own the handles: destroy
+ * it before them.  One host thread drives a server.
+ *   width           : columns per batch, 1..64
+ *   hbm_budget_bytes: > 0 */
+typedef struct amgdg_server_s* amgdg_server;
+int amgdg_server_create(amgdg_server* out, int32_t width, int64_t hbm_budget_bytes);
+/* Queues one right-hand side.  b_dev, x_dev: device, n doubles each, caller
+ * order unless AMGDG_INTERNAL_ORDER; with AMGDG_X0, x_dev holds the initial
+ * guess.  b_dev must hold its values on the device when submitted (the
+ * server's streams are not ordered after the caller's) and both arrays must
+ * stay valid and untouched until the request is reported by amgdg_server_poll,
+ * when x_dev holds the result.  method: AMGDG_PCG or AMGDG_FCG.  tag: the
+ * caller's id, reported back.  AMGDG_ENOMEM if one batch on this handle
+ * exceeds the budget. */
+int amgdg_server_submit(amgdg_server s, amgdg_handle h, const double* b_dev, double* x_dev,
+                        int32_t method, int32_t precision, double rtol, int32_t max_it, int32_t flags,
+                        int64_t tag);
+/* Admits queued requests and advances every batch whose last queued
+ * iteration has finished, without blocking; with wait != 0 it first waits
+ * (spinning) until at least one batch has moved on.  n_pending (may be NULL):
+ * requests queued, running or not yet reported. */
+int amgdg_server_step(amgdg_server s, int32_t wait, int64_t* n_pending);
+/* Reports up to `capacity` finished requests, oldest first, and forgets them:
+ * tag, status (AMGDG_OK, AMGDG_ENOCONV, AMGDG_EBREAKDOWN, AMGDG_ENAN), iteration
+ * count, true relative residual and latency (seconds from submission to the
+ * step that saw x written).  Arrays are host memory of `capacity` entries;
+ * all but tags may be NULL.  *n_done: entries written. */
+int amgdg_server_poll(amgdg_server s, int32_t capacity, int64_t* tags, int32_t* status,
+                      int32_t* iterations, double* rel_residual, double* latency_s, int32_t* n_done);
+/* Waits for the server's streams and frees its batches. */
+int amgdg_server_destroy(amgdg_server s);
 
 /* Message for the last non-zero status returned on the calling thread. */
 const char* amgdg_last_error(void);

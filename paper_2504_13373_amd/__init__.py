@@ -81,6 +81,12 @@ _SIGS = {
                            ctypes.POINTER(amgdg_solve_stats), _P]),
     "amgdg_vcycle": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P]),
     "amgdg_apply": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
+    "amgdg_batch_bytes": (_I32, [_P, _I32, ctypes.POINTER(_I64)]),
+    "amgdg_server_create": (_I32, [ctypes.POINTER(_P), _I32, _I64]),
+    "amgdg_server_submit": (_I32, [_P, _P, _P, _P, _I32, _I32, _D, _I32, _I32, _I64]),
+    "amgdg_server_step": (_I32, [_P, _I32, ctypes.POINTER(_I64)]),
+    "amgdg_server_poll": (_I32, [_P, _I32, _P, _P, _P, _P, _P, ctypes.POINTER(_I32)]),
+    "amgdg_server_destroy": (_I32, [_P]),
 }
 
 
@@ -282,6 +288,62 @@ def amgdg_vcycle(handle, r, z, precision=AMGDG_FP64, flags=0, stream=None):
 def amgdg_apply(handle, k, op, x, b, y, precision=AMGDG_FP64, flags=0, stream=None):
     m = 1 if y.dim() == 1 else y.shape[1]
     _check(lib().amgdg_apply(handle.h, k, op, m, precision, _dptr(x), _dptr(b), _dptr(y), flags, _stream(stream)))
+
+
+def amgdg_batch_bytes(handle, width):
+    out = _I64(0)
+    _check(lib().amgdg_batch_bytes(handle.h, width, ctypes.byref(out)))
+    return out.value
+
+
+class Server:
+    """Continuous-batching solve server (``amgdg_server_*``).  Submitted tensors
+    must stay alive until their tag is reported by :meth:`poll`."""
+
+    def __init__(self, width, hbm_budget_bytes):
+        h = _P()
+        _check(lib().amgdg_server_create(ctypes.byref(h), width, int(hbm_budget_bytes)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, handle, b, x, method=AMGDG_PCG, precision=AMGDG_FP64, rtol=1e-8, max_it=10000, flags=0,
+               tag=0):
+        _check(lib().amgdg_server_submit(self.h, handle.h, _dptr(b), _dptr(x), method, precision, rtol, max_it,
+                                         flags, int(tag)))
+        self._keep[int(tag)] = (b, x)
+
+    def step(self, wait=True):
+        n = _I64(0)
+        _check(lib().amgdg_server_step(self.h, 1 if wait else 0, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, capacity=64):
+        """List of (tag, status, iterations, rel_residual, latency_s)."""
+        import numpy as np
+        tags = np.zeros(capacity, np.int64)
+        stat = np.zeros(capacity, np.int32)
+        its = np.zeros(capacity, np.int32)
+        rel = np.zeros(capacity, np.float64)
+        lat = np.zeros(capacity, np.float64)
+        n = _I32(0)
+        _check(lib().amgdg_server_poll(self.h, capacity, _ptr(tags), _ptr(stat), _ptr(its), _ptr(rel), _ptr(lat),
+                                       ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            out.append((int(tags[i]), int(stat[i]), int(its[i]), float(rel[i]), float(lat[i])))
+            self._keep.pop(int(tags[i]), None)
+        return out
+
+    def close(self):
+        if self.h:
+            _check(lib().amgdg_server_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def setup_from_workload(w, mixed=False, stream=None, **overrides):

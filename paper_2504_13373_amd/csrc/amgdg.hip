@@ -7,10 +7,12 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <limits>
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/amgdg.h"
@@ -37,24 +39,24 @@ struct Error : std::runtime_error {
 // ------------------------------------------------------------ device memory
 struct DevMem {
     std::vector<void*> blocks;
+    std::vector<size_t> sizes;
     ~DevMem() { release(); }
     void release() {
         for (void* p : blocks) (void)hipFree(p);
         blocks.clear();
+        sizes.clear();
     }
     template <typename T>
     T* alloc(int64_t n) {
         void* p = nullptr;
-        HIPCHK(hipMalloc(&p, sizeof(T) * size_t(std::max<int64_t>(n, 1))));
+        const size_t bytes = sizeof(T) * size_t(std::max<int64_t>(n, 1));
+        HIPCHK(hipMalloc(&p, bytes));
         blocks.push_back(p);
+        sizes.push_back(bytes);
         return static_cast<T*>(p);
     }
-    void free(void* p) {
-        auto it = std::find(blocks.begin(), blocks.end(), p);
-        if (it != blocks.end()) {
-            (void)hipFree(p);
-            blocks.erase(it);
-        }
+    void zero_all(hipStream_t st) {
+        for (size_t i = 0; i < blocks.size(); ++i) HIPCHK(hipMemsetAsync(blocks[i], 0, sizes[i], st));
     }
 };
 
@@ -114,41 +116,39 @@ struct Level {
     float* Dinv_nat32 = nullptr;
     MatStore A, T, R;
     double *B_in = nullptr, *B_rel = nullptr, *Pu = nullptr, *sv = nullptr, *T_nat = nullptr, *R_nat = nullptr;
-    VBuf<double> v64;
-    VBuf<float> v32;
 };
 
-struct Ctx {
+// Status record of a Work (doubles): [0, 64) ||r||^2 per column from the CG
+// update; [64, 96) one int32 error flag per column; [96, 160) ||b||^2 and
+// [160, 224) ||b - A x0||^2 of the columns admitted in the iteration;
+// [224, 288) true residual norms^2.
+constexpr int ST_RR = 0, ST_FLAG = 64, ST_BN = 96, ST_R0 = 160, ST_TR = 224, ST_LEN = 288;
+// column masks (int32): direction update, CG update, residual replacement, admission with x0
+constexpr int MASK_DIR = 0, MASK_UPD = 64, MASK_REPL = 128, MASK_ADM = 192, MASK_LEN = 256;
+
+// The device state of one solve, or of one batch of right-hand sides: V-cycle
+// vectors per level, Krylov vectors (row-major n x m), reduction scratch, the
+// status record and masks with their pinned host mirrors, the captured
+// V-cycles and the events the host loop waits on.  A handle owns one for its
+// blocking entry points; a server owns one per batch.  One host thread and
+// one stream use a Work at a time.
+struct Work {
     DevMem mem;
-    DevMem ws;  // workspaces, reallocated when m grows
-    Plan plan;
-    amgdg_params prm{};
-    int N = 0;                  // index of the coarsest level
-    std::vector<Level> lv;      // N + 1 levels
-    int64_t nN = 0;
-    double* Ainv = nullptr;
-    int64_t* perm_d = nullptr;  // internal unit -> caller element
-    std::vector<int32_t> in_rp, in_ci;  // caller's level-0 pattern (for export)
-    double* scratch = nullptr;  // reduction partials: DOT_PARTS * 64 + more
-    double* scal = nullptr;     // device scalars (256)
-    int32_t* flag = nullptr;
-    int ws_m = 0;
+    int m = 0, restart = 0;
     bool mixed = false;
-    // coarse mixed conversion buffers
-    double *cin = nullptr, *cout = nullptr;
-    // Krylov workspace
-    int kr_m = 0, kr_restart = 0;
+    int64_t bytes = 0;  // device bytes held
+    std::vector<VBuf<double>> v64;
+    std::vector<VBuf<float>> v32;
+    double *cin = nullptr, *cout = nullptr;  // FP64 coarse solve of the FP32 V-cycle
     double *kb = nullptr, *kx = nullptr, *kr = nullptr, *kr2 = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr,
            *kt = nullptr;
-    float *kr32 = nullptr, *kz32 = nullptr;
     double *kgin = nullptr, *kgout = nullptr;  // fixed input/output of the FP64 V-cycle graph
-    double *V = nullptr, *Z = nullptr;
-    int32_t* active_d = nullptr;
-    // fused Krylov steps: partial sums, arrival counter, status record (rr[0..64), flag)
-    double* kpart = nullptr;
-    unsigned* counter = nullptr;
-    double* stat = nullptr;
-    double* stat_h = nullptr;  // pinned host mirror of stat
+    float *kr32 = nullptr, *kz32 = nullptr;
+    double *V = nullptr, *Z = nullptr;  // FGMRES basis
+    double *scratch = nullptr, *scal = nullptr, *kpart = nullptr, *stat = nullptr;
+    int32_t* mask = nullptr;
+    double* stat_h = nullptr;   // pinned
+    int32_t* mask_h = nullptr;  // pinned
     // captured V-cycles, keyed by (precision, columns, input, output)
     struct GraphEntry {
         int prec, m;
@@ -159,8 +159,9 @@ struct Ctx {
     };
     std::vector<GraphEntry> graphs;
     hipStream_t cap = nullptr;
-    hipEvent_t ev = nullptr;  // status readback of the Krylov loop
-    bool use_graph = true;  // per call: off with AMGDG_EAGER
+    hipEvent_t ev = nullptr;      // status readback of the host loop
+    hipEvent_t ev_ret = nullptr;  // solutions of retired columns written
+    bool use_graph = true;        // per call: off with AMGDG_EAGER
     void drop_graphs() {
         for (auto& e : graphs) {
             (void)hipGraphExecDestroy(e.e);
@@ -168,12 +169,34 @@ struct Ctx {
         }
         graphs.clear();
     }
-    ~Ctx() {
-        (void)hipDeviceSynchronize();
+    ~Work() {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         if (ev) (void)hipEventDestroy(ev);
+        if (ev_ret) (void)hipEventDestroy(ev_ret);
         if (stat_h) (void)hipHostFree(stat_h);
+        if (mask_h) (void)hipHostFree(mask_h);
+    }
+};
+
+struct Ctx {
+    DevMem mem;
+    Plan plan;
+    amgdg_params prm{};
+    int N = 0;                  // index of the coarsest level
+    std::vector<Level> lv;      // N + 1 levels
+    int64_t nN = 0;
+    double* Ainv = nullptr;
+    int64_t* perm_d = nullptr;  // internal unit -> caller element
+    std::vector<int32_t> in_rp, in_ci;  // caller's level-0 pattern (for export)
+    double* scratch = nullptr;  // reduction partials of the setup
+    double* scal = nullptr;     // device scalars of the setup
+    int32_t* flag = nullptr;
+    bool mixed = false;
+    std::unique_ptr<Work> W0;   // state of the blocking entry points
+    ~Ctx() {
+        (void)hipDeviceSynchronize();
+        W0.reset();
     }
 };
 
@@ -366,18 +389,20 @@ static void mat_sweep(int mode, const Level& L, const T* x, const T* b, T* y, T 
 }
 
 
-static double dot1(Ctx& C, const double* a, const double* b, int64_t n, hipStream_t st) {
-    HIPCHK(launch_dot<double>(a, b, n, 1, C.scratch, C.scal, st));
+// blocking dot products through the partials buffer `part` and device scalars `out`
+static double dot1(double* part, double* out, const double* a, const double* b, int64_t n, hipStream_t st) {
+    HIPCHK(launch_dot<double>(a, b, n, 1, part, out, st));
     double h = 0;
-    HIPCHK(hipMemcpyAsync(&h, C.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&h, out, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return h;
 }
 
-static std::vector<double> dotm(Ctx& C, const double* a, const double* b, int64_t n, int m, hipStream_t st) {
-    HIPCHK(launch_dot<double>(a, b, n, m, C.scratch, C.scal, st));
+static std::vector<double> dotm(double* part, double* out, const double* a, const double* b, int64_t n, int m,
+                                hipStream_t st) {
+    HIPCHK(launch_dot<double>(a, b, n, m, part, out, st));
     std::vector<double> h(m);
-    HIPCHK(hipMemcpyAsync(h.data(), C.scal, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h.data(), out, sizeof(double) * m, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return h;
 }
@@ -397,7 +422,7 @@ static double power_rho(Ctx& C, Level& L, int k, hipStream_t st) {
         std::swap(x, y);
     }
     mat_sweep<double>(DINVA, L, x, nullptr, y, -1.0, 1, nullptr, st);
-    return std::sqrt(dot1(C, y, y, L.n, st));
+    return std::sqrt(dot1(C.scratch, C.scal, y, y, L.n, st));
 }
 
 // eq:bsmooth for all r columns at once: a column stops (mask 0, frozen) after
@@ -410,12 +435,12 @@ static void relax_candidates(Ctx& C, Level& L, double* B, hipStream_t st) {
     int32_t* mask = tmp.alloc<int32_t>(r);
     std::vector<int32_t> act(r, 1);
     L.sweeps.assign(r, 0);
-    std::vector<double> nx = dotm(C, X, X, L.n, r, st);
+    std::vector<double> nx = dotm(C.scratch, C.scal, X, X, L.n, r, st);
     HIPCHK(hipMemcpyAsync(mask, act.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice, st));
     const double thr = 1.0 + C.prm.gamma;
     for (int sweep = 0; sweep < C.prm.relax_max; ++sweep) {
         mat_sweep<double>(RELAX, L, X, nullptr, Y, L.omega, r, mask, st);
-        std::vector<double> ny = dotm(C, Y, Y, L.n, r, st);
+        std::vector<double> ny = dotm(C.scratch, C.scal, Y, Y, L.n, r, st);
         std::swap(X, Y);
         bool any = false;
         for (int c = 0; c < r; ++c) {
@@ -465,12 +490,6 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
     C.scal = C.mem.alloc<double>(2048);
     C.flag = C.mem.alloc<int32_t>(4);
     HIPCHK(hipMemsetAsync(C.flag, 0, 4 * sizeof(int32_t), st));
-    C.kpart = C.mem.alloc<double>(2 * 16 * (KRY_BLOCKS + 1) + 64);
-    C.counter = C.mem.alloc<unsigned>(1);
-    HIPCHK(hipMemsetAsync(C.counter, 0, sizeof(unsigned), st));
-    C.stat = C.mem.alloc<double>(65);
-    HIPCHK(hipMemsetAsync(C.stat, 0, 65 * sizeof(double), st));
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&C.stat_h), 65 * sizeof(double), hipHostMallocDefault));
     C.perm_d = upload(C.mem, C.plan.perm, st);
 
     // level-0 values in internal order
@@ -632,67 +651,134 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
 
 // ------------------------------------------------------------ workspaces
 
-static void ensure_ws(Ctx& C, int m, hipStream_t st) {
-    if (m <= C.ws_m) return;
-    HIPCHK(hipStreamSynchronize(st));
-    C.drop_graphs();
-    C.ws.release();
+// Lays out the device buffers of a Work of m columns (restart > 0: with a
+// restarted-FGMRES basis).  With W == nullptr only the byte count is formed.
+static int64_t work_layout(const Ctx& C, Work* W, int m, int restart) {
+    int64_t bytes = 0;
+    auto get = [&](auto tag, int64_t n) {
+        using T = decltype(tag);
+        bytes += (int64_t(sizeof(T)) * std::max<int64_t>(n, 1) + 255) / 256 * 256;
+        return W ? W->mem.alloc<T>(n) : static_cast<T*>(nullptr);
+    };
+    const double d = 0.0;
+    const float f = 0.0f;
+    const int32_t i = 0;
+    if (W) {
+        W->v64.assign(C.N + 1, VBuf<double>());
+        W->v32.assign(C.N + 1, VBuf<float>());
+    }
     for (int k = 0; k <= C.N; ++k) {
-        Level& L = C.lv[k];
-        const int64_t cnt = L.n * m;
-        L.v64.b = C.ws.alloc<double>(cnt);
-        L.v64.u = C.ws.alloc<double>(cnt);
-        L.v64.w = C.ws.alloc<double>(cnt);
-        L.v64.r = C.ws.alloc<double>(cnt);
+        const int64_t cnt = C.lv[k].n * m;
+        double* b = get(d, cnt);
+        double* u = get(d, cnt);
+        double* w = get(d, cnt);
+        double* r = get(d, cnt);
+        if (W) W->v64[k] = VBuf<double>{b, u, w, r, nullptr};
         if (C.mixed) {
-            L.v32.b = C.ws.alloc<float>(cnt);
-            L.v32.u = C.ws.alloc<float>(cnt);
-            L.v32.w = C.ws.alloc<float>(cnt);
-            L.v32.r = C.ws.alloc<float>(cnt);
+            float* bf = get(f, cnt);
+            float* uf = get(f, cnt);
+            float* wf = get(f, cnt);
+            float* rf = get(f, cnt);
+            if (W) W->v32[k] = VBuf<float>{bf, uf, wf, rf, nullptr};
         }
     }
-    C.cin = C.ws.alloc<double>(C.nN * m);
-    C.cout = C.ws.alloc<double>(C.nN * m);
-    C.ws_m = m;
-    C.kr_m = 0;  // Krylov buffers lived in ws
-    C.kr_restart = 0;
+    const int64_t n = C.lv[0].n * m;
+    double* cin = get(d, C.nN * m);
+    double* cout = get(d, C.nN * m);
+    double* kv[10];
+    for (double*& p : kv) p = get(d, n);
+    float* kr32 = C.mixed ? get(f, n) : nullptr;
+    float* kz32 = C.mixed ? get(f, n) : nullptr;
+    double* V = restart > 0 ? get(d, C.lv[0].n * (restart + 1)) : nullptr;
+    double* Z = restart > 0 ? get(d, C.lv[0].n * restart) : nullptr;
+    double* scratch = get(d, int64_t(DOT_PARTS) * 64 + 1024);
+    double* scal = get(d, 2048);
+    double* kpart = get(d, 2 * 16 * (KRY_BLOCKS + 1) + 64);
+    double* stat = get(d, ST_LEN);
+    int32_t* mask = get(i, MASK_LEN);
+    if (W) {
+        W->cin = cin;
+        W->cout = cout;
+        W->kb = kv[0], W->kx = kv[1], W->kr = kv[2], W->kr2 = kv[3], W->kz = kv[4];
+        W->kp = kv[5], W->kq = kv[6], W->kt = kv[7], W->kgin = kv[8], W->kgout = kv[9];
+        W->kr32 = kr32, W->kz32 = kz32;
+        W->V = V, W->Z = Z;
+        W->scratch = scratch, W->scal = scal, W->kpart = kpart, W->stat = stat, W->mask = mask;
+    }
+    return bytes;
+}
+
+static int64_t work_bytes(const Ctx& C, int m, int restart) { return work_layout(C, nullptr, m, restart); }
+
+// (Re)allocates W for m columns and zeroes it: no column ever holds a value
+// that was not written by this library.
+static void work_init(Ctx& C, Work& W, int m, int restart, hipStream_t st) {
+    if (W.m > 0) HIPCHK(hipStreamSynchronize(st));
+    W.drop_graphs();
+    W.mem.release();
+    W.m = 0;
+    W.bytes = work_layout(C, &W, m, restart);
+    W.mem.zero_all(st);
+    if (!W.stat_h) {
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.stat_h), ST_LEN * sizeof(double), hipHostMallocDefault));
+        std::memset(W.stat_h, 0, ST_LEN * sizeof(double));
+    }
+    if (!W.mask_h) {
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.mask_h), MASK_LEN * sizeof(int32_t), hipHostMallocDefault));
+        std::memset(W.mask_h, 0, MASK_LEN * sizeof(int32_t));
+    }
+    if (!W.ev) HIPCHK(hipEventCreateWithFlags(&W.ev, hipEventDisableTiming));
+    if (!W.ev_ret) HIPCHK(hipEventCreateWithFlags(&W.ev_ret, hipEventDisableTiming));
+    HIPCHK(hipStreamSynchronize(st));
+    W.m = m;
+    W.restart = restart;
+    W.mixed = C.mixed;
+}
+
+// The handle's own Work, grown to at least m columns (and an FGMRES basis of
+// `restart` vectors) when needed.
+static Work& default_work(Ctx& C, int m, int restart, hipStream_t st) {
+    if (!C.W0) C.W0 = std::make_unique<Work>();
+    Work& W = *C.W0;
+    if (W.m >= m && W.restart >= restart) return W;
+    work_init(C, W, std::max(m, W.m), std::max(restart, W.restart), st);
+    return W;
 }
 
 // ------------------------------------------------------------ V-cycle
 
 template <typename T>
-static VBuf<T>& vbuf(Level& L);
+static VBuf<T>& vbuf(Work& W, int k);
 template <>
-VBuf<double>& vbuf<double>(Level& L) { return L.v64; }
+VBuf<double>& vbuf<double>(Work& W, int k) { return W.v64[k]; }
 template <>
-VBuf<float>& vbuf<float>(Level& L) { return L.v32; }
-
+VBuf<float>& vbuf<float>(Work& W, int k) { return W.v32[k]; }
 
 template <typename T>
-static void coarse_solve(Ctx& C, const T* b, T* u, int m, hipStream_t st);
+static void coarse_solve(Ctx& C, Work& W, const T* b, T* u, int m, hipStream_t st);
 template <>
-void coarse_solve<double>(Ctx& C, const double* b, double* u, int m, hipStream_t st) {
+void coarse_solve<double>(Ctx& C, Work&, const double* b, double* u, int m, hipStream_t st) {
     HIPCHK(launch_gemv(C.Ainv, b, u, C.nN, m, st));
 }
 template <>
-void coarse_solve<float>(Ctx& C, const float* b, float* u, int m, hipStream_t st) {
-    HIPCHK((launch_convert<float, double>(b, C.cin, C.nN * m, st)));
-    HIPCHK(launch_gemv(C.Ainv, C.cin, C.cout, C.nN, m, st));
-    HIPCHK((launch_convert<double, float>(C.cout, u, C.nN * m, st)));
+void coarse_solve<float>(Ctx& C, Work& W, const float* b, float* u, int m, hipStream_t st) {
+    HIPCHK((launch_convert<float, double>(b, W.cin, C.nN * m, st)));
+    HIPCHK(launch_gemv(C.Ainv, W.cin, W.cout, C.nN, m, st));
+    HIPCHK((launch_convert<double, float>(W.cout, u, C.nN * m, st)));
 }
 
 // z0 = V(b0), internal order, m columns (Algorithm 2, one pass from u = 0).
 template <typename T>
-static void vcycle_impl(Ctx& C, const T* b0, T* z0, int m, hipStream_t st) {
+static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t st) {
     const int N = C.N;
     const int tpre = C.prm.t_pre, tpost = C.prm.t_post;
     if (N == 0) {
-        coarse_solve<T>(C, b0, z0, m, st);
+        coarse_solve<T>(C, W, b0, z0, m, st);
         return;
     }
     for (int k = 0; k < N; ++k) {
         Level& L = C.lv[k];
-        VBuf<T>& V = vbuf<T>(L);
+        VBuf<T>& V = vbuf<T>(W, k);
         const T* bk = (k == 0) ? b0 : V.b;
         T* cur = V.u;
         T* oth = V.w;
@@ -708,23 +794,22 @@ static void vcycle_impl(Ctx& C, const T* b0, T* z0, int m, hipStream_t st) {
         }
         V.cur = cur;
         mat_spmv<T>(B_MINUS, L.A, cur, bk, V.r, m, st);
-        Level& Ln = C.lv[k + 1];
-        mat_spmv<T>(AX, L.R, V.r, nullptr, vbuf<T>(Ln).b, m, st);
+        mat_spmv<T>(AX, L.R, V.r, nullptr, vbuf<T>(W, k + 1).b, m, st);
     }
     {
-        VBuf<T>& V = vbuf<T>(C.lv[N]);
-        coarse_solve<T>(C, V.b, V.u, m, st);
+        VBuf<T>& V = vbuf<T>(W, N);
+        coarse_solve<T>(C, W, V.b, V.u, m, st);
         V.cur = V.u;
     }
     for (int k = N - 1; k >= 0; --k) {
         Level& L = C.lv[k];
-        VBuf<T>& V = vbuf<T>(L);
+        VBuf<T>& V = vbuf<T>(W, k);
         const T* bk = (k == 0) ? b0 : V.b;
         const T om = T(L.omega);
         T* cur = V.cur;
         auto other = [&](T* c) { return c == V.u ? V.w : V.u; };
         T* dst = (k == 0 && tpost == 0) ? z0 : other(cur);
-        mat_spmv<T>(B_PLUS, L.T, vbuf<T>(C.lv[k + 1]).cur, cur, dst, m, st);
+        mat_spmv<T>(B_PLUS, L.T, vbuf<T>(W, k + 1).cur, cur, dst, m, st);
         cur = dst;
         for (int t = 0; t < tpost; ++t) {
             dst = (k == 0 && t == tpost - 1) ? z0 : other(cur);
@@ -737,49 +822,49 @@ static void vcycle_impl(Ctx& C, const T* b0, T* z0, int m, hipStream_t st) {
 
 // The V-cycle as a captured HIP graph: its ~40 launches (most of them small
 // coarse-level kernels) are submitted as one graph launch, so the host no
-// longer paces the coarse levels.  The graph is captured on a private stream
-// the first time a (precision, m, input, output) combination is seen and
-// replayed on the caller's stream; workspace reallocation drops the cache.  It
+// longer paces the coarse levels.  The graph is captured on the Work's private
+// stream the first time a (precision, m, input, output) combination is seen and
+// replayed on the caller's stream; reallocating the Work drops the cache.  It
 // holds only kernel nodes (no memset or copy nodes).
 template <typename T>
-static void vcycle_run(Ctx& C, const T* b0, T* z0, int m, hipStream_t st, bool allow_graph) {
+static void vcycle_run(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t st, bool allow_graph) {
     if (!allow_graph || C.prm.t_pre == 0 || C.N == 0) {
-        vcycle_impl<T>(C, b0, z0, m, st);
+        vcycle_impl<T>(C, W, b0, z0, m, st);
         return;
     }
     const int prec = int(sizeof(T));
-    for (auto& e : C.graphs)
+    for (auto& e : W.graphs)
         if (e.prec == prec && e.m == m && e.in == b0 && e.out == z0) {
             HIPCHK(hipGraphLaunch(e.e, st));
             return;
         }
-    if (C.graphs.size() >= 8) {
+    if (W.graphs.size() >= 8) {
         HIPCHK(hipStreamSynchronize(st));
-        C.drop_graphs();
+        W.drop_graphs();
     }
-    if (!C.cap) HIPCHK(hipStreamCreateWithFlags(&C.cap, hipStreamNonBlocking));
-    HIPCHK(hipStreamBeginCapture(C.cap, hipStreamCaptureModeThreadLocal));
+    if (!W.cap) HIPCHK(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal));
     try {
-        vcycle_impl<T>(C, b0, z0, m, C.cap);
+        vcycle_impl<T>(C, W, b0, z0, m, W.cap);
     } catch (...) {
         hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(C.cap, &g);
+        (void)hipStreamEndCapture(W.cap, &g);
         if (g) (void)hipGraphDestroy(g);
         throw;
     }
     hipGraph_t g = nullptr;
-    HIPCHK(hipStreamEndCapture(C.cap, &g));
+    HIPCHK(hipStreamEndCapture(W.cap, &g));
     hipGraphExec_t ex = nullptr;
     hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (err != hipSuccess) {
         (void)hipGraphDestroy(g);
         HIPCHK(err);
     }
-    C.graphs.push_back({prec, m, b0, z0, g, ex});
+    W.graphs.push_back({prec, m, b0, z0, g, ex});
     HIPCHK(hipGraphLaunch(ex, st));
 }
 
-// ------------------------------------------------------------ Krylov drivers
+// ------------------------------------------------------------ Krylov helpers
 
 struct KrylovState {
     std::vector<int32_t> its;
@@ -787,71 +872,34 @@ struct KrylovState {
     std::vector<double> bnorm;
 };
 
-static void ensure_krylov(Ctx& C, int m, int restart, int method, hipStream_t st) {
-    const int64_t n = C.lv[0].n;
-    if (C.kr_m >= m && (method != AMGDG_FGMRES || C.kr_restart >= restart) && C.kb) return;
-    HIPCHK(hipStreamSynchronize(st));
-    C.drop_graphs();
-    for (void* p : {(void*)C.kb, (void*)C.kx, (void*)C.kr, (void*)C.kr2, (void*)C.kz, (void*)C.kp, (void*)C.kq,
-                    (void*)C.kt, (void*)C.kr32, (void*)C.kz32, (void*)C.V, (void*)C.Z, (void*)C.active_d,
-                    (void*)C.kgin, (void*)C.kgout})
-        if (p) C.ws.free(p);
-    C.kb = C.ws.alloc<double>(n * m);
-    C.kx = C.ws.alloc<double>(n * m);
-    C.kr = C.ws.alloc<double>(n * m);
-    C.kr2 = C.ws.alloc<double>(n * m);
-    C.kz = C.ws.alloc<double>(n * m);
-    C.kp = C.ws.alloc<double>(n * m);
-    C.kq = C.ws.alloc<double>(n * m);
-    C.kt = C.ws.alloc<double>(n * m);
-    C.kr32 = C.mixed ? C.ws.alloc<float>(n * m) : nullptr;
-    C.kz32 = C.mixed ? C.ws.alloc<float>(n * m) : nullptr;
-    C.kgin = C.ws.alloc<double>(n * m);
-    C.kgout = C.ws.alloc<double>(n * m);
-    C.active_d = C.ws.alloc<int32_t>(128);
-    if (method == AMGDG_FGMRES) {
-        C.V = C.ws.alloc<double>(n * (restart + 1));
-        C.Z = C.ws.alloc<double>(n * restart);
-        C.kr_restart = restart;
-    } else {
-        C.V = C.Z = nullptr;
-        C.kr_restart = 0;
-    }
-    C.kr_m = m;
-}
-
 // z = V(r) in FP64 for arbitrary r, z: through the graph's fixed buffers.
-static void precond_fp64(Ctx& C, const double* r, double* z, int m, hipStream_t st) {
-    if (!C.use_graph) {
-        vcycle_impl<double>(C, r, z, m, st);
+static void precond_fp64(Ctx& C, Work& W, const double* r, double* z, int m, hipStream_t st) {
+    if (!W.use_graph) {
+        vcycle_impl<double>(C, W, r, z, m, st);
         return;
     }
     const size_t bytes = sizeof(double) * size_t(C.lv[0].n) * m;
-    if (r != C.kgin) HIPCHK(hipMemcpyAsync(C.kgin, r, bytes, hipMemcpyDeviceToDevice, st));
-    vcycle_run<double>(C, C.kgin, C.kgout, m, st, true);
-    if (z != C.kgout) HIPCHK(hipMemcpyAsync(z, C.kgout, bytes, hipMemcpyDeviceToDevice, st));
+    if (r != W.kgin) HIPCHK(hipMemcpyAsync(W.kgin, r, bytes, hipMemcpyDeviceToDevice, st));
+    vcycle_run<double>(C, W, W.kgin, W.kgout, m, st, true);
+    if (z != W.kgout) HIPCHK(hipMemcpyAsync(z, W.kgout, bytes, hipMemcpyDeviceToDevice, st));
 }
 
-static void precond(Ctx& C, const double* r, double* z, int m, int precision, hipStream_t st) {
+static void precond(Ctx& C, Work& W, const double* r, double* z, int m, int precision, hipStream_t st) {
     const int64_t n = C.lv[0].n;
     if (precision == AMGDG_MIXED) {
-        HIPCHK((launch_convert<double, float>(r, C.kr32, n * m, st)));
-        vcycle_run<float>(C, C.kr32, C.kz32, m, st, C.use_graph);
-        HIPCHK((launch_convert<float, double>(C.kz32, z, n * m, st)));
+        HIPCHK((launch_convert<double, float>(r, W.kr32, n * m, st)));
+        vcycle_run<float>(C, W, W.kr32, W.kz32, m, st, W.use_graph);
+        HIPCHK((launch_convert<float, double>(W.kz32, z, n * m, st)));
     } else {
-        precond_fp64(C, r, z, m, st);
+        precond_fp64(C, W, r, z, m, st);
     }
 }
 
-// true residual t = b - A x and its per-column norms
-static std::vector<double> true_res(Ctx& C, const double* b, const double* x, int m, hipStream_t st) {
+// true residual W.kt = b - A x and its per-column norms^2
+static std::vector<double> true_res(Ctx& C, Work& W, const double* b, const double* x, int m, hipStream_t st) {
     Level& L = C.lv[0];
-    if (C.N == 0) {
-        // level 0 is the coarsest level: it has no sliced copy; use the dense inverse path's operator
-        throw Error(AMGDG_EUNSUPPORTED, "Krylov solve needs at least two levels");
-    }
-    mat_spmv<double>(B_MINUS, L.A, x, b, C.kt, m, st);
-    return dotm(C, C.kt, C.kt, L.n, m, st);
+    mat_spmv<double>(B_MINUS, L.A, x, b, W.kt, m, st);
+    return dotm(W.scratch, W.scal, W.kt, W.kt, L.n, m, st);
 }
 
 static void check_nan(const std::vector<double>& v, const char* what) {
@@ -859,144 +907,363 @@ static void check_nan(const std::vector<double>& v, const char* what) {
         if (!std::isfinite(d)) throw Error(AMGDG_ENAN, std::string("NaN or Inf in ") + what);
 }
 
-// Preconditioned CG (flexible = false) or flexible CG with residual replacement
-// (flexible = true): in the flexible variant, when the recursive residual of a
-// column claims convergence or has dropped by kReplaceDrop since its last
-// replacement and the true FP64 residual does not meet the tolerance, the true
-// residual replaces the recursive one.  Per iteration: q = A p, p.q, the fused
-// update of x and r (with ||r||^2 and, for the mixed V-cycle, the FP32 copy of
-// r), the preconditioner, the fused r.z (and z.r_old), the new direction, and
-// one readback of the status record (||r||^2 per column and the error flag).
+// ------------------------------------------------------------ CG batch engine
+
 static constexpr double kReplaceDrop = 1e-6;
+using Clock = std::chrono::steady_clock;
 
-static int solve_cg(Ctx& C, int m, int precision, double tol, int maxit, bool flexible, KrylovState& S,
-                    hipStream_t st) {
-    Level& L = C.lv[0];
-    const int64_t n = L.n;
-    const bool mixed = precision == AMGDG_MIXED;
-    double *b = C.kb, *x = C.kx, *r = C.kr, *rn = C.kr2, *z = C.kz, *p = C.kp, *q = C.kq;
-    double* sc = C.scal;
-    double *d_pq = sc, *d_rz = sc + 64, *d_rz2 = sc + 128, *d_zro = sc + 192;
-    int32_t* flag = reinterpret_cast<int32_t*>(C.stat + 64);
-    float* r32 = mixed ? C.kr32 : nullptr;
-    std::vector<int32_t> act(m, 1);
-    std::vector<double> anchor(m, 1.0);
-    std::vector<double> rr0 = true_res(C, b, x, m, st);
-    HIPCHK(hipMemcpyAsync(r, C.kt, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
-    S.its.assign(m, 0);
-    S.rel.assign(m, 0.0);
-    bool any = false;
-    for (int c = 0; c < m; ++c) {
-        S.rel[c] = std::sqrt(rr0[c]) / S.bnorm[c];
-        anchor[c] = S.rel[c];
-        if (S.rel[c] <= tol) act[c] = 0;
-        any = any || act[c];
+// A right-hand side waiting for, or holding, a column of a batch.
+struct Rhs {
+    int64_t tag = 0;
+    const double* b = nullptr;   // caller's b (column start); rows `ld` apart
+    double* x = nullptr;         // caller's x, same addressing
+    const double* x0 = nullptr;  // initial guess, same addressing, or NULL (x0 = 0)
+    int64_t ld = 1;
+    double tol = 1e-8;
+    int32_t maxit = 1000;
+    bool internal = false;       // rows already in internal order
+    Clock::time_point t_submit;
+};
+
+// How a right-hand side left its batch.
+struct Outcome {
+    int64_t tag = 0;
+    int rc = AMGDG_OK;
+    int32_t its = 0;
+    double rel = 0.0;
+    double latency = 0.0;  // seconds from submission to the host seeing x written
+    Clock::time_point t_submit;
+};
+
+// Preconditioned CG (flexible = false) or flexible CG with residual replacement
+// (flexible = true, Polak-Ribiere beta) on up to m right-hand sides at once,
+// the columns of one Work.  Columns are independent: each kernel computes
+// column c from column c only, and every reduction adds in an order fixed by n
+// alone, so a right-hand side gets bit-identical iterates whatever shares the
+// batch and whichever column it occupies.  Columns join between iterations
+// (admit) and leave when they converge, fail or reach their iteration limit
+// (retire).  A column spends the iteration in which it joins with
+// alpha = beta = 0: that iteration forms z = M r0 and r0.z, and its direction
+// update sets p = z, which is the method's start.
+//
+// Host loop, per iteration: the fused update of x and r (with ||r||^2 and, for
+// the FP32 V-cycle, the FP32 copy of r); the status record is copied to pinned
+// memory behind an event; the preconditioner of the new residual and the new
+// r.z are queued at once (run-ahead, so the GPU does not wait for the host);
+// when the event has passed, the host reads the status, retires and admits
+// columns and queues the new direction, q = A p and p.q.  A column whose
+// recursive residual meets its tolerance, has dropped by kReplaceDrop since its
+// last replacement (flexible) or reaches its iteration limit is first checked
+// against its true residual b - A x (one more readback); in the flexible
+// method a true residual above the tolerance replaces the recursive one.
+struct CgBatch {
+    enum { EMPTY = 0, STARTING = 1, RUNNING = 2 };
+    enum { IDLE = 0, WAIT_STATUS = 1, WAIT_TRUE = 2 };
+    struct Col {
+        int state = EMPTY;
+        bool upd = false;    // active in the update of the iteration in flight
+        bool check = false;  // waiting for its true residual
+        Rhs rq;
+        int32_t its = 0;
+        double bnorm = 1.0, rel = 0.0, anchor = 1.0;
+    };
+    Ctx* C = nullptr;
+    Work* W = nullptr;
+    hipStream_t st = nullptr;
+    int m = 0;
+    bool flexible = false, mixed = false, fail_fast = false;
+    int phase = IDLE;
+    std::vector<Col> col;
+    std::vector<int> pending;               // admitted, not yet queued
+    std::vector<std::pair<int, Outcome>> leaving;  // retired in this host step
+    std::vector<Outcome> retiring;          // x scatter queued before ev_ret
+    std::vector<Outcome> done;
+    double *r = nullptr, *rn = nullptr;
+    double *d_pq = nullptr, *d_rz = nullptr, *d_rz2 = nullptr, *d_zro = nullptr;
+    int32_t* flags_d = nullptr;
+    int32_t last_upd[64], last_dir[64];
+
+    void init(Ctx& c, Work& w, hipStream_t s, int width, bool flex, bool mix, bool ff) {
+        C = &c;
+        W = &w;
+        st = s;
+        m = width;
+        flexible = flex;
+        mixed = mix;
+        fail_fast = ff;
+        phase = IDLE;
+        col.assign(m, Col());
+        pending.clear();
+        leaving.clear();
+        retiring.clear();
+        done.clear();
+        r = W->kr;
+        rn = W->kr2;
+        d_pq = W->scal;
+        d_rz = W->scal + 64;
+        d_rz2 = W->scal + 128;
+        d_zro = W->scal + 192;
+        flags_d = reinterpret_cast<int32_t*>(W->stat + ST_FLAG);
+        std::fill(last_upd, last_upd + 64, -1);
+        std::fill(last_dir, last_dir + 64, -1);
     }
-    if (!any) return AMGDG_OK;
-    auto upload_act = [&]() {
-        HIPCHK(hipMemcpyAsync(C.active_d, act.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
-    };
-    upload_act();
-    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
-    auto apply_M = [&](double* rz_out, const double* r_old, double* zro) {
-        if (mixed) vcycle_run<float>(C, C.kr32, C.kz32, m, st, C.use_graph);
-        else if (!flexible) vcycle_run<double>(C, r, z, m, st, C.use_graph);  // r, z are fixed buffers here
-        else precond_fp64(C, r, z, m, st);
-        HIPCHK(launch_zdots(mixed ? C.kz32 : nullptr, z, r, r_old, n, m, C.kpart, C.counter, rz_out, zro, st));
-    };
-    if (mixed) HIPCHK((launch_convert<double, float>(r, r32, n * m, st)));
-    apply_M(d_rz, nullptr, nullptr);
-    HIPCHK(hipMemcpyAsync(p, z, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
-    mat_spmv<double>(AX, L.A, p, nullptr, q, m, st);
-    HIPCHK(launch_dot_tail(p, q, n, m, C.kpart, C.counter, d_pq, st));
-    if (!C.ev) HIPCHK(hipEventCreateWithFlags(&C.ev, hipEventDisableTiming));
-    for (int it = 1; it <= maxit; ++it) {
-        HIPCHK(launch_cg_update(x, r, flexible ? rn : r, p, q, r32, n, m, d_rz, d_pq, C.active_d, C.kpart, C.counter,
-                                C.stat, flag, st));
-        if (flexible) std::swap(r, rn);  // r: new residual, rn: previous
-        HIPCHK(hipMemcpyAsync(C.stat_h, C.stat, sizeof(double) * 65, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(C.ev, st));
-        // run ahead: the preconditioner of the new residual is queued before the
-        // host looks at the status, so the GPU does not wait for the host; it
-        // writes only z and the new dot products, so it is simply redone if the
-        // residual gets replaced below
-        apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
-        HIPCHK(hipEventSynchronize(C.ev));
-        const int32_t f = *reinterpret_cast<const int32_t*>(C.stat_h + 64);
-        if (f) {
-            HIPCHK(hipStreamSynchronize(st));
-            HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
-            throw Error(f & 1 ? AMGDG_EBREAKDOWN : AMGDG_ENAN,
-                        f & 1 ? "CG breakdown: p^T A p <= 0 (matrix or preconditioner not SPD)" : "NaN in CG");
-        }
-        bool need_true = false, changed = false;
-        std::vector<int32_t> check(m, 0), repl(m, 0);
+
+    int free_slot() const {
         for (int c = 0; c < m; ++c)
-            if (act[c]) {
-                S.its[c] = it;
-                S.rel[c] = std::sqrt(C.stat_h[c]) / S.bnorm[c];
-                if (S.rel[c] <= tol || (flexible && S.rel[c] <= anchor[c] * kReplaceDrop)) check[c] = 1;
-                need_true = need_true || check[c];
-            }
-        if (need_true) {
-            std::vector<double> tr = true_res(C, b, x, m, st);  // leaves b - A x in C.kt
-            bool any_repl = false;
-            for (int c = 0; c < m; ++c)
-                if (check[c]) {
-                    const double t = std::sqrt(tr[c]) / S.bnorm[c];
-                    if (t <= tol) {
-                        act[c] = 0;
-                        S.rel[c] = t;
-                        changed = true;
-                    } else if (flexible) {
-                        // residual replacement: the true residual takes the place of the recursive one
-                        repl[c] = 1;
-                        anchor[c] = t;
-                        any_repl = true;
-                    }
-                }
-            if (any_repl) {
-                HIPCHK(hipMemcpyAsync(C.active_d + 64, repl.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
-                HIPCHK(launch_copy_cols(C.kt, r, n, m, C.active_d + 64, st));
-                if (mixed) HIPCHK((launch_convert<double, float>(r, r32, n * m, st)));
-                apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
-                HIPCHK(hipStreamSynchronize(st));
-            }
-        }
-        any = false;
-        for (int c = 0; c < m; ++c) any = any || act[c];
-        if (!any) {
-            HIPCHK(hipStreamSynchronize(st));
-            return AMGDG_OK;
-        }
-        if (changed) upload_act();
-        HIPCHK(launch_cg_dir(p, z, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz, C.active_d, st));
-        std::swap(d_rz, d_rz2);
-        mat_spmv<double>(AX, L.A, p, nullptr, q, m, st);
-        HIPCHK(launch_dot_tail(p, q, n, m, C.kpart, C.counter, d_pq, st));
+            if (col[c].state == EMPTY && std::find(pending.begin(), pending.end(), c) == pending.end()) return c;
+        return -1;
     }
-    HIPCHK(hipStreamSynchronize(st));
-    return AMGDG_ENOCONV;
-}
+    int busy() const {
+        int k = int(pending.size());
+        for (const Col& c : col) k += c.state != EMPTY;
+        return k;
+    }
+    bool ready() const {
+        if (phase == IDLE) return false;
+        const hipError_t e = hipEventQuery(W->ev);
+        if (e == hipSuccess) return true;
+        if (e != hipErrorNotReady) HIPCHK(e);
+        return false;
+    }
+    void admit(int slot, const Rhs& rq) {
+        col[slot].rq = rq;
+        pending.push_back(slot);
+    }
 
-static int solve_stationary(Ctx& C, int m, int precision, double tol, int maxit, KrylovState& S, hipStream_t st) {
+    void apply_M(double* rz_out, const double* r_old, double* zro) {
+        const int64_t n = C->lv[0].n;
+        if (mixed) vcycle_run<float>(*C, *W, W->kr32, W->kz32, m, st, W->use_graph);
+        else if (!flexible) vcycle_run<double>(*C, *W, r, W->kz, m, st, W->use_graph);  // r, z fixed buffers
+        else precond_fp64(*C, *W, r, W->kz, m, st);
+        HIPCHK(launch_zdots(mixed ? W->kz32 : nullptr, W->kz, r, r_old, n, m, W->kpart, nullptr, rz_out, zro, st));
+    }
+
+    // uploads mask region `off` from the pinned mirror if it differs from `last`
+    void upload_mask(int off, int32_t* last) {
+        bool same = true;
+        for (int c = 0; c < m; ++c) same = same && last[c] == W->mask_h[off + c];
+        if (same) return;
+        HIPCHK(hipMemcpyAsync(W->mask + off, W->mask_h + off, sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+        for (int c = 0; c < m; ++c) last[c] = W->mask_h[off + c];
+    }
+
+    // queues admissions and the next iteration (update, status readback, run-ahead M)
+    void issue() {
+        const Level& L = C->lv[0];
+        const int64_t n = L.n;
+        if (!pending.empty()) {
+            bool any_x0 = false;
+            for (int c : pending) {
+                const Rhs& q = col[c].rq;
+                HIPCHK(launch_admit(q.b, q.ld, q.x0, q.ld, q.internal ? nullptr : C->perm_d, L.n_units, L.nb, W->kb,
+                                    W->kx, r, W->kp, W->kq, m, c, flags_d, st));
+                any_x0 = any_x0 || q.x0;
+            }
+            HIPCHK(launch_dot_tail(W->kb, W->kb, n, m, W->kpart, nullptr, W->stat + ST_BN, st));
+            if (any_x0) {
+                // r = b - A x0 for the admitted columns with an initial guess
+                for (int c = 0; c < m; ++c) W->mask_h[MASK_ADM + c] = 0;
+                for (int c : pending) W->mask_h[MASK_ADM + c] = col[c].rq.x0 ? 1 : 0;
+                HIPCHK(hipMemcpyAsync(W->mask + MASK_ADM, W->mask_h + MASK_ADM, sizeof(int32_t) * m,
+                                      hipMemcpyHostToDevice, st));
+                mat_spmv<double>(B_MINUS, L.A, W->kx, W->kb, W->kt, m, st);
+                HIPCHK(launch_copy_cols(W->kt, r, n, m, W->mask + MASK_ADM, st));
+                HIPCHK(launch_dot_tail(r, r, n, m, W->kpart, nullptr, W->stat + ST_R0, st));
+            }
+            for (int c : pending) {
+                col[c].state = STARTING;
+                col[c].its = 0;
+            }
+            pending.clear();
+        }
+        for (int c = 0; c < m; ++c) {
+            col[c].upd = col[c].state == RUNNING;
+            W->mask_h[MASK_UPD + c] = col[c].upd ? 1 : 0;
+        }
+        upload_mask(MASK_UPD, last_upd);
+        HIPCHK(launch_cg_update(W->kx, r, flexible ? rn : r, W->kp, W->kq, mixed ? W->kr32 : nullptr, n, m, d_rz, d_pq,
+                                W->mask + MASK_UPD, W->kpart, nullptr, W->stat + ST_RR, flags_d, st));
+        if (flexible) std::swap(r, rn);  // r: new residual, rn: previous
+        HIPCHK(hipMemcpyAsync(W->stat_h, W->stat, sizeof(double) * ST_TR, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(W->ev, st));
+        apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
+        phase = WAIT_STATUS;
+    }
+
+    void retire(int c, int rc, double rel) {
+        Col& k = col[c];
+        if (fail_fast && rc != AMGDG_OK && rc != AMGDG_ENOCONV) {
+            (void)hipStreamSynchronize(st);
+            phase = IDLE;
+            throw Error(rc, rc == AMGDG_EBREAKDOWN ? "CG breakdown: p^T A p <= 0 (matrix or preconditioner not SPD)"
+                                                   : "NaN or Inf in CG (right-hand side or iterate)");
+        }
+        Outcome o;
+        o.tag = k.rq.tag;
+        o.rc = rc;
+        o.its = k.its;
+        o.rel = rel;
+        o.t_submit = k.rq.t_submit;
+        leaving.push_back({c, o});
+        k.state = EMPTY;
+        k.upd = false;
+        k.check = false;
+    }
+
+    // handles the phase whose event has passed and queues what follows
+    void process() {
+        if (phase == WAIT_STATUS) {
+            const int32_t* fl = reinterpret_cast<const int32_t*>(W->stat_h + ST_FLAG);
+            bool need_true = false;
+            for (int c = 0; c < m; ++c) {
+                Col& k = col[c];
+                if (k.state == STARTING) {
+                    const double bn2 = W->stat_h[ST_BN + c];
+                    const double r02 = k.rq.x0 ? W->stat_h[ST_R0 + c] : bn2;
+                    if (!std::isfinite(bn2) || !std::isfinite(r02)) {
+                        retire(c, AMGDG_ENAN, std::numeric_limits<double>::quiet_NaN());
+                        continue;
+                    }
+                    k.bnorm = std::sqrt(bn2) > 0 ? std::sqrt(bn2) : 1.0;
+                    k.rel = std::sqrt(r02) / k.bnorm;
+                    k.anchor = k.rel;
+                    if (k.rel <= k.rq.tol) retire(c, AMGDG_OK, k.rel);
+                    else if (k.rq.maxit <= 0) retire(c, AMGDG_ENOCONV, k.rel);
+                    else k.state = RUNNING;
+                } else if (k.state == RUNNING && k.upd) {
+                    if (fl[c]) {
+                        retire(c, (fl[c] & 1) ? AMGDG_EBREAKDOWN : AMGDG_ENAN, k.rel);
+                        continue;
+                    }
+                    ++k.its;
+                    k.rel = std::sqrt(W->stat_h[ST_RR + c]) / k.bnorm;
+                    k.check = k.rel <= k.rq.tol || (flexible && k.rel <= k.anchor * kReplaceDrop) ||
+                              k.its >= k.rq.maxit;
+                    need_true = need_true || k.check;
+                }
+            }
+            if (need_true) {
+                const int64_t n = C->lv[0].n;
+                mat_spmv<double>(B_MINUS, C->lv[0].A, W->kx, W->kb, W->kt, m, st);
+                HIPCHK(launch_dot_tail(W->kt, W->kt, n, m, W->kpart, nullptr, W->stat + ST_TR, st));
+                HIPCHK(hipMemcpyAsync(W->stat_h + ST_TR, W->stat + ST_TR, sizeof(double) * m, hipMemcpyDeviceToHost,
+                                      st));
+                HIPCHK(hipEventRecord(W->ev, st));
+                phase = WAIT_TRUE;
+                return;
+            }
+        } else if (phase == WAIT_TRUE) {
+            bool any_repl = false;
+            for (int c = 0; c < m; ++c) W->mask_h[MASK_REPL + c] = 0;
+            for (int c = 0; c < m; ++c) {
+                Col& k = col[c];
+                if (!(k.state == RUNNING && k.check)) continue;
+                k.check = false;
+                const double t = std::sqrt(W->stat_h[ST_TR + c]) / k.bnorm;
+                if (!std::isfinite(t)) retire(c, AMGDG_ENAN, t);
+                else if (t <= k.rq.tol) retire(c, AMGDG_OK, t);
+                else if (k.its >= k.rq.maxit) retire(c, AMGDG_ENOCONV, t);
+                else if (flexible) {
+                    W->mask_h[MASK_REPL + c] = 1;  // the true residual takes the place of the recursive one
+                    k.anchor = t;
+                    any_repl = true;
+                }
+            }
+            if (any_repl) {
+                const int64_t n = C->lv[0].n;
+                HIPCHK(hipMemcpyAsync(W->mask + MASK_REPL, W->mask_h + MASK_REPL, sizeof(int32_t) * m,
+                                      hipMemcpyHostToDevice, st));
+                HIPCHK(launch_copy_cols(W->kt, r, n, m, W->mask + MASK_REPL, st));
+                if (mixed) HIPCHK((launch_convert<double, float>(r, W->kr32, n * m, st)));
+                apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
+            }
+        } else {
+            return;
+        }
+        advance();
+    }
+
+    // x of the columns retired in this host step goes out; the direction
+    // update and the next iteration are queued
+    void advance() {
+        if (!leaving.empty()) {
+            const Level& L = C->lv[0];
+            for (auto& pr : leaving) {
+                const Rhs& q = col[pr.first].rq;
+                HIPCHK(launch_scatter_col(W->kx + pr.first, m, q.x, q.ld, q.internal ? nullptr : C->perm_d, L.n_units,
+                                          L.nb, st));
+                retiring.push_back(pr.second);
+            }
+            leaving.clear();
+            HIPCHK(hipEventRecord(W->ev_ret, st));
+        }
+        bool running = false;
+        for (const Col& k : col) running = running || k.state == RUNNING;
+        if (!running && pending.empty()) {
+            phase = IDLE;
+            return;
+        }
+        if (running) {
+            const int64_t n = C->lv[0].n;
+            for (int c = 0; c < m; ++c) W->mask_h[MASK_DIR + c] = (col[c].state == RUNNING && col[c].upd) ? 1 : 0;
+            upload_mask(MASK_DIR, last_dir);
+            HIPCHK(launch_cg_dir(W->kp, W->kz, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz, W->mask + MASK_DIR, st));
+            std::swap(d_rz, d_rz2);
+            mat_spmv<double>(AX, C->lv[0].A, W->kp, nullptr, W->kq, m, st);
+            HIPCHK(launch_dot_tail(W->kp, W->kq, n, m, W->kpart, nullptr, d_pq, st));
+        }
+        issue();
+    }
+
+    // moves outcomes whose x is written to `done`; blocking waits for them
+    void collect(bool blocking) {
+        if (retiring.empty()) return;
+        if (blocking) {
+            HIPCHK(hipEventSynchronize(W->ev_ret));
+        } else {
+            const hipError_t e = hipEventQuery(W->ev_ret);
+            if (e == hipErrorNotReady) return;
+            HIPCHK(e);
+        }
+        const Clock::time_point now = Clock::now();
+        for (Outcome& o : retiring) {
+            o.latency = std::chrono::duration<double>(now - o.t_submit).count();
+            done.push_back(o);
+        }
+        retiring.clear();
+    }
+
+    // blocking driver: runs until every admitted column has left
+    void run() {
+        if (phase == IDLE && !pending.empty()) issue();
+        while (phase != IDLE) {
+            HIPCHK(hipEventSynchronize(W->ev));
+            process();
+        }
+        collect(true);
+    }
+};
+
+// ------------------------------------------------------------ solvers
+
+static int solve_stationary(Ctx& C, Work& W, int m, int precision, double tol, int maxit, KrylovState& S,
+                            hipStream_t st) {
     Level& L = C.lv[0];
     const int64_t n = L.n;
     std::vector<int32_t> act(m, 1);
     S.its.assign(m, 0);
     S.rel.assign(m, 0.0);
-    std::vector<double> rr = true_res(C, C.kb, C.kx, m, st);
+    std::vector<double> rr = true_res(C, W, W.kb, W.kx, m, st);
     for (int it = 1; it <= maxit; ++it) {
-        HIPCHK(hipMemcpyAsync(C.kr, C.kt, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
-        precond(C, C.kr, C.kz, m, precision, st);
+        HIPCHK(hipMemcpyAsync(W.kr, W.kt, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
+        precond(C, W, W.kr, W.kz, m, precision, st);
         // x += z for active columns: alpha = active
         std::vector<double> a(m);
         for (int c = 0; c < m; ++c) a[c] = act[c] ? 1.0 : 0.0;
-        HIPCHK(hipMemcpyAsync(C.scal + 1024, a.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-        HIPCHK(launch_axpby_dev(C.kz, C.kx, n, m, C.scal + 1024, 1.0, 1.0, st));
+        HIPCHK(hipMemcpyAsync(W.scal + 1024, a.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_axpby_dev(W.kz, W.kx, n, m, W.scal + 1024, 1.0, 1.0, st));
         HIPCHK(hipStreamSynchronize(st));
-        rr = true_res(C, C.kb, C.kx, m, st);
+        rr = true_res(C, W, W.kb, W.kx, m, st);
         check_nan(rr, "residual");
         bool any = false;
         for (int c = 0; c < m; ++c)
@@ -1011,19 +1278,19 @@ static int solve_stationary(Ctx& C, int m, int precision, double tol, int maxit,
     return AMGDG_ENOCONV;
 }
 
-static int solve_fgmres(Ctx& C, int precision, double tol, int restart, int maxit, KrylovState& S,
+static int solve_fgmres(Ctx& C, Work& W, int precision, double tol, int restart, int maxit, KrylovState& S,
                         hipStream_t st) {
     Level& L = C.lv[0];
     const int64_t n = L.n;
-    double* x = C.kx;
-    double* b = C.kb;
+    double* x = W.kx;
+    double* b = W.kb;
     S.its.assign(1, 0);
     S.rel.assign(1, 0.0);
     int total = 0;
     std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
     auto Hat = [&](int i, int j) -> double& { return H[size_t(i) * restart + j]; };
     while (true) {
-        std::vector<double> rr = true_res(C, b, x, 1, st);
+        std::vector<double> rr = true_res(C, W, b, x, 1, st);
         const double beta = std::sqrt(rr[0]);
         check_nan(rr, "residual");
         S.rel[0] = beta / S.bnorm[0];
@@ -1031,30 +1298,30 @@ static int solve_fgmres(Ctx& C, int precision, double tol, int restart, int maxi
         if (S.rel[0] <= tol) return AMGDG_OK;
         if (total >= maxit) return AMGDG_ENOCONV;
         // V_0 = r / beta
-        HIPCHK(launch_axpby_dev(C.kt, C.V, n, 1, nullptr, 1.0 / beta, 0.0, st));
+        HIPCHK(launch_axpby_dev(W.kt, W.V, n, 1, nullptr, 1.0 / beta, 0.0, st));
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int jend = 0;
         for (int j = 0; j < restart; ++j) {
-            double* vj = C.V + int64_t(j) * n;
-            double* zj = C.Z + int64_t(j) * n;
-            double* w = C.V + int64_t(j + 1) * n;
-            precond(C, vj, zj, 1, precision, st);
+            double* vj = W.V + int64_t(j) * n;
+            double* zj = W.Z + int64_t(j) * n;
+            double* w = W.V + int64_t(j + 1) * n;
+            precond(C, W, vj, zj, 1, precision, st);
             mat_spmv<double>(AX, L.A, zj, nullptr, w, 1, st);
             // CGS2
             std::vector<double> h(j + 2, 0.0);
             for (int pass = 0; pass < 2; ++pass) {
-                HIPCHK(launch_multidot(C.V, n, j + 1, w, n, C.scratch, C.scal, st));
+                HIPCHK(launch_multidot(W.V, n, j + 1, w, n, W.scratch, W.scal, st));
                 std::vector<double> hp(j + 1);
-                HIPCHK(hipMemcpyAsync(hp.data(), C.scal, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(hp.data(), W.scal, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
                 HIPCHK(hipStreamSynchronize(st));
-                HIPCHK(hipMemcpyAsync(C.scal + 1024, hp.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
-                HIPCHK(launch_multi_axpy(C.V, n, j + 1, C.scal + 1024, w, n, -1.0, st));
+                HIPCHK(hipMemcpyAsync(W.scal + 1024, hp.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+                HIPCHK(launch_multi_axpy(W.V, n, j + 1, W.scal + 1024, w, n, -1.0, st));
                 HIPCHK(hipStreamSynchronize(st));
                 for (int i = 0; i <= j; ++i) h[i] += hp[i];
             }
-            const double hn = std::sqrt(dot1(C, w, w, n, st));
+            const double hn = std::sqrt(dot1(W.scratch, W.scal, w, w, n, st));
             check_nan({hn}, "Arnoldi");
             if (hn > 0) HIPCHK(launch_axpby_dev(w, w, n, 1, nullptr, 1.0 / hn, 0.0, st));
             for (int i = 0; i <= j; ++i) Hat(i, j) = h[i];
@@ -1081,70 +1348,220 @@ static int solve_fgmres(Ctx& C, int precision, double tol, int restart, int maxi
             for (int l = i + 1; l < jend; ++l) s -= Hat(i, l) * y[l];
             y[i] = s / Hat(i, i);
         }
-        HIPCHK(hipMemcpyAsync(C.scal + 1024, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
-        HIPCHK(launch_multi_axpy(C.Z, n, jend, C.scal + 1024, x, n, 1.0, st));
+        HIPCHK(hipMemcpyAsync(W.scal + 1024, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_multi_axpy(W.Z, n, jend, W.scal + 1024, x, n, 1.0, st));
         HIPCHK(hipStreamSynchronize(st));
     }
 }
 
+static void check_solve_args(const Ctx& C, int m, int method, int precision) {
+    if (C.N == 0) throw Error(AMGDG_EUNSUPPORTED, "Krylov solve needs at least two levels");
+    if (m < 1 || m > 64) throw Error(AMGDG_EUNSUPPORTED, "m must be 1..64");
+    if (precision != AMGDG_FP64 && precision != AMGDG_MIXED) throw Error(AMGDG_EINVAL, "bad precision");
+    if (precision == AMGDG_MIXED && !C.mixed) throw Error(AMGDG_EINVAL, "mixed precision needs params.mixed = 1");
+    if (method < AMGDG_STATIONARY || method > AMGDG_FGMRES) throw Error(AMGDG_EINVAL, "bad method");
+}
+
 static int solve_impl(Ctx& C, int m, const double* b_dev, double* x_dev, int method, int precision, double rtol,
                       int max_it, int restart, int flags, amgdg_solve_stats* stats, hipStream_t st) {
-    if (m < 1 || m > 64) throw Error(AMGDG_EUNSUPPORTED, "m must be 1..64");
+    check_solve_args(C, m, method, precision);
     if (!b_dev || !x_dev) throw Error(AMGDG_EINVAL, "b or x is NULL");
-    if (precision == AMGDG_MIXED && !C.mixed) throw Error(AMGDG_EINVAL, "mixed precision needs params.mixed = 1");
-    if (precision != AMGDG_FP64 && precision != AMGDG_MIXED) throw Error(AMGDG_EINVAL, "bad precision");
     if (method == AMGDG_FGMRES && (m != 1 || restart < 1 || restart > 256))
         throw Error(AMGDG_EUNSUPPORTED, "FGMRES: m = 1 and 1 <= restart <= 256");
-    if (method < AMGDG_STATIONARY || method > AMGDG_FGMRES) throw Error(AMGDG_EINVAL, "bad method");
-    const auto t0 = std::chrono::steady_clock::now();
-    C.use_graph = !(flags & AMGDG_EAGER);
-    ensure_ws(C, m, st);
-    ensure_krylov(C, m, restart, method, st);
+    const auto t0 = Clock::now();
+    Work& W = default_work(C, m, method == AMGDG_FGMRES ? restart : 0, st);
+    W.use_graph = !(flags & AMGDG_EAGER);
     Level& L = C.lv[0];
     const int64_t n = L.n;
     const bool internal = flags & AMGDG_INTERNAL_ORDER;
-    if (internal) HIPCHK(hipMemcpyAsync(C.kb, b_dev, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
-    else HIPCHK((launch_permute<double, double>(b_dev, C.kb, C.perm_d, L.n_units, L.nb, m, 1, st)));
-    if (flags & AMGDG_X0) {
-        if (internal) HIPCHK(hipMemcpyAsync(C.kx, x_dev, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
-        else HIPCHK((launch_permute<double, double>(x_dev, C.kx, C.perm_d, L.n_units, L.nb, m, 1, st)));
+    std::vector<int32_t> its(m, 0);
+    std::vector<double> rel(m, 0.0);
+    int rc = AMGDG_OK;
+    if (method == AMGDG_PCG || method == AMGDG_FCG) {
+        CgBatch B;
+        B.init(C, W, st, m, method == AMGDG_FCG, precision == AMGDG_MIXED, true);
+        for (int c = 0; c < m; ++c) {
+            Rhs q;
+            q.tag = c;
+            q.b = b_dev + c;
+            q.x = x_dev + c;
+            q.x0 = (flags & AMGDG_X0) ? x_dev + c : nullptr;
+            q.ld = m;
+            q.tol = rtol;
+            q.maxit = max_it;
+            q.internal = internal;
+            q.t_submit = t0;
+            B.admit(c, q);
+        }
+        B.run();
+        for (const Outcome& o : B.done) {
+            its[o.tag] = o.its;
+            rel[o.tag] = o.rel;
+            if (o.rc != AMGDG_OK) rc = AMGDG_ENOCONV;
+        }
     } else {
-        HIPCHK(hipMemsetAsync(C.kx, 0, sizeof(double) * n * m, st));
+        if (internal) HIPCHK(hipMemcpyAsync(W.kb, b_dev, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
+        else HIPCHK((launch_permute<double, double>(b_dev, W.kb, C.perm_d, L.n_units, L.nb, m, 1, st)));
+        if (flags & AMGDG_X0) {
+            if (internal) HIPCHK(hipMemcpyAsync(W.kx, x_dev, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
+            else HIPCHK((launch_permute<double, double>(x_dev, W.kx, C.perm_d, L.n_units, L.nb, m, 1, st)));
+        } else {
+            HIPCHK(hipMemsetAsync(W.kx, 0, sizeof(double) * n * m, st));
+        }
+        KrylovState S;
+        S.bnorm = dotm(W.scratch, W.scal, W.kb, W.kb, n, m, st);
+        check_nan(S.bnorm, "b");
+        for (double& v : S.bnorm) v = std::sqrt(v) > 0 ? std::sqrt(v) : 1.0;
+        if (method == AMGDG_STATIONARY) rc = solve_stationary(C, W, m, precision, rtol, max_it, S, st);
+        else rc = solve_fgmres(C, W, precision, rtol, restart, max_it, S, st);
+        // final true residuals
+        std::vector<double> tr = true_res(C, W, W.kb, W.kx, m, st);
+        if (internal) HIPCHK(hipMemcpyAsync(x_dev, W.kx, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
+        else HIPCHK((launch_permute<double, double>(W.kx, x_dev, C.perm_d, L.n_units, L.nb, m, 0, st)));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int c = 0; c < m; ++c) {
+            its[c] = S.its[c];
+            rel[c] = std::sqrt(tr[c]) / S.bnorm[c];
+        }
     }
-    KrylovState S;
-    S.bnorm = dotm(C, C.kb, C.kb, n, m, st);
-    check_nan(S.bnorm, "b");
-    for (double& v : S.bnorm) v = std::sqrt(v) > 0 ? std::sqrt(v) : 1.0;
-    int rc;
-    switch (method) {
-        case AMGDG_STATIONARY: rc = solve_stationary(C, m, precision, rtol, max_it, S, st); break;
-        case AMGDG_PCG: rc = solve_cg(C, m, precision, rtol, max_it, false, S, st); break;
-        case AMGDG_FCG: rc = solve_cg(C, m, precision, rtol, max_it, true, S, st); break;
-        default: rc = solve_fgmres(C, precision, rtol, restart, max_it, S, st); break;
-    }
-    // final true residuals
-    std::vector<double> tr = true_res(C, C.kb, C.kx, m, st);
-    if (internal) HIPCHK(hipMemcpyAsync(x_dev, C.kx, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
-    else HIPCHK((launch_permute<double, double>(C.kx, x_dev, C.perm_d, L.n_units, L.nb, m, 0, st)));
-    HIPCHK(hipStreamSynchronize(st));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         int all = 1, mx = 0;
         for (int c = 0; c < m; ++c) {
-            const double rel = std::sqrt(tr[c]) / S.bnorm[c];
-            if (c < 64) {
-                stats->iterations[c] = S.its[c];
-                stats->rel_residual[c] = rel;
-            }
-            mx = std::max(mx, S.its[c]);
-            if (!(rel <= rtol)) all = 0;
+            stats->iterations[c] = its[c];
+            stats->rel_residual[c] = rel[c];
+            mx = std::max(mx, its[c]);
+            if (!(rel[c] <= rtol)) all = 0;
         }
         stats->max_iterations = mx;
         stats->all_converged = all;
-        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
     }
     return rc;
 }
+
+// ------------------------------------------------------------ serving
+
+// Continuous batching of CG solves.  Requests on the same (handle, method,
+// precision) share a batch of `width` columns; a request takes a free column
+// between iterations and leaves it when done, so the level operators are read
+// once per iteration for every request in the batch.  Batches run on streams
+// of their own and are created while the device bytes of all batch workspaces
+// stay within the budget; an idle batch of another key is released to make
+// room.  Requests wait in submission order; one that cannot be placed does
+// not hold back requests that can.
+struct Request {
+    Ctx* C = nullptr;
+    int method = AMGDG_PCG, precision = AMGDG_FP64;
+    Rhs rq;
+};
+
+struct ServerBatch {
+    Ctx* C = nullptr;
+    int method = 0, precision = 0;
+    hipStream_t st = nullptr;
+    Work W;
+    CgBatch eng;
+    ~ServerBatch() {
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    }
+};
+
+struct Server {
+    int width = 4;
+    int64_t budget = 0, used = 0;
+    std::deque<Request> queue;
+    std::vector<std::unique_ptr<ServerBatch>> batches;
+    std::vector<Outcome> done;
+
+    bool idle(const ServerBatch& b) const {
+        return b.eng.phase == CgBatch::IDLE && b.eng.busy() == 0 && b.eng.retiring.empty();
+    }
+
+    ServerBatch* create(Ctx& C, int method, int precision) {
+        const int64_t need = work_bytes(C, width, 0);
+        if (used + need > budget) {
+            // release idle batches of other keys, oldest first
+            for (size_t i = 0; i < batches.size() && used + need > budget;) {
+                ServerBatch& b = *batches[i];
+                if (idle(b) && !(b.C == &C && b.method == method && b.precision == precision)) {
+                    used -= b.W.bytes;
+                    batches.erase(batches.begin() + i);
+                } else {
+                    ++i;
+                }
+            }
+        }
+        if (used + need > budget) return nullptr;
+        auto b = std::make_unique<ServerBatch>();
+        b->C = &C;
+        b->method = method;
+        b->precision = precision;
+        HIPCHK(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
+        work_init(C, b->W, width, 0, b->st);
+        b->W.use_graph = true;
+        b->eng.init(C, b->W, b->st, width, method == AMGDG_FCG, precision == AMGDG_MIXED, false);
+        used += b->W.bytes;
+        batches.push_back(std::move(b));
+        return batches.back().get();
+    }
+
+    void admit_queued() {
+        std::vector<ServerBatch*> kick;
+        for (auto it = queue.begin(); it != queue.end();) {
+            ServerBatch* tgt = nullptr;
+            for (auto& b : batches)
+                if (b->C == it->C && b->method == it->method && b->precision == it->precision &&
+                    b->eng.free_slot() >= 0) {
+                    tgt = b.get();
+                    break;
+                }
+            if (!tgt) tgt = create(*it->C, it->method, it->precision);
+            if (!tgt) {
+                ++it;
+                continue;
+            }
+            tgt->eng.admit(tgt->eng.free_slot(), it->rq);
+            if (tgt->eng.phase == CgBatch::IDLE && std::find(kick.begin(), kick.end(), tgt) == kick.end())
+                kick.push_back(tgt);
+            it = queue.erase(it);
+        }
+        for (ServerBatch* b : kick) b->eng.issue();
+    }
+
+    int64_t pending() const {
+        int64_t k = int64_t(queue.size());
+        for (auto& b : batches) k += b->eng.busy() + int64_t(b->eng.retiring.size());
+        return k;
+    }
+
+    void step(bool wait) {
+        admit_queued();
+        while (true) {
+            bool progressed = false;
+            for (auto& b : batches) {
+                if (b->eng.ready()) {
+                    b->eng.process();
+                    progressed = true;
+                }
+                const size_t before = b->eng.done.size();
+                b->eng.collect(false);
+                if (b->eng.done.size() != before) progressed = true;
+                for (Outcome& o : b->eng.done) done.push_back(o);
+                b->eng.done.clear();
+            }
+            if (progressed) admit_queued();
+            if (!wait || progressed || pending() == 0) return;
+            bool in_flight = false;
+            for (auto& b : batches) in_flight = in_flight || b->eng.phase != CgBatch::IDLE || !b->eng.retiring.empty();
+            if (!in_flight) return;  // queued requests that no budget can place
+            std::this_thread::yield();
+        }
+    }
+};
 
 // ------------------------------------------------------------ single steps
 
@@ -1154,11 +1571,11 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
     if (op != AMGDG_OP_COARSE && k == C.N) throw Error(AMGDG_EINVAL, "operation needs a non-coarsest level");
     if (op == AMGDG_OP_COARSE && k != C.N) throw Error(AMGDG_EINVAL, "AMGDG_OP_COARSE works on the coarsest level");
     if (m < 1 || m > 64) throw Error(AMGDG_EUNSUPPORTED, "m must be 1..64");
-    ensure_ws(C, m, st);
+    if (sizeof(T) == 4 && !C.mixed) throw Error(AMGDG_EINVAL, "FP32 operators not built (params.mixed = 0)");
+    Work& W = default_work(C, m, 0, st);
     Level& L = C.lv[k];
     const bool perm = (k == 0) && !(flags & AMGDG_INTERNAL_ORDER);
-    VBuf<T>& V = vbuf<T>(L);
-    if (!V.b) throw Error(AMGDG_EINVAL, "FP32 operators not built (params.mixed = 0)");
+    VBuf<T>& V = vbuf<T>(W, k);
     const int64_t nun = L.n_units;
     auto in = [&](const T* p, T* tmp) -> const T* {
         if (!p) return nullptr;
@@ -1186,7 +1603,7 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
         case AMGDG_OP_SWEEP0: mat_sweep<T>(SWEEP0, L, nullptr, bi, out, T(L.omega), m, nullptr, st); break;
         case AMGDG_OP_RESTRICT: mat_spmv<T>(AX, L.R, xi, nullptr, out, m, st); break;
         case AMGDG_OP_PROLONG: mat_spmv<T>(B_PLUS, L.T, xi, bi, out, m, st); break;
-        case AMGDG_OP_COARSE: coarse_solve<T>(C, xi, out, m, st); break;
+        case AMGDG_OP_COARSE: coarse_solve<T>(C, W, xi, out, m, st); break;
         default: throw Error(AMGDG_EINVAL, "bad op");
     }
     if (perm && fine_out) HIPCHK((launch_permute<T, T>(out, y, C.perm_d, nun, L.nb, m, 0, st)));
@@ -1376,6 +1793,9 @@ struct amgdg_ctx {
 struct amgdg_plan_s {
     Plan p;
 };
+struct amgdg_server_s {
+    Server s;
+};
 
 #define ABI_BEGIN try {
 #define ABI_END                                                        \
@@ -1548,8 +1968,8 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
     Ctx& C = h->c;
     if (m < 1 || m > 64) throw Error(AMGDG_EUNSUPPORTED, "m must be 1..64");
     hipStream_t st = hipStream_t(stream);
-    ensure_ws(C, m, st);
-    ensure_krylov(C, m, 0, AMGDG_PCG, st);
+    if (precision == AMGDG_MIXED && !C.mixed) throw Error(AMGDG_EINVAL, "mixed precision needs params.mixed = 1");
+    Work& W = default_work(C, m, 0, st);
     Level& L = C.lv[0];
     const bool internal = flags & AMGDG_INTERNAL_ORDER;
     const bool graph = !(flags & AMGDG_EAGER);
@@ -1557,22 +1977,21 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
         const double* r = static_cast<const double*>(r_dev);
         double* z = static_cast<double*>(z_dev);
         if (internal) {
-            vcycle_run<double>(C, r, z, m, st, graph);
+            vcycle_run<double>(C, W, r, z, m, st, graph);
         } else {
-            HIPCHK((launch_permute<double, double>(r, C.kr, C.perm_d, L.n_units, L.nb, m, 1, st)));
-            vcycle_run<double>(C, C.kr, C.kz, m, st, graph);
-            HIPCHK((launch_permute<double, double>(C.kz, z, C.perm_d, L.n_units, L.nb, m, 0, st)));
+            HIPCHK((launch_permute<double, double>(r, W.kr, C.perm_d, L.n_units, L.nb, m, 1, st)));
+            vcycle_run<double>(C, W, W.kr, W.kz, m, st, graph);
+            HIPCHK((launch_permute<double, double>(W.kz, z, C.perm_d, L.n_units, L.nb, m, 0, st)));
         }
     } else if (precision == AMGDG_MIXED) {
-        if (!C.mixed) throw Error(AMGDG_EINVAL, "mixed precision needs params.mixed = 1");
         const float* r = static_cast<const float*>(r_dev);
         float* z = static_cast<float*>(z_dev);
         if (internal) {
-            vcycle_run<float>(C, r, z, m, st, graph);
+            vcycle_run<float>(C, W, r, z, m, st, graph);
         } else {
-            HIPCHK((launch_permute<float, float>(r, C.kr32, C.perm_d, L.n_units, L.nb, m, 1, st)));
-            vcycle_run<float>(C, C.kr32, C.kz32, m, st, graph);
-            HIPCHK((launch_permute<float, float>(C.kz32, z, C.perm_d, L.n_units, L.nb, m, 0, st)));
+            HIPCHK((launch_permute<float, float>(r, W.kr32, C.perm_d, L.n_units, L.nb, m, 1, st)));
+            vcycle_run<float>(C, W, W.kr32, W.kz32, m, st, graph);
+            HIPCHK((launch_permute<float, float>(W.kz32, z, C.perm_d, L.n_units, L.nb, m, 0, st)));
         }
     } else {
         throw Error(AMGDG_EINVAL, "bad precision");
@@ -1596,6 +2015,94 @@ int amgdg_apply(amgdg_handle h, int32_t k, int32_t op, int32_t m, int32_t precis
         return apply_impl<float>(h->c, k, op, m, static_cast<const float*>(x), static_cast<const float*>(b),
                                  static_cast<float*>(y), flags, hipStream_t(stream));
     throw Error(AMGDG_EINVAL, "bad precision");
+    ABI_END
+}
+
+int amgdg_batch_bytes(amgdg_handle h, int32_t width, int64_t* bytes) {
+    ABI_BEGIN
+    if (!h || !bytes) throw Error(AMGDG_EINVAL, "NULL argument");
+    if (width < 1 || width > 64) throw Error(AMGDG_EUNSUPPORTED, "width must be 1..64");
+    *bytes = work_bytes(h->c, width, 0);
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_server_create(amgdg_server* out, int32_t width, int64_t hbm_budget_bytes) {
+    ABI_BEGIN
+    if (!out) throw Error(AMGDG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (width < 1 || width > 64) throw Error(AMGDG_EUNSUPPORTED, "width must be 1..64");
+    if (hbm_budget_bytes <= 0) throw Error(AMGDG_EINVAL, "budget must be positive");
+    auto s = std::make_unique<amgdg_server_s>();
+    s->s.width = width;
+    s->s.budget = hbm_budget_bytes;
+    *out = s.release();
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_server_submit(amgdg_server s, amgdg_handle h, const double* b_dev, double* x_dev, int32_t method,
+                        int32_t precision, double rtol, int32_t max_it, int32_t flags, int64_t tag) {
+    ABI_BEGIN
+    if (!s || !h || !b_dev || !x_dev) throw Error(AMGDG_EINVAL, "NULL argument");
+    Ctx& C = h->c;
+    check_solve_args(C, 1, method, precision);
+    if (method != AMGDG_PCG && method != AMGDG_FCG) throw Error(AMGDG_EUNSUPPORTED, "the server runs PCG and FCG");
+    if (max_it < 0 || !(rtol >= 0)) throw Error(AMGDG_EINVAL, "bad rtol or max_it");
+    if (flags & ~(AMGDG_X0 | AMGDG_INTERNAL_ORDER)) throw Error(AMGDG_EINVAL, "bad flags");
+    const int64_t need = work_bytes(C, s->s.width, 0);
+    if (need > s->s.budget)
+        throw Error(AMGDG_ENOMEM, "a batch on this handle needs " + std::to_string(need) + " bytes, over the budget");
+    Request r;
+    r.C = &C;
+    r.method = method;
+    r.precision = precision;
+    r.rq.tag = tag;
+    r.rq.b = b_dev;
+    r.rq.x = x_dev;
+    r.rq.x0 = (flags & AMGDG_X0) ? x_dev : nullptr;
+    r.rq.ld = 1;
+    r.rq.tol = rtol;
+    r.rq.maxit = max_it;
+    r.rq.internal = flags & AMGDG_INTERNAL_ORDER;
+    r.rq.t_submit = Clock::now();
+    s->s.queue.push_back(r);
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_server_step(amgdg_server s, int32_t wait, int64_t* n_pending) {
+    ABI_BEGIN
+    if (!s) throw Error(AMGDG_EINVAL, "NULL server");
+    s->s.step(wait != 0);
+    if (n_pending) *n_pending = s->s.pending();
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_server_poll(amgdg_server s, int32_t capacity, int64_t* tags, int32_t* status, int32_t* iterations,
+                      double* rel_residual, double* latency_s, int32_t* n_done) {
+    ABI_BEGIN
+    if (!s || !n_done || (capacity > 0 && !tags)) throw Error(AMGDG_EINVAL, "NULL argument");
+    std::vector<Outcome>& d = s->s.done;
+    const int32_t k = int32_t(std::min<int64_t>(std::max(capacity, 0), int64_t(d.size())));
+    for (int32_t i = 0; i < k; ++i) {
+        tags[i] = d[i].tag;
+        if (status) status[i] = d[i].rc;
+        if (iterations) iterations[i] = d[i].its;
+        if (rel_residual) rel_residual[i] = d[i].rel;
+        if (latency_s) latency_s[i] = d[i].latency;
+    }
+    d.erase(d.begin(), d.begin() + k);
+    *n_done = k;
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_server_destroy(amgdg_server s) {
+    ABI_BEGIN
+    delete s;
+    return AMGDG_OK;
     ABI_END
 }
 

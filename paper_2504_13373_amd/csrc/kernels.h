@@ -129,9 +129,9 @@ constexpr int KRY_BLOCKS = 2048;
 // out[c] = sum_i a[i,c] b[i,c]   (part: KRY_BLOCKS * m doubles, counter: 1 uint)
 hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, unsigned* counter,
                            double* out, hipStream_t st);
-// CG update of m columns: alpha = active ? rz / pq : 0 (flag |= 1 if an active pq <= 0,
-// 2 if alpha is not finite); x += alpha p; r_out = r_in - alpha q; r32 = float(r_out)
-// if r32 != NULL; rr[c] = ||r_out[:,c]||^2.
+// CG update of m columns: alpha = active ? rz / pq : 0 (flag[c] |= 1 if an active pq <= 0,
+// 2 if alpha or rr[c] is not finite); x += alpha p; r_out = r_in - alpha q; r32 = float(r_out)
+// if r32 != NULL; rr[c] = ||r_out[:,c]||^2.  flag holds one int32 per column.
 hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const double* p, const double* q,
                             float* r32, int64_t n, int m, const double* rz, const double* pq,
                             const int32_t* active, double* part, unsigned* counter, double* rr, int32_t* flag,
@@ -143,6 +143,16 @@ hipError_t launch_zdots(const float* z32, double* z, const double* r, const doub
 hipError_t launch_cg_dir(double* p, const double* z, int64_t n, int m, const double* rz_new, const double* zro,
                          const double* rz_old, const int32_t* active, hipStream_t st);
 
+// Column c of a batch (row-major n x ld arrays kb, kx, r, p, q) takes a new
+// right-hand side: kb = r = b (caller column, stride ldb, rows reordered by perm
+// if perm != NULL), kx = x0 (same addressing, or 0 if x0 == NULL), p = q = 0,
+// flag[c] = 0.
+hipError_t launch_admit(const double* b, int64_t ldb, const double* x0, int64_t ldx, const int64_t* perm,
+                        int64_t n_units, int nb, double* kb, double* kx, double* r, double* p, double* q, int ld,
+                        int c, int32_t* flag, hipStream_t st);
+// out[row(i) * ldo] = in[i * ldi], row(i) = perm[i / nb] * nb + i % nb (i if perm == NULL)
+hipError_t launch_scatter_col(const double* in, int64_t ldi, double* out, int64_t ldo, const int64_t* perm,
+                              int64_t n_units, int nb, hipStream_t st);
 // dst[i,c] = src[i,c] for the columns c with mask[c] != 0
 hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, const int32_t* mask, hipStream_t st);
 // p = z + beta p

@@ -1251,7 +1251,7 @@ __device__ __forceinline__ void block_partials(double (&s)[M], double* __restric
 }
 
 // out1[c] = sum_i part[c*np + i] for c < split, out2[c - split] for c >= split;
-// flag |= 2 if a sum is not finite (flag may be NULL).
+// flag[c] |= 2 if sum c is not finite (flag may be NULL).
 __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int np, int mt,
                                                  double* __restrict__ out1, int split, double* __restrict__ out2,
                                                  int32_t* __restrict__ flag) {
@@ -1268,7 +1268,7 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part
         if (threadIdx.x == 0) {
             if (c < split) out1[c] = sh[0];
             else out2[c - split] = sh[0];
-            if (flag && !isfinite(sh[0])) atomicOr(flag, 2);
+            if (flag && !isfinite(sh[0])) atomicOr(flag + c, 2);
         }
         __syncthreads();
     }
@@ -1305,8 +1305,8 @@ __global__ __launch_bounds__(WG) void k_cg_update(double* __restrict__ x, const 
             const double d = pq[c];
             al[c] = rz[c] / d;
             if (blockIdx.x == 0 && threadIdx.x == 0) {
-                if (!(d > 0.0)) atomicOr(flag, 1);
-                if (!isfinite(al[c])) atomicOr(flag, 2);
+                if (!(d > 0.0)) atomicOr(flag + c, 1);
+                if (!isfinite(al[c])) atomicOr(flag + c, 2);
             }
             if (!isfinite(al[c])) al[c] = 0.0;
         }
@@ -1408,9 +1408,9 @@ hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const 
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
         KRY_DISPATCH(w, k_cg_update, dim3(g), dim3(WG), 0, st, x + c0, r_in + c0, r_out + c0, p + c0, q + c0,
-                     r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag);
+                     r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag + c0);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), w, rr + c0, w,
-                           static_cast<double*>(nullptr), flag);
+                           static_cast<double*>(nullptr), flag + c0);
         return hipGetLastError();
     });
 }
@@ -1538,6 +1538,62 @@ hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n
         }
         c0 += w;
     }
+    return hipGetLastError();
+}
+
+// Admission of one right-hand side into column c of a batch (row-major n x ld
+// arrays): b is gathered from the caller's array (stride ldb, rows reordered by
+// perm when perm != NULL) into kb and r; x takes x0 the same way, or 0; p and q
+// are zeroed; the column's error flag is cleared.
+__global__ void k_admit(const double* __restrict__ b, int64_t ldb, const double* __restrict__ x0, int64_t ldx,
+                        const int64_t* __restrict__ perm, int64_t n_units, int nb, double* __restrict__ kb,
+                        double* __restrict__ kx, double* __restrict__ r, double* __restrict__ p,
+                        double* __restrict__ q, int ld, int c, int32_t* __restrict__ flag) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i == 0) flag[c] = 0;
+    if (i >= n_units * nb) return;
+    int64_t src = i;
+    if (perm) {
+        const int64_t u = i / nb;
+        src = perm[u] * nb + (i - u * nb);
+    }
+    const int64_t e = i * ld + c;
+    const double bv = b[src * ldb];
+    kb[e] = bv;
+    r[e] = bv;
+    kx[e] = x0 ? x0[src * ldx] : 0.0;
+    p[e] = 0.0;
+    q[e] = 0.0;
+}
+
+hipError_t launch_admit(const double* b, int64_t ldb, const double* x0, int64_t ldx, const int64_t* perm,
+                        int64_t n_units, int nb, double* kb, double* kx, double* r, double* p, double* q, int ld,
+                        int c, int32_t* flag, hipStream_t st) {
+    const int64_t n = std::max<int64_t>(n_units * nb, 1);
+    hipLaunchKernelGGL(k_admit, dim3(grid_for(n)), dim3(WG), 0, st, b, ldb, x0, ldx, perm, n_units, nb, kb, kx, r, p,
+                       q, ld, c, flag);
+    return hipGetLastError();
+}
+
+// out[row(i) * ldo] = in[i * ldi] with row(i) the caller row of internal row i
+// (identity when perm == NULL): one column out of a batch.
+__global__ void k_scatter_col(const double* __restrict__ in, int64_t ldi, double* __restrict__ out, int64_t ldo,
+                              const int64_t* __restrict__ perm, int64_t n_units, int nb) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_units * nb) return;
+    int64_t dst = i;
+    if (perm) {
+        const int64_t u = i / nb;
+        dst = perm[u] * nb + (i - u * nb);
+    }
+    out[dst * ldo] = in[i * ldi];
+}
+
+hipError_t launch_scatter_col(const double* in, int64_t ldi, double* out, int64_t ldo, const int64_t* perm,
+                              int64_t n_units, int nb, hipStream_t st) {
+    const int64_t n = n_units * nb;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_col, dim3(grid_for(n)), dim3(WG), 0, st, in, ldi, out, ldo, perm, n_units, nb);
     return hipGetLastError();
 }
 
