@@ -76,6 +76,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a plain elementwise copy of MB megabytes (reads and writes MB each), "
                          "the reference for the HBM traffic counters")
+    ap.add_argument("--serve", type=int, default=16, metavar="N",
+                    help="requests of the serving run (0: skip it)")
+    ap.add_argument("--serve-width", type=int, default=4, help="right-hand sides per server batch")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="Poisson arrival rate in requests/s (0: all requests arrive at once)")
     ap.add_argument("--max-it", type=int, default=50000,
                     help="iteration cap per solve (profiling runs cap it; the reported value needs convergence)")
     args = ap.parse_args()
@@ -187,6 +192,10 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 x elementwise copy of {nbytes} bytes")
 
+    serving = None
+    if args.serve > 0:
+        serving = serve_bench(am, h, w.A.n, dev, args.serve, args.serve_width, args.serve_rate, maxit)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, res["fp64"]["its"])
@@ -240,9 +249,55 @@ def main():
         },
         "vcycle": {name: {"ms": v["ms"], "GBps": v["gbps"], "frac": v["gbps"] / HBM_PEAK_GBS} for name, v in vc.items()},
         "setup_s": setup_s,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def serve_bench(am, h, n, dev, n_req, width, rate, maxit):
+    """Continuous batching: n_req single-RHS requests (mixed FCG to 1e-8,
+    right-hand sides standard normal, seeds 1000 + i) through one server of
+    batches of `width` columns; all at once (rate 0) or with Poisson arrivals.
+    Latency runs from submission to the step that saw x written."""
+    import numpy as np
+    import torch
+    B = [torch.as_tensor(np.random.default_rng(1000 + i).standard_normal(n)).to(dev).contiguous()
+         for i in range(n_req)]
+    X = [torch.zeros_like(b) for b in B]
+    gaps = np.random.default_rng(7).exponential(1.0 / rate, n_req) if rate > 0 else np.zeros(n_req)
+    arrive = np.cumsum(gaps) - gaps[0]
+    torch.cuda.synchronize()
+    srv = am.Server(width=width, hbm_budget_bytes=64 << 30)
+    log(f"serving: {n_req} requests, batch width {width}, "
+        f"{'all at once' if rate <= 0 else f'Poisson arrivals at {rate} /s'}")
+    out = {}
+    nxt = 0
+    t0 = time.perf_counter()
+    while len(out) < n_req:
+        now = time.perf_counter() - t0
+        while nxt < n_req and arrive[nxt] <= now:
+            srv.submit(h, B[nxt], X[nxt], am.AMGDG_FCG, am.AMGDG_MIXED, 1e-8, maxit, tag=nxt)
+            nxt += 1
+        srv.step(wait=nxt == n_req)
+        for tag, status, its, rel, lat in srv.poll():
+            out[tag] = (status, its, rel, lat)
+            log(f"serving: request {tag} done, status {status}, {its} iterations, {lat:.2f} s")
+    makespan = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([out[i][3] for i in range(n_req)])
+    its = np.array([out[i][1] for i in range(n_req)])
+    return {
+        "requests": n_req,
+        "batch_width": width,
+        "arrivals": "all at t=0" if rate <= 0 else f"Poisson, {rate} requests/s",
+        "solves_per_s": n_req / makespan,
+        "makespan_s": makespan,
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_iterations": float(its.mean()),
+        "all_converged": bool(all(out[i][0] == am.AMGDG_OK and out[i][2] <= 1e-8 for i in range(n_req))),
+    }
 
 
 def cpu_baseline(w, gpu_iterations, n_iter=5):

@@ -230,18 +230,21 @@ int amgdg_apply(amgdg_handle h, int32_t k, int32_t op, int32_t m, int32_t precis
                 const void* b, void* y, int32_t flags, void* stream);
 
 /* Device bytes of the solve state of one batch of `width` right-hand sides on
- * this hierarchy (what a server counts against its budget per batch). */
-int amgdg_batch_bytes(amgdg_handle h, int32_t width, int64_t* bytes);
+ * this hierarchy, with an FGMRES basis of `restart` vectors if restart > 0
+ * (what a server counts against its budget per batch: CG batches have the
+ * server's width and restart 0, FGMRES batches width 1). */
+int amgdg_batch_bytes(amgdg_handle h, int32_t width, int32_t restart, int64_t* bytes);
 
-/* Serving: continuous batching of the PCG / FCG solves of amgdg_solve
- * (section 5), submitted one right-hand side at a time.
- * Requests on the same (handle, method, precision) share a batch of `width`
+/* Serving: continuous batching of the PCG / FCG / FGMRES solves of
+ * amgdg_solve (section 5), submitted one right-hand side at a time.
+ * CG requests on the same (handle, method, precision) share a batch of `width`
  * columns: a request takes a free column between two iterations and leaves it
  * when it converges, fails or reaches max_it, so every level operator is read
  * once per iteration for all requests of the batch (the multi-RHS kernels).
+ * An FGMRES request takes a batch of one column with its Krylov basis.
  * Each request's iterates, iteration count and x are bit-identical to
  * amgdg_solve of that right-hand side alone (m = 1).  Each batch runs on a
- * stream of its own.  A new batch is created only while the device bytes of
+ * stream of its own, so the work of different batches overlaps.  A new batch is created only while the device bytes of
  * all batches (amgdg_batch_bytes) stay within hbm_budget_bytes; an idle batch
  * of another key is released to make room; otherwise the request waits.
  * Requests are admitted in submission order; one that cannot be placed does
@@ -256,12 +259,12 @@ int amgdg_server_create(amgdg_server* out, int32_t width, int64_t hbm_budget_byt
  * guess.  b_dev must hold its values on the device when submitted (the
  * server's streams are not ordered after the caller's) and both arrays must
  * stay valid and untouched until the request is reported by amgdg_server_poll,
- * when x_dev holds the result.  method: AMGDG_PCG or AMGDG_FCG.  tag: the
- * caller's id, reported back.  AMGDG_ENOMEM if one batch on this handle
- * exceeds the budget. */
+ * when x_dev holds the result.  tag: the caller's id, reported back.  method: AMGDG_PCG, AMGDG_FCG or AMGDG_FGMRES
+ * (restart 1..256, ignored otherwise).  AMGDG_ENOMEM if one batch on this
+ * handle exceeds the budget. */
 int amgdg_server_submit(amgdg_server s, amgdg_handle h, const double* b_dev, double* x_dev,
-                        int32_t method, int32_t precision, double rtol, int32_t max_it, int32_t flags,
-                        int64_t tag);
+                        int32_t method, int32_t precision, double rtol, int32_t max_it, int32_t restart,
+                        int32_t flags, int64_t tag);
 /* Admits queued requests and advances every batch whose last queued
  * iteration has finished, without blocking; with wait != 0 it first waits
  * (spinning) until at least one batch has moved on.  n_pending (may be NULL):

@@ -81,9 +81,9 @@ _SIGS = {
                            ctypes.POINTER(amgdg_solve_stats), _P]),
     "amgdg_vcycle": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P]),
     "amgdg_apply": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
-    "amgdg_batch_bytes": (_I32, [_P, _I32, ctypes.POINTER(_I64)]),
+    "amgdg_batch_bytes": (_I32, [_P, _I32, _I32, ctypes.POINTER(_I64)]),
     "amgdg_server_create": (_I32, [ctypes.POINTER(_P), _I32, _I64]),
-    "amgdg_server_submit": (_I32, [_P, _P, _P, _P, _I32, _I32, _D, _I32, _I32, _I64]),
+    "amgdg_server_submit": (_I32, [_P, _P, _P, _P, _I32, _I32, _D, _I32, _I32, _I32, _I64]),
     "amgdg_server_step": (_I32, [_P, _I32, ctypes.POINTER(_I64)]),
     "amgdg_server_poll": (_I32, [_P, _I32, _P, _P, _P, _P, _P, ctypes.POINTER(_I32)]),
     "amgdg_server_destroy": (_I32, [_P]),
@@ -290,9 +290,9 @@ def amgdg_apply(handle, k, op, x, b, y, precision=AMGDG_FP64, flags=0, stream=No
     _check(lib().amgdg_apply(handle.h, k, op, m, precision, _dptr(x), _dptr(b), _dptr(y), flags, _stream(stream)))
 
 
-def amgdg_batch_bytes(handle, width):
+def amgdg_batch_bytes(handle, width, restart=0):
     out = _I64(0)
-    _check(lib().amgdg_batch_bytes(handle.h, width, ctypes.byref(out)))
+    _check(lib().amgdg_batch_bytes(handle.h, width, restart, ctypes.byref(out)))
     return out.value
 
 
@@ -306,10 +306,10 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, handle, b, x, method=AMGDG_PCG, precision=AMGDG_FP64, rtol=1e-8, max_it=10000, flags=0,
-               tag=0):
+    def submit(self, handle, b, x, method=AMGDG_PCG, precision=AMGDG_FP64, rtol=1e-8, max_it=10000, restart=30,
+               flags=0, tag=0):
         _check(lib().amgdg_server_submit(self.h, handle.h, _dptr(b), _dptr(x), method, precision, rtol, max_it,
-                                         flags, int(tag)))
+                                         restart, flags, int(tag)))
         self._keep[int(tag)] = (b, x)
 
     def step(self, wait=True):

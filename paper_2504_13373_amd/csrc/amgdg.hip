@@ -125,6 +125,8 @@ struct Level {
 constexpr int ST_RR = 0, ST_FLAG = 64, ST_BN = 96, ST_R0 = 160, ST_TR = 224, ST_LEN = 288;
 // column masks (int32): direction update, CG update, residual replacement, admission with x0
 constexpr int MASK_DIR = 0, MASK_UPD = 64, MASK_REPL = 128, MASK_ADM = 192, MASK_LEN = 256;
+// pinned FGMRES records: two step records of 2 * 257 + 1 doubles, 8 residual slots, y (<= 256)
+constexpr int GM_H_LEN = 2 * 515 + 8 + 256;
 
 // The device state of one solve, or of one batch of right-hand sides: V-cycle
 // vectors per level, Krylov vectors (row-major n x m), reduction scratch, the
@@ -149,6 +151,7 @@ struct Work {
     int32_t* mask = nullptr;
     double* stat_h = nullptr;   // pinned
     int32_t* mask_h = nullptr;  // pinned
+    double* gm_h = nullptr;     // pinned FGMRES records (Works with a basis)
     // captured V-cycles, keyed by (precision, columns, input, output)
     struct GraphEntry {
         int prec, m;
@@ -160,6 +163,7 @@ struct Work {
     std::vector<GraphEntry> graphs;
     hipStream_t cap = nullptr;
     hipEvent_t ev = nullptr;      // status readback of the host loop
+    hipEvent_t ev2 = nullptr;     // second readback slot (FGMRES run-ahead)
     hipEvent_t ev_ret = nullptr;  // solutions of retired columns written
     bool use_graph = true;        // per call: off with AMGDG_EAGER
     void drop_graphs() {
@@ -173,9 +177,11 @@ struct Work {
         drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         if (ev) (void)hipEventDestroy(ev);
+        if (ev2) (void)hipEventDestroy(ev2);
         if (ev_ret) (void)hipEventDestroy(ev_ret);
         if (stat_h) (void)hipHostFree(stat_h);
         if (mask_h) (void)hipHostFree(mask_h);
+        if (gm_h) (void)hipHostFree(gm_h);
     }
 };
 
@@ -727,7 +733,12 @@ static void work_init(Ctx& C, Work& W, int m, int restart, hipStream_t st) {
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.mask_h), MASK_LEN * sizeof(int32_t), hipHostMallocDefault));
         std::memset(W.mask_h, 0, MASK_LEN * sizeof(int32_t));
     }
+    if (restart > 0 && !W.gm_h) {
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.gm_h), GM_H_LEN * sizeof(double), hipHostMallocDefault));
+        std::memset(W.gm_h, 0, GM_H_LEN * sizeof(double));
+    }
     if (!W.ev) HIPCHK(hipEventCreateWithFlags(&W.ev, hipEventDisableTiming));
+    if (!W.ev2) HIPCHK(hipEventCreateWithFlags(&W.ev2, hipEventDisableTiming));
     if (!W.ev_ret) HIPCHK(hipEventCreateWithFlags(&W.ev_ret, hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(st));
     W.m = m;
@@ -956,7 +967,60 @@ struct Outcome {
 // last replacement (flexible) or reaches its iteration limit is first checked
 // against its true residual b - A x (one more readback); in the flexible
 // method a true residual above the tolerance replaces the recursive one.
-struct CgBatch {
+// What a batch runs: right-hand sides are admitted into its columns, the
+// engine queues its work on its stream and the host advances it whenever the
+// event it waits on has passed.  An outcome moves to `done` once the solution
+// of its retired right-hand side is written (W->ev_ret).
+struct Engine {
+    Ctx* C = nullptr;
+    Work* W = nullptr;
+    hipStream_t st = nullptr;
+    bool fail_fast = false;  // an error fails the call instead of one column
+    std::vector<Outcome> retiring;
+    std::vector<Outcome> done;
+    virtual ~Engine() = default;
+    virtual int free_slot() const = 0;
+    virtual void admit(int slot, const Rhs& rq) = 0;
+    virtual int busy() const = 0;        // right-hand sides admitted and not retired
+    virtual bool idle() const = 0;       // no event to wait for
+    virtual void start() = 0;            // queues admitted work on an idle engine
+    virtual hipEvent_t waiting() const = 0;
+    virtual void process() = 0;          // called once the awaited event has passed
+    bool ready() const {
+        if (idle()) return false;
+        const hipError_t e = hipEventQuery(waiting());
+        if (e == hipSuccess) return true;
+        if (e != hipErrorNotReady) HIPCHK(e);
+        return false;
+    }
+    void collect(bool blocking) {
+        if (retiring.empty()) return;
+        if (blocking) {
+            HIPCHK(hipEventSynchronize(W->ev_ret));
+        } else {
+            const hipError_t e = hipEventQuery(W->ev_ret);
+            if (e == hipErrorNotReady) return;
+            HIPCHK(e);
+        }
+        const Clock::time_point now = Clock::now();
+        for (Outcome& o : retiring) {
+            o.latency = std::chrono::duration<double>(now - o.t_submit).count();
+            done.push_back(o);
+        }
+        retiring.clear();
+    }
+    // blocking driver: runs until every admitted right-hand side has left
+    void run() {
+        if (idle()) start();
+        while (!idle()) {
+            HIPCHK(hipEventSynchronize(waiting()));
+            process();
+        }
+        collect(true);
+    }
+};
+
+struct CgBatch : Engine {
     enum { EMPTY = 0, STARTING = 1, RUNNING = 2 };
     enum { IDLE = 0, WAIT_STATUS = 1, WAIT_TRUE = 2 };
     struct Col {
@@ -967,17 +1031,12 @@ struct CgBatch {
         int32_t its = 0;
         double bnorm = 1.0, rel = 0.0, anchor = 1.0;
     };
-    Ctx* C = nullptr;
-    Work* W = nullptr;
-    hipStream_t st = nullptr;
     int m = 0;
-    bool flexible = false, mixed = false, fail_fast = false;
+    bool flexible = false, mixed = false;
     int phase = IDLE;
     std::vector<Col> col;
     std::vector<int> pending;               // admitted, not yet queued
     std::vector<std::pair<int, Outcome>> leaving;  // retired in this host step
-    std::vector<Outcome> retiring;          // x scatter queued before ev_ret
-    std::vector<Outcome> done;
     double *r = nullptr, *rn = nullptr;
     double *d_pq = nullptr, *d_rz = nullptr, *d_rz2 = nullptr, *d_zro = nullptr;
     int32_t* flags_d = nullptr;
@@ -1008,24 +1067,22 @@ struct CgBatch {
         std::fill(last_dir, last_dir + 64, -1);
     }
 
-    int free_slot() const {
+    int free_slot() const override {
         for (int c = 0; c < m; ++c)
             if (col[c].state == EMPTY && std::find(pending.begin(), pending.end(), c) == pending.end()) return c;
         return -1;
     }
-    int busy() const {
+    int busy() const override {
         int k = int(pending.size());
         for (const Col& c : col) k += c.state != EMPTY;
         return k;
     }
-    bool ready() const {
-        if (phase == IDLE) return false;
-        const hipError_t e = hipEventQuery(W->ev);
-        if (e == hipSuccess) return true;
-        if (e != hipErrorNotReady) HIPCHK(e);
-        return false;
+    bool idle() const override { return phase == IDLE; }
+    hipEvent_t waiting() const override { return W->ev; }
+    void start() override {
+        if (phase == IDLE && !pending.empty()) issue();
     }
-    void admit(int slot, const Rhs& rq) {
+    void admit(int slot, const Rhs& rq) override {
         col[slot].rq = rq;
         pending.push_back(slot);
     }
@@ -1111,7 +1168,7 @@ struct CgBatch {
     }
 
     // handles the phase whose event has passed and queues what follows
-    void process() {
+    void process() override {
         if (phase == WAIT_STATUS) {
             const int32_t* fl = reinterpret_cast<const int32_t*>(W->stat_h + ST_FLAG);
             bool need_true = false;
@@ -1214,34 +1271,6 @@ struct CgBatch {
         }
         issue();
     }
-
-    // moves outcomes whose x is written to `done`; blocking waits for them
-    void collect(bool blocking) {
-        if (retiring.empty()) return;
-        if (blocking) {
-            HIPCHK(hipEventSynchronize(W->ev_ret));
-        } else {
-            const hipError_t e = hipEventQuery(W->ev_ret);
-            if (e == hipErrorNotReady) return;
-            HIPCHK(e);
-        }
-        const Clock::time_point now = Clock::now();
-        for (Outcome& o : retiring) {
-            o.latency = std::chrono::duration<double>(now - o.t_submit).count();
-            done.push_back(o);
-        }
-        retiring.clear();
-    }
-
-    // blocking driver: runs until every admitted column has left
-    void run() {
-        if (phase == IDLE && !pending.empty()) issue();
-        while (phase != IDLE) {
-            HIPCHK(hipEventSynchronize(W->ev));
-            process();
-        }
-        collect(true);
-    }
 };
 
 // ------------------------------------------------------------ solvers
@@ -1278,81 +1307,196 @@ static int solve_stationary(Ctx& C, Work& W, int m, int precision, double tol, i
     return AMGDG_ENOCONV;
 }
 
-static int solve_fgmres(Ctx& C, Work& W, int precision, double tol, int restart, int maxit, KrylovState& S,
-                        hipStream_t st) {
-    Level& L = C.lv[0];
-    const int64_t n = L.n;
-    double* x = W.kx;
-    double* b = W.kb;
-    S.its.assign(1, 0);
-    S.rel.assign(1, 0.0);
-    int total = 0;
-    std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
-    auto Hat = [&](int i, int j) -> double& { return H[size_t(i) * restart + j]; };
-    while (true) {
-        std::vector<double> rr = true_res(C, W, b, x, 1, st);
-        const double beta = std::sqrt(rr[0]);
-        check_nan(rr, "residual");
-        S.rel[0] = beta / S.bnorm[0];
-        S.its[0] = total;
-        if (S.rel[0] <= tol) return AMGDG_OK;
-        if (total >= maxit) return AMGDG_ENOCONV;
-        // V_0 = r / beta
-        HIPCHK(launch_axpby_dev(W.kt, W.V, n, 1, nullptr, 1.0 / beta, 0.0, st));
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int jend = 0;
-        for (int j = 0; j < restart; ++j) {
-            double* vj = W.V + int64_t(j) * n;
-            double* zj = W.Z + int64_t(j) * n;
-            double* w = W.V + int64_t(j + 1) * n;
-            precond(C, W, vj, zj, 1, precision, st);
-            mat_spmv<double>(AX, L.A, zj, nullptr, w, 1, st);
-            // CGS2
-            std::vector<double> h(j + 2, 0.0);
-            for (int pass = 0; pass < 2; ++pass) {
-                HIPCHK(launch_multidot(W.V, n, j + 1, w, n, W.scratch, W.scal, st));
-                std::vector<double> hp(j + 1);
-                HIPCHK(hipMemcpyAsync(hp.data(), W.scal, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                HIPCHK(hipMemcpyAsync(W.scal + 1024, hp.data(), sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
-                HIPCHK(launch_multi_axpy(W.V, n, j + 1, W.scal + 1024, w, n, -1.0, st));
-                HIPCHK(hipStreamSynchronize(st));
-                for (int i = 0; i <= j; ++i) h[i] += hp[i];
-            }
-            const double hn = std::sqrt(dot1(W.scratch, W.scal, w, w, n, st));
-            check_nan({hn}, "Arnoldi");
-            if (hn > 0) HIPCHK(launch_axpby_dev(w, w, n, 1, nullptr, 1.0 / hn, 0.0, st));
-            for (int i = 0; i <= j; ++i) Hat(i, j) = h[i];
-            Hat(j + 1, j) = hn;
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
-                Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
-                Hat(i, j) = t;
-            }
-            const double den = std::hypot(Hat(j, j), Hat(j + 1, j));
-            if (!(den > 0)) throw Error(AMGDG_EBREAKDOWN, "GMRES breakdown");
-            cs[j] = Hat(j, j) / den;
-            sn[j] = Hat(j + 1, j) / den;
-            Hat(j, j) = den;
-            Hat(j + 1, j) = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++total;
-            jend = j + 1;
-            if (std::fabs(g[j + 1]) <= tol * S.bnorm[0] || total >= maxit) break;
-        }
-        for (int i = jend - 1; i >= 0; --i) {
-            double s = g[i];
-            for (int l = i + 1; l < jend; ++l) s -= Hat(i, l) * y[l];
-            y[i] = s / Hat(i, i);
-        }
-        HIPCHK(hipMemcpyAsync(W.scal + 1024, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
-        HIPCHK(launch_multi_axpy(W.Z, n, jend, W.scal + 1024, x, n, 1.0, st));
-        HIPCHK(hipStreamSynchronize(st));
+// Right-preconditioned restarted FGMRES(restart) on one right-hand side: the
+// preconditioned vectors z_j = M(v_j) are kept, so M may change between steps
+// (as the FP32 V-cycle's rounding does), and every restart begins from the
+// true FP64 residual, which makes the mixed-precision variant iterative
+// refinement with an FGMRES inner solver.  Arnoldi uses classical Gram-Schmidt
+// applied twice.  A step needs no host value: both passes' coefficients and
+// the new vector's norm stay on the device, which also normalises the vector,
+// so the host queues step j + 1 before it reads step j (a two-slot ring of
+// pinned records) and only applies the Givens rotations and the stopping test.
+// A cycle ends when the least-squares residual meets the tolerance, the basis
+// is full or the iteration limit is reached; then x += Z y and the true
+// residual decides between stopping and restarting.
+struct GmresRun : Engine {
+    enum { IDLE = 0, WAIT_STEP = 1, WAIT_RES = 2 };
+    // device scalars (W->scal) and the pinned record of a step
+    static constexpr int H1 = 0, H2 = 257, NRM = 514, REC = 515, YD = 1024, BN = 1536, RR = 1537;
+    // pinned layout (W->gm_h): two step records, then ||b||^2 and ||r||^2, then y
+    static constexpr int RES = 2 * REC, YH = 2 * REC + 8;
+    int restart = 30;
+    bool mixed = false;
+    int phase = IDLE;
+    bool pend = false, has = false, first = true;
+    Rhs rq;
+    int32_t total = 0, cyc0 = 0;
+    int j = 0, queued = 0;
+    double bnorm = 1.0;
+    std::vector<double> H, cs, sn, g, y;
+
+    void init(Ctx& c, Work& w, hipStream_t s, int rst, bool mix, bool ff) {
+        C = &c;
+        W = &w;
+        st = s;
+        restart = rst;
+        mixed = mix;
+        fail_fast = ff;
+        phase = IDLE;
+        pend = has = false;
+        H.assign(size_t(restart + 1) * restart, 0.0);
+        cs.assign(restart, 0.0);
+        sn.assign(restart, 0.0);
+        g.assign(restart + 1, 0.0);
+        y.assign(restart, 0.0);
     }
-}
+    int free_slot() const override { return (pend || has) ? -1 : 0; }
+    void admit(int, const Rhs& q) override {
+        rq = q;
+        pend = true;
+    }
+    int busy() const override { return (pend || has) ? 1 : 0; }
+    bool idle() const override { return phase == IDLE; }
+    hipEvent_t waiting() const override {
+        return (phase == WAIT_STEP && (j & 1)) ? W->ev2 : W->ev;
+    }
+    double& Hat(int i, int k) { return H[size_t(i) * restart + k]; }
+
+    void start() override {
+        if (!pend) return;
+        pend = false;
+        has = true;
+        first = true;
+        total = 0;
+        const Level& L = C->lv[0];
+        int32_t* flags_d = reinterpret_cast<int32_t*>(W->stat + ST_FLAG);
+        HIPCHK(launch_admit(rq.b, rq.ld, rq.x0, rq.ld, rq.internal ? nullptr : C->perm_d, L.n_units, L.nb, W->kb,
+                            W->kx, W->kt, W->kp, W->kq, 1, 0, flags_d, st));
+        HIPCHK(launch_dot<double>(W->kb, W->kb, L.n, 1, W->scratch, W->scal + BN, st));
+        queue_residual();
+    }
+
+    // t = b - A x, ||t||^2 and (first time) ||b||^2 to the host
+    void queue_residual() {
+        const Level& L = C->lv[0];
+        mat_spmv<double>(B_MINUS, L.A, W->kx, W->kb, W->kt, 1, st);
+        HIPCHK(launch_dot<double>(W->kt, W->kt, L.n, 1, W->scratch, W->scal + RR, st));
+        HIPCHK(hipMemcpyAsync(W->gm_h + RES, W->scal + BN, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(W->ev, st));
+        phase = WAIT_RES;
+    }
+
+    // Arnoldi step k of the cycle: z_k = M v_k, w = A z_k, CGS2, ||w||, v_{k+1} = w / ||w||
+    void queue_step() {
+        const int k = queued;
+        if (k >= restart || cyc0 + k >= rq.maxit) return;
+        const int64_t n = C->lv[0].n;
+        double* vk = W->V + int64_t(k) * n;
+        double* zk = W->Z + int64_t(k) * n;
+        double* w = W->V + int64_t(k + 1) * n;
+        precond(*C, *W, vk, zk, 1, mixed ? AMGDG_MIXED : AMGDG_FP64, st);
+        mat_spmv<double>(AX, C->lv[0].A, zk, nullptr, w, 1, st);
+        HIPCHK(launch_multidot(W->V, n, k + 1, w, n, W->scratch, W->scal + H1, st));
+        HIPCHK(launch_multi_axpy(W->V, n, k + 1, W->scal + H1, w, n, -1.0, st));
+        HIPCHK(launch_multidot(W->V, n, k + 1, w, n, W->scratch, W->scal + H2, st));
+        HIPCHK(launch_multi_axpy(W->V, n, k + 1, W->scal + H2, w, n, -1.0, st));
+        HIPCHK(launch_dot<double>(w, w, n, 1, W->scratch, W->scal + NRM, st));
+        HIPCHK(hipMemcpyAsync(W->gm_h + (k & 1) * REC, W->scal, REC * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord((k & 1) ? W->ev2 : W->ev, st));
+        HIPCHK(launch_scale_by_inv_norm(w, n, W->scal + NRM, st));
+        ++queued;
+    }
+
+    void retire(int rc, double rel) {
+        if (fail_fast && rc != AMGDG_OK && rc != AMGDG_ENOCONV) {
+            (void)hipStreamSynchronize(st);
+            phase = IDLE;
+            has = false;
+            throw Error(rc, rc == AMGDG_EBREAKDOWN ? "GMRES breakdown" : "NaN or Inf in GMRES (right-hand side or iterate)");
+        }
+        const Level& L = C->lv[0];
+        HIPCHK(launch_scatter_col(W->kx, 1, rq.x, rq.ld, rq.internal ? nullptr : C->perm_d, L.n_units, L.nb, st));
+        HIPCHK(hipEventRecord(W->ev_ret, st));
+        Outcome o;
+        o.tag = rq.tag;
+        o.rc = rc;
+        o.its = total;
+        o.rel = rel;
+        o.t_submit = rq.t_submit;
+        retiring.push_back(o);
+        has = false;
+        phase = IDLE;
+        if (pend) start();
+    }
+
+    void process() override {
+        if (phase == WAIT_RES) {
+            if (first) {
+                const double bn2 = W->gm_h[RES];
+                if (!std::isfinite(bn2)) return retire(AMGDG_ENAN, std::numeric_limits<double>::quiet_NaN());
+                bnorm = std::sqrt(bn2) > 0 ? std::sqrt(bn2) : 1.0;
+                first = false;
+            }
+            const double rr = W->gm_h[RES + 1];
+            if (!std::isfinite(rr)) return retire(AMGDG_ENAN, rr);
+            const double beta = std::sqrt(rr);
+            const double rel = beta / bnorm;
+            if (rel <= rq.tol) return retire(AMGDG_OK, rel);
+            if (total >= rq.maxit) return retire(AMGDG_ENOCONV, rel);
+            HIPCHK(launch_axpby_dev(W->kt, W->V, C->lv[0].n, 1, nullptr, 1.0 / beta, 0.0, st));
+            std::fill(H.begin(), H.end(), 0.0);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            cyc0 = total;
+            j = 0;
+            queued = 0;
+            queue_step();
+            queue_step();  // run-ahead
+            phase = WAIT_STEP;
+            return;
+        }
+        if (phase != WAIT_STEP) return;
+        const double* rec = W->gm_h + (j & 1) * REC;
+        const double hn = std::sqrt(rec[NRM]);
+        bool finite = std::isfinite(hn);
+        for (int i = 0; i <= j; ++i) {
+            Hat(i, j) = rec[H1 + i] + rec[H2 + i];
+            finite = finite && std::isfinite(Hat(i, j));
+        }
+        if (!finite) return retire(AMGDG_ENAN, std::numeric_limits<double>::quiet_NaN());
+        Hat(j + 1, j) = hn;
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * Hat(i, j) + sn[i] * Hat(i + 1, j);
+            Hat(i + 1, j) = -sn[i] * Hat(i, j) + cs[i] * Hat(i + 1, j);
+            Hat(i, j) = t;
+        }
+        const double den = std::hypot(Hat(j, j), Hat(j + 1, j));
+        if (!(den > 0)) return retire(AMGDG_EBREAKDOWN, std::numeric_limits<double>::quiet_NaN());
+        cs[j] = Hat(j, j) / den;
+        sn[j] = Hat(j + 1, j) / den;
+        Hat(j, j) = den;
+        Hat(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++total;
+        const int jend = j + 1;
+        if (std::fabs(g[j + 1]) <= rq.tol * bnorm || jend == restart || total >= rq.maxit) {
+            // x += Z y with H[:jend, :jend] y = g[:jend]
+            for (int i = jend - 1; i >= 0; --i) {
+                double s = g[i];
+                for (int l = i + 1; l < jend; ++l) s -= Hat(i, l) * y[l];
+                y[i] = s / Hat(i, i);
+            }
+            std::memcpy(W->gm_h + YH, y.data(), sizeof(double) * jend);
+            HIPCHK(hipMemcpyAsync(W->scal + YD, W->gm_h + YH, sizeof(double) * jend, hipMemcpyHostToDevice, st));
+            HIPCHK(launch_multi_axpy(W->Z, C->lv[0].n, jend, W->scal + YD, W->kx, C->lv[0].n, 1.0, st));
+            queue_residual();
+            return;
+        }
+        ++j;
+        queue_step();  // keeps one step queued ahead of the one awaited
+    }
+};
 
 static void check_solve_args(const Ctx& C, int m, int method, int precision) {
     if (C.N == 0) throw Error(AMGDG_EUNSUPPORTED, "Krylov solve needs at least two levels");
@@ -1377,9 +1521,16 @@ static int solve_impl(Ctx& C, int m, const double* b_dev, double* x_dev, int met
     std::vector<int32_t> its(m, 0);
     std::vector<double> rel(m, 0.0);
     int rc = AMGDG_OK;
-    if (method == AMGDG_PCG || method == AMGDG_FCG) {
-        CgBatch B;
-        B.init(C, W, st, m, method == AMGDG_FCG, precision == AMGDG_MIXED, true);
+    if (method != AMGDG_STATIONARY) {
+        CgBatch cg;
+        GmresRun gm;
+        Engine* E = &cg;
+        if (method == AMGDG_FGMRES) {
+            gm.init(C, W, st, restart, precision == AMGDG_MIXED, true);
+            E = &gm;
+        } else {
+            cg.init(C, W, st, m, method == AMGDG_FCG, precision == AMGDG_MIXED, true);
+        }
         for (int c = 0; c < m; ++c) {
             Rhs q;
             q.tag = c;
@@ -1391,10 +1542,10 @@ static int solve_impl(Ctx& C, int m, const double* b_dev, double* x_dev, int met
             q.maxit = max_it;
             q.internal = internal;
             q.t_submit = t0;
-            B.admit(c, q);
+            E->admit(c, q);
         }
-        B.run();
-        for (const Outcome& o : B.done) {
+        E->run();
+        for (const Outcome& o : E->done) {
             its[o.tag] = o.its;
             rel[o.tag] = o.rel;
             if (o.rc != AMGDG_OK) rc = AMGDG_ENOCONV;
@@ -1412,8 +1563,7 @@ static int solve_impl(Ctx& C, int m, const double* b_dev, double* x_dev, int met
         S.bnorm = dotm(W.scratch, W.scal, W.kb, W.kb, n, m, st);
         check_nan(S.bnorm, "b");
         for (double& v : S.bnorm) v = std::sqrt(v) > 0 ? std::sqrt(v) : 1.0;
-        if (method == AMGDG_STATIONARY) rc = solve_stationary(C, W, m, precision, rtol, max_it, S, st);
-        else rc = solve_fgmres(C, W, precision, rtol, restart, max_it, S, st);
+        rc = solve_stationary(C, W, m, precision, rtol, max_it, S, st);
         // final true residuals
         std::vector<double> tr = true_res(C, W, W.kb, W.kx, m, st);
         if (internal) HIPCHK(hipMemcpyAsync(x_dev, W.kx, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st));
@@ -1442,31 +1592,36 @@ static int solve_impl(Ctx& C, int m, const double* b_dev, double* x_dev, int met
 
 // ------------------------------------------------------------ serving
 
-// Continuous batching of CG solves.  Requests on the same (handle, method,
-// precision) share a batch of `width` columns; a request takes a free column
-// between iterations and leaves it when done, so the level operators are read
-// once per iteration for every request in the batch.  Batches run on streams
-// of their own and are created while the device bytes of all batch workspaces
-// stay within the budget; an idle batch of another key is released to make
-// room.  Requests wait in submission order; one that cannot be placed does
-// not hold back requests that can.
+// Continuous batching.  Requests on the same (handle, method, precision,
+// restart) share a batch: CG requests the `width` columns of one CgBatch,
+// where a request takes a free column between iterations and leaves it when
+// done, so the level operators are read once per iteration for every request
+// of the batch; an FGMRES request a batch of its own (one column and its
+// Krylov basis).  Batches run on streams of their own, so their work overlaps
+// on the device, and are created while the device bytes of all batch
+// workspaces stay within the budget; an idle batch of another key is released
+// to make room.  Requests wait in submission order; one that cannot be placed
+// does not hold back requests that can.
 struct Request {
     Ctx* C = nullptr;
-    int method = AMGDG_PCG, precision = AMGDG_FP64;
+    int method = AMGDG_PCG, precision = AMGDG_FP64, restart = 0;
     Rhs rq;
 };
 
 struct ServerBatch {
     Ctx* C = nullptr;
-    int method = 0, precision = 0;
+    int method = 0, precision = 0, restart = 0;
     hipStream_t st = nullptr;
     Work W;
-    CgBatch eng;
+    std::unique_ptr<Engine> eng;
     ~ServerBatch() {
         if (st) {
             (void)hipStreamSynchronize(st);
             (void)hipStreamDestroy(st);
         }
+    }
+    bool same_key(const Request& r) const {
+        return C == r.C && method == r.method && precision == r.precision && restart == r.restart;
     }
 };
 
@@ -1477,17 +1632,19 @@ struct Server {
     std::vector<std::unique_ptr<ServerBatch>> batches;
     std::vector<Outcome> done;
 
-    bool idle(const ServerBatch& b) const {
-        return b.eng.phase == CgBatch::IDLE && b.eng.busy() == 0 && b.eng.retiring.empty();
+    static int batch_width(int method, int width) { return method == AMGDG_FGMRES ? 1 : width; }
+    static int64_t batch_bytes(const Ctx& C, int method, int width, int restart) {
+        return work_bytes(C, batch_width(method, width), method == AMGDG_FGMRES ? restart : 0);
     }
+    static bool idle(const ServerBatch& b) { return b.eng->idle() && b.eng->busy() == 0 && b.eng->retiring.empty(); }
 
-    ServerBatch* create(Ctx& C, int method, int precision) {
-        const int64_t need = work_bytes(C, width, 0);
+    ServerBatch* create(const Request& r) {
+        const int64_t need = batch_bytes(*r.C, r.method, width, r.restart);
         if (used + need > budget) {
             // release idle batches of other keys, oldest first
             for (size_t i = 0; i < batches.size() && used + need > budget;) {
                 ServerBatch& b = *batches[i];
-                if (idle(b) && !(b.C == &C && b.method == method && b.precision == precision)) {
+                if (idle(b) && !b.same_key(r)) {
                     used -= b.W.bytes;
                     batches.erase(batches.begin() + i);
                 } else {
@@ -1497,13 +1654,23 @@ struct Server {
         }
         if (used + need > budget) return nullptr;
         auto b = std::make_unique<ServerBatch>();
-        b->C = &C;
-        b->method = method;
-        b->precision = precision;
+        b->C = r.C;
+        b->method = r.method;
+        b->precision = r.precision;
+        b->restart = r.restart;
         HIPCHK(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
-        work_init(C, b->W, width, 0, b->st);
+        const bool fgm = r.method == AMGDG_FGMRES;
+        work_init(*r.C, b->W, batch_width(r.method, width), fgm ? r.restart : 0, b->st);
         b->W.use_graph = true;
-        b->eng.init(C, b->W, b->st, width, method == AMGDG_FCG, precision == AMGDG_MIXED, false);
+        if (fgm) {
+            auto e = std::make_unique<GmresRun>();
+            e->init(*r.C, b->W, b->st, r.restart, r.precision == AMGDG_MIXED, false);
+            b->eng = std::move(e);
+        } else {
+            auto e = std::make_unique<CgBatch>();
+            e->init(*r.C, b->W, b->st, width, r.method == AMGDG_FCG, r.precision == AMGDG_MIXED, false);
+            b->eng = std::move(e);
+        }
         used += b->W.bytes;
         batches.push_back(std::move(b));
         return batches.back().get();
@@ -1514,27 +1681,25 @@ struct Server {
         for (auto it = queue.begin(); it != queue.end();) {
             ServerBatch* tgt = nullptr;
             for (auto& b : batches)
-                if (b->C == it->C && b->method == it->method && b->precision == it->precision &&
-                    b->eng.free_slot() >= 0) {
+                if (b->same_key(*it) && b->eng->free_slot() >= 0) {
                     tgt = b.get();
                     break;
                 }
-            if (!tgt) tgt = create(*it->C, it->method, it->precision);
+            if (!tgt) tgt = create(*it);
             if (!tgt) {
                 ++it;
                 continue;
             }
-            tgt->eng.admit(tgt->eng.free_slot(), it->rq);
-            if (tgt->eng.phase == CgBatch::IDLE && std::find(kick.begin(), kick.end(), tgt) == kick.end())
-                kick.push_back(tgt);
+            tgt->eng->admit(tgt->eng->free_slot(), it->rq);
+            if (tgt->eng->idle() && std::find(kick.begin(), kick.end(), tgt) == kick.end()) kick.push_back(tgt);
             it = queue.erase(it);
         }
-        for (ServerBatch* b : kick) b->eng.issue();
+        for (ServerBatch* b : kick) b->eng->start();
     }
 
     int64_t pending() const {
         int64_t k = int64_t(queue.size());
-        for (auto& b : batches) k += b->eng.busy() + int64_t(b->eng.retiring.size());
+        for (auto& b : batches) k += b->eng->busy() + int64_t(b->eng->retiring.size());
         return k;
     }
 
@@ -1543,20 +1708,21 @@ struct Server {
         while (true) {
             bool progressed = false;
             for (auto& b : batches) {
-                if (b->eng.ready()) {
-                    b->eng.process();
+                Engine& e = *b->eng;
+                if (e.ready()) {
+                    e.process();
                     progressed = true;
                 }
-                const size_t before = b->eng.done.size();
-                b->eng.collect(false);
-                if (b->eng.done.size() != before) progressed = true;
-                for (Outcome& o : b->eng.done) done.push_back(o);
-                b->eng.done.clear();
+                const size_t before = e.done.size();
+                e.collect(false);
+                if (e.done.size() != before) progressed = true;
+                for (Outcome& o : e.done) done.push_back(o);
+                e.done.clear();
             }
             if (progressed) admit_queued();
             if (!wait || progressed || pending() == 0) return;
             bool in_flight = false;
-            for (auto& b : batches) in_flight = in_flight || b->eng.phase != CgBatch::IDLE || !b->eng.retiring.empty();
+            for (auto& b : batches) in_flight = in_flight || !b->eng->idle() || !b->eng->retiring.empty();
             if (!in_flight) return;  // queued requests that no budget can place
             std::this_thread::yield();
         }
@@ -2018,11 +2184,12 @@ int amgdg_apply(amgdg_handle h, int32_t k, int32_t op, int32_t m, int32_t precis
     ABI_END
 }
 
-int amgdg_batch_bytes(amgdg_handle h, int32_t width, int64_t* bytes) {
+int amgdg_batch_bytes(amgdg_handle h, int32_t width, int32_t restart, int64_t* bytes) {
     ABI_BEGIN
     if (!h || !bytes) throw Error(AMGDG_EINVAL, "NULL argument");
     if (width < 1 || width > 64) throw Error(AMGDG_EUNSUPPORTED, "width must be 1..64");
-    *bytes = work_bytes(h->c, width, 0);
+    if (restart < 0 || restart > 256) throw Error(AMGDG_EUNSUPPORTED, "restart must be 0..256");
+    *bytes = work_bytes(h->c, width, restart);
     return AMGDG_OK;
     ABI_END
 }
@@ -2042,21 +2209,25 @@ int amgdg_server_create(amgdg_server* out, int32_t width, int64_t hbm_budget_byt
 }
 
 int amgdg_server_submit(amgdg_server s, amgdg_handle h, const double* b_dev, double* x_dev, int32_t method,
-                        int32_t precision, double rtol, int32_t max_it, int32_t flags, int64_t tag) {
+                        int32_t precision, double rtol, int32_t max_it, int32_t restart, int32_t flags,
+                        int64_t tag) {
     ABI_BEGIN
     if (!s || !h || !b_dev || !x_dev) throw Error(AMGDG_EINVAL, "NULL argument");
     Ctx& C = h->c;
     check_solve_args(C, 1, method, precision);
-    if (method != AMGDG_PCG && method != AMGDG_FCG) throw Error(AMGDG_EUNSUPPORTED, "the server runs PCG and FCG");
+    if (method == AMGDG_STATIONARY) throw Error(AMGDG_EUNSUPPORTED, "the server runs PCG, FCG and FGMRES");
+    if (method == AMGDG_FGMRES && (restart < 1 || restart > 256))
+        throw Error(AMGDG_EUNSUPPORTED, "FGMRES: 1 <= restart <= 256");
     if (max_it < 0 || !(rtol >= 0)) throw Error(AMGDG_EINVAL, "bad rtol or max_it");
     if (flags & ~(AMGDG_X0 | AMGDG_INTERNAL_ORDER)) throw Error(AMGDG_EINVAL, "bad flags");
-    const int64_t need = work_bytes(C, s->s.width, 0);
+    const int64_t need = Server::batch_bytes(C, method, s->s.width, restart);
     if (need > s->s.budget)
         throw Error(AMGDG_ENOMEM, "a batch on this handle needs " + std::to_string(need) + " bytes, over the budget");
     Request r;
     r.C = &C;
     r.method = method;
     r.precision = precision;
+    r.restart = method == AMGDG_FGMRES ? restart : 0;
     r.rq.tag = tag;
     r.rq.b = b_dev;
     r.rq.x = x_dev;

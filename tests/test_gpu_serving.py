@@ -9,7 +9,6 @@ import numpy as np
 import pytest
 
 import paper_2504_13373_amd as am
-from oracle import rcb
 from workloads import configs
 
 torch = pytest.importorskip("torch")
@@ -23,7 +22,8 @@ def handle(name):
     if name not in _H:
         print(f"[gpu-serving] building case {name}", flush=True)
         w = {"sipg3": lambda: configs.poisson2d_delaunay(side=33, p=3, n_levels=4, r=3),
-             "c1": lambda: configs.poisson2d_split()}[name]()
+             "c1": lambda: configs.poisson2d_split(),
+             "ldg2": lambda: configs.convdiff2d_delaunay(side=17, p=2, peclet=100.0, n_levels=3, r=4)}[name]()
         h, _ = am.setup_from_workload(w, mixed=True)
         _H[name] = (w, h)
     return _H[name]
@@ -33,9 +33,10 @@ def rhs(n, seed):
     return torch.as_tensor(np.random.default_rng(seed).standard_normal(n)).to(DEV).contiguous()
 
 
-def alone(h, b, method, prec, rtol, max_it, x0=None):
+def alone(h, b, method, prec, rtol, max_it, x0=None, restart=30):
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    rc, st = am.amgdg_solve(h, b, x, method, prec, rtol, max_it, flags=am.AMGDG_X0 if x0 is not None else 0)
+    rc, st = am.amgdg_solve(h, b, x, method, prec, rtol, max_it, restart=restart,
+                            flags=am.AMGDG_X0 if x0 is not None else 0)
     torch.cuda.synchronize()
     return rc, st.iterations[0], st.rel_residual[0], x
 
@@ -144,13 +145,62 @@ def test_server_failures_stay_in_their_column():
     assert torch.count_nonzero(Xz).item() == 0
 
 
+def test_server_mixes_fgmres_and_cg():
+    """Non-symmetric requests (FGMRES, one batch each, FP64 and mixed, two
+    restart lengths) overlap with CG batches on another hierarchy; every
+    result equals its solo run bit for bit."""
+    wl, hl = handle("ldg2")
+    ws, hs = handle("sipg3")
+    jobs = []
+    for i in range(8):
+        if i % 2 == 0:
+            meth, prec, rst = am.AMGDG_FGMRES, (am.AMGDG_FP64 if i % 4 == 0 else am.AMGDG_MIXED), (30 if i < 4 else 7)
+            w, h = wl, hl
+        else:
+            meth, prec, rst = am.AMGDG_PCG, am.AMGDG_FP64, 0
+            w, h = ws, hs
+        b = rhs(w.A.n, 900 + i)
+        jobs.append((h, b, meth, prec, rst, alone(h, b, meth, prec, 1e-8, 3000, restart=max(rst, 1))))
+    X = [torch.zeros_like(j[1]) for j in jobs]
+    srv = am.Server(width=2, hbm_budget_bytes=1 << 40)
+    subs = [(lambda i=i: srv.submit(jobs[i][0], jobs[i][1], X[i], jobs[i][2], jobs[i][3], 1e-8, 3000,
+                                    restart=max(jobs[i][4], 1), tag=i)) for i in range(8)]
+    out = run_server(srv, [subs[:3], subs[3:6], subs[6:]], steps_between=4)
+    srv.close()
+    assert sorted(out) == list(range(8))
+    for i in range(8):
+        check_equal(out[i], jobs[i][5], X[i], i)
+
+
+def test_fgmres_nan_rhs():
+    w, h = handle("ldg2")
+    b = rhs(w.A.n, 950)
+    b[3] = float("nan")
+    x = torch.zeros_like(b)
+    with pytest.raises(am.AmgdgError) as e:
+        am.amgdg_solve(h, b, x, am.AMGDG_FGMRES, am.AMGDG_FP64, 1e-8, 100)
+    assert e.value.code == am.AMGDG_ENAN
+    good = rhs(w.A.n, 951)
+    ref = alone(h, good, am.AMGDG_FGMRES, am.AMGDG_FP64, 1e-8, 3000)
+    xg = torch.zeros_like(good)
+    srv = am.Server(width=2, hbm_budget_bytes=1 << 40)
+    out = run_server(srv, [[lambda: srv.submit(h, b, x, am.AMGDG_FGMRES, tag=0),
+                            lambda: srv.submit(h, good, xg, am.AMGDG_FGMRES, max_it=3000, tag=1)]])
+    srv.close()
+    assert out[0][1] == am.AMGDG_ENAN
+    check_equal(out[1], ref, xg, 1)
+
+
 def test_server_rejects_bad_requests():
     w, h = handle("c1")
     b = rhs(w.A.n, 1)
     x = torch.zeros_like(b)
     srv = am.Server(width=2, hbm_budget_bytes=1 << 40)
     with pytest.raises(am.AmgdgError) as e:
-        srv.submit(h, b, x, am.AMGDG_FGMRES, tag=0)
+        srv.submit(h, b, x, am.AMGDG_STATIONARY, tag=0)
+    assert e.value.code == am.AMGDG_EUNSUPPORTED
+    with pytest.raises(am.AmgdgError) as e:
+        srv.submit(h, b, x, am.AMGDG_FGMRES, restart=0, tag=0)
     assert e.value.code == am.AMGDG_EUNSUPPORTED
     srv.close()
     small = am.Server(width=2, hbm_budget_bytes=am.amgdg_batch_bytes(h, 2) - 1)
