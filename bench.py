@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -70,7 +72,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rhs", type=int, default=1, help="right-hand sides per solve")
-    ap.add_argument("--side", type=int, default=256, help="grid points per side (256: the full workload)")
+    ap.add_argument("--workload", choices=["poisson2d", "convdiff", "poisson3d"], default="poisson2d",
+                    help="poisson2d: the headline workload; convdiff: LDG convection-diffusion Peclet sweep "
+                         "with FGMRES(30); poisson3d: 3D tetrahedra, 16 right-hand sides")
+    ap.add_argument("--side", type=int, default=None,
+                    help="grid points per side (2D; defaults 256 / 363) or cells per side (3D; default 64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -81,6 +87,7 @@ def main():
     ap.add_argument("--serve-width", type=int, default=4, help="right-hand sides per server batch")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate in requests/s (0: all requests arrive at once)")
+    ap.add_argument("--skip-fp64", action="store_true", help="poisson3d: time the mixed path only")
     ap.add_argument("--max-it", type=int, default=50000,
                     help="iteration cap per solve (profiling runs cap it; the reported value needs convergence)")
     args = ap.parse_args()
@@ -96,6 +103,11 @@ def main():
     from workloads import configs
 
     dev = torch.device("cuda:0")
+    if args.workload == "convdiff":
+        return bench_convdiff(args, am, torch, dev)
+    if args.workload == "poisson3d":
+        return bench_poisson3d(args, am, torch, dev)
+    args.side = args.side or 256
     log(f"generating workload (side {args.side})")
     t0 = time.perf_counter()
     w = configs.poisson2d_delaunay(side=args.side, n_rhs=args.rhs)
@@ -253,6 +265,160 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _contract(args, metric_value, ms, dtype, workload, extra):
+    line = {
+        "metric": "solves/sec + HBM GB/s of V-cycle to 1e-8 rel. resid; mixed vs FP64, p99 latency",
+        "value": metric_value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": workload},
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def _timed_solves(am, torch, h, b, x, method, prec, maxit, steps, restart=30):
+    """A two-iteration warm-up solve (captures the V-cycle graphs), then
+    max(steps, 1) timed solves; returns the last status and the median time."""
+    def one(it):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = am.amgdg_solve(h, b, x, method, prec, 1e-8, it, restart=restart)
+        torch.cuda.synchronize()
+        return rc, st, time.perf_counter() - t0
+    one(2)
+    times = []
+    for _ in range(max(steps, 1)):
+        rc, st, t = one(maxit)
+        times.append(t)
+    return rc, st, float(np.median(times))
+
+
+def bench_convdiff(args, am, torch, dev):
+    """LDG + upwind convection-diffusion, p = 2, on the Delaunay triangulation
+    of 363^2 jittered points (262,088 triangles); 6-level hierarchy, r = 4,
+    V(3,3); right-hand side U(-1, 1) from seed 1; right-preconditioned
+    FGMRES(30) to 1e-8 with the FP64 and the FP32 V-cycle, per Peclet number."""
+    from workloads import configs
+    side = args.side or 363
+    maxit = min(args.max_it, 5000)
+    sweep = {}
+    for pe in (1.0, 1e2, 1e4):
+        log(f"convdiff: generating Pe = {pe:g} (side {side})")
+        w = configs.convdiff2d_delaunay(side=side, peclet=pe)
+        A = w.A.to_scipy()
+        t0 = time.perf_counter()
+        h, _ = am.setup_from_workload(w, mixed=True)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
+        log(f"convdiff Pe {pe:g}: {w.mesh.n_elem} triangles, {w.A.n} dofs, {w.A.nnzb} blocks; setup {setup_s:.2f} s; "
+            f"levels n = {[i.n for i in infos]}")
+        b = torch.as_tensor(w.b).to(dev).contiguous()
+        x = torch.zeros_like(b)
+        res = {"setup_s": setup_s, "levels_n": [i.n for i in infos]}
+        for name, prec in (("fp64", am.AMGDG_FP64), ("mixed", am.AMGDG_MIXED)):
+            rc, st, t = _timed_solves(am, torch, h, b, x, am.AMGDG_FGMRES, prec, maxit, args.steps)
+            xh = x.cpu().numpy()
+            tr = float(np.linalg.norm(w.b - A @ xh) / np.linalg.norm(w.b))
+            res[name] = {"iterations": st.iterations[0], "converged": rc == am.AMGDG_OK, "seconds": t,
+                         "solves_per_s": 1.0 / t if rc == am.AMGDG_OK else None, "true_rel_residual": tr}
+            log(f"convdiff Pe {pe:g} {name}: rc {rc}, {st.iterations[0]} iterations, {t:.2f} s, true rel {tr:.2e}")
+        sweep[f"{pe:g}"] = res
+        h.close()
+    mid = sweep["100"]
+    _contract(args, mid["fp64"]["solves_per_s"], mid["fp64"]["seconds"] * 1e3, "f64 (and f32 V-cycle + f64 Krylov)",
+              f"2D convection-diffusion, LDG + upwind p=2 on the Delaunay triangulation of {side}^2 jittered points, "
+              f"6-level RCB hierarchy, r=4, V(3,3), FGMRES(30) to 1e-8; value: FP64 at Peclet 100",
+              {"peclet_sweep": sweep, "max_it": maxit})
+
+
+def bench_poisson3d(args, am, torch, dev):
+    """3D Poisson, SIPG p = 2 on 64^3 cube cells x 6 Kuhn tetrahedra with vertex
+    jitter 0.2h (1,572,864 tets, 15,728,640 dofs); 5-level hierarchy, r = 4,
+    V(2,2); 16 right-hand sides N(0,1) from seed 1 solved together (every
+    kernel of the V-cycle and the Krylov loop handles the 16 columns in one
+    launch) to 1e-8: FP32 V-cycle in FP64 flexible CG, and FP64 CG."""
+    from workloads import configs
+    cells = args.side or 64
+    m = 16
+    maxit = args.max_it
+    log(f"poisson3d: generating {cells}^3 x 6 tetrahedra, {m} right-hand sides")
+    t0 = time.perf_counter()
+    w = configs.poisson3d_kuhn(n=cells, n_rhs=m, log=log)
+    log(f"poisson3d: {w.mesh.n_elem} tets, {w.A.n} dofs, {w.A.nnzb} blocks ({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    h, _ = am.setup_from_workload(w, mixed=True)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
+    log(f"poisson3d: setup {setup_s:.2f} s; levels n = {[i.n for i in infos]}, "
+        f"omega = {[round(i.omega, 4) for i in infos[:-1]]}")
+    b = torch.as_tensor(w.b).to(dev).contiguous()
+    w.b = None
+    x = torch.zeros_like(b)
+    y = torch.zeros_like(b)
+    res = {}
+    paths = [("mixed", am.AMGDG_FCG, am.AMGDG_MIXED)]
+    if not args.skip_fp64:
+        paths.append(("fp64", am.AMGDG_PCG, am.AMGDG_FP64))
+    for name, meth, prec in paths:
+        rc, st, t = _timed_solves(am, torch, h, b, x, meth, prec, maxit, args.steps)
+        am.amgdg_apply(h, 0, am.AMGDG_OP_RESIDUAL, x, b, y)
+        tr = float((torch.linalg.norm(y, dim=0) / torch.linalg.norm(b, dim=0)).max())
+        res[name] = {"iterations_max": st.max_iterations, "converged": rc == am.AMGDG_OK, "seconds": t,
+                     "solves_per_s": m / t if rc == am.AMGDG_OK else None, "true_rel_residual_max": tr}
+        log(f"poisson3d {name}: rc {rc}, {st.max_iterations} iterations, {t:.2f} s, max true rel {tr:.2e}")
+    nu = 2
+    stream = torch.cuda.current_stream()
+    vc = {}
+    for name, (prec, wb, dt) in {"fp32": (am.AMGDG_MIXED, 4, torch.float32),
+                                 "fp64": (am.AMGDG_FP64, 8, torch.float64)}.items():
+        r = torch.randn(b.shape, dtype=dt, device=dev)
+        z = torch.zeros_like(r)
+        for _ in range(2):
+            am.amgdg_vcycle(h, r, z, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 5
+        for _ in range(reps):
+            am.amgdg_vcycle(h, r, z, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps * 1e-3
+        nN = infos[-1].n
+        byts = sum(level_bytes(i, wb, m, nu) for i in infos[:-1]) + nN * nN * 8 + 2 * nN * m * 8
+        xx, bb, yy = torch.randn_like(r), torch.randn_like(r), torch.zeros_like(r)
+        for _ in range(2):
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e0.record(stream)
+        for _ in range(reps):
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts = e0.elapsed_time(e1) / reps * 1e-3
+        sb = sweep_bytes(infos[0], wb, m)
+        vc[name] = {"vcycle_ms": t * 1e3, "vcycle_GBps": byts / t / 1e9, "sweep_us": ts * 1e6,
+                    "sweep_GBps": sb / ts / 1e9, "sweep_frac": sb / ts / 1e9 / HBM_PEAK_GBS}
+        log(f"poisson3d V-cycle {name}: {t * 1e3:.2f} ms ({byts / t / 1e9:.0f} GB/s); level-0 sweep "
+            f"{ts * 1e6:.0f} us ({sb / ts / 1e9:.0f} GB/s)")
+        del r, z, xx, bb, yy
+    mx = res["mixed"]
+    _contract(args, mx["solves_per_s"], mx["seconds"] * 1e3, "f32 V-cycle + f64 Krylov",
+              f"3D Poisson SIPG p=2 on {cells}^3 x 6 jittered Kuhn tetrahedra ({infos[0].n_units} tets, "
+              f"{infos[0].n} dofs), 5-level RCB hierarchy, r=4, V(2,2), {m} RHS per solve, tol 1e-8",
+              {"solves": res, "kernels_m16": vc, "setup_s": setup_s, "levels_n": [i.n for i in infos]})
 
 
 def serve_bench(am, h, n, dev, n_req, width, rate, maxit):

@@ -57,4 +57,4 @@ class SimplexBasis:
     def grad(self, xi):
         """Reference gradients at xi (..., dim) -> (..., nb, dim)."""
         g = self._monomial_grads(xi)
-        return np.einsum("ij,...jd->...id", self.C, g)
+        return np.matmul(self.C, g)

@@ -100,8 +100,8 @@ def convdiff2d_delaunay(side=363, p=2, peclet=1e2, n_levels=6, bisections=2, r=4
                    rhs_kind="uniform", n_rhs=n_rhs, extra={"peclet": peclet})
 
 
-def poisson3d_kuhn(n=64, p=2, n_levels=5, bisections=3, r=4, nu=2, n_rhs=1):
+def poisson3d_kuhn(n=64, p=2, n_levels=5, bisections=3, r=4, nu=2, n_rhs=1, log=None):
     m = meshes.kuhn_cube(n, 0.2, seed=0)
-    A = dg.assemble_sipg(m, p)
+    A = dg.assemble_sipg(m, p, log=log)
     prm = Params(n_levels, bisections, r, nu, nu, n_cut=n_cut_default(3))
     return _finish(f"poisson3d_p{p}_kuhn{n}", m, p, A, prm, "pcg", n_rhs=n_rhs)

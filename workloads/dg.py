@@ -61,6 +61,11 @@ def _face_points(fv, dim, nq):
     return x, 2.0 * w[None, :] * area[:, None]
 
 
+def _wgram(w, a, b):
+    """sum_q w[f,q] a[f,q,i] b[f,q,j] -> (f, i, j), as one batched product."""
+    return np.matmul(np.swapaxes(a * w[..., None], -1, -2), b)
+
+
 class _Geo:
     def __init__(self, mesh):
         self.J = mesh.jacobians()
@@ -71,11 +76,11 @@ class _Geo:
 
     def to_ref(self, elem, x):
         """Reference coordinates of physical points x (nf, q, d) in elements elem (nf,)."""
-        return np.einsum("fab,fqb->fqa", self.Jinv[elem], x - self.v0[elem][:, None, :])
+        return np.matmul(x - self.v0[elem][:, None, :], np.swapaxes(self.Jinv[elem], 1, 2))
 
     def phys_grad(self, elem, ghat):
         """Physical gradients from reference gradients ghat (nf, q, nb, d)."""
-        return np.einsum("fba,fqib->fqia", self.Jinv[elem], ghat)
+        return np.matmul(ghat, self.Jinv[elem][:, None, :, :])
 
 
 def face_pattern(mesh):
@@ -135,8 +140,9 @@ class BSR:
 # SIPG
 # ----------------------------------------------------------------------------
 
-def assemble_sipg(mesh, p, penalty=10.0, chunk=200_000):
-    """SIPG stiffness for -Laplace(u) = f, homogeneous Dirichlet on the boundary."""
+def assemble_sipg(mesh, p, penalty=10.0, chunk=200_000, log=None):
+    """SIPG stiffness for -Laplace(u) = f, homogeneous Dirichlet on the boundary.
+    log: optional callable given a progress message per chunk of faces."""
     dim = mesh.dim
     basis = SimplexBasis(dim, p)
     nb = basis.nb
@@ -152,12 +158,15 @@ def assemble_sipg(mesh, p, penalty=10.0, chunk=200_000):
     gh = basis.grad(xq)  # (q, nb, d)
     S = np.einsum("q,qia,qjb->abij", wq, gh, gh)
     Mt = np.einsum("eac,ebc->eab", geo.Jinv, geo.Jinv)  # J^-1 J^-T
-    vals[dpos] += np.abs(geo.detJ)[:, None, None] * np.einsum("eab,abij->eij", Mt, S)
+    d2 = dim * dim
+    vals[dpos] += np.abs(geo.detJ)[:, None, None] * (Mt.reshape(-1, d2) @ S.reshape(d2, -1)).reshape(-1, nb, nb)
 
     sig0 = penalty * p * p
     nqf = p + 1
     F = mesh.int_faces
     for s in range(0, len(F), chunk):
+        if log:
+            log(f"SIPG interior faces {s}/{len(F)}")
         f = F[s:s + chunk]
         ep, fp, em, fm = f[:, 0], f[:, 1], f[:, 2], f[:, 3]
         fv, n, meas = _face_geometry(mesh, ep, fp)
@@ -172,9 +181,9 @@ def assemble_sipg(mesh, p, penalty=10.0, chunk=200_000):
         sides = {"P": (vP, dnP, 1.0), "M": (vM, dnM, -1.0)}
         for sname, (vs, dns, cs) in sides.items():        # test side (rows)
             for tname, (vt, dnt, ct) in sides.items():    # trial side (cols)
-                blk = (-0.5 * cs * np.einsum("fq,fqj,fqi->fij", w, dnt, vs)
-                       - 0.5 * ct * np.einsum("fq,fqi,fqj->fij", w, dns, vt)
-                       + cs * ct * np.einsum("fq,f,fqi,fqj->fij", w, sig, vs, vt))
+                blk = (-0.5 * cs * _wgram(w, vs, dnt)
+                       - 0.5 * ct * _wgram(w, dns, vt)
+                       + cs * ct * sig[:, None, None] * _wgram(w, vs, vt))
                 vals_f[sname + tname] = blk
         vals[_block_positions(row_ptr, col_idx, ep, em)] = vals_f["PM"]
         vals[_block_positions(row_ptr, col_idx, em, ep)] = vals_f["MP"]
@@ -191,8 +200,7 @@ def assemble_sipg(mesh, p, penalty=10.0, chunk=200_000):
     sig = sig0 / (geo.vol[eb] / meas)
     v = basis.eval(geo.to_ref(eb, x))
     dn = np.einsum("fqid,fd->fqi", geo.phys_grad(eb, basis.grad(geo.to_ref(eb, x))), n)
-    blk = (-np.einsum("fq,fqj,fqi->fij", w, dn, v) - np.einsum("fq,fqi,fqj->fij", w, dn, v)
-           + np.einsum("fq,f,fqi,fqj->fij", w, sig, v, v))
+    blk = -_wgram(w, v, dn) - _wgram(w, dn, v) + sig[:, None, None] * _wgram(w, v, v)
     for lf in range(dim + 1):
         m = fb == lf
         vals[dpos[eb[m]]] += blk[m]
@@ -260,8 +268,8 @@ def assemble_ldg_upwind(mesh, p, beta, eps, penalty=10.0):
         wk = w[m] / absdet[ek][:, None]
         for a in range(dim):
             # tau_i = phi_i^{K'} e_a ; test row on K', trial on switch element / K'
-            b_s = np.einsum("fq,fqi,fqj->fij", wk * nk[:, a][:, None], vk_, vs_)
-            b_k = -np.einsum("fq,fqi,fqj->fij", wk * nk[:, a][:, None], vk_, vk_)
+            b_s = _wgram(wk * nk[:, a][:, None], vk_, vs_)
+            b_k = -_wgram(wk * nk[:, a][:, None], vk_, vk_)
             Gblocks[a].append((ek, es, b_s))
             Gblocks[a].append((ek, ek, b_k))
     B = mesh.bnd_faces
@@ -271,7 +279,7 @@ def assemble_ldg_upwind(mesh, p, beta, eps, penalty=10.0):
     vb = basis.eval(geo.to_ref(eb, xb))
     wkb = wb / absdet[eb][:, None]
     for a in range(dim):
-        b_k = -np.einsum("fq,fqi,fqj->fij", wkb * nb_[:, a][:, None], vb, vb)
+        b_k = -_wgram(wkb * nb_[:, a][:, None], vb, vb)
         Gblocks[a].append((eb, eb, b_k))
 
     def blocks_to_sparse(blist):
@@ -289,7 +297,7 @@ def assemble_ldg_upwind(mesh, p, beta, eps, penalty=10.0):
         Adiff = Adiff + (Ga.T @ Mdiag @ Ga)
     # boundary penalty (minimal dissipation: boundary faces only)
     sigb = penalty * p * p / (geo.vol[eb] / measb)
-    pen = np.einsum("fq,f,fqi,fqj->fij", wb, sigb, vb, vb)
+    pen = sigb[:, None, None] * _wgram(wb, vb, vb)
     Apen = blocks_to_sparse([(eb, eb, pen)])
 
     # upwind convection: -(u, beta.grad v)_K + <beta.n u_up, [v]>
@@ -303,12 +311,12 @@ def assemble_ldg_upwind(mesh, p, beta, eps, penalty=10.0):
         eu = ep[m] if up else em[m]
         vu = vP[m] if up else vM[m]
         fl = w[m] * bn[m][:, None]
-        cblocks.append((ep[m], eu, np.einsum("fq,fqi,fqj->fij", fl, vP[m], vu)))
-        cblocks.append((em[m], eu, -np.einsum("fq,fqi,fqj->fij", fl, vM[m], vu)))
+        cblocks.append((ep[m], eu, _wgram(fl, vP[m], vu)))
+        cblocks.append((em[m], eu, -_wgram(fl, vM[m], vu)))
     # boundary: outflow carries u, inflow carries 0
     bnb = nb_ @ beta
     out = bnb > 0
-    cblocks.append((eb[out], eb[out], np.einsum("fq,fqi,fqj->fij", wb[out] * bnb[out][:, None], vb[out], vb[out])))
+    cblocks.append((eb[out], eb[out], _wgram(wb[out] * bnb[out][:, None], vb[out], vb[out])))
     Aconv = blocks_to_sparse(cblocks)
 
     A = (eps * Adiff + eps * Apen + Aconv).tocsr()
