@@ -42,6 +42,18 @@ struct Bcsr {
 };
 constexpr int BCSR_MAXBR = 4;
 
+// Block-sparse matrix in its natural layout (row-major br x bc blocks, block
+// CSR rp/ci), read by the MFMA product of 16-column tiles (br, bc <= 16).
+template <typename T>
+struct Nbsr {
+    int32_t n_brow = 0, br = 0, bc = 0;
+    const int32_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    const T* vals = nullptr;
+};
+constexpr int MFMA_COLS = 16;
+constexpr int NBSR_MAXB = 16;
+
 // sweep modes
 enum SweepMode : int {
     SWEEP = 0,   // y = x + omega D^{-1} (b - A x)
@@ -70,6 +82,18 @@ hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, 
                          const int32_t* colmask, hipStream_t st);
 template <typename T>
 hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st);
+
+// MFMA products of 16-column tiles (m a multiple of 16, row-major n x m
+// vectors): one wavefront per block row computes the block row's br x 16 tile
+// of A x with 16x16x4 matrix instructions (FP32 or FP64 accumulation, the
+// type of T); then, by mode:
+//   MF_AX y = A x, MF_BMINUS y = b - A x, MF_BPLUS y = b + A x,
+//   MF_SWEEP y = x + omega D^{-1} (b - A x), MF_SWEEP0 y = omega D^{-1} b
+// with D^{-1} natural (n_brow x br x br, row-major), applied by MFMA too.
+enum MfmaMode : int { MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4 };
+template <typename T>
+hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
+                       hipStream_t st);
 
 // ---- setup ----
 // Fill the sliced values of type T from natural FP64 blocks: for slot q (one

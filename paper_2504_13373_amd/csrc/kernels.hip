@@ -498,6 +498,149 @@ template hipError_t launch_bspmv<double>(int, const Bcsr<double>&, const double*
 template hipError_t launch_bspmv<float>(int, const Bcsr<float>&, const float*, const float*, float*, int,
                                         hipStream_t);
 
+// ============================================================ MFMA tiles
+// Lane layout of the 16x16x4 matrix instructions (wave64), as measured on
+// gfx950: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it receives
+// D[4 (l / 16) + v][l % 16] (FP32) or D[l / 16 + 4 v][l % 16] (FP64), v = 0..3.
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc step(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct Mma<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc step(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+};
+
+// One wavefront per block row, one 16-column tile per blockIdx.y.  Block
+// (brow, col) contributes A_blk (br x bc, zero-padded to 16 x 4t) times the
+// x block rows col*bc .. col*bc + bc - 1 of the tile; lanes l / 16 = g take
+// k = 4t + g, so each step loads 16 consecutive x values per k.  The operand
+// fragments of up to four blocks are loaded before their products, and the
+// epilogue's b, x and D^{-1} fragments before the block loop, so that a
+// wavefront keeps several blocks' loads in flight.
+template <typename T, int MODE>
+__global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
+                                             const T* __restrict__ b, T* __restrict__ y, T omega, int ld) {
+    constexpr int U = 4;  // blocks per batch of loads
+    __shared__ T tile[WAVES_PER_WG][16][17];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int brow = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave);
+    if (brow >= A.n_brow) return;
+    const int i = lane & 15, g = lane >> 4;
+    const int br = A.br, bc = A.bc;
+    const int64_t col0 = int64_t(blockIdx.y) * MFMA_COLS + i;
+    const int64_t r0 = int64_t(brow) * br;
+    constexpr bool SW = (MODE == MF_SWEEP || MODE == MF_SWEEP0);
+    // epilogue operands first
+    T bpre[4], xpre[4], dpre[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = Mma<T>::row(g, v);
+        const int64_t e = (r0 + row) * ld + col0;
+        bpre[v] = (MODE != MF_AX && row < br) ? b[e] : T(0);
+        xpre[v] = (MODE == MF_SWEEP && row < br) ? x[e] : T(0);
+    }
+    if (SW) {
+        const T* __restrict__ Db = dinv + int64_t(brow) * br * br;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * t + g;
+            dpre[t] = (i < br && k < br) ? Db[i * br + k] : T(0);
+        }
+    }
+    typename Mma<T>::acc acc = {T(0), T(0), T(0), T(0)};
+    if (MODE != MF_SWEEP0) {
+        const int kt = (bc + 3) >> 2;
+        const int beg = A.rp[brow], end = A.rp[brow + 1];
+        for (int blk = beg; blk < end; blk += U) {
+            T av[U][4], xv[U][4];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool on = blk + u < end;
+                const int bq = on ? blk + u : blk;
+                const T* __restrict__ Ab = A.vals + int64_t(bq) * br * bc;
+                const T* __restrict__ Xb = x + int64_t(A.ci[bq]) * bc * ld + col0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 4 * t + g;
+                    av[u][t] = (on && t < kt && i < br && k < bc) ? Ab[i * bc + k] : T(0);
+                    xv[u][t] = (on && t < kt && k < bc) ? Xb[int64_t(k) * ld] : T(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (blk + u < end) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (t < kt) acc = Mma<T>::step(av[u][t], xv[u][t], acc);
+                }
+        }
+    }
+    if (!SW) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = Mma<T>::row(g, v);
+            if (row < br) {
+                T val = acc[v];
+                if (MODE == MF_BMINUS) val = bpre[v] - val;
+                if (MODE == MF_BPLUS) val = bpre[v] + val;
+                y[(r0 + row) * ld + col0] = val;
+            }
+        }
+        return;
+    }
+    // residual tile (rows >= br are zero) through LDS into the B operand of D^{-1} R
+    T(*tl)[17] = tile[wave];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = Mma<T>::row(g, v);
+        tl[row][i] = (row < br) ? ((MODE == MF_SWEEP) ? bpre[v] - acc[v] : bpre[v]) : T(0);
+    }
+    wave_lds_sync();
+    typename Mma<T>::acc acc2 = {T(0), T(0), T(0), T(0)};
+    const int kd = (br + 3) >> 2;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        if (t < kd) acc2 = Mma<T>::step(dpre[t], tl[4 * t + g][i], acc2);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = Mma<T>::row(g, v);
+        if (row < br) y[(r0 + row) * ld + col0] = xpre[v] + omega * acc2[v];
+    }
+}
+
+template <typename T>
+hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
+                       hipStream_t st) {
+    if (A.n_brow == 0) return hipSuccess;
+    if (m % MFMA_COLS != 0 || A.br > NBSR_MAXB || A.bc > NBSR_MAXB) return hipErrorInvalidValue;
+    dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
+    switch (mode) {
+        case MF_AX: hipLaunchKernelGGL((k_mfma<T, MF_AX>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_BMINUS: hipLaunchKernelGGL((k_mfma<T, MF_BMINUS>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_BPLUS: hipLaunchKernelGGL((k_mfma<T, MF_BPLUS>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_SWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_SWEEP0: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP0>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_mfma<float>(int, const Nbsr<float>&, const float*, const float*, const float*, float*,
+                                       float, int, hipStream_t);
+template hipError_t launch_mfma<double>(int, const Nbsr<double>&, const double*, const double*, const double*,
+                                        double*, double, int, hipStream_t);
+
 // ============================================================ layout conversion
 
 // one thread per (slot q, i, j): t = k*bc + j goes to
@@ -1290,12 +1433,17 @@ __global__ __launch_bounds__(WG) void k_dot_part2(const double* __restrict__ a, 
     block_partials<M>(s, part);
 }
 
-template <int M>
-__global__ __launch_bounds__(WG) void k_cg_update(double* __restrict__ x, const double* r_in, double* r_out,
-                                                  const double* __restrict__ p, const double* __restrict__ q,
-                                                  float* __restrict__ r32, int64_t n, int ld,
-                                                  const double* __restrict__ rz, const double* __restrict__ pq,
-                                                  const int32_t* __restrict__ active, double* part, int32_t* flag) {
+// The CG update of one grid-stride pass.  In place (INPLACE: the residual r_out
+// is read and written through one pointer, r_in unused) or out of place; every
+// pointer that is accessed is restrict, so the loads of a row's M columns are
+// not held behind the previous column's stores.
+template <int M, bool INPLACE>
+__device__ __forceinline__ void cg_update_body(double* __restrict__ x, const double* __restrict__ r_in,
+                                               double* __restrict__ r_out, const double* __restrict__ p,
+                                               const double* __restrict__ q, float* __restrict__ r32, int64_t n,
+                                               int ld, const double* __restrict__ rz, const double* __restrict__ pq,
+                                               const int32_t* __restrict__ active, double* __restrict__ part,
+                                               int32_t* __restrict__ flag) {
     double al[M], s[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
@@ -1312,13 +1460,21 @@ __global__ __launch_bounds__(WG) void k_cg_update(double* __restrict__ x, const 
         }
     }
     for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) {
+        const int64_t e0 = i * ld;
+        double xv[M], pv[M], rv[M], qv[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            const int64_t e = i * ld + c;
-            x[e] += al[c] * p[e];
-            const double v = r_in[e] - al[c] * q[e];
-            r_out[e] = v;
-            if (r32) r32[e] = float(v);
+            xv[c] = x[e0 + c];
+            pv[c] = p[e0 + c];
+            rv[c] = INPLACE ? r_out[e0 + c] : r_in[e0 + c];
+            qv[c] = q[e0 + c];
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            x[e0 + c] = xv[c] + al[c] * pv[c];
+            const double v = rv[c] - al[c] * qv[c];
+            r_out[e0 + c] = v;
+            if (r32) r32[e0 + c] = float(v);
             s[c] += v * v;
         }
     }
@@ -1326,25 +1482,46 @@ __global__ __launch_bounds__(WG) void k_cg_update(double* __restrict__ x, const 
 }
 
 template <int M>
-__global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, double* z, const double* __restrict__ r,
-                                              const double* __restrict__ r_old, int64_t n, int ld, double* part) {
+__global__ __launch_bounds__(WG) void k_cg_update_ip(double* x, double* r, const double* p, const double* q,
+                                                     float* r32, int64_t n, int ld, const double* rz,
+                                                     const double* pq, const int32_t* active, double* part,
+                                                     int32_t* flag) {
+    cg_update_body<M, true>(x, nullptr, r, p, q, r32, n, ld, rz, pq, active, part, flag);
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_cg_update_oop(double* x, const double* r_in, double* r_out, const double* p,
+                                                      const double* q, float* r32, int64_t n, int ld,
+                                                      const double* rz, const double* pq, const int32_t* active,
+                                                      double* part, int32_t* flag) {
+    cg_update_body<M, false>(x, r_in, r_out, p, q, r32, n, ld, rz, pq, active, part, flag);
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, double* __restrict__ z,
+                                              const double* __restrict__ r, const double* __restrict__ r_old,
+                                              int64_t n, int ld, double* __restrict__ part) {
     constexpr int M2 = 2 * M;
     double s[M2];
 #pragma unroll
     for (int c = 0; c < M2; ++c) s[c] = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) {
+        const int64_t e0 = i * ld;
+        double zv[M], rv[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            const int64_t e = i * ld + c;
-            double zv;
-            if (z32) {
-                zv = double(z32[e]);
-                z[e] = zv;
-            } else {
-                zv = z[e];
-            }
-            s[c] += r[e] * zv;
-            if (r_old) s[M + c] += zv * r_old[e];
+            zv[c] = z32 ? double(z32[e0 + c]) : z[e0 + c];
+            rv[c] = r[e0 + c];
+        }
+        if (z32) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) z[e0 + c] = zv[c];
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) s[c] += rv[c] * zv[c];
+        if (r_old) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) s[M + c] += zv[c] * r_old[e0 + c];
         }
     }
     block_partials<M2>(s, part);
@@ -1407,8 +1584,13 @@ hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const 
     (void)counter;
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
-        KRY_DISPATCH(w, k_cg_update, dim3(g), dim3(WG), 0, st, x + c0, r_in + c0, r_out + c0, p + c0, q + c0,
-                     r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag + c0);
+        if (r_in == r_out) {
+            KRY_DISPATCH(w, k_cg_update_ip, dim3(g), dim3(WG), 0, st, x + c0, r_out + c0, p + c0, q + c0,
+                         r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag + c0)
+        } else {
+            KRY_DISPATCH(w, k_cg_update_oop, dim3(g), dim3(WG), 0, st, x + c0, r_in + c0, r_out + c0, p + c0, q + c0,
+                         r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag + c0)
+        }
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), w, rr + c0, w,
                            static_cast<double*>(nullptr), flag + c0);
         return hipGetLastError();

@@ -139,8 +139,10 @@ def host_op(op, k, h, w, x, b, prec):
 
 @pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2"])
 @pytest.mark.parametrize("prec", [am.AMGDG_FP64, am.AMGDG_MIXED])
-@pytest.mark.parametrize("m", [1, 3, 5])
+@pytest.mark.parametrize("m", [1, 3, 5, 16, 32])
 def test_single_kernels(name, prec, m):
+    """Every single step on every level against the host product of the
+    exported operators; m = 16 and 32 take the MFMA tiles on sliced levels."""
     w, H, h = case(name)
     N = h.n_levels - 1
     g = np.random.default_rng(17 + m)
@@ -301,6 +303,44 @@ def test_multi_rhs_equals_single(method, prec):
         assert st1.iterations[0] == st.iterations[c]
         assert st1.rel_residual[0] == st.rel_residual[c]
         assert torch.equal(X[:, c].contiguous(), x), c
+
+
+@pytest.mark.parametrize("prec", [am.AMGDG_FP64, am.AMGDG_MIXED])
+def test_mfma_vcycle_matches_single_columns(prec):
+    """16 columns through the MFMA tiles give each column's V-cycle within
+    rounding of the single-column kernels."""
+    w, H, h = case("sipg3")
+    dt = torch.float64 if prec == am.AMGDG_FP64 else torch.float32
+    R = np.random.default_rng(41).standard_normal((w.A.n, 16))
+    Z = torch.zeros((w.A.n, 16), dtype=dt, device=DEV)
+    am.amgdg_vcycle(h, to_dev(R, dt), Z, precision=prec)
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == am.AMGDG_FP64 else 2e-5
+    for c in (0, 7, 15):
+        z = torch.zeros(w.A.n, dtype=dt, device=DEV)
+        am.amgdg_vcycle(h, to_dev(R[:, c], dt), z, precision=prec)
+        torch.cuda.synchronize()
+        assert rel(Z[:, c].double().cpu().numpy(), z.double().cpu().numpy()) <= tol, c
+
+
+def test_mfma_multi_rhs_solve():
+    """A 16-column solve (MFMA tiles) converges every column to the tolerance and
+    agrees with the single-column solves within it."""
+    w, H, h = case("sipg3")
+    A = w.A.to_scipy()
+    B = np.random.default_rng(43).standard_normal((w.A.n, 16))
+    for meth, prec in ((am.AMGDG_PCG, am.AMGDG_FP64), (am.AMGDG_FCG, am.AMGDG_MIXED)):
+        X = torch.zeros((w.A.n, 16), dtype=torch.float64, device=DEV)
+        rc, st = am.amgdg_solve(h, to_dev(B), X, meth, prec, 1e-9, 5000)
+        assert rc == am.AMGDG_OK and st.all_converged
+        Xh = X.cpu().numpy()
+        tr = np.linalg.norm(B - A @ Xh, axis=0) / np.linalg.norm(B, axis=0)
+        assert np.all(tr <= 1e-9), tr
+        for c in (0, 9):
+            x = torch.zeros(w.A.n, dtype=torch.float64, device=DEV)
+            rc1, st1 = am.amgdg_solve(h, to_dev(B[:, c]), x, meth, prec, 1e-9, 5000)
+            assert abs(st1.iterations[0] - st.iterations[c]) <= 2
+            assert rel(Xh[:, c], x.cpu().numpy()) <= 1e-6
 
 
 def test_stationary_solver_matches_oracle():
