@@ -1542,6 +1542,244 @@ __global__ __launch_bounds__(WG) void k_cg_dir(double* __restrict__ p, const dou
         }
 }
 
+// ---- coalesced forms (ld == M, M divides 64) ----
+// A wavefront handles the 64 consecutive rows that its threads own in the
+// per-row kernels (thread t: rows t + k * stride), in two sub-chunks of 32
+// rows.  Lane l updates the values j * 64 + l of the sub-chunk's 32 * M
+// contiguous values, all in column l % M, with coalesced accesses; the
+// operands of the sums go through LDS to the owner lane of each row, which adds
+// them in column order with the same multiply-adds as the per-row kernels.
+// Every partial sum, and so every result, is bit-identical to theirs.
+constexpr int CO_ROWS = 32;
+
+template <int M, bool INPLACE>
+__device__ __forceinline__ void cg_update_co_body(double* __restrict__ x, const double* __restrict__ r_in,
+                                                     double* __restrict__ r_out, const double* __restrict__ p,
+                                                     const double* __restrict__ q, float* __restrict__ r32,
+                                                     int64_t n, const double* __restrict__ rz,
+                                                     const double* __restrict__ pq,
+                                                     const int32_t* __restrict__ active, double* __restrict__ part,
+                                                     int32_t* __restrict__ flag) {
+    __shared__ double buf[WAVES_PER_WG][CO_ROWS][M + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cl = lane % M;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int c = 0; c < M; ++c)
+            if (active[c]) {
+                const double d = pq[c];
+                if (!(d > 0.0)) atomicOr(flag + c, 1);
+                if (!isfinite(rz[c] / d)) atomicOr(flag + c, 2);
+            }
+    }
+    double alc = 0.0;
+    if (active[cl]) {
+        alc = rz[cl] / pq[cl];
+        if (!isfinite(alc)) alc = 0.0;
+    }
+    double s[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) s[c] = 0.0;
+    constexpr int PER = (CO_ROWS * M + 63) / 64;
+    const int64_t stride = int64_t(gridDim.x) * WG;
+    for (int64_t row0 = int64_t(blockIdx.x) * WG + wv * 64; row0 < n; row0 += stride) {
+        for (int h = 0; h < 64 / CO_ROWS; ++h) {
+            const int64_t rb = row0 + CO_ROWS * h;
+            if (rb >= n) break;
+            const int64_t lim = min(n - rb, int64_t(CO_ROWS)) * M;
+            const int64_t base = rb * M;
+            // all loads first (index clamped into the sub-chunk), then the stores
+            double xv[PER], pv[PER], qv[PER], rv[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int el = j * 64 + lane;
+                const int64_t e = base + (el < lim ? el : 0);
+                xv[j] = x[e];
+                pv[j] = p[e];
+                qv[j] = q[e];
+                rv[j] = INPLACE ? r_out[e] : r_in[e];
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int el = j * 64 + lane;
+                if (el < lim) {
+                    const int64_t e = base + el;
+                    x[e] = xv[j] + alc * pv[j];
+                    const double v = rv[j] - alc * qv[j];
+                    r_out[e] = v;
+                    if (r32) r32[e] = float(v);
+                    buf[wv][el / M][el % M] = v;
+                }
+            }
+            wave_lds_sync();
+            const int ro = lane - CO_ROWS * h;
+            if (ro >= 0 && ro < CO_ROWS && rb + ro < n) {
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    const double v = buf[wv][ro][c];
+                    s[c] += v * v;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+    block_partials<M>(s, part);
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_cg_update_co_ip(double* x, double* r, const double* p, const double* q,
+                                                        float* r32, int64_t n, const double* rz, const double* pq,
+                                                        const int32_t* active, double* part, int32_t* flag) {
+    cg_update_co_body<M, true>(x, nullptr, r, p, q, r32, n, rz, pq, active, part, flag);
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_cg_update_co_oop(double* x, const double* r_in, double* r_out,
+                                                         const double* p, const double* q, float* r32, int64_t n,
+                                                         const double* rz, const double* pq, const int32_t* active,
+                                                         double* part, int32_t* flag) {
+    cg_update_co_body<M, false>(x, r_in, r_out, p, q, r32, n, rz, pq, active, part, flag);
+}
+
+// 16-row sub-chunks keep the LDS of the three-operand and two-operand sums small
+// enough for several workgroups per CU
+constexpr int ZR = 16;
+
+template <int M, bool Z32, bool ROLD>
+__device__ __forceinline__ void zdots_co_body(const float* __restrict__ z32, double* __restrict__ z,
+                                              const double* __restrict__ r, const double* __restrict__ r_old,
+                                              int64_t n, double* __restrict__ part) {
+    constexpr int M2 = 2 * M;
+    __shared__ double buf[WAVES_PER_WG][3][ZR][M + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double s[M2];
+#pragma unroll
+    for (int c = 0; c < M2; ++c) s[c] = 0.0;
+    constexpr int PER = (ZR * M + 63) / 64;
+    const int64_t stride = int64_t(gridDim.x) * WG;
+    for (int64_t row0 = int64_t(blockIdx.x) * WG + wv * 64; row0 < n; row0 += stride) {
+        for (int h = 0; h < 64 / ZR; ++h) {
+            const int64_t rb = row0 + ZR * h;
+            if (rb >= n) break;
+            const int64_t lim = min(n - rb, int64_t(ZR)) * M;
+            const int64_t base = rb * M;
+            double zv[PER], rv[PER], ov[PER];
+            float fz[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int el = j * 64 + lane;
+                const int64_t e = base + (el < lim ? el : 0);
+                if (Z32) fz[j] = z32[e];
+                else zv[j] = z[e];
+                rv[j] = r[e];
+                ov[j] = ROLD ? r_old[e] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                if (Z32) zv[j] = double(fz[j]);
+                const int el = j * 64 + lane;
+                if (el < lim) {
+                    if (Z32) z[base + el] = zv[j];
+                    buf[wv][0][el / M][el % M] = zv[j];
+                    buf[wv][1][el / M][el % M] = rv[j];
+                    buf[wv][2][el / M][el % M] = ov[j];
+                }
+            }
+            wave_lds_sync();
+            const int ro = lane - ZR * h;
+            if (ro >= 0 && ro < ZR && rb + ro < n) {
+#pragma unroll
+                for (int c = 0; c < M; ++c) s[c] += buf[wv][1][ro][c] * buf[wv][0][ro][c];
+                if (ROLD) {
+#pragma unroll
+                    for (int c = 0; c < M; ++c) s[M + c] += buf[wv][0][ro][c] * buf[wv][2][ro][c];
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+    block_partials<M2>(s, part);
+}
+
+#define ZDOTS_CO_KERNEL(NAME, Z, R)                                                                    \
+    template <int M>                                                                                 \
+    __global__ __launch_bounds__(WG) void NAME(const float* z32, double* z, const double* r,          \
+                                               const double* r_old, int64_t n, double* part) {        \
+        zdots_co_body<M, Z, R>(z32, z, r, r_old, n, part);                                           \
+    }
+ZDOTS_CO_KERNEL(k_zdots_co_ff, false, false)
+ZDOTS_CO_KERNEL(k_zdots_co_ft, false, true)
+ZDOTS_CO_KERNEL(k_zdots_co_tf, true, false)
+ZDOTS_CO_KERNEL(k_zdots_co_tt, true, true)
+#undef ZDOTS_CO_KERNEL
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_dot_co(const double* __restrict__ a, const double* __restrict__ b,
+                                               int64_t n, double* __restrict__ part) {
+    __shared__ double buf[WAVES_PER_WG][2][ZR][M + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double s[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) s[c] = 0.0;
+    constexpr int PER = (ZR * M + 63) / 64;
+    const int64_t stride = int64_t(gridDim.x) * WG;
+    for (int64_t row0 = int64_t(blockIdx.x) * WG + wv * 64; row0 < n; row0 += stride) {
+        for (int h = 0; h < 64 / ZR; ++h) {
+            const int64_t rb = row0 + ZR * h;
+            if (rb >= n) break;
+            const int64_t lim = min(n - rb, int64_t(ZR)) * M;
+            const int64_t base = rb * M;
+            double av[PER], bv[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int el = j * 64 + lane;
+                const int64_t e = base + (el < lim ? el : 0);
+                av[j] = a[e];
+                bv[j] = b[e];
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int el = j * 64 + lane;
+                if (el < lim) {
+                    buf[wv][0][el / M][el % M] = av[j];
+                    buf[wv][1][el / M][el % M] = bv[j];
+                }
+            }
+            wave_lds_sync();
+            const int ro = lane - ZR * h;
+            if (ro >= 0 && ro < ZR && rb + ro < n) {
+#pragma unroll
+                for (int c = 0; c < M; ++c) s[c] += buf[wv][0][ro][c] * buf[wv][1][ro][c];
+            }
+            wave_lds_sync();
+        }
+    }
+    block_partials<M>(s, part);
+}
+
+template <int M>
+__global__ __launch_bounds__(WG) void k_cg_dir_co(double* __restrict__ p, const double* __restrict__ z, int64_t n,
+                                                  const double* __restrict__ rzn, const double* __restrict__ zro,
+                                                  const double* __restrict__ rzo,
+                                                  const int32_t* __restrict__ active) {
+    const int cl = (threadIdx.x & 63) % M;
+    const double be = active[cl] ? (rzn[cl] - (zro ? zro[cl] : 0.0)) / rzo[cl] : 0.0;
+    const int64_t tot = n * M;
+    for (int64_t e = int64_t(blockIdx.x) * WG + threadIdx.x; e < tot; e += int64_t(gridDim.x) * WG)
+        p[e] = z[e] + be * p[e];
+}
+
+#define CO_DISPATCH(w, KERNEL, ...)                                                                    \
+    switch (w) {                                                                                     \
+        case 16: hipLaunchKernelGGL((KERNEL<16>), __VA_ARGS__); break;                                \
+        case 8: hipLaunchKernelGGL((KERNEL<8>), __VA_ARGS__); break;                                  \
+        case 4: hipLaunchKernelGGL((KERNEL<4>), __VA_ARGS__); break;                                  \
+        case 2: hipLaunchKernelGGL((KERNEL<2>), __VA_ARGS__); break;                                  \
+        default: hipLaunchKernelGGL((KERNEL<1>), __VA_ARGS__); break;                                 \
+    }
+
+// the coalesced forms apply when one chunk covers all m columns and m divides 64
+static inline bool co_ok(int m, int w) { return w == m && 64 % m == 0; }
+
 template <typename F>
 static hipError_t for_chunks(int m, F&& f) {
     int c0 = 0;
@@ -1570,7 +1808,11 @@ hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, d
     (void)counter;
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
-        KRY_DISPATCH(w, k_dot_part2, dim3(g), dim3(WG), 0, st, a + c0, b + c0, n, m, part);
+        if (co_ok(m, w)) {
+            CO_DISPATCH(w, k_dot_co, dim3(g), dim3(WG), 0, st, a, b, n, part)
+        } else {
+            KRY_DISPATCH(w, k_dot_part2, dim3(g), dim3(WG), 0, st, a + c0, b + c0, n, m, part)
+        }
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), w, out + c0, w,
                            static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr));
         return hipGetLastError();
@@ -1584,7 +1826,13 @@ hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const 
     (void)counter;
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
-        if (r_in == r_out) {
+        if (co_ok(m, w) && r_in == r_out) {
+            CO_DISPATCH(w, k_cg_update_co_ip, dim3(g), dim3(WG), 0, st, x, r_out, p, q, r32, n, rz, pq, active, part,
+                        flag)
+        } else if (co_ok(m, w)) {
+            CO_DISPATCH(w, k_cg_update_co_oop, dim3(g), dim3(WG), 0, st, x, r_in, r_out, p, q, r32, n, rz, pq, active,
+                        part, flag)
+        } else if (r_in == r_out) {
             KRY_DISPATCH(w, k_cg_update_ip, dim3(g), dim3(WG), 0, st, x + c0, r_out + c0, p + c0, q + c0,
                          r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag + c0)
         } else {
@@ -1602,8 +1850,15 @@ hipError_t launch_zdots(const float* z32, double* z, const double* r, const doub
     (void)counter;
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
-        KRY_DISPATCH(w, k_zdots, dim3(g), dim3(WG), 0, st, z32 ? z32 + c0 : nullptr, z + c0, r + c0,
-                     r_old ? r_old + c0 : nullptr, n, m, part);
+        if (co_ok(m, w)) {
+            if (z32 && r_old) CO_DISPATCH(w, k_zdots_co_tt, dim3(g), dim3(WG), 0, st, z32, z, r, r_old, n, part)
+            else if (z32) CO_DISPATCH(w, k_zdots_co_tf, dim3(g), dim3(WG), 0, st, z32, z, r, r_old, n, part)
+            else if (r_old) CO_DISPATCH(w, k_zdots_co_ft, dim3(g), dim3(WG), 0, st, z32, z, r, r_old, n, part)
+            else CO_DISPATCH(w, k_zdots_co_ff, dim3(g), dim3(WG), 0, st, z32, z, r, r_old, n, part)
+        } else {
+            KRY_DISPATCH(w, k_zdots, dim3(g), dim3(WG), 0, st, z32 ? z32 + c0 : nullptr, z + c0, r + c0,
+                         r_old ? r_old + c0 : nullptr, n, m, part)
+        }
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), r_old ? 2 * w : w, rz + c0, w,
                            zro ? zro + c0 : static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr));
         return hipGetLastError();
@@ -1614,8 +1869,12 @@ hipError_t launch_cg_dir(double* p, const double* z, int64_t n, int m, const dou
                          const double* rz_old, const int32_t* active, hipStream_t st) {
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
-        KRY_DISPATCH(w, k_cg_dir, dim3(g), dim3(WG), 0, st, p + c0, z + c0, n, m, rz_new + c0,
-                     zro ? zro + c0 : nullptr, rz_old + c0, active + c0);
+        if (co_ok(m, w)) {
+            CO_DISPATCH(w, k_cg_dir_co, dim3(g), dim3(WG), 0, st, p, z, n, rz_new, zro, rz_old, active)
+        } else {
+            KRY_DISPATCH(w, k_cg_dir, dim3(g), dim3(WG), 0, st, p + c0, z + c0, n, m, rz_new + c0,
+                         zro ? zro + c0 : nullptr, rz_old + c0, active + c0)
+        }
         return hipGetLastError();
     });
 }
