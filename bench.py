@@ -50,18 +50,24 @@ def sweep_bytes(info, w, m):
             + info.n_units * info.nb * info.nb * w + 3 * info.n * m * w)
 
 
+def sliced_kernels_sha256():
+    """sha256 of the source of the sliced-layout kernels (the section of
+    kernels.hip that holds the level-0 sweep), which the counters depend on."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2504_13373_amd", "csrc", "kernels.hip")).read()
+    a = src.index("// ============================================================ BSR kernels")
+    b = src.index("// ============================================================ block-CSR kernels")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernels.hip (else None)."""
-    import hashlib
+    summary, if it was taken on the current sliced kernels (else None)."""
     f = os.path.join(ROOT, "profiles", "sweep_level0_poisson2d_p3_256_traffic.txt")
-    src = os.path.join(ROOT, "paper_2504_13373_amd", "csrc", "kernels.hip")
     if not os.path.exists(f):
         return None
     kv = dict(l.strip().split("=", 1) for l in open(f) if "=" in l)
-    if kv.get("kernel") != kernel:
-        return None
-    if kv.get("kernels_hip_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if kv.get("kernel") != kernel or kv.get("sliced_kernels_sha256") != sliced_kernels_sha256():
         return None
     return float(kv["hbm_bytes"])
 
