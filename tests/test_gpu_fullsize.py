@@ -1,0 +1,160 @@
+"""Parity at the benchmark sizes, in the launch configurations bench.py times.
+
+* 2D Poisson SIPG p=3 on 256^2 jittered points (1,300,500 dofs) and 2D LDG +
+  upwind p=2 on 363^2 points (1,572,528 dofs, Peclet 100): the FP64 oracle is
+  set up at full size on the host, so setup, V-cycle and a prefix of the
+  Krylov iterations are compared with it directly.
+* 3D Poisson SIPG p=2 on 64^3 x 6 tetrahedra (15,728,640 dofs) with 16 columns:
+  too large for the oracle's setup in seconds, so sampled element rows of the
+  16-column MFMA products are checked against the caller's own matrix on the
+  host, and the 16-column V-cycle against the single-column one.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2504_13373_amd as am
+from oracle import amg, krylov, rcb
+from workloads import configs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+_C = {}
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dtype=dtype).contiguous()
+
+
+def case(name):
+    if name not in _C:
+        print(f"[gpu-fullsize] building {name}", flush=True)
+        if name == "poisson2d":
+            w = configs.poisson2d_delaunay(side=256)
+        else:
+            w = configs.convdiff2d_delaunay(side=363, peclet=100.0)
+        aggs, _ = rcb.rcb_hierarchy(w.centroids, w.params.n_levels, w.params.bisections)
+        H = amg.setup(w.A.to_scipy(), w.A.nb, aggs, w.params, w.B1)
+        h, _ = am.setup_from_workload(w, mixed=True)
+        print(f"[gpu-fullsize] {name}: {w.A.n} dofs, {h.n_levels} levels", flush=True)
+        _C[name] = (w, H, h)
+    return _C[name]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["poisson2d", "convdiff"])
+def test_fullsize_setup_and_vcycle(name):
+    w, H, h = case(name)
+    N = len(H.levels) - 1
+    assert h.n_levels == N + 1
+    for k in range(N):
+        info = am.amgdg_level_info_get(h, k)
+        L = H.levels[k]
+        assert info.n == L.A.shape[0] and info.s == L.s
+        assert abs(info.omega - L.omega) <= 1e-12 * L.omega, (k, info.omega, L.omega)
+        assert list(info.sweeps)[: L.B.shape[1]] == list(L.sweeps), k
+    A1 = sp.bsr_matrix((am.amgdg_export_level(h, 1, am.AMGDG_A_VALS), am.amgdg_export_level(h, 1, am.AMGDG_A_COLIDX),
+                        am.amgdg_export_level(h, 1, am.AMGDG_A_ROWPTR)), shape=H.levels[1].A.shape).tocsr()
+    assert sp.linalg.norm(A1 - H.levels[1].A) <= 1e-9 * sp.linalg.norm(H.levels[1].A)
+    r = np.random.default_rng(61).standard_normal(w.A.n)
+    zo = amg.vcycle(H, r)
+    z = torch.zeros(w.A.n, dtype=torch.float64, device=DEV)
+    am.amgdg_vcycle(h, to_dev(r), z)
+    z32 = torch.zeros(w.A.n, dtype=torch.float32, device=DEV)
+    am.amgdg_vcycle(h, to_dev(r, torch.float32), z32, precision=am.AMGDG_MIXED)
+    torch.cuda.synchronize()
+    assert rel(z.cpu().numpy(), zo) <= 1e-10
+    assert rel(z32.double().cpu().numpy(), zo) <= 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_pcg_prefix_matches_oracle():
+    """40 PCG iterations (capped) on the 1.3M-dof case: the iterate equals the
+    oracle's after the same 40 iterations."""
+    w, H, h = case("poisson2d")
+    A = w.A.to_scipy()
+    xo, ito, _ = krylov.pcg(A, w.b, lambda v: amg.vcycle(H, v), 1e-30, 40)
+    x = torch.zeros(w.A.n, dtype=torch.float64, device=DEV)
+    rc, st = am.amgdg_solve(h, to_dev(w.b), x, am.AMGDG_PCG, am.AMGDG_FP64, 1e-30, 40)
+    assert rc == am.AMGDG_ENOCONV and st.iterations[0] == 40 == ito
+    assert rel(x.cpu().numpy(), xo) <= 1e-9
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_fgmres_prefix_matches_oracle():
+    """FGMRES(30) capped at 45 iterations (one restart) on the 1.57M-dof
+    non-symmetric case, against the oracle's FGMRES."""
+    w, H, h = case("convdiff")
+    A = w.A.to_scipy()
+    xo, ito, _ = krylov.fgmres(A, w.b, lambda v: amg.vcycle(H, v), 1e-30, 30, 45)
+    x = torch.zeros(w.A.n, dtype=torch.float64, device=DEV)
+    rc, st = am.amgdg_solve(h, to_dev(w.b), x, am.AMGDG_FGMRES, am.AMGDG_FP64, 1e-30, 45, restart=30)
+    assert rc == am.AMGDG_ENOCONV and st.iterations[0] == 45 == ito
+    assert rel(x.cpu().numpy(), xo) <= 1e-8
+
+
+def _block_rows_product(Ab, elems, X, absolute=False):
+    """(A X), or (|A| |X|), restricted to the dofs of the element rows `elems`,
+    from the caller's BSR."""
+    nb = Ab.nb
+    out = np.zeros((len(elems), nb, X.shape[1]))
+    for t, e in enumerate(elems):
+        for j in range(Ab.row_ptr[e], Ab.row_ptr[e + 1]):
+            c = Ab.col_idx[j]
+            blk, xb = Ab.vals[j], X[c * nb:(c + 1) * nb]
+            out[t] += (np.abs(blk) @ np.abs(xb)) if absolute else (blk @ xb)
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_3d_mfma_products_and_vcycle():
+    print("[gpu-fullsize] building poisson3d 64^3 x 6, 16 columns", flush=True)
+    w = configs.poisson3d_kuhn(n=64, n_rhs=16)
+    h, _ = am.setup_from_workload(w, mixed=True)
+    n, nb, m = w.A.n, w.A.nb, 16
+    info = am.amgdg_level_info_get(h, 0)
+    g = np.random.default_rng(71)
+    X = g.standard_normal((n, m))
+    B = g.standard_normal((n, m))
+    elems = np.sort(g.choice(w.A.n_brow, 400, replace=False))
+    dofs = (elems[:, None] * nb + np.arange(nb)).ravel()
+    AX = _block_rows_product(w.A, elems, X).reshape(-1, m)
+    absAX = _block_rows_product(w.A, elems, X, absolute=True).reshape(-1, m)
+    Dinv = np.stack([np.linalg.inv(w.A.vals[w.A.row_ptr[e] + np.nonzero(
+        w.A.col_idx[w.A.row_ptr[e]:w.A.row_ptr[e + 1]] == e)[0][0]]) for e in elems])
+    for prec, dt, tol in ((am.AMGDG_FP64, torch.float64, 1e-12), (am.AMGDG_MIXED, torch.float32, 2e-5)):
+        Y = torch.zeros((n, m), dtype=dt, device=DEV)
+        am.amgdg_apply(h, 0, am.AMGDG_OP_SPMV, to_dev(X, dt), None, Y, precision=prec)
+        torch.cuda.synchronize()
+        err = np.abs(Y.double().cpu().numpy()[dofs] - AX).max() / np.abs(absAX).max()
+        assert err <= tol, (prec, err)
+        am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, to_dev(X, dt), to_dev(B, dt), Y, precision=prec)
+        torch.cuda.synchronize()
+        R = (B[dofs] - AX).reshape(len(elems), nb, m)
+        want = X[dofs] + info.omega * np.einsum("eij,ejc->eic", Dinv, R).reshape(-1, m)
+        scale = np.abs(X[dofs]).max() + info.omega * np.abs(Dinv).max() * nb * (np.abs(B).max() + np.abs(absAX).max())
+        err = np.abs(Y.double().cpu().numpy()[dofs] - want).max() / scale
+        assert err <= tol, (prec, err)
+        del Y
+    # 16-column V-cycle (MFMA level 0) against single-column V-cycles
+    Z = torch.zeros((n, m), dtype=torch.float64, device=DEV)
+    Bd = to_dev(B)
+    am.amgdg_vcycle(h, Bd, Z)
+    for c in (0, 11):
+        z = torch.zeros(n, dtype=torch.float64, device=DEV)
+        am.amgdg_vcycle(h, Bd[:, c].contiguous(), z)
+        torch.cuda.synchronize()
+        assert rel(Z[:, c].cpu().numpy(), z.cpu().numpy()) <= 1e-12, c
+    # a capped 16-column mixed solve: every column's true residual falls and stays finite
+    Xs = torch.zeros((n, m), dtype=torch.float64, device=DEV)
+    rc, st = am.amgdg_solve(h, to_dev(w.b), Xs, am.AMGDG_FCG, am.AMGDG_MIXED, 1e-30, 30)
+    assert rc == am.AMGDG_ENOCONV and st.max_iterations == 30
+    relres = np.array(list(st.rel_residual)[:m])
+    assert np.all(np.isfinite(relres)) and np.all(relres < 1.0), relres
+    h.close()
