@@ -51,12 +51,13 @@ def sweep_bytes(info, w, m):
 
 
 def sliced_kernels_sha256():
-    """sha256 of the source of the sliced-layout kernels (the section of
-    kernels.hip that holds the level-0 sweep), which the counters depend on."""
+    """sha256 of the device code of the sliced-layout kernels (sell_row,
+    k_sweep, k_spmv: the level-0 sweep the counters measure), up to their
+    host-side launchers."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2504_13373_amd", "csrc", "kernels.hip")).read()
     a = src.index("// ============================================================ BSR kernels")
-    b = src.index("// ============================================================ block-CSR kernels")
+    b = src.index("template <typename T, int M>\nstatic hipError_t sweep_m")
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
@@ -78,9 +79,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rhs", type=int, default=1, help="right-hand sides per solve")
-    ap.add_argument("--workload", choices=["poisson2d", "convdiff", "poisson3d"], default="poisson2d",
+    ap.add_argument("--workload", choices=["poisson2d", "convdiff", "poisson3d", "serving"], default="poisson2d",
                     help="poisson2d: the headline workload; convdiff: LDG convection-diffusion Peclet sweep "
-                         "with FGMRES(30); poisson3d: 3D tetrahedra, 16 right-hand sides")
+                         "with FGMRES(30); poisson3d: 3D tetrahedra, 16 right-hand sides; serving: a Poisson "
+                         "stream of solve requests over a catalogue of operators")
+    ap.add_argument("--catalogue", type=int, default=32, help="serving: operator instances")
+    ap.add_argument("--t-max", type=float, default=2e5, help="serving: largest triangle count")
+    ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals counted")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="serving: seconds of arrivals not counted")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: HBM budget of the request state")
     ap.add_argument("--side", type=int, default=None,
                     help="grid points per side (2D; defaults 256 / 363) or cells per side (3D; default 64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,6 +101,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate in requests/s (0: all requests arrive at once)")
     ap.add_argument("--skip-fp64", action="store_true", help="poisson3d: time the mixed path only")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes (no amgdg_autotune before timing)")
+    ap.add_argument("--tune-lanes", action="store_true",
+                    help="let the autotuner also pick the block-CSR lane widths (changes rounding)")
     ap.add_argument("--max-it", type=int, default=50000,
                     help="iteration cap per solve (profiling runs cap it; the reported value needs convergence)")
     args = ap.parse_args()
@@ -113,6 +124,8 @@ def main():
         return bench_convdiff(args, am, torch, dev)
     if args.workload == "poisson3d":
         return bench_poisson3d(args, am, torch, dev)
+    if args.workload == "serving":
+        return bench_serving_stream(args, am, torch, dev)
     args.side = args.side or 256
     log(f"generating workload (side {args.side})")
     t0 = time.perf_counter()
@@ -127,6 +140,7 @@ def main():
     log(f"setup {setup_s:.2f} s; levels n = {[i.n for i in infos]}, omega = {[round(i.omega, 4) for i in infos[:-1]]}")
 
     m = args.rhs
+    tuning = _autotune(args, am, torch, h, m)
     b = torch.as_tensor(w.b.reshape(w.A.n, m) if m > 1 else w.b).to(dev).contiguous()
     x = torch.zeros_like(b)
     maxit = args.max_it
@@ -267,10 +281,28 @@ def main():
         },
         "vcycle": {name: {"ms": v["ms"], "GBps": v["gbps"], "frac": v["gbps"] / HBM_PEAK_GBS} for name, v in vc.items()},
         "setup_s": setup_s,
+        "autotune": tuning,
         "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _autotune(args, am, torch, h, m):
+    """amgdg_autotune for m columns unless disabled: launch shapes that leave
+    every result unchanged, plus the block-CSR lane widths with --tune-lanes;
+    returns the shapes chosen per level and the seconds spent."""
+    if args.no_autotune:
+        return None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    am.amgdg_autotune(h, m, am.AMGDG_TUNE_LANES if args.tune_lanes else 0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    shapes = [am.amgdg_tuning_get(h, k, m) for k in range(h.n_levels - 1)]
+    log(f"autotune ({dt:.2f} s): " + "; ".join(
+        f"L{k} lanes {t['lanes']} cols32 {t['cols32']} mfma32 {t['mfma32']}" for k, t in enumerate(shapes)))
+    return {"seconds": dt, "levels": shapes}
 
 
 def _contract(args, metric_value, ms, dtype, workload, extra):
@@ -331,9 +363,10 @@ def bench_convdiff(args, am, torch, dev):
         infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
         log(f"convdiff Pe {pe:g}: {w.mesh.n_elem} triangles, {w.A.n} dofs, {w.A.nnzb} blocks; setup {setup_s:.2f} s; "
             f"levels n = {[i.n for i in infos]}")
+        tuning = _autotune(args, am, torch, h, 1)
         b = torch.as_tensor(w.b).to(dev).contiguous()
         x = torch.zeros_like(b)
-        res = {"setup_s": setup_s, "levels_n": [i.n for i in infos]}
+        res = {"setup_s": setup_s, "levels_n": [i.n for i in infos], "autotune": tuning}
         for name, prec in (("fp64", am.AMGDG_FP64), ("mixed", am.AMGDG_MIXED)):
             rc, st, t = _timed_solves(am, torch, h, b, x, am.AMGDG_FGMRES, prec, maxit, args.steps)
             xh = x.cpu().numpy()
@@ -371,6 +404,7 @@ def bench_poisson3d(args, am, torch, dev):
     infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
     log(f"poisson3d: setup {setup_s:.2f} s; levels n = {[i.n for i in infos]}, "
         f"omega = {[round(i.omega, 4) for i in infos[:-1]]}")
+    tuning = _autotune(args, am, torch, h, m)
     b = torch.as_tensor(w.b).to(dev).contiguous()
     w.b = None
     x = torch.zeros_like(b)
@@ -424,7 +458,105 @@ def bench_poisson3d(args, am, torch, dev):
     _contract(args, mx["solves_per_s"], mx["seconds"] * 1e3, "f32 V-cycle + f64 Krylov",
               f"3D Poisson SIPG p=2 on {cells}^3 x 6 jittered Kuhn tetrahedra ({infos[0].n_units} tets, "
               f"{infos[0].n} dofs), 5-level RCB hierarchy, r=4, V(2,2), {m} RHS per solve, tol 1e-8",
-              {"solves": res, "kernels_m16": vc, "setup_s": setup_s, "levels_n": [i.n for i in infos]})
+              {"solves": res, "kernels_m16": vc, "setup_s": setup_s, "levels_n": [i.n for i in infos],
+               "autotune": tuning})
+
+
+def bench_serving_stream(args, am, torch, dev):
+    """Serving stream: a catalogue of operator instances (2D jittered Delaunay
+    meshes, 1k-200k triangles, p = 1..4, SIPG-Poisson or LDG-upwind
+    convection-diffusion) with hierarchies resident on the device; solve
+    requests arrive as a Poisson process (exponential gaps, seed 4), each a
+    uniform pick from the catalogue with a fresh right-hand side (seed 10000 +
+    request).  SIPG requests run flexible CG, LDG requests FGMRES(30), both
+    with the FP32 V-cycle, to 1e-8.  Requests arriving in the warm-up window
+    are served but not counted."""
+    from workloads import configs
+    log(f"serving: generating {args.catalogue} operators (up to {args.t_max:g} triangles)")
+    cat = configs.serving_catalogue(n_ops=args.catalogue, t_max=args.t_max, log=log)
+    handles, setup_s = [], []
+    for w in cat:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, _ = am.setup_from_workload(w, mixed=True)
+        torch.cuda.synchronize()
+        setup_s.append(time.perf_counter() - t0)
+        handles.append(h)
+    log(f"serving: {len(cat)} hierarchies set up, {sum(setup_s):.1f} s in total")
+    rate = args.serve_rate if args.serve_rate > 0 else 20.0
+    horizon = args.serve_warmup + args.serve_duration
+    rng = np.random.default_rng(4)
+    t_arr, picks = [], []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > horizon:
+            break
+        t_arr.append(t)
+        picks.append(int(rng.integers(0, len(cat))))
+    n_req = len(t_arr)
+    srv = am.Server(width=args.serve_width, hbm_budget_bytes=int(args.budget_gb * (1 << 30)))
+    maxit = min(args.max_it, 20000)
+    out = {}
+    keep = {}
+    stream = torch.cuda.current_stream()
+    nxt = 0
+    log(f"serving: {n_req} requests at {rate:g}/s over {horizon:g} s")
+    t0 = time.perf_counter()
+    last_log = t0
+    while len(out) < n_req:
+        now = time.perf_counter() - t0
+        while nxt < n_req and t_arr[nxt] <= now:
+            w = cat[picks[nxt]]
+            g = np.random.default_rng(10000 + nxt)
+            bh = g.standard_normal(w.A.n) if w.krylov == "pcg" else g.uniform(-1.0, 1.0, w.A.n)
+            b = torch.as_tensor(bh).to(dev)
+            x = torch.zeros_like(b)
+            stream.synchronize()
+            meth = am.AMGDG_FCG if w.krylov == "pcg" else am.AMGDG_FGMRES
+            srv.submit(handles[picks[nxt]], b, x, meth, am.AMGDG_MIXED, 1e-8, maxit, restart=30, tag=nxt)
+            keep[nxt] = (b, x)
+            nxt += 1
+        srv.step(wait=nxt == n_req)
+        for tag, status, its, relres, lat in srv.poll(256):
+            out[tag] = (status, its, relres, lat)
+            keep.pop(tag, None)
+        if time.perf_counter() - last_log > 10.0:
+            last_log = time.perf_counter()
+            log(f"serving: t = {last_log - t0:.0f} s, {nxt} submitted, {len(out)} done")
+    makespan = time.perf_counter() - t0
+    srv.close()
+    counted = [i for i in range(n_req) if t_arr[i] >= args.serve_warmup]
+    lat = np.array([out[i][3] for i in counted])
+    done_in = [i for i in counted if t_arr[i] + out[i][3] <= horizon]
+    conv = sum(1 for i in counted if out[i][0] == am.AMGDG_OK)
+    by_kind = {}
+    for kind in ("pcg", "gmres"):
+        ids = [i for i in counted if cat[picks[i]].krylov == kind]
+        if ids:
+            by_kind["sipg_fcg" if kind == "pcg" else "ldg_fgmres"] = {
+                "requests": len(ids), "mean_iterations": float(np.mean([out[i][1] for i in ids])),
+                "p50_latency_s": float(np.percentile([out[i][3] for i in ids], 50)),
+                "p99_latency_s": float(np.percentile([out[i][3] for i in ids], 99))}
+    res = {
+        "catalogue": [{"name": w.name, "dofs": w.A.n, "levels": w.params.n_levels, "setup_s": st}
+                      for w, st in zip(cat, setup_s)],
+        "arrival_rate_per_s": rate, "warmup_s": args.serve_warmup, "duration_s": args.serve_duration,
+        "requests_counted": len(counted), "converged": conv,
+        "completed_per_s": len(done_in) / args.serve_duration,
+        "throughput_solves_per_s": n_req / makespan, "makespan_s": makespan,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "by_kind": by_kind, "batch_width": args.serve_width, "budget_gb": args.budget_gb,
+    }
+    for hnd in handles:
+        hnd.close()
+    log(f"serving: {len(counted)} counted requests, {conv} converged, p50 {res['p50_latency_s']:.3f} s, "
+        f"p99 {res['p99_latency_s']:.3f} s, {n_req / makespan:.1f} solves/s over {makespan:.1f} s")
+    _contract(args, res["throughput_solves_per_s"], 1e3 / max(res["throughput_solves_per_s"], 1e-12),
+              "f32 V-cycle + f64 Krylov",
+              f"serving stream: {len(cat)} operators (2D jittered Delaunay, up to {args.t_max:g} triangles, p=1..4, "
+              f"SIPG flexible CG / LDG-upwind FGMRES(30)), Poisson arrivals at {rate:g}/s, tol 1e-8",
+              {"serving": res})
 
 
 def serve_bench(am, h, n, dev, n_req, width, rate, maxit):

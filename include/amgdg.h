@@ -280,6 +280,29 @@ int amgdg_server_poll(amgdg_server s, int32_t capacity, int64_t* tags, int32_t* 
 /* Waits for the server's streams and frees its batches. */
 int amgdg_server_destroy(amgdg_server s);
 
+/* Autotuner: picks the launch shapes for m columns (1..64) by timing the
+ * candidates on this hierarchy's operators (HIP events on `stream`):
+ *   - columns per launch of the sliced and block-CSR kernels (1, 2, 4, 8, 16);
+ *   - operand blocks loaded ahead in the 16-column MFMA tiles (1, 2, 4);
+ *   - with AMGDG_TUNE_LANES, the lanes per block row of every block-CSR
+ *     operator (4..64, timed at one column).
+ * The first two never change a result.  The lane-group width changes the
+ * summation order, hence rounding, of the block-CSR products: it can be tuned
+ * once per handle (AMGDG_EINVAL on a second attempt), before use, and then
+ * holds for every column count, so columns stay independent of m.  Drops the
+ * handle's captured V-cycles; not to be called while a server uses the
+ * handle.  Untuned shapes: 4 (FP64) / 8 (FP32) columns per sliced launch, 16
+ * per block-CSR launch, 4 MFMA blocks ahead, and lanes per block row the power
+ * of two >= the mean blocks per row (4..64). */
+#define AMGDG_TUNE_LANES 1
+int amgdg_autotune(amgdg_handle h, int32_t m, int32_t flags, void* stream);
+/* The shapes in use on level k (0..levels-2) for m columns, out[16]:
+ * [0..3) lanes per block row of A_k, T_k, R_k (0: sliced layout);
+ * [3..6) FP64 and [6..9) FP32 columns per launch (0: default rule);
+ * [9..12) FP64 and [12..15) FP32 MFMA blocks loaded ahead (0: default 4);
+ * [15] 1 if the lane widths were tuned. */
+int amgdg_tuning_get(amgdg_handle h, int32_t k, int32_t m, int32_t* out);
+
 /* Message for the last non-zero status returned on the calling thread. */
 const char* amgdg_last_error(void);
 

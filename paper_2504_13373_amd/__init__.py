@@ -27,6 +27,7 @@ AMGDG_B_RELAXED, AMGDG_B_INPUT, AMGDG_PTILDE, AMGDG_SVALS = 14, 15, 16, 17
 AMGDG_FP64, AMGDG_MIXED = 0, 1
 AMGDG_STATIONARY, AMGDG_PCG, AMGDG_FCG, AMGDG_FGMRES = 0, 1, 2, 3
 AMGDG_X0, AMGDG_INTERNAL_ORDER, AMGDG_EAGER = 1, 2, 4
+AMGDG_TUNE_LANES = 1
 (AMGDG_OP_SPMV, AMGDG_OP_SWEEP, AMGDG_OP_SWEEP0, AMGDG_OP_RESIDUAL, AMGDG_OP_RESTRICT,
  AMGDG_OP_PROLONG, AMGDG_OP_COARSE) = range(7)
 
@@ -87,6 +88,8 @@ _SIGS = {
     "amgdg_server_step": (_I32, [_P, _I32, ctypes.POINTER(_I64)]),
     "amgdg_server_poll": (_I32, [_P, _I32, _P, _P, _P, _P, _P, ctypes.POINTER(_I32)]),
     "amgdg_server_destroy": (_I32, [_P]),
+    "amgdg_autotune": (_I32, [_P, _I32, _I32, _P]),
+    "amgdg_tuning_get": (_I32, [_P, _I32, _I32, _P]),
 }
 
 
@@ -288,6 +291,21 @@ def amgdg_vcycle(handle, r, z, precision=AMGDG_FP64, flags=0, stream=None):
 def amgdg_apply(handle, k, op, x, b, y, precision=AMGDG_FP64, flags=0, stream=None):
     m = 1 if y.dim() == 1 else y.shape[1]
     _check(lib().amgdg_apply(handle.h, k, op, m, precision, _dptr(x), _dptr(b), _dptr(y), flags, _stream(stream)))
+
+
+def amgdg_autotune(handle, m=1, flags=0, stream=None):
+    _check(lib().amgdg_autotune(handle.h, m, flags, _stream(stream)))
+
+
+def amgdg_tuning_get(handle, k, m=1):
+    """dict of the launch shapes in use on level k for m columns."""
+    import numpy as np
+    out = np.zeros(16, np.int32)
+    _check(lib().amgdg_tuning_get(handle.h, k, m, _ptr(out)))
+    names = ("A", "T", "R")
+    return {"lanes": dict(zip(names, out[0:3].tolist())), "cols64": dict(zip(names, out[3:6].tolist())),
+            "cols32": dict(zip(names, out[6:9].tolist())), "mfma64": dict(zip(names, out[9:12].tolist())),
+            "mfma32": dict(zip(names, out[12:15].tolist())), "lanes_tuned": bool(out[15])}
 
 
 def amgdg_batch_bytes(handle, width, restart=0):

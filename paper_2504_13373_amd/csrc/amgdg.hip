@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -98,6 +99,10 @@ struct MatStore {
     Nbsr<double> nd;  // natural layout of a sliced matrix, for 16-column MFMA tiles
     Nbsr<float> nf;
     int64_t n_vals = 0;
+    // tuned launch shapes per column count (0: the default rule): columns per
+    // launch, and blocks loaded ahead in the MFMA tiles (per m / 16)
+    std::array<int8_t, 65> cap64{}, cap32{};
+    std::array<int8_t, 5> mfu64{}, mfu32{};
 };
 
 template <typename T>
@@ -201,6 +206,7 @@ struct Ctx {
     double* scal = nullptr;     // device scalars of the setup
     int32_t* flag = nullptr;
     bool mixed = false;
+    bool lanes_tuned = false;   // lane-group widths fixed by the autotuner
     std::unique_ptr<Work> W0;   // state of the blocking entry points
     ~Ctx() {
         (void)hipDeviceSynchronize();
@@ -425,24 +431,34 @@ template <typename T>
 static bool use_mfma(const MatStore& M, int m) {
     return !M.vec && m % MFMA_COLS == 0 && nsel<T>(M).vals != nullptr;
 }
+template <typename T>
+static int cap_of(const MatStore& M, int m) {
+    return m <= 64 ? (sizeof(T) == 8 ? M.cap64[m] : M.cap32[m]) : 0;
+}
+template <typename T>
+static int mfu_of(const MatStore& M, int m) {
+    return m / MFMA_COLS <= 4 ? (sizeof(T) == 8 ? M.mfu64[m / MFMA_COLS] : M.mfu32[m / MFMA_COLS]) : 0;
+}
 
 template <typename T>
 static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, int m, hipStream_t st) {
-    if (M.vec) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st));
+    if (M.vec) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m)));
     else if (use_mfma<T>(M, m))
         HIPCHK(launch_mfma<T>(mode == AX ? MF_AX : mode == B_MINUS ? MF_BMINUS : MF_BPLUS, nsel<T>(M), nullptr, x, b,
-                              y, T(0), m, st));
-    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st));
+                              y, T(0), m, st, mfu_of<T>(M, m)));
+    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st, cap_of<T>(M, m)));
 }
 
 template <typename T>
 static void mat_sweep(int mode, const Level& L, const T* x, const T* b, T* y, T omega, int m, const int32_t* mask,
                       hipStream_t st) {
-    if (L.A.vec) HIPCHK(launch_bsweep<T>(mode, bsel<T>(L.A), dinv_of<T>(L), x, b, y, omega, m, mask, st));
+    if (L.A.vec)
+        HIPCHK(launch_bsweep<T>(mode, bsel<T>(L.A), dinv_of<T>(L), x, b, y, omega, m, mask, st, cap_of<T>(L.A, m)));
     else if ((mode == SWEEP || mode == SWEEP0) && use_mfma<T>(L.A, m) && dinv_nat_of<T>(L))
         HIPCHK(launch_mfma<T>(mode == SWEEP ? MF_SWEEP : MF_SWEEP0, nsel<T>(L.A), dinv_nat_of<T>(L), x, b, y, omega, m,
-                              st));
-    else HIPCHK(launch_sweep<T>(mode, sel<T>(L.A.s), dinv_of<T>(L), x, b, y, omega, m, mask, st));
+                              st, mfu_of<T>(L.A, m)));
+    else
+        HIPCHK(launch_sweep<T>(mode, sel<T>(L.A.s), dinv_of<T>(L), x, b, y, omega, m, mask, st, cap_of<T>(L.A, m)));
 }
 
 
@@ -1781,6 +1797,115 @@ struct Server {
     }
 };
 
+// ------------------------------------------------------------ autotuner
+
+// Picks launch shapes for m columns by timing the candidates on the
+// hierarchy's own operators (HIP events on the handle's vectors: A_k in its
+// sweep, T_k and R_k in their products):
+//   - columns per launch of the sliced and block-CSR kernels (1, 2, 4, 8(, 16));
+//   - blocks loaded ahead in the MFMA tiles (1, 2, 4) when m is a multiple of 16;
+//   - with `lanes`, the lanes per block row of every block-CSR operator
+//     (4 .. 64, timed at one column), once per handle.
+// The first two leave every column's arithmetic unchanged; the lane-group
+// width changes the summation order (hence rounding) and is therefore chosen
+// once, before use, and then applies to every column count.
+static void autotune_impl(Ctx& C, int m, bool lanes, hipStream_t st) {
+    if (C.N == 0) return;
+    if (m < 1 || m > 64) throw Error(AMGDG_EUNSUPPORTED, "m must be 1..64");
+    if (lanes && C.lanes_tuned) throw Error(AMGDG_EINVAL, "lane-group widths are already tuned for this handle");
+    Work& W = default_work(C, std::max(m, 1), 0, st);
+    W.drop_graphs();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    // average time of `launch`: one warm-up, then repetitions spanning at least
+    // about 0.2 ms (3 .. 200 launches), so that small coarse-level kernels are
+    // timed above the event resolution
+    auto timed = [&](auto&& launch) {
+        launch();
+        HIPCHK(hipEventRecord(e0, st));
+        launch();
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float one = 0.f;
+        HIPCHK(hipEventElapsedTime(&one, e0, e1));
+        const int reps = std::max(3, std::min(200, int(0.2f / std::max(one, 1e-4f))));
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) launch();
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        return ms / float(reps);
+    };
+    for (int k = 0; k < C.N; ++k) {
+        Level& L = C.lv[k];
+        struct Op {
+            MatStore* M;
+            int kin, kout;
+        } ops[3] = {{&L.A, k, k}, {&L.T, k + 1, k}, {&L.R, k, k + 1}};
+        for (Op& o : ops) {
+            MatStore& M = *o.M;
+            // A_k is timed in its block-Jacobi sweep (2 nu of them per level and
+            // cycle), T_k and R_k in their products
+            auto run = [&](auto tag, int cols) {
+                using T = decltype(tag);
+                VBuf<T>& vin = vbuf<T>(W, o.kin);
+                VBuf<T>& vout = vbuf<T>(W, o.kout);
+                if (o.M == &L.A) mat_sweep<T>(SWEEP, L, vin.u, vin.b, vout.w, T(L.omega), cols, nullptr, st);
+                else mat_spmv<T>(AX, M, vin.u, nullptr, vout.w, cols, st);
+            };
+            auto tune_type = [&](auto tag) {
+                using T = decltype(tag);
+                if (sizeof(T) == 4 && !C.mixed) return;
+                auto& cap = sizeof(T) == 8 ? M.cap64 : M.cap32;
+                auto& mfu = sizeof(T) == 8 ? M.mfu64 : M.mfu32;
+                if (use_mfma<T>(M, m)) {
+                    int best = 0;
+                    float bt = 0.f;
+                    for (int u : {1, 2, 4}) {
+                        mfu[m / MFMA_COLS] = int8_t(u);
+                        const float t = timed([&] { run(tag, m); });
+                        if (best == 0 || t < bt) best = u, bt = t;
+                    }
+                    mfu[m / MFMA_COLS] = int8_t(best);
+                } else if (m > 1) {
+                    int best = 0;
+                    float bt = 0.f;
+                    for (int c : {1, 2, 4, 8, 16}) {
+                        if (!M.vec && c == 16) continue;
+                        cap[m] = int8_t(c);
+                        const float t = timed([&] { run(tag, m); });
+                        if (best == 0 || t < bt) best = c, bt = t;
+                    }
+                    cap[m] = int8_t(best);
+                }
+            };
+            if (lanes && M.vec) {
+                int best = 0;
+                float bt = 0.f;
+                for (int P : {4, 8, 16, 32, 64}) {
+                    M.bd.P = M.bf.P = P;
+                    const float t = C.mixed ? timed([&] { run(0.0f, 1); }) : timed([&] { run(0.0, 1); });
+                    if (best == 0 || t < bt) best = P, bt = t;
+                }
+                M.bd.P = M.bf.P = best;
+            }
+            tune_type(0.0);
+            tune_type(0.0f);
+        }
+    }
+    if (lanes) C.lanes_tuned = true;
+    HIPCHK(hipStreamSynchronize(st));
+}
+
 // ------------------------------------------------------------ single steps
 
 template <typename T>
@@ -2325,6 +2450,36 @@ int amgdg_server_poll(amgdg_server s, int32_t capacity, int64_t* tags, int32_t* 
 int amgdg_server_destroy(amgdg_server s) {
     ABI_BEGIN
     delete s;
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_autotune(amgdg_handle h, int32_t m, int32_t flags, void* stream) {
+    ABI_BEGIN
+    if (!h) throw Error(AMGDG_EINVAL, "NULL handle");
+    if (flags & ~AMGDG_TUNE_LANES) throw Error(AMGDG_EINVAL, "bad flags");
+    autotune_impl(h->c, m, (flags & AMGDG_TUNE_LANES) != 0, hipStream_t(stream));
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_tuning_get(amgdg_handle h, int32_t k, int32_t m, int32_t* out) {
+    ABI_BEGIN
+    if (!h || !out) throw Error(AMGDG_EINVAL, "NULL argument");
+    Ctx& C = h->c;
+    if (k < 0 || k >= C.N) throw Error(AMGDG_EINVAL, "bad level (no transfer operators on the coarsest level)");
+    if (m < 1 || m > 64) throw Error(AMGDG_EUNSUPPORTED, "m must be 1..64");
+    const Level& L = C.lv[k];
+    const MatStore* ms[3] = {&L.A, &L.T, &L.R};
+    for (int i = 0; i < 3; ++i) {
+        const MatStore& M = *ms[i];
+        out[i] = M.vec ? M.bd.P : 0;
+        out[3 + i] = M.cap64[m];
+        out[6 + i] = M.cap32[m];
+        out[9 + i] = m / MFMA_COLS <= 4 ? M.mfu64[m / MFMA_COLS] : 0;
+        out[12 + i] = m / MFMA_COLS <= 4 ? M.mfu32[m / MFMA_COLS] : 0;
+    }
+    out[15] = C.lanes_tuned ? 1 : 0;
     return AMGDG_OK;
     ABI_END
 }

@@ -71,17 +71,21 @@ enum SpmvMode : int {
 // D^{-1} in sliced layout: the br x br block of block row g is stored like a
 // one-slot slice with its columns padded to brpad (a multiple of VW):
 // value (i, j) at dinv[s * brpad * L + (j / VW) * L * VW + (g * br + i) * VW + j % VW].
+// `cap` bounds the columns processed per launch (1, 2, 4, 8; 0: 4 FP64 / 8 FP32);
+// it does not change the arithmetic of any column.
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
-                        int m, const int32_t* colmask, hipStream_t st);
+                        int m, const int32_t* colmask, hipStream_t st, int cap = 0);
 template <typename T>
-hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st);
-// the same operations on a block-CSR matrix; dinv: natural layout (n_brow x br x br)
+hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap = 0);
+// the same operations on a block-CSR matrix; dinv: natural layout (n_brow x br x br);
+// cap: 1, 2, 4, 8 or 16 columns per launch (0: 16)
 template <typename T>
 hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                         const int32_t* colmask, hipStream_t st);
+                         const int32_t* colmask, hipStream_t st, int cap = 0);
 template <typename T>
-hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st);
+hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st,
+                        int cap = 0);
 
 // MFMA products of 16-column tiles (m a multiple of 16, row-major n x m
 // vectors): one wavefront per block row computes the block row's br x 16 tile
@@ -91,9 +95,11 @@ hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y
 //   MF_SWEEP y = x + omega D^{-1} (b - A x), MF_SWEEP0 y = omega D^{-1} b
 // with D^{-1} natural (n_brow x br x br, row-major), applied by MFMA too.
 enum MfmaMode : int { MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4 };
+// u: blocks whose operand fragments are loaded before their products (1, 2 or 4;
+// 0: 4); it does not change the arithmetic.
 template <typename T>
 hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                       hipStream_t st);
+                       hipStream_t st, int u = 0);
 
 // ---- setup ----
 // Fill the sliced values of type T from natural FP64 blocks: for slot q (one

@@ -214,21 +214,23 @@ static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* 
 // Columns are processed in chunks (each a separate launch): the LDS staging
 // buffers grow with the chunk width, so it is capped at 4 (FP64) / 8 (FP32).
 // and kept within 64 KB of LDS per workgroup.
+// `want` (1, 2, 4 or 8; 0: the default 4 FP64 / 8 FP32) bounds the chunk width; the
+// chunk width does not change the arithmetic of any column.
 template <typename T>
-static int sell_chunk(int rem, const Sell<T>& A, bool with_dinv) {
-    int cap = sizeof(T) == 8 ? 4 : 8;
+static int sell_chunk(int rem, const Sell<T>& A, bool with_dinv, int want) {
+    int cap = want > 0 ? want : (sizeof(T) == 8 ? 4 : 8);
     const size_t per_col = size_t(WAVES_PER_WG) * A.G * (A.tpad + (with_dinv ? A.brpad : 0)) * sizeof(T);
     while (cap > 1 && per_col * cap > 65536) cap = cap == 8 ? 4 : cap - 1;
     const int w = rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
-    return w <= cap ? w : cap;
+    return w <= cap ? w : (cap >= 4 ? 4 : cap >= 2 ? 2 : 1);
 }
 
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                        const int32_t* colmask, hipStream_t st) {
+                        const int32_t* colmask, hipStream_t st, int cap) {
     int c0 = 0;
     while (c0 < m) {
-        const int w = sell_chunk<T>(m - c0, A, true);
+        const int w = sell_chunk<T>(m - c0, A, true, cap);
         if (size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * w * sizeof(T) > 65536) return hipErrorInvalidConfiguration;
         const T* xc = x ? x + c0 : nullptr;
         const T* bc = b ? b + c0 : nullptr;
@@ -248,10 +250,10 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
 }
 
 template <typename T>
-hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st) {
+hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap) {
     int c0 = 0;
     while (c0 < m) {
-        const int w = sell_chunk<T>(m - c0, A, false);
+        const int w = sell_chunk<T>(m - c0, A, false, cap);
         if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(T) > 65536) return hipErrorInvalidConfiguration;
         const T* bc = b ? b + c0 : nullptr;
         hipError_t e;
@@ -269,13 +271,13 @@ hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y,
 }
 
 template hipError_t launch_sweep<double>(int, const Sell<double>&, const double*, const double*, const double*,
-                                         double*, double, int, const int32_t*, hipStream_t);
+                                         double*, double, int, const int32_t*, hipStream_t, int);
 template hipError_t launch_sweep<float>(int, const Sell<float>&, const float*, const float*, const float*, float*,
-                                        float, int, const int32_t*, hipStream_t);
+                                        float, int, const int32_t*, hipStream_t, int);
 template hipError_t launch_spmv<double>(int, const Sell<double>&, const double*, const double*, double*, int,
-                                        hipStream_t);
+                                        hipStream_t, int);
 template hipError_t launch_spmv<float>(int, const Sell<float>&, const float*, const float*, float*, int,
-                                       hipStream_t);
+                                       hipStream_t, int);
 
 // ============================================================ block-CSR kernels (small blocks)
 
@@ -442,13 +444,21 @@ static hipError_t bspmv_m(int mode, const Bcsr<T>& A, const T* x, const T* b, T*
     }
 }
 
+// chunk width of the block-CSR kernels: up to 16 columns per launch, bounded
+// by `cap` (1, 2, 4, 8 or 16; 0: 16); it does not change any column's arithmetic
+static int bcsr_chunk(int rem, int cap) {
+    const int c = cap > 0 ? cap : 16;
+    int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+    while (w > c) w = w == 16 ? 8 : w == 8 ? 4 : w >= 4 ? 2 : 1;
+    return w;
+}
+
 template <typename T>
 hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                         const int32_t* colmask, hipStream_t st) {
+                         const int32_t* colmask, hipStream_t st, int cap) {
     int c0 = 0;
     while (c0 < m) {
-        const int rem = m - c0;
-        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const int w = bcsr_chunk(m - c0, cap);
         const T* xc = x ? x + c0 : nullptr;
         const T* bc = b ? b + c0 : nullptr;
         const int32_t* mc = colmask ? colmask + c0 : nullptr;
@@ -468,11 +478,10 @@ hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, 
 }
 
 template <typename T>
-hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st) {
+hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap) {
     int c0 = 0;
     while (c0 < m) {
-        const int rem = m - c0;
-        const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
+        const int w = bcsr_chunk(m - c0, cap);
         const T* bc = b ? b + c0 : nullptr;
         hipError_t e;
         switch (w) {
@@ -490,13 +499,13 @@ hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y
 }
 
 template hipError_t launch_bsweep<double>(int, const Bcsr<double>&, const double*, const double*, const double*,
-                                          double*, double, int, const int32_t*, hipStream_t);
+                                          double*, double, int, const int32_t*, hipStream_t, int);
 template hipError_t launch_bsweep<float>(int, const Bcsr<float>&, const float*, const float*, const float*, float*,
-                                         float, int, const int32_t*, hipStream_t);
+                                         float, int, const int32_t*, hipStream_t, int);
 template hipError_t launch_bspmv<double>(int, const Bcsr<double>&, const double*, const double*, double*, int,
-                                         hipStream_t);
+                                         hipStream_t, int);
 template hipError_t launch_bspmv<float>(int, const Bcsr<float>&, const float*, const float*, float*, int,
-                                        hipStream_t);
+                                        hipStream_t, int);
 
 // ============================================================ MFMA tiles
 // Lane layout of the 16x16x4 matrix instructions (wave64), as measured on
@@ -526,13 +535,12 @@ struct Mma<double> {
 // (brow, col) contributes A_blk (br x bc, zero-padded to 16 x 4t) times the
 // x block rows col*bc .. col*bc + bc - 1 of the tile; lanes l / 16 = g take
 // k = 4t + g, so each step loads 16 consecutive x values per k.  The operand
-// fragments of up to four blocks are loaded before their products, and the
+// fragments of up to U blocks are loaded before their products, and the
 // epilogue's b, x and D^{-1} fragments before the block loop, so that a
 // wavefront keeps several blocks' loads in flight.
-template <typename T, int MODE>
+template <typename T, int MODE, int U>
 __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                              const T* __restrict__ b, T* __restrict__ y, T omega, int ld) {
-    constexpr int U = 4;  // blocks per batch of loads
     __shared__ T tile[WAVES_PER_WG][16][17];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int brow = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave);
@@ -620,26 +628,36 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
     }
 }
 
-template <typename T>
-hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                       hipStream_t st) {
-    if (A.n_brow == 0) return hipSuccess;
-    if (m % MFMA_COLS != 0 || A.br > NBSR_MAXB || A.bc > NBSR_MAXB) return hipErrorInvalidValue;
+template <typename T, int U>
+static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
+                         hipStream_t st) {
     dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
     switch (mode) {
-        case MF_AX: hipLaunchKernelGGL((k_mfma<T, MF_AX>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_BMINUS: hipLaunchKernelGGL((k_mfma<T, MF_BMINUS>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_BPLUS: hipLaunchKernelGGL((k_mfma<T, MF_BPLUS>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_SWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_SWEEP0: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP0>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_AX: hipLaunchKernelGGL((k_mfma<T, MF_AX, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_BMINUS: hipLaunchKernelGGL((k_mfma<T, MF_BMINUS, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_BPLUS: hipLaunchKernelGGL((k_mfma<T, MF_BPLUS, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_SWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_SWEEP0: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP0, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
+                       hipStream_t st, int u) {
+    if (A.n_brow == 0) return hipSuccess;
+    if (m % MFMA_COLS != 0 || A.br > NBSR_MAXB || A.bc > NBSR_MAXB) return hipErrorInvalidValue;
+    switch (u) {
+        case 1: return mfma_u<T, 1>(mode, A, dinv, x, b, y, omega, m, st);
+        case 2: return mfma_u<T, 2>(mode, A, dinv, x, b, y, omega, m, st);
+        default: return mfma_u<T, 4>(mode, A, dinv, x, b, y, omega, m, st);
+    }
+}
 template hipError_t launch_mfma<float>(int, const Nbsr<float>&, const float*, const float*, const float*, float*,
-                                       float, int, hipStream_t);
+                                       float, int, hipStream_t, int);
 template hipError_t launch_mfma<double>(int, const Nbsr<double>&, const double*, const double*, const double*,
-                                        double*, double, int, hipStream_t);
+                                        double*, double, int, hipStream_t, int);
 
 // ============================================================ layout conversion
 

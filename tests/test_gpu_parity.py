@@ -424,3 +424,52 @@ def test_graph_solve_equals_eager_solve():
         assert rc1 == rc2 == am.AMGDG_OK
         assert st1.iterations[0] == st2.iterations[0]
         assert torch.equal(x1, x2)
+
+
+# ------------------------------------------------------------------ autotuner
+
+def test_autotune_shapes_keep_results_and_lanes_keep_columns_independent():
+    """Tuning columns per launch and MFMA load batching leaves results bit for
+    bit unchanged; after tuning the lane-group widths too, the V-cycle still
+    matches the oracle and columns stay bit-identical to single-column solves."""
+    w = configs.poisson2d_delaunay(side=33, p=3, n_levels=4, r=3)
+    aggs, _ = rcb.rcb_hierarchy(w.centroids, w.params.n_levels, w.params.bisections)
+    H = amg.setup(w.A.to_scipy(), w.A.nb, aggs, w.params, w.B1)
+    h, _ = am.setup_from_workload(w, mixed=True)
+    B = np.random.default_rng(91).standard_normal((w.A.n, 5))
+    R16 = np.random.default_rng(92).standard_normal((w.A.n, 16))
+
+    def runs():
+        X = torch.zeros((w.A.n, 5), dtype=torch.float64, device=DEV)
+        am.amgdg_solve(h, to_dev(B), X, am.AMGDG_FCG, am.AMGDG_MIXED, 1e-8, 5000)
+        Z = torch.zeros((w.A.n, 16), dtype=torch.float32, device=DEV)
+        am.amgdg_vcycle(h, to_dev(R16, torch.float32), Z, precision=am.AMGDG_MIXED)
+        torch.cuda.synchronize()
+        return X.cpu(), Z.cpu()
+
+    X0, Z0 = runs()
+    for m in (5, 16):
+        am.amgdg_autotune(h, m)
+    X1, Z1 = runs()
+    assert torch.equal(X0, X1) and torch.equal(Z0, Z1)
+    t = am.amgdg_tuning_get(h, 0, 16)
+    assert t["mfma32"]["A"] in (1, 2, 4) and not t["lanes_tuned"]
+    am.amgdg_autotune(h, 1, am.AMGDG_TUNE_LANES)
+    t = am.amgdg_tuning_get(h, 1, 1)
+    assert t["lanes_tuned"] and t["lanes"]["A"] in (4, 8, 16, 32, 64)
+    with pytest.raises(am.AmgdgError) as e:
+        am.amgdg_autotune(h, 1, am.AMGDG_TUNE_LANES)
+    assert e.value.code == am.AMGDG_EINVAL
+    b = np.random.default_rng(93).standard_normal(w.A.n)
+    z = torch.zeros(w.A.n, dtype=torch.float64, device=DEV)
+    am.amgdg_vcycle(h, to_dev(b), z)
+    torch.cuda.synchronize()
+    assert rel(z.cpu().numpy(), amg.vcycle(H, b)) <= 1e-10
+    X = torch.zeros((w.A.n, 5), dtype=torch.float64, device=DEV)
+    rc, st = am.amgdg_solve(h, to_dev(B), X, am.AMGDG_PCG, am.AMGDG_FP64, 1e-8, 5000)
+    for c in (0, 3):
+        x = torch.zeros(w.A.n, dtype=torch.float64, device=DEV)
+        rc1, st1 = am.amgdg_solve(h, to_dev(B[:, c]), x, am.AMGDG_PCG, am.AMGDG_FP64, 1e-8, 5000)
+        assert st1.iterations[0] == st.iterations[c]
+        assert torch.equal(X[:, c].contiguous(), x)
+    h.close()

@@ -211,3 +211,30 @@ def test_server_rejects_bad_requests():
     with pytest.raises(am.AmgdgError) as e:
         am.Server(width=65, hbm_budget_bytes=1 << 30)
     assert e.value.code == am.AMGDG_EUNSUPPORTED
+
+
+def test_server_catalogue_mix():
+    """Requests over a catalogue of operators of different sizes and orders
+    (SIPG with flexible CG, LDG-upwind with FGMRES(30), FP32 V-cycle), all in
+    flight together: each equals its solo solve bit for bit."""
+    cat = configs.serving_catalogue(n_ops=6, t_min=300, t_max=3000, seed=5)
+    hs = [am.setup_from_workload(w, mixed=True)[0] for w in cat]
+    jobs = []
+    for i in range(12):
+        k = i % len(cat)
+        w = cat[k]
+        g = np.random.default_rng(2000 + i)
+        b = torch.as_tensor(g.standard_normal(w.A.n) if w.krylov == "pcg" else g.uniform(-1, 1, w.A.n)).to(DEV)
+        meth = am.AMGDG_FCG if w.krylov == "pcg" else am.AMGDG_FGMRES
+        jobs.append((hs[k], b, meth, alone(hs[k], b, meth, am.AMGDG_MIXED, 1e-8, 4000)))
+    assert {j[2] for j in jobs} == {am.AMGDG_FCG, am.AMGDG_FGMRES}
+    X = [torch.zeros_like(j[1]) for j in jobs]
+    srv = am.Server(width=3, hbm_budget_bytes=1 << 40)
+    subs = [(lambda i=i: srv.submit(jobs[i][0], jobs[i][1], X[i], jobs[i][2], am.AMGDG_MIXED, 1e-8, 4000, tag=i))
+            for i in range(12)]
+    out = run_server(srv, [subs[:5], subs[5:9], subs[9:]], steps_between=3)
+    srv.close()
+    for i in range(12):
+        check_equal(out[i], jobs[i][3], X[i], i)
+    for h in hs:
+        h.close()

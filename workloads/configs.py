@@ -12,8 +12,13 @@ right-hand side 1, B^1 2.  Sizes follow the benchmark configurations:
 * ``poisson3d_p2_64``  : 64^3 jittered Kuhn cube, SIPG p=2
                          (1,572,864 tetrahedra, 15,728,640 dofs)
 
+* ``serving_catalogue``: the operator instances of the serving stream (2D
+                         jittered Delaunay meshes of 1k-200k triangles, p = 1..4,
+                         SIPG-Poisson or LDG + upwind convection-diffusion)
+
 Scaled-down variants (same recipe, fewer elements) are used by the tests.
 """
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -105,3 +110,49 @@ def poisson3d_kuhn(n=64, p=2, n_levels=5, bisections=3, r=4, nu=2, n_rhs=1, log=
     A = dg.assemble_sipg(m, p, log=log)
     prm = Params(n_levels, bisections, r, nu, nu, n_cut=n_cut_default(3))
     return _finish(f"poisson3d_p{p}_kuhn{n}", m, p, A, prm, "pcg", n_rhs=n_rhs)
+
+
+def levels_for_coarsest(n_elem, bisections=2, r=3, max_coarse=2048):
+    """Fewest levels whose coarsest level has at most max_coarse dofs: level k
+    holds 2^(D - k*bisections) aggregates (D = ceil(log2 n_elem)) of r dofs."""
+    D = max(1, math.ceil(math.log2(max(n_elem, 2))))
+    N = 1
+    while D - N * bisections > 0 and (2 ** (D - N * bisections)) * r > max_coarse:
+        N += 1
+    return N + 1
+
+
+def serving_catalogue(n_ops=32, t_min=1e3, t_max=2e5, seed=0, log=None):
+    """Operator instances of the serving stream.  Per instance i (parameters
+    from one generator seeded `seed`): triangle count T log-uniform in
+    [t_min, t_max] (grid side round(sqrt(T/2)) + 1, mesh seed i), p uniform in
+    {1, 2, 3, 4}, and with probability 1/2 each SIPG-Poisson (PCG, N(0,1)
+    right-hand sides) or LDG + upwind convection-diffusion with Peclet number
+    log-uniform in [1, 1e4] (FGMRES, U(-1, 1) right-hand sides).  r = 3,
+    V(3,3), levels chosen so that the coarsest level has at most 2,048 dofs.
+    Aggregation is 4-way per level for p >= 2 and 8-way for p = 1 (as in the
+    16x16 p=1 workload): a level-1 aggregate then holds at least 12 dofs, so
+    every aggregate keeps s = r = 3 coarse dofs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    beta = np.array([np.cos(0.3), np.sin(0.3)])
+    for i in range(n_ops):
+        T = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
+        side = int(round(math.sqrt(T / 2.0))) + 1
+        p = int(rng.integers(1, 5))
+        sipg = bool(rng.random() < 0.5)
+        pe = float(10.0 ** rng.uniform(0.0, 4.0))
+        m = meshes.jittered_delaunay(side, 0.25, seed=i)
+        bis = 3 if p == 1 else 2
+        prm = Params(levels_for_coarsest(m.n_elem, bis), bis, 3, 3, 3, n_cut=n_cut_default(2))
+        if sipg:
+            A = dg.assemble_sipg(m, p)
+            w = _finish(f"serve{i}_sipg_p{p}_{m.n_elem}", m, p, A, prm, "pcg")
+        else:
+            A = dg.assemble_ldg_upwind(m, p, beta, 1.0 / pe)
+            w = _finish(f"serve{i}_ldg_p{p}_{m.n_elem}_pe{pe:.3g}", m, p, A, prm, "gmres", rhs_kind="uniform",
+                        extra={"peclet": pe})
+        if log:
+            log(f"catalogue {i}: {w.name}, {A.n} dofs, {prm.n_levels} levels")
+        out.append(w)
+    return out
