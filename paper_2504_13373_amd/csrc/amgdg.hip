@@ -1160,7 +1160,7 @@ struct CgBatch : Engine {
         if (mixed) vcycle_run<float>(*C, *W, W->kr32, W->kz32, m, st, W->use_graph);
         else if (!flexible) vcycle_run<double>(*C, *W, r, W->kz, m, st, W->use_graph);  // r, z fixed buffers
         else precond_fp64(*C, *W, r, W->kz, m, st);
-        HIPCHK(launch_zdots(mixed ? W->kz32 : nullptr, W->kz, r, r_old, n, m, W->kpart, nullptr, rz_out, zro, st));
+        HIPCHK(launch_zdots(mixed ? W->kz32 : nullptr, W->kz, r, r_old, n, m, W->kpart, rz_out, zro, st));
     }
 
     // uploads mask region `off` from the pinned mirror if it differs from `last`
@@ -1184,7 +1184,7 @@ struct CgBatch : Engine {
                                     W->kx, r, W->kp, W->kq, m, c, flags_d, st));
                 any_x0 = any_x0 || q.x0;
             }
-            HIPCHK(launch_dot_tail(W->kb, W->kb, n, m, W->kpart, nullptr, W->stat + ST_BN, st));
+            HIPCHK(launch_dot_tail(W->kb, W->kb, n, m, W->kpart, W->stat + ST_BN, st));
             if (any_x0) {
                 // r = b - A x0 for the admitted columns with an initial guess
                 for (int c = 0; c < m; ++c) W->mask_h[MASK_ADM + c] = 0;
@@ -1193,7 +1193,7 @@ struct CgBatch : Engine {
                                       hipMemcpyHostToDevice, st));
                 mat_spmv<double>(B_MINUS, L.A, W->kx, W->kb, W->kt, m, st);
                 HIPCHK(launch_copy_cols(W->kt, r, n, m, W->mask + MASK_ADM, st));
-                HIPCHK(launch_dot_tail(r, r, n, m, W->kpart, nullptr, W->stat + ST_R0, st));
+                HIPCHK(launch_dot_tail(r, r, n, m, W->kpart, W->stat + ST_R0, st));
             }
             for (int c : pending) {
                 col[c].state = STARTING;
@@ -1207,7 +1207,7 @@ struct CgBatch : Engine {
         }
         upload_mask(MASK_UPD, last_upd);
         HIPCHK(launch_cg_update(W->kx, r, flexible ? rn : r, W->kp, W->kq, mixed ? W->kr32 : nullptr, n, m, d_rz, d_pq,
-                                W->mask + MASK_UPD, W->kpart, nullptr, W->stat + ST_RR, flags_d, st));
+                                W->mask + MASK_UPD, W->kpart, W->stat + ST_RR, flags_d, st));
         if (flexible) std::swap(r, rn);  // r: new residual, rn: previous
         HIPCHK(hipMemcpyAsync(W->stat_h, W->stat, sizeof(double) * ST_TR, hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(W->ev, st));
@@ -1270,7 +1270,7 @@ struct CgBatch : Engine {
             if (need_true) {
                 const int64_t n = C->lv[0].n;
                 mat_spmv<double>(B_MINUS, C->lv[0].A, W->kx, W->kb, W->kt, m, st);
-                HIPCHK(launch_dot_tail(W->kt, W->kt, n, m, W->kpart, nullptr, W->stat + ST_TR, st));
+                HIPCHK(launch_dot_tail(W->kt, W->kt, n, m, W->kpart, W->stat + ST_TR, st));
                 HIPCHK(hipMemcpyAsync(W->stat_h + ST_TR, W->stat + ST_TR, sizeof(double) * m, hipMemcpyDeviceToHost,
                                       st));
                 HIPCHK(hipEventRecord(W->ev, st));
@@ -1335,7 +1335,7 @@ struct CgBatch : Engine {
             HIPCHK(launch_cg_dir(W->kp, W->kz, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz, W->mask + MASK_DIR, st));
             std::swap(d_rz, d_rz2);
             mat_spmv<double>(AX, C->lv[0].A, W->kp, nullptr, W->kq, m, st);
-            HIPCHK(launch_dot_tail(W->kp, W->kq, n, m, W->kpart, nullptr, d_pq, st));
+            HIPCHK(launch_dot_tail(W->kp, W->kq, n, m, W->kpart, d_pq, st));
         }
         issue();
     }

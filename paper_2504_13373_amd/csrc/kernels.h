@@ -113,7 +113,6 @@ template <typename T>
 hipError_t launch_dinv_to_sell(const double* dinv_nat, int64_t n_brow, int br, int G, int L, int brpad, T* dinv_sell,
                                hipStream_t st);
 hipError_t launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st);
-hipError_t launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st);
 hipError_t launch_block_inverse(const double* Avals, const int32_t* diag_pos, int64_t n_brow, int nb, double* dinv,
                                 int32_t* flag, hipStream_t st);
 hipError_t launch_svd(const double* B, int r, const int32_t* first_child, int64_t n_agg, int nb, int s,
@@ -149,26 +148,21 @@ hipError_t launch_dot(const T* a, const T* b, int64_t n, int m, double* part, do
 // y[i,c] = a*x[i,c] + by*y[i,c] with per-column device scalars (alpha[c] * sa)
 hipError_t launch_axpby_dev(const double* x, double* y, int64_t n, int m, const double* alpha, double sa,
                             double by, hipStream_t st);
-// CG updates: x += alpha p ; r -= alpha q  (per column alpha)
-hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const double* p, const double* q, int64_t n,
-                        int m, const double* alpha, hipStream_t st);
 // ---- fused Krylov steps (deterministic: each workgroup writes partial sums,
-// a one-workgroup finalize kernel adds them in a fixed order; `counter` is
-// unused and kept for the call signature) ----
+// a one-workgroup finalize kernel adds them in a fixed order) ----
 constexpr int KRY_BLOCKS = 2048;
-// out[c] = sum_i a[i,c] b[i,c]   (part: KRY_BLOCKS * m doubles, counter: 1 uint)
-hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, unsigned* counter,
-                           double* out, hipStream_t st);
+// out[c] = sum_i a[i,c] b[i,c]   (part: 2 * 16 * KRY_BLOCKS doubles)
+hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, double* out,
+                           hipStream_t st);
 // CG update of m columns: alpha = active ? rz / pq : 0 (flag[c] |= 1 if an active pq <= 0,
 // 2 if alpha or rr[c] is not finite); x += alpha p; r_out = r_in - alpha q; r32 = float(r_out)
 // if r32 != NULL; rr[c] = ||r_out[:,c]||^2.  flag holds one int32 per column.
 hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const double* p, const double* q,
                             float* r32, int64_t n, int m, const double* rz, const double* pq,
-                            const int32_t* active, double* part, unsigned* counter, double* rr, int32_t* flag,
-                            hipStream_t st);
+                            const int32_t* active, double* part, double* rr, int32_t* flag, hipStream_t st);
 // z = double(z32) if z32 != NULL; rz[c] = r.z ; zro[c] = z.r_old if r_old != NULL
 hipError_t launch_zdots(const float* z32, double* z, const double* r, const double* r_old, int64_t n, int m,
-                        double* part, unsigned* counter, double* rz, double* zro, hipStream_t st);
+                        double* part, double* rz, double* zro, hipStream_t st);
 // p = z + beta p, beta = active ? (rz_new - zro) / rz_old : 0  (zro may be NULL)
 hipError_t launch_cg_dir(double* p, const double* z, int64_t n, int m, const double* rz_new, const double* zro,
                          const double* rz_old, const int32_t* active, hipStream_t st);
@@ -185,14 +179,6 @@ hipError_t launch_scatter_col(const double* in, int64_t ldi, double* out, int64_
                               int64_t n_units, int nb, hipStream_t st);
 // dst[i,c] = src[i,c] for the columns c with mask[c] != 0
 hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, const int32_t* mask, hipStream_t st);
-// p = z + beta p
-hipError_t launch_cg_p(double* p, const double* z, int64_t n, int m, const double* beta, hipStream_t st);
-// alpha[c] = active ? num[c] / den[c] : 0 ; flags breakdown if den <= 0 (CG) or not finite
-hipError_t launch_div_scalars(const double* num, const double* den, const int32_t* active, int m, double* out,
-                              int32_t check_positive, int32_t* flag, hipStream_t st);
-// beta[c] = active ? (rz_new[c] - sub[c]) / rz[c] : 0 ; then rz[c] = rz_new[c]
-hipError_t launch_beta(const double* rz_new, const double* sub, double* rz, const int32_t* active, int m,
-                       double* beta, hipStream_t st);
 // y = Ainv x (dense, row-major n x n, FP64), m columns
 hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n, int m, hipStream_t st);
 // level-0 reorder: out[internal unit u] = in[caller element perm[u]] (gather) or the inverse (scatter)

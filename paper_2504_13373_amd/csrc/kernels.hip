@@ -740,9 +740,6 @@ template hipError_t launch_convert<float, float>(const float*, float*, int64_t, 
 hipError_t launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st) {
     return launch_convert<double, float>(a, b, n, st);
 }
-hipError_t launch_f32_to_f64(const float* a, double* b, int64_t n, hipStream_t st) {
-    return launch_convert<float, double>(a, b, n, st);
-}
 
 // ============================================================ block inverse
 // Batched Gauss-Jordan with partial pivoting (LAPACK-style pivot choice: the
@@ -1374,22 +1371,6 @@ hipError_t launch_axpby_dev(const double* x, double* y, int64_t n, int m, const 
     return hipGetLastError();
 }
 
-__global__ void k_cg_xr(double* __restrict__ x, const double* r_in, double* r_out, const double* __restrict__ p,
-                        const double* __restrict__ q, int64_t n, int m, const double* __restrict__ alpha) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n * m) return;
-    const double a = alpha[t % m];
-    x[t] += a * p[t];
-    r_out[t] = r_in[t] - a * q[t];
-}
-
-hipError_t launch_cg_xr(double* x, const double* r_in, double* r_out, const double* p, const double* q, int64_t n,
-                        int m, const double* alpha, hipStream_t st) {
-    if (n * m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cg_xr, dim3(grid_for(n * m)), dim3(WG), 0, st, x, r_in, r_out, p, q, n, m, alpha);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------------ fused Krylov steps
 
 // Each workgroup writes its partial sums s[c] to part[c * gridDim.x + block];
@@ -1821,9 +1802,8 @@ static hipError_t for_chunks(int m, F&& f) {
         default: hipLaunchKernelGGL((KERNEL<1>), __VA_ARGS__); break;                                 \
     }
 
-hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, unsigned* counter,
-                           double* out, hipStream_t st) {
-    (void)counter;
+hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, double* part, double* out,
+                           hipStream_t st) {
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
         if (co_ok(m, w)) {
@@ -1839,9 +1819,7 @@ hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, d
 
 hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const double* p, const double* q,
                             float* r32, int64_t n, int m, const double* rz, const double* pq,
-                            const int32_t* active, double* part, unsigned* counter, double* rr, int32_t* flag,
-                            hipStream_t st) {
-    (void)counter;
+                            const int32_t* active, double* part, double* rr, int32_t* flag, hipStream_t st) {
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
         if (co_ok(m, w) && r_in == r_out) {
@@ -1864,8 +1842,7 @@ hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const 
 }
 
 hipError_t launch_zdots(const float* z32, double* z, const double* r, const double* r_old, int64_t n, int m,
-                        double* part, unsigned* counter, double* rz, double* zro, hipStream_t st) {
-    (void)counter;
+                        double* part, double* rz, double* zro, hipStream_t st) {
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
         if (co_ok(m, w)) {
@@ -1907,53 +1884,6 @@ __global__ void k_copy_cols(const double* __restrict__ src, double* __restrict__
 hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, const int32_t* mask, hipStream_t st) {
     if (n * m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy_cols, dim3(grid_for(n * m)), dim3(WG), 0, st, src, dst, n, m, mask);
-    return hipGetLastError();
-}
-
-__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, int64_t n, int m,
-                       const double* __restrict__ beta) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n * m) return;
-    p[t] = z[t] + beta[t % m] * p[t];
-}
-
-hipError_t launch_cg_p(double* p, const double* z, int64_t n, int m, const double* beta, hipStream_t st) {
-    if (n * m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cg_p, dim3(grid_for(n * m)), dim3(WG), 0, st, p, z, n, m, beta);
-    return hipGetLastError();
-}
-
-__global__ void k_div_scalars(const double* __restrict__ num, const double* __restrict__ den,
-                              const int32_t* __restrict__ active, int m, double* __restrict__ out, int32_t checkpos,
-                              int32_t* __restrict__ flag) {
-    const int c = threadIdx.x;
-    if (c >= m) return;
-    if (!active[c]) { out[c] = 0.0; return; }
-    const double d = den[c];
-    if (checkpos && !(d > 0.0)) atomicOr(flag, 1);
-    const double v = num[c] / d;
-    if (!isfinite(v)) atomicOr(flag, 2);
-    out[c] = isfinite(v) ? v : 0.0;
-}
-
-hipError_t launch_div_scalars(const double* num, const double* den, const int32_t* active, int m, double* out,
-                              int32_t check_positive, int32_t* flag, hipStream_t st) {
-    hipLaunchKernelGGL(k_div_scalars, dim3(1), dim3(64), 0, st, num, den, active, m, out, check_positive, flag);
-    return hipGetLastError();
-}
-
-__global__ void k_beta(const double* __restrict__ rz_new, const double* __restrict__ sub, double* __restrict__ rz,
-                       const int32_t* __restrict__ active, int m, double* __restrict__ beta) {
-    const int c = threadIdx.x;
-    if (c >= m) return;
-    const double nw = rz_new[c];
-    beta[c] = active[c] ? (nw - (sub ? sub[c] : 0.0)) / rz[c] : 0.0;
-    rz[c] = nw;
-}
-
-hipError_t launch_beta(const double* rz_new, const double* sub, double* rz, const int32_t* active, int m,
-                       double* beta, hipStream_t st) {
-    hipLaunchKernelGGL(k_beta, dim3(1), dim3(64), 0, st, rz_new, sub, rz, active, m, beta);
     return hipGetLastError();
 }
 
