@@ -85,3 +85,26 @@ def test_mesh_statistics():
 def test_config_c1_sizes():
     w = configs.poisson2d_split()
     assert w.A.n == 1536 and w.A.nnzb == 512 + 2 * 736
+
+
+@pytest.mark.parametrize("n_elem", [513, 700, 1100, 2049, 3000, 4097, 5500])
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_catalogue_aggregation_keeps_uniform_coarse_size(n_elem, p):
+    """The serving catalogue's rule (8-way aggregation for p = 1, 4-way
+    otherwise; levels until the coarsest holds at most 2,048 dofs) gives every
+    aggregate of every level at least r = 3 dofs, hence one coarse block size
+    s = min(ceil(|A_J| / n_cut), |A_J|, r) = 3 per level (eq:sik)."""
+    from oracle import rcb
+    rng = np.random.default_rng(n_elem)
+    cent = rng.random((n_elem, 2))
+    nb = (p + 1) * (p + 2) // 2
+    bis = 3 if p == 1 else 2
+    L = configs.levels_for_coarsest(n_elem, bis)
+    aggs, _ = rcb.rcb_hierarchy(cent, L, bis)
+    dofs = np.full(n_elem, nb)
+    for k, a in enumerate(aggs):
+        per = np.bincount(a, weights=dofs).astype(int)
+        s = {min(-(-int(d) // 3), int(d), 3) for d in per}
+        assert s == {3}, (k, sorted(set(per.tolist()))[:5])
+        dofs = np.full(len(per), 3)
+    assert len(dofs) * 3 <= 2048 or L == 2
