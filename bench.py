@@ -12,7 +12,8 @@ relative residual of 1e-8 from x = 0, with the V-cycle as preconditioner:
 * mixed : FP32 V-cycle inside FP64 flexible CG (the reported value),
 * fp64  : FP64 V-cycle inside FP64 CG (reported beside it).
 
-Prints one JSON line (see the README section of the design doc for its fields).
+Prints one JSON line: metric, value (solves/s), timing, roofline of the
+dominant kernel, CPU baseline and the per-path details.
 """
 import argparse
 import json
@@ -109,7 +110,7 @@ def main():
                     help="iteration cap per solve (profiling runs cap it; the reported value needs convergence)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

@@ -45,7 +45,7 @@ extern "C" {
 #define AMGDG_EHIP         -4  /* HIP runtime error */
 #define AMGDG_ENAN         -5  /* NaN or Inf in the data or the iteration */
 #define AMGDG_EBREAKDOWN   -6  /* Krylov breakdown, e.g. p^T A p <= 0 in CG */
-#define AMGDG_EUNSUPPORTED -7  /* valid input outside what this build implements */
+#define AMGDG_EUNSUPPORTED -7  /* valid input outside what the library implements */
 #define AMGDG_ENOCONV       1  /* iteration limit reached; x holds the last iterate */
 
 /* --------------------------------------------------------------- parameters */

@@ -13,7 +13,7 @@ SOURCES = ["kernels.hip", "amgdg.hip", "index.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-    # no packed FP32 instructions (see the build notes in the design doc)
+    # no packed FP32 instructions: the compiler keeps FP32 arithmetic scalar
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

@@ -3,7 +3,8 @@
 Sizes: the 16x16 split-square SIPG p=1 case (1,536 dofs), a 33^2-point
 Delaunay SIPG p=3 case (20,480 dofs, 4 levels: several slices per level and a
 ragged last slice) and a 17^2-point LDG+upwind p=2 convection-diffusion case
-(3,072 dofs).  Tolerances follow the parity protocol stated in the design doc.
+(3,072 dofs).  FP64 results are held to 1e-10 (1e-12 or 1e-13 for single
+steps), FP32 steps to a few units of 2^-24 of |A||x| + |b|.
 """
 import numpy as np
 import pytest
