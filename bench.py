@@ -216,14 +216,7 @@ def main():
         kern[name] = dict(us=t * 1e6, gbps=byts / t / 1e9, bytes=byts)
         log(f"level-0 sweep {name}: {t * 1e6:.1f} us, {byts / 1e6:.1f} MB, {byts / t / 1e9:.0f} GB/s")
 
-    if args.copy_calibration:
-        nbytes = args.copy_calibration * 1000 * 1000
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 x elementwise copy of {nbytes} bytes")
+    _copy_calibration(args, torch, dev)
 
     serving = None
     if args.serve > 0:
@@ -304,6 +297,19 @@ def _autotune(args, am, torch, h, m):
     log(f"autotune ({dt:.2f} s): " + "; ".join(
         f"L{k} lanes {t['lanes']} cols32 {t['cols32']} mfma32 {t['mfma32']}" for k, t in enumerate(shapes)))
     return {"seconds": dt, "levels": shapes}
+
+
+def _copy_calibration(args, torch, dev):
+    """Three elementwise copies of a known size, for scaling HBM counters."""
+    if not args.copy_calibration:
+        return
+    nbytes = args.copy_calibration * 1000 * 1000
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 x elementwise copy of {nbytes} bytes")
 
 
 def _contract(args, metric_value, ms, dtype, workload, extra):
@@ -455,6 +461,7 @@ def bench_poisson3d(args, am, torch, dev):
         log(f"poisson3d V-cycle {name}: {t * 1e3:.2f} ms ({byts / t / 1e9:.0f} GB/s); level-0 sweep "
             f"{ts * 1e6:.0f} us ({sb / ts / 1e9:.0f} GB/s)")
         del r, z, xx, bb, yy
+    _copy_calibration(args, torch, dev)
     mx = res["mixed"]
     _contract(args, mx["solves_per_s"], mx["seconds"] * 1e3, "f32 V-cycle + f64 Krylov",
               f"3D Poisson SIPG p=2 on {cells}^3 x 6 jittered Kuhn tetrahedra ({infos[0].n_units} tets, "
