@@ -35,20 +35,23 @@ def log(msg):
 
 
 def level_bytes(info, w, m, nu):
-    """Algorithmic bytes of one V(nu,nu) visit of a non-coarsest level: 2nu passes
-    over A_k and D_k^{-1}, (6nu+5) passes over level-k vectors, one over T_k and R_k."""
-    A = info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
+    """Algorithmic bytes of one V(nu,nu) visit of a non-coarsest level: one pass
+    over D_k^{-1} (the first sweep, which also forms c = D^{-1} b), 2nu passes over
+    S_k = D_k^{-1} A_k (2nu - 1 sweeps and the residual), one over T_k and R_k D_k,
+    and (6nu+6) passes over level-k vectors."""
+    S = info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
     D = info.n_units * info.nb * info.nb * w
     TR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_units + 1)
     RR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_agg + 1)
-    return 2 * nu * (A + D) + (6 * nu + 5) * info.n * m * w + TR + RR
+    return 2 * nu * S + D + (6 * nu + 6) * info.n * m * w + TR + RR
 
 
 def sweep_bytes(info, w, m):
-    """Algorithmic bytes of one block-Jacobi sweep y = x + omega D^-1 (b - A x):
-    A (values and indices), D^-1, and x, b read once, y written once."""
+    """Algorithmic bytes of one block-Jacobi sweep as the V-cycle runs it,
+    y = x + omega (c - S x) with S = D^-1 A and c = D^-1 b: S (values and
+    indices), x and c read once, y written once."""
     return (info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
-            + info.n_units * info.nb * info.nb * w + 3 * info.n * m * w)
+            + 3 * info.n * m * w)
 
 
 def sliced_kernels_sha256():
@@ -195,8 +198,9 @@ def main():
         vc[name] = dict(ms=t * 1e3, gbps=byts / t / 1e9, bytes=byts)
         log(f"V-cycle {name}: {t * 1e3:.3f} ms, {byts / 1e9:.3f} GB algorithmic, {byts / t / 1e9:.0f} GB/s")
 
-    # dominant kernel: the level-0 block-Jacobi sweep, timed with HIP events on the
-    # stream it is launched on (one kernel launch per call with internal ordering)
+    # dominant kernel: the level-0 block-Jacobi sweep in the row-scaled form the
+    # V-cycle runs, timed with HIP events on the stream it is launched on (one
+    # kernel launch per call with internal ordering)
     kern = {}
     for name, (prec, wb, dt) in {"fp32": (am.AMGDG_MIXED, 4, torch.float32),
                                  "fp64": (am.AMGDG_FP64, 8, torch.float64)}.items():
@@ -204,11 +208,11 @@ def main():
         bb = torch.randn_like(xx)
         yy = torch.zeros_like(xx)
         for _ in range(5):
-            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP_SCALED, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(args.kernel_reps):
-            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP_SCALED, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
         e1.record(stream)
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
@@ -251,12 +255,12 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "level-0 FP32 block-Jacobi sweep (k_sweep<float,1,SWEEP>)",
+            "kernel": "level-0 FP32 block-Jacobi sweep on D^-1 A (k_spmv<float,1,S_SWEEP>)",
             "achieved": k["gbps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": k["gbps"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_sweep<float, 1, 0>"),
+            "traffic": measured_traffic("k_spmv<float, 1, 3>"),
             "bytes_per_launch": k["bytes"],
             "us_per_launch": k["us"],
         },
@@ -448,10 +452,10 @@ def bench_poisson3d(args, am, torch, dev):
         byts = sum(level_bytes(i, wb, m, nu) for i in infos[:-1]) + nN * nN * 8 + 2 * nN * m * 8
         xx, bb, yy = torch.randn_like(r), torch.randn_like(r), torch.zeros_like(r)
         for _ in range(2):
-            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP_SCALED, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
         e0.record(stream)
         for _ in range(reps):
-            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP_SCALED, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
         e1.record(stream)
         torch.cuda.synchronize()
         ts = e0.elapsed_time(e1) / reps * 1e-3

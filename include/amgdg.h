@@ -209,7 +209,12 @@ int amgdg_solve(amgdg_handle h, int32_t m, const double* b_dev, double* x_dev, i
                 amgdg_solve_stats* stats, void* stream);
 
 /* One V-cycle z = V(r) from z = 0 (Algorithm 2, one pass), m columns.
- * precision AMGDG_FP64: r, z are double*; AMGDG_MIXED: float*. */
+ * precision AMGDG_FP64: r, z are double*; AMGDG_MIXED: float*.
+ * On level k the first pre-smoothing sweep (from u = 0) forms omega D^{-1} b_k
+ * and keeps c = D^{-1} b_k; every later sweep is u + omega (c - S_k u) with
+ * S_k = D^{-1} A_k precomputed at setup, and the restricted residual is
+ * (R_k D)(c - S_k u), the same operator as Algorithm 1's sweep and
+ * R_k (b_k - A_k u) with one matrix read per sweep instead of A_k and D^{-1}. */
 int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int32_t precision,
                  int32_t flags, void* stream);
 
@@ -226,6 +231,10 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
 #define AMGDG_OP_RESTRICT  4  /* y = R_k x   (x: n_k, y: n_{k+1})                    */
 #define AMGDG_OP_PROLONG   5  /* y = b + T_k x (x: n_{k+1}, b, y: n_k)               */
 #define AMGDG_OP_COARSE    6  /* y = A_N^{-1} x on the coarsest level (always FP64)  */
+/* The forms the V-cycle runs (its sweeps after the first, and its restriction,
+ * on the row-scaled operators; b here is the scaled right-hand side D^{-1} b_k): */
+#define AMGDG_OP_SWEEP_SCALED    7  /* y = x + omega (b - D^{-1} A_k x)               */
+#define AMGDG_OP_RESTRICT_SCALED 8  /* y = R_k D x  (x: n_k, y: n_{k+1})              */
 int amgdg_apply(amgdg_handle h, int32_t k, int32_t op, int32_t m, int32_t precision, const void* x,
                 const void* b, void* y, int32_t flags, void* stream);
 
@@ -281,7 +290,8 @@ int amgdg_server_poll(amgdg_server s, int32_t capacity, int64_t* tags, int32_t* 
 int amgdg_server_destroy(amgdg_server s);
 
 /* Autotuner: picks the launch shapes for m columns (1..64) by timing the
- * candidates on this hierarchy's operators (HIP events on `stream`):
+ * candidates on the operators of this hierarchy's V-cycle (HIP events on
+ * `stream`):
  *   - columns per launch of the sliced and block-CSR kernels (1, 2, 4, 8, 16);
  *   - operand blocks loaded ahead in the 16-column MFMA tiles (1, 2, 4);
  *   - with AMGDG_TUNE_LANES, the lanes per block row of every block-CSR
@@ -297,7 +307,8 @@ int amgdg_server_destroy(amgdg_server s);
 #define AMGDG_TUNE_LANES 1
 int amgdg_autotune(amgdg_handle h, int32_t m, int32_t flags, void* stream);
 /* The shapes in use on level k (0..levels-2) for m columns, out[16]:
- * [0..3) lanes per block row of A_k, T_k, R_k (0: sliced layout);
+ * [0..3) lanes per block row of A_k, T_k, R_k (0: sliced layout); D^{-1} A_k
+ * and R_k D, the operators the V-cycle runs, share the shapes of A_k and R_k;
  * [3..6) FP64 and [6..9) FP32 columns per launch (0: default rule);
  * [9..12) FP64 and [12..15) FP32 MFMA blocks loaded ahead (0: default 4);
  * [15] 1 if the lane widths were tuned. */

@@ -29,7 +29,7 @@ AMGDG_STATIONARY, AMGDG_PCG, AMGDG_FCG, AMGDG_FGMRES = 0, 1, 2, 3
 AMGDG_X0, AMGDG_INTERNAL_ORDER, AMGDG_EAGER = 1, 2, 4
 AMGDG_TUNE_LANES = 1
 (AMGDG_OP_SPMV, AMGDG_OP_SWEEP, AMGDG_OP_SWEEP0, AMGDG_OP_RESIDUAL, AMGDG_OP_RESTRICT,
- AMGDG_OP_PROLONG, AMGDG_OP_COARSE) = range(7)
+ AMGDG_OP_PROLONG, AMGDG_OP_COARSE, AMGDG_OP_SWEEP_SCALED, AMGDG_OP_RESTRICT_SCALED) = range(9)
 
 
 class amgdg_params(ctypes.Structure):

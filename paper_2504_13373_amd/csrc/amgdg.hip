@@ -109,6 +109,7 @@ template <typename T>
 struct VBuf {
     T *b = nullptr, *u = nullptr, *w = nullptr, *r = nullptr;
     T* cur = nullptr;  // buffer holding u_k during a V-cycle
+    T* c = nullptr;    // D_k^{-1} b_k of the V-cycle's level-k right-hand side
 };
 
 struct Level {
@@ -122,6 +123,10 @@ struct Level {
     float* Dinv_sell32 = nullptr;
     float* Dinv_nat32 = nullptr;
     MatStore A, T, R;
+    // the row-scaled operators the V-cycle runs on: S = D^{-1} A (A's pattern)
+    // and RD = R D (R's pattern), so that R (b - A u) = RD (D^{-1} b - S u)
+    MatStore S, RD;
+    double *S_nat = nullptr, *RD_nat = nullptr;
     double *B_in = nullptr, *B_rel = nullptr, *Pu = nullptr, *sv = nullptr, *T_nat = nullptr, *R_nat = nullptr;
 };
 
@@ -440,25 +445,29 @@ static int mfu_of(const MatStore& M, int m) {
     return m / MFMA_COLS <= 4 ? (sizeof(T) == 8 ? M.mfu64[m / MFMA_COLS] : M.mfu32[m / MFMA_COLS]) : 0;
 }
 
+// omega is read by S_SWEEP only
 template <typename T>
-static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, int m, hipStream_t st) {
-    if (M.vec) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m)));
+static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, int m, hipStream_t st,
+                     T omega = T(0)) {
+    if (M.vec) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m), omega));
     else if (use_mfma<T>(M, m))
-        HIPCHK(launch_mfma<T>(mode == AX ? MF_AX : mode == B_MINUS ? MF_BMINUS : MF_BPLUS, nsel<T>(M), nullptr, x, b,
-                              y, T(0), m, st, mfu_of<T>(M, m)));
-    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st, cap_of<T>(M, m)));
+        HIPCHK(launch_mfma<T>(mode == AX ? MF_AX : mode == B_MINUS ? MF_BMINUS : mode == B_PLUS ? MF_BPLUS : MF_SSWEEP,
+                              nsel<T>(M), nullptr, x, b, y, omega, m, st, mfu_of<T>(M, m)));
+    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st, cap_of<T>(M, m), omega));
 }
 
+// y2 (SWEEP0 only, may be null) receives D^{-1} b
 template <typename T>
 static void mat_sweep(int mode, const Level& L, const T* x, const T* b, T* y, T omega, int m, const int32_t* mask,
-                      hipStream_t st) {
+                      hipStream_t st, T* y2 = nullptr) {
     if (L.A.vec)
-        HIPCHK(launch_bsweep<T>(mode, bsel<T>(L.A), dinv_of<T>(L), x, b, y, omega, m, mask, st, cap_of<T>(L.A, m)));
+        HIPCHK(launch_bsweep<T>(mode, bsel<T>(L.A), dinv_of<T>(L), x, b, y, omega, m, mask, st, cap_of<T>(L.A, m), y2));
     else if ((mode == SWEEP || mode == SWEEP0) && use_mfma<T>(L.A, m) && dinv_nat_of<T>(L))
         HIPCHK(launch_mfma<T>(mode == SWEEP ? MF_SWEEP : MF_SWEEP0, nsel<T>(L.A), dinv_nat_of<T>(L), x, b, y, omega, m,
-                              st, mfu_of<T>(L.A, m)));
+                              st, mfu_of<T>(L.A, m), y2));
     else
-        HIPCHK(launch_sweep<T>(mode, sel<T>(L.A.s), dinv_of<T>(L), x, b, y, omega, m, mask, st, cap_of<T>(L.A, m)));
+        HIPCHK(launch_sweep<T>(mode, sel<T>(L.A.s), dinv_of<T>(L), x, b, y, omega, m, mask, st, cap_of<T>(L.A, m),
+                               y2));
 }
 
 
@@ -632,6 +641,14 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
                 throw Error(AMGDG_ESINGULAR, "diagonal block singular to working precision on level " + std::to_string(k));
         }
         build_mat(C, L.A, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.A_nat, C.mixed, st);
+        {
+            DevMem tmp;
+            int32_t* rp_d = upload(tmp, P.A_rp, st);
+            L.S_nat = C.mem.alloc<double>(L.nnzb * L.nb * L.nb);
+            HIPCHK(launch_row_scale(L.A_nat, rp_d, L.n_units, L.nb, L.Dinv_nat, L.S_nat, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        build_mat(C, L.S, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.S_nat, C.mixed, st);
         if (!L.A.vec) {
             L.Dinv_sell = sell_dinv<double>(C, L.A.s.d, L.Dinv_nat, st);
             if (C.mixed) L.Dinv_sell32 = sell_dinv<float>(C, L.A.s.f, L.Dinv_nat, st);
@@ -693,6 +710,15 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         }
         build_mat(C, L.T, L.n_units, L.nb, s, P.T_rp, P.T_ci, L.T_nat, C.mixed, st);
         build_mat(C, L.R, P.n_agg, s, L.nb, P.R_rp, P.R_ci, L.R_nat, C.mixed, st);
+        {
+            DevMem t1;
+            int32_t* rci = upload(t1, P.R_ci, st);
+            int32_t* dpos = upload(t1, P.A_diag, st);
+            L.RD_nat = C.mem.alloc<double>(L.nT * L.nb * s);
+            HIPCHK(launch_right_diag(L.R_nat, rci, L.nT, L.nb, s, L.A_nat, dpos, L.RD_nat, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        build_mat(C, L.RD, P.n_agg, s, L.nb, P.R_rp, P.R_ci, L.RD_nat, C.mixed, st);
         // A_{k+1} = R (A T)
         Level& Ln = C.lv[k + 1];
         {
@@ -747,13 +773,15 @@ static int64_t work_layout(const Ctx& C, Work* W, int m, int restart) {
         double* u = get(d, cnt);
         double* w = get(d, cnt);
         double* r = get(d, cnt);
-        if (W) W->v64[k] = VBuf<double>{b, u, w, r, nullptr};
+        double* c = k < C.N ? get(d, cnt) : nullptr;
+        if (W) W->v64[k] = VBuf<double>{b, u, w, r, nullptr, c};
         if (C.mixed) {
             float* bf = get(f, cnt);
             float* uf = get(f, cnt);
             float* wf = get(f, cnt);
             float* rf = get(f, cnt);
-            if (W) W->v32[k] = VBuf<float>{bf, uf, wf, rf, nullptr};
+            float* cf = k < C.N ? get(f, cnt) : nullptr;
+            if (W) W->v32[k] = VBuf<float>{bf, uf, wf, rf, nullptr, cf};
         }
     }
     const int64_t n = C.lv[0].n * m;
@@ -862,18 +890,23 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
         T* cur = V.u;
         T* oth = V.w;
         const T om = T(L.omega);
+        // Every sweep after the first runs on S = D^{-1} A with c = D^{-1} b:
+        // u + omega D^{-1} (b - A u) = u + omega (c - S u), one matrix read
+        // instead of A and D^{-1}.  The first sweep (from u = 0) also writes c.
         if (tpre == 0) {
             HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * L.n * m, st));
+            mat_sweep<T>(SWEEP0, L, nullptr, bk, V.c, T(1), m, nullptr, st);
         } else {
-            mat_sweep<T>(SWEEP0, L, nullptr, bk, cur, om, m, nullptr, st);
+            mat_sweep<T>(SWEEP0, L, nullptr, bk, cur, om, m, nullptr, st, V.c);
             for (int t = 1; t < tpre; ++t) {
-                mat_sweep<T>(SWEEP, L, cur, bk, oth, om, m, nullptr, st);
+                mat_spmv<T>(S_SWEEP, L.S, cur, V.c, oth, m, st, om);
                 std::swap(cur, oth);
             }
         }
         V.cur = cur;
-        mat_spmv<T>(B_MINUS, L.A, cur, bk, V.r, m, st);
-        mat_spmv<T>(AX, L.R, V.r, nullptr, vbuf<T>(W, k + 1).b, m, st);
+        // R (b - A u) = RD (c - S u)
+        mat_spmv<T>(B_MINUS, L.S, cur, V.c, V.r, m, st);
+        mat_spmv<T>(AX, L.RD, V.r, nullptr, vbuf<T>(W, k + 1).b, m, st);
     }
     {
         VBuf<T>& V = vbuf<T>(W, N);
@@ -883,7 +916,6 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
     for (int k = N - 1; k >= 0; --k) {
         Level& L = C.lv[k];
         VBuf<T>& V = vbuf<T>(W, k);
-        const T* bk = (k == 0) ? b0 : V.b;
         const T om = T(L.omega);
         T* cur = V.cur;
         auto other = [&](T* c) { return c == V.u ? V.w : V.u; };
@@ -892,7 +924,7 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
         cur = dst;
         for (int t = 0; t < tpost; ++t) {
             dst = (k == 0 && t == tpost - 1) ? z0 : other(cur);
-            mat_sweep<T>(SWEEP, L, cur, bk, dst, om, m, nullptr, st);
+            mat_spmv<T>(S_SWEEP, L.S, cur, V.c, dst, m, st, om);
             cur = dst;
         }
         V.cur = cur;
@@ -1800,8 +1832,9 @@ struct Server {
 // ------------------------------------------------------------ autotuner
 
 // Picks launch shapes for m columns by timing the candidates on the
-// hierarchy's own operators (HIP events on the handle's vectors: A_k in its
-// sweep, T_k and R_k in their products):
+// operators the V-cycle runs (HIP events on the handle's vectors: S_k =
+// D^{-1} A_k in its sweep, T_k and R_k D in their products; A_k and R_k, which
+// have the same shapes, take the same choices):
 //   - columns per launch of the sliced and block-CSR kernels (1, 2, 4, 8(, 16));
 //   - blocks loaded ahead in the MFMA tiles (1, 2, 4) when m is a multiple of 16;
 //   - with `lanes`, the lanes per block row of every block-CSR operator
@@ -1849,17 +1882,18 @@ static void autotune_impl(Ctx& C, int m, bool lanes, hipStream_t st) {
         Level& L = C.lv[k];
         struct Op {
             MatStore* M;
+            MatStore* twin;
             int kin, kout;
-        } ops[3] = {{&L.A, k, k}, {&L.T, k + 1, k}, {&L.R, k, k + 1}};
+        } ops[3] = {{&L.S, &L.A, k, k}, {&L.T, nullptr, k + 1, k}, {&L.RD, &L.R, k, k + 1}};
         for (Op& o : ops) {
             MatStore& M = *o.M;
-            // A_k is timed in its block-Jacobi sweep (2 nu of them per level and
-            // cycle), T_k and R_k in their products
+            // S_k is timed in its block-Jacobi sweep (2 nu - 1 of them per level
+            // and cycle), T_k and R_k D in their products
             auto run = [&](auto tag, int cols) {
                 using T = decltype(tag);
                 VBuf<T>& vin = vbuf<T>(W, o.kin);
                 VBuf<T>& vout = vbuf<T>(W, o.kout);
-                if (o.M == &L.A) mat_sweep<T>(SWEEP, L, vin.u, vin.b, vout.w, T(L.omega), cols, nullptr, st);
+                if (o.M == &L.S) mat_spmv<T>(S_SWEEP, M, vin.u, vin.b, vout.w, cols, st, T(L.omega));
                 else mat_spmv<T>(AX, M, vin.u, nullptr, vout.w, cols, st);
             };
             auto tune_type = [&](auto tag) {
@@ -1900,6 +1934,11 @@ static void autotune_impl(Ctx& C, int m, bool lanes, hipStream_t st) {
             }
             tune_type(0.0);
             tune_type(0.0f);
+            if (o.twin) {
+                MatStore& Tw = *o.twin;
+                Tw.cap64 = M.cap64, Tw.cap32 = M.cap32, Tw.mfu64 = M.mfu64, Tw.mfu32 = M.mfu32;
+                Tw.bd.P = Tw.bf.P = M.bd.P;
+            }
         }
     }
     if (lanes) C.lanes_tuned = true;
@@ -1931,10 +1970,10 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
     // gathered into internal order; the coarse x of PROLONG and the coarse y of
     // RESTRICT are not level-0 arrays and are used as they are.
     const bool uses_b = (op == AMGDG_OP_SWEEP || op == AMGDG_OP_SWEEP0 || op == AMGDG_OP_RESIDUAL ||
-                         op == AMGDG_OP_PROLONG);
+                         op == AMGDG_OP_PROLONG || op == AMGDG_OP_SWEEP_SCALED);
     const bool uses_x = (op != AMGDG_OP_SWEEP0);
     if ((uses_b && !b) || (uses_x && !x)) throw Error(AMGDG_EINVAL, "missing input array");
-    const bool fine_out = (op != AMGDG_OP_RESTRICT);
+    const bool fine_out = (op != AMGDG_OP_RESTRICT && op != AMGDG_OP_RESTRICT_SCALED);
     const bool fine_x = (op != AMGDG_OP_PROLONG);
     T* out = (perm && fine_out) ? V.u : y;
     const T* xi = !uses_x ? nullptr : (fine_x ? in(x, V.b) : x);
@@ -1947,6 +1986,8 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
         case AMGDG_OP_RESTRICT: mat_spmv<T>(AX, L.R, xi, nullptr, out, m, st); break;
         case AMGDG_OP_PROLONG: mat_spmv<T>(B_PLUS, L.T, xi, bi, out, m, st); break;
         case AMGDG_OP_COARSE: coarse_solve<T>(C, W, xi, out, m, st); break;
+        case AMGDG_OP_SWEEP_SCALED: mat_spmv<T>(S_SWEEP, L.S, xi, bi, out, m, st, T(L.omega)); break;
+        case AMGDG_OP_RESTRICT_SCALED: mat_spmv<T>(AX, L.RD, xi, nullptr, out, m, st); break;
         default: throw Error(AMGDG_EINVAL, "bad op");
     }
     if (perm && fine_out) HIPCHK((launch_permute<T, T>(out, y, C.perm_d, nun, L.nb, m, 0, st)));

@@ -57,7 +57,7 @@ constexpr int NBSR_MAXB = 16;
 // sweep modes
 enum SweepMode : int {
     SWEEP = 0,   // y = x + omega D^{-1} (b - A x)
-    SWEEP0 = 1,  // y = omega D^{-1} b
+    SWEEP0 = 1,  // y = omega D^{-1} b; with y2, also y2 = D^{-1} b
     RELAX = 2,   // y = x - omega D^{-1} A x   (columns with mask 0 are copied)
     DINVA = 3,   // y = D^{-1} A x
 };
@@ -66,6 +66,8 @@ enum SpmvMode : int {
     AX = 0,      // y = A x
     B_MINUS = 1, // y = b - A x
     B_PLUS = 2,  // y = b + A x
+    S_SWEEP = 3, // y = x + omega (b - A x): the block-Jacobi sweep on the row-scaled
+                 // operator A = D^{-1} A_k, with b = D^{-1} b_k
 };
 
 // D^{-1} in sliced layout: the br x br block of block row g is stored like a
@@ -73,33 +75,36 @@ enum SpmvMode : int {
 // value (i, j) at dinv[s * brpad * L + (j / VW) * L * VW + (g * br + i) * VW + j % VW].
 // `cap` bounds the columns processed per launch (1, 2, 4, 8; 0: 4 FP64 / 8 FP32);
 // it does not change the arithmetic of any column.
+// y2 (SWEEP0 only, may be null) receives D^{-1} b.  omega is read by S_SWEEP only.
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
-                        int m, const int32_t* colmask, hipStream_t st, int cap = 0);
+                        int m, const int32_t* colmask, hipStream_t st, int cap = 0, T* y2 = nullptr);
 template <typename T>
-hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap = 0);
+hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap = 0,
+                       T omega = T(0));
 // the same operations on a block-CSR matrix; dinv: natural layout (n_brow x br x br);
 // cap: 1, 2, 4, 8 or 16 columns per launch (0: 16)
 template <typename T>
 hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                         const int32_t* colmask, hipStream_t st, int cap = 0);
+                         const int32_t* colmask, hipStream_t st, int cap = 0, T* y2 = nullptr);
 template <typename T>
 hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st,
-                        int cap = 0);
+                        int cap = 0, T omega = T(0));
 
 // MFMA products of 16-column tiles (m a multiple of 16, row-major n x m
 // vectors): one wavefront per block row computes the block row's br x 16 tile
 // of A x with 16x16x4 matrix instructions (FP32 or FP64 accumulation, the
 // type of T); then, by mode:
 //   MF_AX y = A x, MF_BMINUS y = b - A x, MF_BPLUS y = b + A x,
-//   MF_SWEEP y = x + omega D^{-1} (b - A x), MF_SWEEP0 y = omega D^{-1} b
+//   MF_SWEEP y = x + omega D^{-1} (b - A x), MF_SWEEP0 y = omega D^{-1} b (and
+//   y2 = D^{-1} b when y2 is not null), MF_SSWEEP y = x + omega (b - A x)
 // with D^{-1} natural (n_brow x br x br, row-major), applied by MFMA too.
-enum MfmaMode : int { MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4 };
+enum MfmaMode : int { MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4, MF_SSWEEP = 5 };
 // u: blocks whose operand fragments are loaded before their products (1, 2 or 4;
 // 0: 4); it does not change the arithmetic.
 template <typename T>
 hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                       hipStream_t st, int u = 0);
+                       hipStream_t st, int u = 0, T* y2 = nullptr);
 
 // ---- setup ----
 // Fill the sliced values of type T from natural FP64 blocks: for slot q (one
@@ -123,6 +128,13 @@ hipError_t launch_T_build(const double* Avals, const int32_t* A_ci, const int32_
                           hipStream_t st);
 hipError_t launch_R_from_T(const double* Tvals, const int32_t* R_t, int64_t nR, int nb, int s, double* Rvals,
                            hipStream_t st);
+// S = D^{-1} A block row by block row (S has A's pattern; dinv natural)
+hipError_t launch_row_scale(const double* Avals, const int32_t* rp, int64_t n_brow, int nb, const double* dinv,
+                            double* Svals, hipStream_t st);
+// RD = R D with D the diagonal blocks of A (A_diag: position of block row i's
+// diagonal block in Avals); RD has R's pattern
+hipError_t launch_right_diag(const double* Rvals, const int32_t* R_ci, int64_t nR, int nb, int s, const double* Avals,
+                             const int32_t* A_diag, double* RDvals, hipStream_t st);
 hipError_t launch_AT(const double* Avals, const double* Tvals, const int64_t* pp, const int32_t* pa,
                      const int32_t* pt, int64_t nAT, int nb, int s, double* ATvals, hipStream_t st);
 hipError_t launch_galerkin(const double* Tvals, const double* ATvals, const int64_t* pp, const int32_t* pt,

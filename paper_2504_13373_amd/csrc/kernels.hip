@@ -90,7 +90,7 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
 template <typename T, int M, int MODE>
 __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ y, T omega,
-                                               const int32_t* __restrict__ colmask, int ld) {
+                                               const int32_t* __restrict__ colmask, int ld, T* __restrict__ y2) {
     constexpr bool HAS_B = (MODE == SWEEP || MODE == SWEEP0);
     constexpr bool HAS_A = (MODE != SWEEP0);
     constexpr int VW = 16 / int(sizeof(T));
@@ -148,12 +148,13 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
         else if (MODE == RELAX) v = colmask[c] ? x[row * ld + c] + omega * o[c] : x[row * ld + c];
         else v = -o[c];  // DINVA: r = -A x
         y[row * ld + c] = v;
+        if (MODE == SWEEP0 && y2) y2[row * ld + c] = o[c];
     }
 }
 
 template <typename T, int M, int MODE>
 __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
-                                              T* __restrict__ y, int ldx, int ldy) {
+                                              T* __restrict__ y, int ldx, int ldy, T omega) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
@@ -176,21 +177,22 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
         T v = acc[c];
         if (MODE == B_MINUS) v = b[row * ldy + c] - v;
         else if (MODE == B_PLUS) v = b[row * ldy + c] + v;
+        else if (MODE == S_SWEEP) v = x[row * ldx + c] + omega * (b[row * ldy + c] - v);
         y[row * ldy + c] = v;
     }
 }
 
 template <typename T, int M>
 static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
-                          const int32_t* mask, int ld, hipStream_t st) {
+                          const int32_t* mask, int ld, hipStream_t st, T* y2) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
     const size_t lds = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * M * sizeof(T);
     switch (mode) {
-        case SWEEP: hipLaunchKernelGGL((k_sweep<T, M, SWEEP>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case SWEEP0: hipLaunchKernelGGL((k_sweep<T, M, SWEEP0>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case RELAX: hipLaunchKernelGGL((k_sweep<T, M, RELAX>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case DINVA: hipLaunchKernelGGL((k_sweep<T, M, DINVA>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case SWEEP: hipLaunchKernelGGL((k_sweep<T, M, SWEEP>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case SWEEP0: hipLaunchKernelGGL((k_sweep<T, M, SWEEP0>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case RELAX: hipLaunchKernelGGL((k_sweep<T, M, RELAX>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case DINVA: hipLaunchKernelGGL((k_sweep<T, M, DINVA>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -198,14 +200,15 @@ static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x,
 
 template <typename T, int M>
 static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int ldx, int ldy,
-                         hipStream_t st) {
+                         hipStream_t st, T omega) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
     const size_t lds = size_t(WAVES_PER_WG) * A.G * A.tpad * M * sizeof(T);
     switch (mode) {
-        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, lds, st, A, x, b, y, ldx, ldy); break;
-        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, lds, st, A, x, b, y, ldx, ldy); break;
-        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, lds, st, A, x, b, y, ldx, ldy); break;
+        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
+        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
+        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
+        case S_SWEEP: hipLaunchKernelGGL((k_spmv<T, M, S_SWEEP>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -227,7 +230,7 @@ static int sell_chunk(int rem, const Sell<T>& A, bool with_dinv, int want) {
 
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                        const int32_t* colmask, hipStream_t st, int cap) {
+                        const int32_t* colmask, hipStream_t st, int cap, T* y2) {
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, true, cap);
@@ -235,13 +238,14 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
         const T* xc = x ? x + c0 : nullptr;
         const T* bc = b ? b + c0 : nullptr;
         const int32_t* mc = colmask ? colmask + c0 : nullptr;
+        T* y2c = y2 ? y2 + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 8: e = sweep_m<T, 8>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            case 4: e = sweep_m<T, 4>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            case 3: e = sweep_m<T, 3>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            case 2: e = sweep_m<T, 2>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            default: e = sweep_m<T, 1>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 8: e = sweep_m<T, 8>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            case 4: e = sweep_m<T, 4>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            case 3: e = sweep_m<T, 3>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            case 2: e = sweep_m<T, 2>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            default: e = sweep_m<T, 1>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
         }
         if (e != hipSuccess) return e;
         c0 += w;
@@ -250,7 +254,8 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
 }
 
 template <typename T>
-hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap) {
+hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
+                       T omega) {
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, false, cap);
@@ -258,11 +263,11 @@ hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y,
         const T* bc = b ? b + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 8: e = spmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, m, st); break;
-            case 4: e = spmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, m, st); break;
-            case 3: e = spmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, m, st); break;
-            case 2: e = spmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, m, st); break;
-            default: e = spmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, m, st); break;
+            case 8: e = spmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
+            case 4: e = spmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
+            case 3: e = spmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
+            case 2: e = spmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
+            default: e = spmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
         }
         if (e != hipSuccess) return e;
         c0 += w;
@@ -271,13 +276,13 @@ hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y,
 }
 
 template hipError_t launch_sweep<double>(int, const Sell<double>&, const double*, const double*, const double*,
-                                         double*, double, int, const int32_t*, hipStream_t, int);
+                                         double*, double, int, const int32_t*, hipStream_t, int, double*);
 template hipError_t launch_sweep<float>(int, const Sell<float>&, const float*, const float*, const float*, float*,
-                                        float, int, const int32_t*, hipStream_t, int);
+                                        float, int, const int32_t*, hipStream_t, int, float*);
 template hipError_t launch_spmv<double>(int, const Sell<double>&, const double*, const double*, double*, int,
-                                        hipStream_t, int);
+                                        hipStream_t, int, double);
 template hipError_t launch_spmv<float>(int, const Sell<float>&, const float*, const float*, float*, int,
-                                       hipStream_t, int);
+                                       hipStream_t, int, float);
 
 // ============================================================ block-CSR kernels (small blocks)
 
@@ -320,7 +325,7 @@ __device__ __forceinline__ void bcsr_row(const Bcsr<T>& A, int64_t brow, bool va
 template <typename T, int M, int MODE, int BR>
 __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ y, T omega,
-                                                const int32_t* __restrict__ colmask, int ld) {
+                                                const int32_t* __restrict__ colmask, int ld, T* __restrict__ y2) {
     constexpr bool HAS_B = (MODE == SWEEP || MODE == SWEEP0);
     constexpr bool HAS_A = (MODE != SWEEP0);
     const int gpw = 64 / A.P;
@@ -362,12 +367,13 @@ __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ 
         else if (MODE == RELAX) v = colmask[c] ? x[row * ld + c] + omega * o[c] : x[row * ld + c];
         else v = -o[c];
         y[row * ld + c] = v;
+        if (MODE == SWEEP0 && y2) y2[row * ld + c] = o[c];
     }
 }
 
 template <typename T, int M, int MODE, int BR>
 __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, int ld) {
+                                               T* __restrict__ y, int ld, T omega) {
     const int gpw = 64 / A.P;
     const int64_t wv = int64_t(xcd_remap(blockIdx.x, gridDim.x)) * WAVES_PER_WG + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -386,6 +392,7 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
             T v = acc[i][c];
             if (MODE == B_MINUS) v = b[row * ld + c] - v;
             else if (MODE == B_PLUS) v = b[row * ld + c] + v;
+            else if (MODE == S_SWEEP) v = x[row * ld + c] + omega * (b[row * ld + c] - v);
             y[row * ld + c] = v;
         }
     }
@@ -393,29 +400,31 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
 
 template <typename T, int M, int BR>
 static hipError_t bsweep_mb(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
-                            const int32_t* mask, int ld, hipStream_t st) {
+                            const int32_t* mask, int ld, hipStream_t st, T* y2) {
     const int64_t waves = (A.n_brow + (64 / A.P) - 1) / (64 / A.P);
     if (waves == 0) return hipSuccess;
     dim3 grid(grid_for(waves, WAVES_PER_WG)), block(WG);
     switch (mode) {
-        case SWEEP: hipLaunchKernelGGL((k_bsweep<T, M, SWEEP, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case SWEEP0: hipLaunchKernelGGL((k_bsweep<T, M, SWEEP0, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case RELAX: hipLaunchKernelGGL((k_bsweep<T, M, RELAX, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
-        case DINVA: hipLaunchKernelGGL((k_bsweep<T, M, DINVA, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld); break;
+        case SWEEP: hipLaunchKernelGGL((k_bsweep<T, M, SWEEP, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case SWEEP0: hipLaunchKernelGGL((k_bsweep<T, M, SWEEP0, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case RELAX: hipLaunchKernelGGL((k_bsweep<T, M, RELAX, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case DINVA: hipLaunchKernelGGL((k_bsweep<T, M, DINVA, BR>), grid, block, 0, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename T, int M, int BR>
-static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st) {
+static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st,
+                           T omega) {
     const int64_t waves = (A.n_brow + (64 / A.P) - 1) / (64 / A.P);
     if (waves == 0) return hipSuccess;
     dim3 grid(grid_for(waves, WAVES_PER_WG)), block(WG);
     switch (mode) {
-        case AX: hipLaunchKernelGGL((k_bspmv<T, M, AX, BR>), grid, block, 0, st, A, x, b, y, ld); break;
-        case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld); break;
-        case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld); break;
+        case AX: hipLaunchKernelGGL((k_bspmv<T, M, AX, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        case S_SWEEP: hipLaunchKernelGGL((k_bspmv<T, M, S_SWEEP, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -423,23 +432,24 @@ static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T
 
 template <typename T, int M>
 static hipError_t bsweep_m(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
-                           const int32_t* mask, int ld, hipStream_t st) {
+                           const int32_t* mask, int ld, hipStream_t st, T* y2) {
     switch (A.br) {
-        case 1: return bsweep_mb<T, M, 1>(mode, A, dinv, x, b, y, omega, mask, ld, st);
-        case 2: return bsweep_mb<T, M, 2>(mode, A, dinv, x, b, y, omega, mask, ld, st);
-        case 3: return bsweep_mb<T, M, 3>(mode, A, dinv, x, b, y, omega, mask, ld, st);
-        case 4: return bsweep_mb<T, M, 4>(mode, A, dinv, x, b, y, omega, mask, ld, st);
+        case 1: return bsweep_mb<T, M, 1>(mode, A, dinv, x, b, y, omega, mask, ld, st, y2);
+        case 2: return bsweep_mb<T, M, 2>(mode, A, dinv, x, b, y, omega, mask, ld, st, y2);
+        case 3: return bsweep_mb<T, M, 3>(mode, A, dinv, x, b, y, omega, mask, ld, st, y2);
+        case 4: return bsweep_mb<T, M, 4>(mode, A, dinv, x, b, y, omega, mask, ld, st, y2);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T, int M>
-static hipError_t bspmv_m(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st) {
+static hipError_t bspmv_m(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st,
+                          T omega) {
     switch (A.br) {
-        case 1: return bspmv_mb<T, M, 1>(mode, A, x, b, y, ld, st);
-        case 2: return bspmv_mb<T, M, 2>(mode, A, x, b, y, ld, st);
-        case 3: return bspmv_mb<T, M, 3>(mode, A, x, b, y, ld, st);
-        case 4: return bspmv_mb<T, M, 4>(mode, A, x, b, y, ld, st);
+        case 1: return bspmv_mb<T, M, 1>(mode, A, x, b, y, ld, st, omega);
+        case 2: return bspmv_mb<T, M, 2>(mode, A, x, b, y, ld, st, omega);
+        case 3: return bspmv_mb<T, M, 3>(mode, A, x, b, y, ld, st, omega);
+        case 4: return bspmv_mb<T, M, 4>(mode, A, x, b, y, ld, st, omega);
         default: return hipErrorInvalidValue;
     }
 }
@@ -455,21 +465,22 @@ static int bcsr_chunk(int rem, int cap) {
 
 template <typename T>
 hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                         const int32_t* colmask, hipStream_t st, int cap) {
+                         const int32_t* colmask, hipStream_t st, int cap, T* y2) {
     int c0 = 0;
     while (c0 < m) {
         const int w = bcsr_chunk(m - c0, cap);
         const T* xc = x ? x + c0 : nullptr;
         const T* bc = b ? b + c0 : nullptr;
         const int32_t* mc = colmask ? colmask + c0 : nullptr;
+        T* y2c = y2 ? y2 + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 16: e = bsweep_m<T, 16>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            case 8: e = bsweep_m<T, 8>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            case 4: e = bsweep_m<T, 4>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            case 3: e = bsweep_m<T, 3>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            case 2: e = bsweep_m<T, 2>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
-            default: e = bsweep_m<T, 1>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st); break;
+            case 16: e = bsweep_m<T, 16>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            case 8: e = bsweep_m<T, 8>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            case 4: e = bsweep_m<T, 4>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            case 3: e = bsweep_m<T, 3>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            case 2: e = bsweep_m<T, 2>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
+            default: e = bsweep_m<T, 1>(mode, A, dinv, xc, bc, y + c0, omega, mc, m, st, y2c); break;
         }
         if (e != hipSuccess) return e;
         c0 += w;
@@ -478,19 +489,20 @@ hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, 
 }
 
 template <typename T>
-hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap) {
+hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
+                        T omega) {
     int c0 = 0;
     while (c0 < m) {
         const int w = bcsr_chunk(m - c0, cap);
         const T* bc = b ? b + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 16: e = bspmv_m<T, 16>(mode, A, x + c0, bc, y + c0, m, st); break;
-            case 8: e = bspmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, st); break;
-            case 4: e = bspmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, st); break;
-            case 3: e = bspmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, st); break;
-            case 2: e = bspmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, st); break;
-            default: e = bspmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, st); break;
+            case 16: e = bspmv_m<T, 16>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
+            case 8: e = bspmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
+            case 4: e = bspmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
+            case 3: e = bspmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
+            case 2: e = bspmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
+            default: e = bspmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
         }
         if (e != hipSuccess) return e;
         c0 += w;
@@ -499,13 +511,13 @@ hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y
 }
 
 template hipError_t launch_bsweep<double>(int, const Bcsr<double>&, const double*, const double*, const double*,
-                                          double*, double, int, const int32_t*, hipStream_t, int);
+                                          double*, double, int, const int32_t*, hipStream_t, int, double*);
 template hipError_t launch_bsweep<float>(int, const Bcsr<float>&, const float*, const float*, const float*, float*,
-                                         float, int, const int32_t*, hipStream_t, int);
+                                         float, int, const int32_t*, hipStream_t, int, float*);
 template hipError_t launch_bspmv<double>(int, const Bcsr<double>&, const double*, const double*, double*, int,
-                                         hipStream_t, int);
+                                         hipStream_t, int, double);
 template hipError_t launch_bspmv<float>(int, const Bcsr<float>&, const float*, const float*, float*, int,
-                                        hipStream_t, int);
+                                        hipStream_t, int, float);
 
 // ============================================================ MFMA tiles
 // Lane layout of the 16x16x4 matrix instructions (wave64), as measured on
@@ -540,7 +552,8 @@ struct Mma<double> {
 // wavefront keeps several blocks' loads in flight.
 template <typename T, int MODE, int U>
 __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
-                                             const T* __restrict__ b, T* __restrict__ y, T omega, int ld) {
+                                             const T* __restrict__ b, T* __restrict__ y, T omega, int ld,
+                                             T* __restrict__ y2) {
     __shared__ T tile[WAVES_PER_WG][16][17];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int brow = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave);
@@ -557,7 +570,7 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
         const int row = Mma<T>::row(g, v);
         const int64_t e = (r0 + row) * ld + col0;
         bpre[v] = (MODE != MF_AX && row < br) ? b[e] : T(0);
-        xpre[v] = (MODE == MF_SWEEP && row < br) ? x[e] : T(0);
+        xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP) && row < br) ? x[e] : T(0);
     }
     if (SW) {
         const T* __restrict__ Db = dinv + int64_t(brow) * br * br;
@@ -603,6 +616,7 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
                 T val = acc[v];
                 if (MODE == MF_BMINUS) val = bpre[v] - val;
                 if (MODE == MF_BPLUS) val = bpre[v] + val;
+                if (MODE == MF_SSWEEP) val = xpre[v] + omega * (bpre[v] - val);
                 y[(r0 + row) * ld + col0] = val;
             }
         }
@@ -624,20 +638,24 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = Mma<T>::row(g, v);
-        if (row < br) y[(r0 + row) * ld + col0] = xpre[v] + omega * acc2[v];
+        if (row < br) {
+            y[(r0 + row) * ld + col0] = xpre[v] + omega * acc2[v];
+            if (MODE == MF_SWEEP0 && y2) y2[(r0 + row) * ld + col0] = acc2[v];
+        }
     }
 }
 
 template <typename T, int U>
 static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                         hipStream_t st) {
+                         hipStream_t st, T* y2) {
     dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
     switch (mode) {
-        case MF_AX: hipLaunchKernelGGL((k_mfma<T, MF_AX, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_BMINUS: hipLaunchKernelGGL((k_mfma<T, MF_BMINUS, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_BPLUS: hipLaunchKernelGGL((k_mfma<T, MF_BPLUS, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_SWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
-        case MF_SWEEP0: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP0, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m); break;
+        case MF_AX: hipLaunchKernelGGL((k_mfma<T, MF_AX, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
+        case MF_BMINUS: hipLaunchKernelGGL((k_mfma<T, MF_BMINUS, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
+        case MF_BPLUS: hipLaunchKernelGGL((k_mfma<T, MF_BPLUS, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
+        case MF_SWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
+        case MF_SWEEP0: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP0, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
+        case MF_SSWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SSWEEP, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -645,19 +663,19 @@ static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, 
 
 template <typename T>
 hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
-                       hipStream_t st, int u) {
+                       hipStream_t st, int u, T* y2) {
     if (A.n_brow == 0) return hipSuccess;
     if (m % MFMA_COLS != 0 || A.br > NBSR_MAXB || A.bc > NBSR_MAXB) return hipErrorInvalidValue;
     switch (u) {
-        case 1: return mfma_u<T, 1>(mode, A, dinv, x, b, y, omega, m, st);
-        case 2: return mfma_u<T, 2>(mode, A, dinv, x, b, y, omega, m, st);
-        default: return mfma_u<T, 4>(mode, A, dinv, x, b, y, omega, m, st);
+        case 1: return mfma_u<T, 1>(mode, A, dinv, x, b, y, omega, m, st, y2);
+        case 2: return mfma_u<T, 2>(mode, A, dinv, x, b, y, omega, m, st, y2);
+        default: return mfma_u<T, 4>(mode, A, dinv, x, b, y, omega, m, st, y2);
     }
 }
 template hipError_t launch_mfma<float>(int, const Nbsr<float>&, const float*, const float*, const float*, float*,
-                                       float, int, hipStream_t, int);
+                                       float, int, hipStream_t, int, float*);
 template hipError_t launch_mfma<double>(int, const Nbsr<double>&, const double*, const double*, const double*,
-                                        double*, double, int, hipStream_t, int);
+                                        double*, double, int, hipStream_t, int, double*);
 
 // ============================================================ layout conversion
 
@@ -1015,6 +1033,59 @@ hipError_t launch_R_from_T(const double* Tv, const int32_t* R_t, int64_t nR, int
     const int64_t tot = nR * nb * s;
     if (tot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_R_from_T, dim3(grid_for(tot)), dim3(WG), 0, st, Tv, R_t, nR, nb, s, Rv);
+    return hipGetLastError();
+}
+
+// S = D^{-1} A: block (row, blk) of S is D^{-1}_row A_blk; one thread per
+// entry (i, j) of one block row's blocks.
+__global__ void k_row_scale(const double* __restrict__ Av, const int32_t* __restrict__ rp, int64_t n_brow, int nb,
+                            const double* __restrict__ dinv, double* __restrict__ Sv) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(nb) * nb;
+    if (tid >= n_brow * per) return;
+    const int64_t row = tid / per;
+    const int rem = int(tid - row * per);
+    const int i = rem / nb, j = rem - (rem / nb) * nb;
+    const double* __restrict__ Dr = dinv + row * per + int64_t(i) * nb;
+    for (int32_t blk = rp[row]; blk < rp[row + 1]; ++blk) {
+        const double* __restrict__ Ab = Av + int64_t(blk) * per;
+        double acc = 0.0;
+        for (int k = 0; k < nb; ++k) acc += Dr[k] * Ab[int64_t(k) * nb + j];
+        Sv[int64_t(blk) * per + int64_t(i) * nb + j] = acc;
+    }
+}
+
+hipError_t launch_row_scale(const double* Av, const int32_t* rp, int64_t n_brow, int nb, const double* dinv,
+                            double* Sv, hipStream_t st) {
+    const int64_t tot = n_brow * nb * nb;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_scale, dim3(grid_for(tot)), dim3(WG), 0, st, Av, rp, n_brow, nb, dinv, Sv);
+    return hipGetLastError();
+}
+
+// RD = R D: block (J, col) of RD is R_blk (s x nb) times the diagonal block of
+// A in block row col, found at A_diag[col]; one thread per entry.
+__global__ void k_right_diag(const double* __restrict__ Rv, const int32_t* __restrict__ R_ci, int64_t nR, int nb,
+                             int s, const double* __restrict__ Av, const int32_t* __restrict__ A_diag,
+                             double* __restrict__ RDv) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(s) * nb;
+    if (tid >= nR * per) return;
+    const int64_t rb = tid / per;
+    const int rem = int(tid - rb * per);
+    const int l = rem / nb, j = rem - (rem / nb) * nb;
+    const double* __restrict__ Rr = Rv + rb * per + int64_t(l) * nb;
+    const double* __restrict__ D = Av + int64_t(A_diag[R_ci[rb]]) * nb * nb;
+    double acc = 0.0;
+    for (int k = 0; k < nb; ++k) acc += Rr[k] * D[int64_t(k) * nb + j];
+    RDv[tid] = acc;
+}
+
+hipError_t launch_right_diag(const double* Rv, const int32_t* R_ci, int64_t nR, int nb, int s, const double* Av,
+                             const int32_t* A_diag, double* RDv, hipStream_t st) {
+    const int64_t tot = nR * nb * s;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_right_diag, dim3(grid_for(tot)), dim3(WG), 0, st, Rv, R_ci, nR, nb, s, Av, A_diag, RDv);
     return hipGetLastError();
 }
 
@@ -1887,32 +1958,47 @@ hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, co
     return hipGetLastError();
 }
 
-// dense y = A x, one wavefront per row, lanes stride the columns
+// dense y = A x, one workgroup per row: its 256 threads stride the columns,
+// each keeping 4 loads of the row (and of x) in flight, and the four waves'
+// partial sums are added in a fixed order through LDS.
 template <int M>
 __global__ __launch_bounds__(WG) void k_gemv(const double* __restrict__ A, const double* __restrict__ x,
                                              double* __restrict__ y, int64_t n, int ld) {
-    const int64_t row = int64_t(blockIdx.x) * WAVES_PER_WG + (threadIdx.x >> 6);
-    if (row >= n) return;
-    const int lane = threadIdx.x & 63;
+    constexpr int U = 4;
+    __shared__ double red[WAVES_PER_WG][M];
+    const int64_t row = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double acc[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = 0.0;
-    const double* Ar = A + row * n;
-    for (int64_t j = lane; j < n; j += 64) {
-        const double a = Ar[j];
+    const double* __restrict__ Ar = A + row * n;
+    for (int64_t j0 = t; j0 < n; j0 += int64_t(WG) * U) {
+        double a[U], xv[U][M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) acc[c] += a * x[j * ld + c];
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + int64_t(u) * WG;
+            a[u] = j < n ? Ar[j] : 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) xv[u][c] = j < n ? x[j * ld + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + int64_t(u) * WG < n)
+#pragma unroll
+                for (int c = 0; c < M; ++c) acc[c] += a[u] * xv[u][c];
     }
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         const double v = wave_sum(acc[c]);
-        if (lane == 0) y[row * ld + c] = v;
+        if (lane == 0) red[wave][c] = v;
     }
+    __syncthreads();
+    if (t < M) y[row * ld + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
 hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n, int m, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    dim3 grid(grid_for(n, WAVES_PER_WG));
+    const dim3 grid{unsigned(n), 1u, 1u};
     int c0 = 0;
     while (c0 < m) {
         const int rem = m - c0;

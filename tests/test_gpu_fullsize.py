@@ -6,8 +6,9 @@
   Krylov iterations are compared with it directly.
 * 3D Poisson SIPG p=2 on 64^3 x 6 tetrahedra (15,728,640 dofs) with 16 columns:
   too large for the oracle's setup in seconds, so sampled element rows of the
-  16-column MFMA products are checked against the caller's own matrix on the
-  host, and the 16-column V-cycle against the single-column one.
+  16-column MFMA products (A x, the sweep, and the sweep on D^{-1} A) are
+  checked against the caller's own matrix on the host, and the 16-column
+  V-cycle against the single-column one.
 """
 import numpy as np
 import pytest
@@ -139,6 +140,15 @@ def test_fullsize_3d_mfma_products_and_vcycle():
         R = (B[dofs] - AX).reshape(len(elems), nb, m)
         want = X[dofs] + info.omega * np.einsum("eij,ejc->eic", Dinv, R).reshape(-1, m)
         scale = np.abs(X[dofs]).max() + info.omega * np.abs(Dinv).max() * nb * (np.abs(B).max() + np.abs(absAX).max())
+        err = np.abs(Y.double().cpu().numpy()[dofs] - want).max() / scale
+        assert err <= tol, (prec, err)
+        # the V-cycle's sweep on S = D^{-1} A, with B standing for D^{-1} b
+        am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP_SCALED, to_dev(X, dt), to_dev(B, dt), Y, precision=prec)
+        torch.cuda.synchronize()
+        SX = np.einsum("eij,ejc->eic", Dinv, AX.reshape(len(elems), nb, m)).reshape(-1, m)
+        absSX = np.einsum("eij,ejc->eic", np.abs(Dinv), absAX.reshape(len(elems), nb, m)).reshape(-1, m)
+        want = X[dofs] + info.omega * (B[dofs] - SX)
+        scale = np.abs(X[dofs]).max() + info.omega * (np.abs(B).max() + np.abs(absSX).max())
         err = np.abs(Y.double().cpu().numpy()[dofs] - want).max() / scale
         assert err <= tol, (prec, err)
         del Y

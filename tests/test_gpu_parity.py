@@ -105,7 +105,7 @@ def test_setup_parity(name):
 
 # ------------------------------------------------------------------ single kernels
 
-OPS = ["spmv", "sweep", "sweep0", "residual", "restrict", "prolong"]
+OPS = ["spmv", "sweep", "sweep0", "residual", "restrict", "prolong", "sweep_scaled", "restrict_scaled"]
 
 
 def host_op(op, k, h, w, x, b, prec):
@@ -118,8 +118,18 @@ def host_op(op, k, h, w, x, b, prec):
     R, _ = bsr_export(h, k, "R", (n1, n))
     Dinv = am.amgdg_export_level(h, k, am.AMGDG_DINV)
     om = info.omega
+    # the row-scaled operators of the V-cycle: S = D^{-1} A and R D, with D the
+    # diagonal blocks of A, formed in FP64 (then rounded, like A, for FP32);
+    # their error scales carry |D^{-1}| |A| and |R| |D|, the bounds of forming them
+    nb = info.nb
+    Ac = A.tocoo()
+    on = (Ac.row // nb) == (Ac.col // nb)
+    Dblk = sp.csr_matrix((Ac.data[on], (Ac.row[on], Ac.col[on])), shape=A.shape)
+    D64 = amg.blockdiag_csr(Dinv)
+    S, RD = (D64 @ A).tocsr(), (R @ Dblk).tocsr()
+    absDA, absRD = abs(D64) @ abs(A), abs(R) @ abs(Dblk)
     if prec == am.AMGDG_MIXED:
-        A, T, R = (M.astype(np.float32).astype(np.float64) for M in (A, T, R))
+        A, T, R, S, RD = (M.astype(np.float32).astype(np.float64) for M in (A, T, R, S, RD))
         Dinv = Dinv.astype(np.float32).astype(np.float64)
         om = float(np.float32(om))
     D = amg.blockdiag_csr(Dinv)
@@ -136,6 +146,10 @@ def host_op(op, k, h, w, x, b, prec):
         return R @ x, abs(R) @ abs(x)
     if op == "prolong":
         return b + T @ x, abs(b) + abs(T) @ abs(x)
+    if op == "sweep_scaled":
+        return x + om * (b - S @ x), abs(x) + om * (abs(b) + absDA @ abs(x))
+    if op == "restrict_scaled":
+        return RD @ x, absRD @ abs(x)
 
 
 @pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2"])
@@ -153,7 +167,7 @@ def test_single_kernels(name, prec, m):
         n, n1 = info.n, info.n_agg * info.s
         for op in OPS:
             nx = n1 if op == "prolong" else n
-            ny = n1 if op == "restrict" else n
+            ny = n1 if op.startswith("restrict") else n
             x = g.standard_normal((nx, m))
             b = g.standard_normal((ny, m))
             if prec == am.AMGDG_MIXED:
