@@ -219,6 +219,7 @@ def main():
         byts = sweep_bytes(infos[0], wb, m)
         kern[name] = dict(us=t * 1e6, gbps=byts / t / 1e9, bytes=byts)
         log(f"level-0 sweep {name}: {t * 1e6:.1f} us, {byts / 1e6:.1f} MB, {byts / t / 1e9:.0f} GB/s")
+    copy_gbps = _copy_bandwidth(torch, dev, stream)
 
     _copy_calibration(args, torch, dev)
 
@@ -263,6 +264,7 @@ def main():
             "traffic": measured_traffic("k_spmv<float, 1, 3>"),
             "bytes_per_launch": k["bytes"],
             "us_per_launch": k["us"],
+            "copy_GBps": copy_gbps,
         },
         "fp64": {
             "solves_per_s": m / fp64_t,
@@ -301,6 +303,24 @@ def _autotune(args, am, torch, h, m):
     log(f"autotune ({dt:.2f} s): " + "; ".join(
         f"L{k} lanes {t['lanes']} cols32 {t['cols32']} mfma32 {t['mfma32']}" for k, t in enumerate(shapes)))
     return {"seconds": dt, "levels": shapes}
+
+
+def _copy_bandwidth(torch, dev, stream, nbytes=2 << 30, reps=10):
+    """GB/s of a plain elementwise copy of nbytes (read + write counted), far
+    larger than the caches: the HBM rate a streaming kernel reaches on this part."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    del src, dst
+    log(f"elementwise copy of {nbytes / 1e9:.2f} GB: {2 * nbytes / t / 1e9:.0f} GB/s")
+    return 2 * nbytes / t / 1e9
 
 
 def _copy_calibration(args, torch, dev):

@@ -9,6 +9,7 @@ is missing, every call raises.
 """
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -191,7 +192,11 @@ class Plan:
             lib().amgdg_plan_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the module's globals may already be gone; the
+        # process's memory is released with it
+        if not _finalizing():
+            self.close()
 
 
 def amgdg_plan_create(n_elem, row_ptr, col_idx, n_levels, agg_of_elem):
@@ -220,7 +225,9 @@ class Handle:
             lib().amgdg_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():
+            self.close()
 
 
 def amgdg_setup(n_elem, nb, row_ptr, col_idx, vals, agg_of_elem, params, B1=None, adj_ptr=None, adj_idx=None,

@@ -153,7 +153,6 @@ struct Work {
     int64_t bytes = 0;  // device bytes held
     std::vector<VBuf<double>> v64;
     std::vector<VBuf<float>> v32;
-    double *cin = nullptr, *cout = nullptr;  // FP64 coarse solve of the FP32 V-cycle
     double *kb = nullptr, *kx = nullptr, *kr = nullptr, *kr2 = nullptr, *kz = nullptr, *kp = nullptr, *kq = nullptr,
            *kt = nullptr;
     double *kgin = nullptr, *kgout = nullptr;  // fixed input/output of the FP64 V-cycle graph
@@ -343,9 +342,12 @@ static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const
     if (br <= BCSR_MAXBR) {
         M.vec = true;
         const int64_t nnzb = int64_t(ci.size());
+        // lanes per block row: about one block each, or, for wide blocks (whose
+        // rows are read as one flat run of values), about 20 values each
         const double avg = n_brow > 0 ? double(nnzb) / double(n_brow) : 1.0;
+        const double want = bc >= 2 * br ? avg * br * bc / 20.0 : avg;
         int P = 4;
-        while (P < avg && P < 64) P *= 2;
+        while (P < want && P < 64) P *= 2;
         Bcsr<double> d;
         d.n_brow = int32_t(n_brow);
         d.br = br;
@@ -785,8 +787,6 @@ static int64_t work_layout(const Ctx& C, Work* W, int m, int restart) {
         }
     }
     const int64_t n = C.lv[0].n * m;
-    double* cin = get(d, C.nN * m);
-    double* cout = get(d, C.nN * m);
     double* kv[10];
     for (double*& p : kv) p = get(d, n);
     float* kr32 = C.mixed ? get(f, n) : nullptr;
@@ -799,8 +799,6 @@ static int64_t work_layout(const Ctx& C, Work* W, int m, int restart) {
     double* stat = get(d, ST_LEN);
     int32_t* mask = get(i, MASK_LEN);
     if (W) {
-        W->cin = cin;
-        W->cout = cout;
         W->kb = kv[0], W->kx = kv[1], W->kr = kv[2], W->kr2 = kv[3], W->kz = kv[4];
         W->kp = kv[5], W->kq = kv[6], W->kt = kv[7], W->kgin = kv[8], W->kgout = kv[9];
         W->kr32 = kr32, W->kz32 = kz32;
@@ -868,10 +866,8 @@ void coarse_solve<double>(Ctx& C, Work&, const double* b, double* u, int m, hipS
     HIPCHK(launch_gemv(C.Ainv, b, u, C.nN, m, st));
 }
 template <>
-void coarse_solve<float>(Ctx& C, Work& W, const float* b, float* u, int m, hipStream_t st) {
-    HIPCHK((launch_convert<float, double>(b, W.cin, C.nN * m, st)));
-    HIPCHK(launch_gemv(C.Ainv, W.cin, W.cout, C.nN, m, st));
-    HIPCHK((launch_convert<double, float>(W.cout, u, C.nN * m, st)));
+void coarse_solve<float>(Ctx& C, Work&, const float* b, float* u, int m, hipStream_t st) {
+    HIPCHK(launch_gemv<float>(C.Ainv, b, u, C.nN, m, st));
 }
 
 // z0 = V(b0), internal order, m columns (Algorithm 2, one pass from u = 0).

@@ -191,8 +191,10 @@ hipError_t launch_scatter_col(const double* in, int64_t ldi, double* out, int64_
                               int64_t n_units, int nb, hipStream_t st);
 // dst[i,c] = src[i,c] for the columns c with mask[c] != 0
 hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, const int32_t* mask, hipStream_t st);
-// y = Ainv x (dense, row-major n x n, FP64), m columns
-hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n, int m, hipStream_t st);
+// y = Ainv x (dense, row-major n x n, FP64, FP64 sums), m columns; V = float
+// vectors are widened on load and the result is rounded once on store
+template <typename V>
+hipError_t launch_gemv(const double* Ainv, const V* x, V* y, int64_t n, int m, hipStream_t st);
 // level-0 reorder: out[internal unit u] = in[caller element perm[u]] (gather) or the inverse (scatter)
 template <typename Ti, typename To>
 hipError_t launch_permute(const Ti* in, To* out, const int64_t* perm, int64_t n_units, int nb, int m,

@@ -322,6 +322,48 @@ __device__ __forceinline__ void bcsr_row(const Bcsr<T>& A, int64_t brow, bool va
     }
 }
 
+// The same sums for wide blocks (bc >= 2 br: the restriction, s x nb): the
+// values of a block row are contiguous, so the P lanes of the group stride
+// them as one flat run (value v is entry (v / bc % br, v % bc) of block
+// v / (br bc)); every value load of the group is coalesced.
+template <typename T, int M, int BR>
+__device__ __forceinline__ void bcsr_row_flat(const Bcsr<T>& A, int64_t brow, bool valid, int p,
+                                              const T* __restrict__ x, int ld, T (&acc)[BR][M]) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[i][c] = T(0);
+    if (valid) {
+        const int bc = A.bc, per = BR * bc;
+        const int beg = A.rp[brow];
+        const int nv = (A.rp[brow + 1] - beg) * per;
+        const T* __restrict__ a = A.vals + int64_t(beg) * per;
+        const int32_t* __restrict__ ci = A.ci + beg;
+#pragma unroll 4
+        for (int v = p; v < nv; v += A.P) {
+            const int bl = v / per;
+            const int rem = v - bl * per;
+            const int i = rem / bc, j = rem - i * bc;
+            const T av = a[v];
+            const T* __restrict__ xr = x + (int64_t(ci[bl]) * bc + j) * ld;
+            T xv[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) xv[c] = xr[c];
+#pragma unroll
+            for (int ii = 0; ii < BR; ++ii)
+                if (ii == i)
+#pragma unroll
+                    for (int c = 0; c < M; ++c) acc[ii][c] += av * xv[c];
+        }
+    }
+    for (int off = A.P >> 1; off > 0; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int c = 0; c < M; ++c) acc[i][c] += __shfl_xor(acc[i][c], off);
+    }
+}
+
 template <typename T, int M, int MODE, int BR>
 __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ y, T omega,
@@ -371,7 +413,7 @@ __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ 
     }
 }
 
-template <typename T, int M, int MODE, int BR>
+template <typename T, int M, int MODE, int BR, bool WIDE>
 __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
                                                T* __restrict__ y, int ld, T omega) {
     const int gpw = 64 / A.P;
@@ -381,7 +423,8 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
     const int64_t brow = wv * gpw + g;
     const bool valid = brow < A.n_brow;
     T acc[BR][M];
-    bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
+    if (WIDE) bcsr_row_flat<T, M, BR>(A, brow, valid, p, x, ld, acc);
+    else bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
     if (!valid || p >= BR) return;
     const int64_t row = brow * BR + p;
 #pragma unroll
@@ -420,13 +463,20 @@ static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T
     const int64_t waves = (A.n_brow + (64 / A.P) - 1) / (64 / A.P);
     if (waves == 0) return hipSuccess;
     dim3 grid(grid_for(waves, WAVES_PER_WG)), block(WG);
+    const bool wide = A.bc >= 2 * A.br;
+#define BSPMV_CASE(MD)                                                                                      \
+    case MD:                                                                                                \
+        if (wide) hipLaunchKernelGGL((k_bspmv<T, M, MD, BR, true>), grid, block, 0, st, A, x, b, y, ld, omega); \
+        else hipLaunchKernelGGL((k_bspmv<T, M, MD, BR, false>), grid, block, 0, st, A, x, b, y, ld, omega);   \
+        break;
     switch (mode) {
-        case AX: hipLaunchKernelGGL((k_bspmv<T, M, AX, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
-        case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
-        case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
-        case S_SWEEP: hipLaunchKernelGGL((k_bspmv<T, M, S_SWEEP, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        BSPMV_CASE(AX)
+        BSPMV_CASE(B_MINUS)
+        BSPMV_CASE(B_PLUS)
+        BSPMV_CASE(S_SWEEP)
         default: return hipErrorInvalidValue;
     }
+#undef BSPMV_CASE
     return hipGetLastError();
 }
 
@@ -1960,10 +2010,12 @@ hipError_t launch_copy_cols(const double* src, double* dst, int64_t n, int m, co
 
 // dense y = A x, one workgroup per row: its 256 threads stride the columns,
 // each keeping 4 loads of the row (and of x) in flight, and the four waves'
-// partial sums are added in a fixed order through LDS.
-template <int M>
-__global__ __launch_bounds__(WG) void k_gemv(const double* __restrict__ A, const double* __restrict__ x,
-                                             double* __restrict__ y, int64_t n, int ld) {
+// partial sums are added in a fixed order through LDS.  A and the sums are
+// FP64; x and y are of type V (FP32 vectors are widened on load and the
+// result rounded once on store).
+template <typename V, int M>
+__global__ __launch_bounds__(WG) void k_gemv(const double* __restrict__ A, const V* __restrict__ x,
+                                             V* __restrict__ y, int64_t n, int ld) {
     constexpr int U = 4;
     __shared__ double red[WAVES_PER_WG][M];
     const int64_t row = blockIdx.x;
@@ -1979,7 +2031,7 @@ __global__ __launch_bounds__(WG) void k_gemv(const double* __restrict__ A, const
             const int64_t j = j0 + int64_t(u) * WG;
             a[u] = j < n ? Ar[j] : 0.0;
 #pragma unroll
-            for (int c = 0; c < M; ++c) xv[u][c] = j < n ? x[j * ld + c] : 0.0;
+            for (int c = 0; c < M; ++c) xv[u][c] = j < n ? double(x[j * ld + c]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -1993,10 +2045,11 @@ __global__ __launch_bounds__(WG) void k_gemv(const double* __restrict__ A, const
         if (lane == 0) red[wave][c] = v;
     }
     __syncthreads();
-    if (t < M) y[row * ld + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    if (t < M) y[row * ld + t] = V((red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
 }
 
-hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n, int m, hipStream_t st) {
+template <typename V>
+hipError_t launch_gemv(const double* Ainv, const V* x, V* y, int64_t n, int m, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const dim3 grid{unsigned(n), 1u, 1u};
     int c0 = 0;
@@ -2004,17 +2057,19 @@ hipError_t launch_gemv(const double* Ainv, const double* x, double* y, int64_t n
         const int rem = m - c0;
         const int w = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem;
         switch (w) {
-            case 16: hipLaunchKernelGGL((k_gemv<16>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
-            case 8: hipLaunchKernelGGL((k_gemv<8>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
-            case 4: hipLaunchKernelGGL((k_gemv<4>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
-            case 3: hipLaunchKernelGGL((k_gemv<3>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
-            case 2: hipLaunchKernelGGL((k_gemv<2>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
-            default: hipLaunchKernelGGL((k_gemv<1>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 16: hipLaunchKernelGGL((k_gemv<V, 16>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 8: hipLaunchKernelGGL((k_gemv<V, 8>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 4: hipLaunchKernelGGL((k_gemv<V, 4>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 3: hipLaunchKernelGGL((k_gemv<V, 3>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            case 2: hipLaunchKernelGGL((k_gemv<V, 2>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
+            default: hipLaunchKernelGGL((k_gemv<V, 1>), grid, dim3(WG), 0, st, Ainv, x + c0, y + c0, n, m); break;
         }
         c0 += w;
     }
     return hipGetLastError();
 }
+template hipError_t launch_gemv<double>(const double*, const double*, double*, int64_t, int, hipStream_t);
+template hipError_t launch_gemv<float>(const double*, const float*, float*, int64_t, int, hipStream_t);
 
 // Admission of one right-hand side into column c of a batch (row-major n x ld
 // arrays): b is gathered from the caller's array (stride ldb, rows reordered by
