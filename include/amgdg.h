@@ -303,8 +303,7 @@ int amgdg_server_destroy(amgdg_server s);
  * handle's captured V-cycles; not to be called while a server uses the
  * handle.  Untuned shapes: 4 (FP64) / 8 (FP32) columns per sliced launch, 16
  * per block-CSR launch, 4 MFMA blocks ahead, and lanes per block row the power
- * of two >= the mean blocks per row, or >= the mean values per row / 20 for
- * wide blocks (bc >= 2 br, the restriction) (4..64). */
+ * of two >= the mean blocks per row (4..64). */
 #define AMGDG_TUNE_LANES 1
 int amgdg_autotune(amgdg_handle h, int32_t m, int32_t flags, void* stream);
 /* The shapes in use on level k (0..levels-2) for m columns, out[16]:

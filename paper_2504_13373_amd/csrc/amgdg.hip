@@ -342,12 +342,9 @@ static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const
     if (br <= BCSR_MAXBR) {
         M.vec = true;
         const int64_t nnzb = int64_t(ci.size());
-        // lanes per block row: about one block each, or, for wide blocks (whose
-        // rows are read as one flat run of values), about 20 values each
         const double avg = n_brow > 0 ? double(nnzb) / double(n_brow) : 1.0;
-        const double want = bc >= 2 * br ? avg * br * bc / 20.0 : avg;
         int P = 4;
-        while (P < want && P < 64) P *= 2;
+        while (P < avg && P < 64) P *= 2;
         Bcsr<double> d;
         d.n_brow = int32_t(n_brow);
         d.br = br;
@@ -368,6 +365,11 @@ static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const
             float* fv = C.mem.alloc<float>(M.n_vals);
             HIPCHK(launch_f64_to_f32(nat_d, fv, M.n_vals, st));
             M.bf.vals = fv;
+        }
+        // the same natural blocks, read by the MFMA tiles at multiples of 16 columns
+        if (bc <= NBSR_MAXB) {
+            M.nd.n_brow = d.n_brow, M.nd.br = br, M.nd.bc = bc, M.nd.rp = d.rp, M.nd.ci = d.ci, M.nd.vals = nat_d;
+            M.nf.n_brow = d.n_brow, M.nf.br = br, M.nf.bc = bc, M.nf.rp = d.rp, M.nf.ci = d.ci, M.nf.vals = M.bf.vals;
         }
     } else {
         M.vec = false;
@@ -431,12 +433,13 @@ const double* dinv_nat_of<double>(const Level& L) { return L.Dinv_nat; }
 template <>
 const float* dinv_nat_of<float>(const Level& L) { return L.Dinv_nat32; }
 
-// 16-column tiles of a sliced (tall-block) matrix go through the MFMA kernel:
-// one read of the matrix per 16 columns instead of one per 4 (FP64) or 8
-// (FP32) columns.
+// 16-column tiles go through the MFMA kernel (blocks up to 16 x 16): for a
+// sliced (tall-block) matrix one read of it per 16 columns instead of one per
+// 4 (FP64) or 8 (FP32) columns; for the block-CSR operators 16-value x rows
+// loaded by 16 lanes and one wavefront per block row.
 template <typename T>
 static bool use_mfma(const MatStore& M, int m) {
-    return !M.vec && m % MFMA_COLS == 0 && nsel<T>(M).vals != nullptr;
+    return m % MFMA_COLS == 0 && nsel<T>(M).vals != nullptr;
 }
 template <typename T>
 static int cap_of(const MatStore& M, int m) {
@@ -451,7 +454,7 @@ static int mfu_of(const MatStore& M, int m) {
 template <typename T>
 static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, int m, hipStream_t st,
                      T omega = T(0)) {
-    if (M.vec) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m), omega));
+    if (M.vec && !use_mfma<T>(M, m)) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m), omega));
     else if (use_mfma<T>(M, m))
         HIPCHK(launch_mfma<T>(mode == AX ? MF_AX : mode == B_MINUS ? MF_BMINUS : mode == B_PLUS ? MF_BPLUS : MF_SSWEEP,
                               nsel<T>(M), nullptr, x, b, y, omega, m, st, mfu_of<T>(M, m)));

@@ -62,12 +62,20 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     const int TQ = (Tn + VW - 1) / VW;
     const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
     T* xr = xs + g * TP * M;
+    // rows of M values move as 16-byte vectors when the stride and the base allow
+    const bool vx = M % VW == 0 && ld % VW == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     if (lane < L) {
         if (i < bc) {
             for (int kk = 0; kk < K; ++kk) {
                 const T* __restrict__ src = x + (int64_t(cp[kk * G]) * bc + i) * ld;
+                T* dst = xr + (kk * bc + i) * M;
+                if (vx) {
 #pragma unroll
-                for (int c = 0; c < M; ++c) xr[(kk * bc + i) * M + c] = src[c];
+                    for (int q = 0; q < M / VW; ++q) reinterpret_cast<V*>(dst)[q] = reinterpret_cast<const V*>(src)[q];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < M; ++c) dst[c] = src[c];
+                }
             }
         }
         for (int t = Tn + i; t < TQ * VW; t += A.br)
@@ -295,6 +303,11 @@ __device__ __forceinline__ void bcsr_row(const Bcsr<T>& A, int64_t brow, bool va
     for (int i = 0; i < BR; ++i)
 #pragma unroll
         for (int c = 0; c < M; ++c) acc[i][c] = T(0);
+    // the M values of an x row are read as 16-byte vectors when the row stride
+    // and the base keep them aligned (the same values, so the same sums)
+    constexpr int VW = 16 / int(sizeof(T));
+    using V = typename Vec16<T>::type;
+    const bool vx = M % VW == 0 && ld % VW == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     if (valid) {
         const int bc = A.bc;
         const int e = A.rp[brow + 1];
@@ -303,8 +316,14 @@ __device__ __forceinline__ void bcsr_row(const Bcsr<T>& A, int64_t brow, bool va
             const T* __restrict__ a = A.vals + int64_t(blk) * BR * bc;
             for (int j = 0; j < bc; ++j) {
                 T xv[M];
+                const T* __restrict__ xr = x + (cb + j) * ld;
+                if (vx) {
 #pragma unroll
-                for (int c = 0; c < M; ++c) xv[c] = x[(cb + j) * ld + c];
+                    for (int q = 0; q < M / VW; ++q) *reinterpret_cast<V*>(xv + q * VW) = reinterpret_cast<const V*>(xr)[q];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < M; ++c) xv[c] = xr[c];
+                }
 #pragma unroll
                 for (int i = 0; i < BR; ++i) {
                     const T av = a[i * bc + j];
@@ -312,48 +331,6 @@ __device__ __forceinline__ void bcsr_row(const Bcsr<T>& A, int64_t brow, bool va
                     for (int c = 0; c < M; ++c) acc[i][c] += av * xv[c];
                 }
             }
-        }
-    }
-    for (int off = A.P >> 1; off > 0; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < BR; ++i)
-#pragma unroll
-            for (int c = 0; c < M; ++c) acc[i][c] += __shfl_xor(acc[i][c], off);
-    }
-}
-
-// The same sums for wide blocks (bc >= 2 br: the restriction, s x nb): the
-// values of a block row are contiguous, so the P lanes of the group stride
-// them as one flat run (value v is entry (v / bc % br, v % bc) of block
-// v / (br bc)); every value load of the group is coalesced.
-template <typename T, int M, int BR>
-__device__ __forceinline__ void bcsr_row_flat(const Bcsr<T>& A, int64_t brow, bool valid, int p,
-                                              const T* __restrict__ x, int ld, T (&acc)[BR][M]) {
-#pragma unroll
-    for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int c = 0; c < M; ++c) acc[i][c] = T(0);
-    if (valid) {
-        const int bc = A.bc, per = BR * bc;
-        const int beg = A.rp[brow];
-        const int nv = (A.rp[brow + 1] - beg) * per;
-        const T* __restrict__ a = A.vals + int64_t(beg) * per;
-        const int32_t* __restrict__ ci = A.ci + beg;
-#pragma unroll 4
-        for (int v = p; v < nv; v += A.P) {
-            const int bl = v / per;
-            const int rem = v - bl * per;
-            const int i = rem / bc, j = rem - i * bc;
-            const T av = a[v];
-            const T* __restrict__ xr = x + (int64_t(ci[bl]) * bc + j) * ld;
-            T xv[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) xv[c] = xr[c];
-#pragma unroll
-            for (int ii = 0; ii < BR; ++ii)
-                if (ii == i)
-#pragma unroll
-                    for (int c = 0; c < M; ++c) acc[ii][c] += av * xv[c];
         }
     }
     for (int off = A.P >> 1; off > 0; off >>= 1) {
@@ -413,7 +390,7 @@ __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ 
     }
 }
 
-template <typename T, int M, int MODE, int BR, bool WIDE>
+template <typename T, int M, int MODE, int BR>
 __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
                                                T* __restrict__ y, int ld, T omega) {
     const int gpw = 64 / A.P;
@@ -423,8 +400,7 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
     const int64_t brow = wv * gpw + g;
     const bool valid = brow < A.n_brow;
     T acc[BR][M];
-    if (WIDE) bcsr_row_flat<T, M, BR>(A, brow, valid, p, x, ld, acc);
-    else bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
+    bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
     if (!valid || p >= BR) return;
     const int64_t row = brow * BR + p;
 #pragma unroll
@@ -463,20 +439,13 @@ static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T
     const int64_t waves = (A.n_brow + (64 / A.P) - 1) / (64 / A.P);
     if (waves == 0) return hipSuccess;
     dim3 grid(grid_for(waves, WAVES_PER_WG)), block(WG);
-    const bool wide = A.bc >= 2 * A.br;
-#define BSPMV_CASE(MD)                                                                                      \
-    case MD:                                                                                                \
-        if (wide) hipLaunchKernelGGL((k_bspmv<T, M, MD, BR, true>), grid, block, 0, st, A, x, b, y, ld, omega); \
-        else hipLaunchKernelGGL((k_bspmv<T, M, MD, BR, false>), grid, block, 0, st, A, x, b, y, ld, omega);   \
-        break;
     switch (mode) {
-        BSPMV_CASE(AX)
-        BSPMV_CASE(B_MINUS)
-        BSPMV_CASE(B_PLUS)
-        BSPMV_CASE(S_SWEEP)
+        case AX: hipLaunchKernelGGL((k_bspmv<T, M, AX, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        case S_SWEEP: hipLaunchKernelGGL((k_bspmv<T, M, S_SWEEP, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
         default: return hipErrorInvalidValue;
     }
-#undef BSPMV_CASE
     return hipGetLastError();
 }
 
