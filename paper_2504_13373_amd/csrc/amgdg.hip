@@ -159,6 +159,7 @@ struct Work {
     float *kr32 = nullptr, *kz32 = nullptr;
     double *V = nullptr, *Z = nullptr;  // FGMRES basis
     double *scratch = nullptr, *scal = nullptr, *kpart = nullptr, *stat = nullptr;
+    double* kslice = nullptr;  // per-slice partials of the level-0 product A p with p.(A p)
     int32_t* mask = nullptr;
     double* stat_h = nullptr;   // pinned
     int32_t* mask_h = nullptr;  // pinned
@@ -799,6 +800,7 @@ static int64_t work_layout(const Ctx& C, Work* W, int m, int restart) {
     double* scratch = get(d, int64_t(DOT_PARTS) * 64 + 1024);
     double* scal = get(d, 2048);
     double* kpart = get(d, 2 * 16 * (KRY_BLOCKS + 1) + 64);
+    double* kslice = get(d, (C.lv[0].A.vec ? 1 : int64_t(C.lv[0].A.s.d.n_slices)) * 8);
     double* stat = get(d, ST_LEN);
     int32_t* mask = get(i, MASK_LEN);
     if (W) {
@@ -807,6 +809,7 @@ static int64_t work_layout(const Ctx& C, Work* W, int m, int restart) {
         W->kr32 = kr32, W->kz32 = kz32;
         W->V = V, W->Z = Z;
         W->scratch = scratch, W->scal = scal, W->kpart = kpart, W->stat = stat, W->mask = mask;
+        W->kslice = kslice;
     }
     return bytes;
 }
@@ -1238,9 +1241,9 @@ struct CgBatch : Engine {
         }
         upload_mask(MASK_UPD, last_upd);
         HIPCHK(launch_cg_update(W->kx, r, flexible ? rn : r, W->kp, W->kq, mixed ? W->kr32 : nullptr, n, m, d_rz, d_pq,
-                                W->mask + MASK_UPD, W->kpart, W->stat + ST_RR, flags_d, st));
+                                W->mask + MASK_UPD, W->kpart, W->stat + ST_RR, flags_d, st, W->stat, W->stat_h, ST_TR));
         if (flexible) std::swap(r, rn);  // r: new residual, rn: previous
-        HIPCHK(hipMemcpyAsync(W->stat_h, W->stat, sizeof(double) * ST_TR, hipMemcpyDeviceToHost, st));
+        // (the update's last finalize has mirrored the status record [0, ST_TR) to stat_h)
         HIPCHK(hipEventRecord(W->ev, st));
         apply_M(d_rz2, flexible ? rn : nullptr, flexible ? d_zro : nullptr);
         phase = WAIT_STATUS;
@@ -1365,8 +1368,14 @@ struct CgBatch : Engine {
             upload_mask(MASK_DIR, last_dir);
             HIPCHK(launch_cg_dir(W->kp, W->kz, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz, W->mask + MASK_DIR, st));
             std::swap(d_rz, d_rz2);
-            mat_spmv<double>(AX, C->lv[0].A, W->kp, nullptr, W->kq, m, st);
-            HIPCHK(launch_dot_tail(W->kp, W->kq, n, m, W->kpart, d_pq, st));
+            const MatStore& A0 = C->lv[0].A;
+            if (!A0.vec && !use_mfma<double>(A0, m)) {
+                // q = A p with p.q from per-slice partials of the product itself
+                HIPCHK(launch_spmv_dot(sel<double>(A0.s), W->kp, W->kq, m, W->kslice, d_pq, st, cap_of<double>(A0, m)));
+            } else {
+                mat_spmv<double>(AX, A0, W->kp, nullptr, W->kq, m, st);
+                HIPCHK(launch_dot_tail(W->kp, W->kq, n, m, W->kpart, d_pq, st));
+            }
         }
         issue();
     }

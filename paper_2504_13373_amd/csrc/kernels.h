@@ -68,6 +68,7 @@ enum SpmvMode : int {
     B_PLUS = 2,  // y = b + A x
     S_SWEEP = 3, // y = x + omega (b - A x): the block-Jacobi sweep on the row-scaled
                  // operator A = D^{-1} A_k, with b = D^{-1} b_k
+    AX_DOT = 4,  // y = A x, and one partial of x . y per workgroup and column (launch_spmv_dot)
 };
 
 // D^{-1} in sliced layout: the br x br block of block row g is stored like a
@@ -82,6 +83,12 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap = 0,
                        T omega = T(0));
+// y = A x and xy[c] = x[:,c] . y[:,c] (FP64, sliced layout): each workgroup of
+// the product writes one partial sum per column (its four slices in order) to
+// part (n_slices * 8 doubles suffice), which a one-workgroup kernel adds in a
+// fixed order (the same for every column count)
+hipError_t launch_spmv_dot(const Sell<double>& A, const double* x, double* y, int m, double* part, double* xy,
+                           hipStream_t st, int cap = 0);
 // the same operations on a block-CSR matrix; dinv: natural layout (n_brow x br x br);
 // cap: 1, 2, 4, 8 or 16 columns per launch (0: 16)
 template <typename T>
@@ -169,9 +176,12 @@ hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, d
 // CG update of m columns: alpha = active ? rz / pq : 0 (flag[c] |= 1 if an active pq <= 0,
 // 2 if alpha or rr[c] is not finite); x += alpha p; r_out = r_in - alpha q; r32 = float(r_out)
 // if r32 != NULL; rr[c] = ||r_out[:,c]||^2.  flag holds one int32 per column.
+// With stat_host (pinned host memory), the last finalize also copies the
+// stat_len doubles at stat (device) there, after rr and the flags are final.
 hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const double* p, const double* q,
                             float* r32, int64_t n, int m, const double* rz, const double* pq,
-                            const int32_t* active, double* part, double* rr, int32_t* flag, hipStream_t st);
+                            const int32_t* active, double* part, double* rr, int32_t* flag, hipStream_t st,
+                            const double* stat = nullptr, double* stat_host = nullptr, int stat_len = 0);
 // z = double(z32) if z32 != NULL; rz[c] = r.z ; zro[c] = z.r_old if r_old != NULL
 hipError_t launch_zdots(const float* z32, double* z, const double* r, const double* r_old, int64_t n, int m,
                         double* part, double* rz, double* zro, hipStream_t st);

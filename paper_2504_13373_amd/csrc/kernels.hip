@@ -162,23 +162,41 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
 
 template <typename T, int M, int MODE>
 __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
-                                              T* __restrict__ y, int ldx, int ldy, T omega) {
+                                              T* __restrict__ y, int ldx, int ldy, T omega, T* __restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
-    if (slice >= A.n_slices) return;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int slice = wg * WAVES_PER_WG + wave;
+    const bool live = slice < A.n_slices;
+    if (!live && MODE != AX_DOT) return;  // AX_DOT: every wave reaches the workgroup barrier
     const int L = A.L, br = A.br, G = A.G;
     const int lc = lane < L ? lane : L - 1;
     const int g = lc / br;
     const int i = lc - g * br;
     const int64_t brow = int64_t(slice) * G + g;
-    const bool own = lane < L && brow < A.n_brow;
+    const bool own = live && lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
     T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * A.tpad * M;
     T acc[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = T(0);
-    sell_row<T, M>(A, slice, lane, lc, g, i, x, ldx, xs, acc, T(1));
+    if (live) sell_row<T, M>(A, slice, lane, lc, g, i, x, ldx, xs, acc, T(1));
+    if (MODE == AX_DOT) {
+        // the workgroup's partial of x . y per column: lanes of each wave by an
+        // xor tree, then the four waves in order
+        __shared__ T red[WAVES_PER_WG][M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            T v = own ? x[row * ldx + c] * acc[c] : T(0);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) red[wave][c] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < M)
+            part[int64_t(threadIdx.x) * gridDim.x + wg] =
+                (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    }
     if (!own) return;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
@@ -208,15 +226,16 @@ static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x,
 
 template <typename T, int M>
 static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int ldx, int ldy,
-                         hipStream_t st, T omega) {
+                         hipStream_t st, T omega, T* part = nullptr) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
     const size_t lds = size_t(WAVES_PER_WG) * A.G * A.tpad * M * sizeof(T);
     switch (mode) {
-        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
-        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
-        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
-        case S_SWEEP: hipLaunchKernelGGL((k_spmv<T, M, S_SWEEP>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega); break;
+        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
+        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
+        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
+        case S_SWEEP: hipLaunchKernelGGL((k_spmv<T, M, S_SWEEP>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
+        case AX_DOT: hipLaunchKernelGGL((k_spmv<T, M, AX_DOT>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1486,11 +1505,25 @@ __device__ __forceinline__ void block_partials(double (&s)[M], double* __restric
 // flag[c] |= 2 if sum c is not finite (flag may be NULL).
 __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part, int np, int mt,
                                                  double* __restrict__ out1, int split, double* __restrict__ out2,
-                                                 int32_t* __restrict__ flag) {
+                                                 int32_t* __restrict__ flag, const uint32_t* __restrict__ msrc = nullptr,
+                                                 uint32_t* __restrict__ mdst = nullptr, int mwords = 0) {
     __shared__ double sh[WG];
     for (int c = 0; c < mt; ++c) {
-        double v = 0.0;
-        for (int i = threadIdx.x; i < np; i += WG) v += part[int64_t(c) * np + i];
+        // thread t adds the partials t + WG k in four interleaved sums (k mod 4),
+        // so four loads are in flight; the order is fixed by np alone
+        const double* __restrict__ pc = part + int64_t(c) * np;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = threadIdx.x;
+        for (; i + 3 * WG < np; i += 4 * WG) {
+            a0 += pc[i];
+            a1 += pc[i + WG];
+            a2 += pc[i + 2 * WG];
+            a3 += pc[i + 3 * WG];
+        }
+        if (i < np) a0 += pc[i];
+        if (i + WG < np) a1 += pc[i + WG];
+        if (i + 2 * WG < np) a2 += pc[i + 2 * WG];
+        const double v = (a0 + a1) + (a2 + a3);
         sh[threadIdx.x] = v;
         __syncthreads();
         for (int o = WG / 2; o > 0; o >>= 1) {
@@ -1503,6 +1536,14 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part
             if (flag && !isfinite(sh[0])) atomicOr(flag + c, 2);
         }
         __syncthreads();
+    }
+    // optional mirror of a status record into pinned host memory: agent-scope
+    // loads see this kernel's sums, system-scope stores write through to the host
+    if (mdst) {
+        __syncthreads();
+        for (int w = threadIdx.x; w < mwords; w += WG)
+            __hip_atomic_store(mdst + w, __hip_atomic_load(msrc + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1907,11 +1948,36 @@ hipError_t launch_dot_tail(const double* a, const double* b, int64_t n, int m, d
     });
 }
 
+hipError_t launch_spmv_dot(const Sell<double>& A, const double* x, double* y, int m, double* part, double* xy,
+                           hipStream_t st, int cap) {
+    int c0 = 0;
+    while (c0 < m) {
+        const int w = sell_chunk<double>(m - c0, A, false, cap);
+        if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(double) > 65536) return hipErrorInvalidConfiguration;
+        hipError_t e;
+        switch (w) {
+            case 8: e = spmv_m<double, 8>(AX_DOT, A, x + c0, nullptr, y + c0, m, m, st, 0.0, part); break;
+            case 4: e = spmv_m<double, 4>(AX_DOT, A, x + c0, nullptr, y + c0, m, m, st, 0.0, part); break;
+            case 3: e = spmv_m<double, 3>(AX_DOT, A, x + c0, nullptr, y + c0, m, m, st, 0.0, part); break;
+            case 2: e = spmv_m<double, 2>(AX_DOT, A, x + c0, nullptr, y + c0, m, m, st, 0.0, part); break;
+            default: e = spmv_m<double, 1>(AX_DOT, A, x + c0, nullptr, y + c0, m, m, st, 0.0, part); break;
+        }
+        if (e != hipSuccess) return e;
+        if (A.n_slices > 0)
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(grid_for(A.n_slices, WAVES_PER_WG)), w,
+                               xy + c0, w, static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr));
+        c0 += w;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const double* p, const double* q,
                             float* r32, int64_t n, int m, const double* rz, const double* pq,
-                            const int32_t* active, double* part, double* rr, int32_t* flag, hipStream_t st) {
+                            const int32_t* active, double* part, double* rr, int32_t* flag, hipStream_t st,
+                            const double* stat, double* stat_host, int stat_len) {
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
+        const bool last = c0 + w == m && stat_host;
         if (co_ok(m, w) && r_in == r_out) {
             CO_DISPATCH(w, k_cg_update_co_ip, dim3(g), dim3(WG), 0, st, x, r_out, p, q, r32, n, rz, pq, active, part,
                         flag)
@@ -1926,7 +1992,9 @@ hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const 
                          r32 ? r32 + c0 : nullptr, n, m, rz + c0, pq + c0, active + c0, part, flag + c0)
         }
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), w, rr + c0, w,
-                           static_cast<double*>(nullptr), flag + c0);
+                           static_cast<double*>(nullptr), flag + c0,
+                           last ? reinterpret_cast<const uint32_t*>(stat) : nullptr,
+                           last ? reinterpret_cast<uint32_t*>(stat_host) : nullptr, last ? 2 * stat_len : 0);
         return hipGetLastError();
     });
 }
