@@ -633,6 +633,7 @@ def serve_bench(am, h, n, dev, n_req, width, rate, maxit):
         "p99_latency_s": float(np.percentile(lat, 99)),
         "mean_iterations": float(its.mean()),
         "all_converged": bool(all(out[i][0] == am.AMGDG_OK and out[i][2] <= 1e-8 for i in range(n_req))),
+        "batch_bytes": am.amgdg_batch_bytes(h, width),
     }
 
 
