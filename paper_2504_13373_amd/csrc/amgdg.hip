@@ -477,6 +477,22 @@ static void mat_sweep(int mode, const Level& L, const T* x, const T* b, T* y, T 
 }
 
 
+// y = omega D'^{-1} (R x), y2 = D'^{-1} (R x) with D'^{-1} and omega of the level
+// R restricts to (its first sweep from zero on the right-hand side R x), when
+// R is stored as block CSR or runs on the MFMA tiles; false if not possible.
+template <typename T>
+static bool restrict_start(const MatStore& R, const Level& Ln, const T* x, T* y, T* y2, int m, hipStream_t st) {
+    const T* dinv = dinv_nat_of<T>(Ln);
+    if (!dinv) return false;
+    if (use_mfma<T>(R, m))
+        HIPCHK(launch_mfma<T>(MF_RDINV, nsel<T>(R), dinv, x, nullptr, y, T(Ln.omega), m, st, mfu_of<T>(R, m), y2));
+    else if (R.vec)
+        HIPCHK(launch_bspmv<T>(AX_DSCALE, bsel<T>(R), x, nullptr, y, m, st, cap_of<T>(R, m), T(Ln.omega), dinv, y2));
+    else
+        return false;
+    return true;
+}
+
 // blocking dot products through the partials buffer `part` and device scalars `out`
 static double dot1(double* part, double* out, const double* a, const double* b, int64_t n, hipStream_t st) {
     HIPCHK(launch_dot<double>(a, b, n, 1, part, out, st));
@@ -885,6 +901,7 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
         coarse_solve<T>(C, W, b0, z0, m, st);
         return;
     }
+    bool started = false;  // level k's first sweep was done by the restriction into it
     for (int k = 0; k < N; ++k) {
         Level& L = C.lv[k];
         VBuf<T>& V = vbuf<T>(W, k);
@@ -899,7 +916,7 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
             HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * L.n * m, st));
             mat_sweep<T>(SWEEP0, L, nullptr, bk, V.c, T(1), m, nullptr, st);
         } else {
-            mat_sweep<T>(SWEEP0, L, nullptr, bk, cur, om, m, nullptr, st, V.c);
+            if (!started) mat_sweep<T>(SWEEP0, L, nullptr, bk, cur, om, m, nullptr, st, V.c);
             for (int t = 1; t < tpre; ++t) {
                 mat_spmv<T>(S_SWEEP, L.S, cur, V.c, oth, m, st, om);
                 std::swap(cur, oth);
@@ -908,7 +925,14 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
         V.cur = cur;
         // R (b - A u) = RD (c - S u)
         mat_spmv<T>(B_MINUS, L.S, cur, V.c, V.r, m, st);
-        mat_spmv<T>(AX, L.RD, V.r, nullptr, vbuf<T>(W, k + 1).b, m, st);
+        // Into a non-coarsest level the restriction also takes that level's first
+        // sweep: it writes omega D^{-1} b_{k+1} and c_{k+1} = D^{-1} b_{k+1} (the
+        // same operations as the first sweep on the stored b_{k+1}); b_{k+1}
+        // itself is not needed then.
+        VBuf<T>& Vn = vbuf<T>(W, k + 1);
+        started = k + 1 < N && tpre > 0 &&
+                  restrict_start<T>(L.RD, C.lv[k + 1], V.r, Vn.u, Vn.c, m, st);
+        if (!started) mat_spmv<T>(AX, L.RD, V.r, nullptr, Vn.b, m, st);
     }
     {
         VBuf<T>& V = vbuf<T>(W, N);

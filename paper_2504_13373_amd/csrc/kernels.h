@@ -69,6 +69,8 @@ enum SpmvMode : int {
     S_SWEEP = 3, // y = x + omega (b - A x): the block-Jacobi sweep on the row-scaled
                  // operator A = D^{-1} A_k, with b = D^{-1} b_k
     AX_DOT = 4,  // y = A x, and one partial of x . y per workgroup and column (launch_spmv_dot)
+    AX_DSCALE = 5, // y = omega D'^{-1} (A x), y2 = D'^{-1} (A x), D'^{-1} the br x br blocks of the
+                   // output rows (block CSR only): a restriction that starts the coarse smoothing
 };
 
 // D^{-1} in sliced layout: the br x br block of block row g is stored like a
@@ -96,7 +98,7 @@ hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, 
                          const int32_t* colmask, hipStream_t st, int cap = 0, T* y2 = nullptr);
 template <typename T>
 hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st,
-                        int cap = 0, T omega = T(0));
+                        int cap = 0, T omega = T(0), const T* dinv = nullptr, T* y2 = nullptr);
 
 // MFMA products of 16-column tiles (m a multiple of 16, row-major n x m
 // vectors): one wavefront per block row computes the block row's br x 16 tile
@@ -104,9 +106,10 @@ hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y
 // type of T); then, by mode:
 //   MF_AX y = A x, MF_BMINUS y = b - A x, MF_BPLUS y = b + A x,
 //   MF_SWEEP y = x + omega D^{-1} (b - A x), MF_SWEEP0 y = omega D^{-1} b (and
-//   y2 = D^{-1} b when y2 is not null), MF_SSWEEP y = x + omega (b - A x)
+//   y2 = D^{-1} b when y2 is not null), MF_SSWEEP y = x + omega (b - A x),
+//   MF_RDINV y = omega D^{-1} (A x), y2 = D^{-1} (A x)
 // with D^{-1} natural (n_brow x br x br, row-major), applied by MFMA too.
-enum MfmaMode : int { MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4, MF_SSWEEP = 5 };
+enum MfmaMode : int { MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4, MF_SSWEEP = 5, MF_RDINV = 6 };
 // u: blocks whose operand fragments are loaded before their products (1, 2 or 4;
 // 0: 4); it does not change the arithmetic.
 template <typename T>

@@ -411,7 +411,8 @@ __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ 
 
 template <typename T, int M, int MODE, int BR>
 __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, int ld, T omega) {
+                                               T* __restrict__ y, int ld, T omega, const T* __restrict__ dinv,
+                                               T* __restrict__ y2) {
     const int gpw = 64 / A.P;
     const int64_t wv = int64_t(xcd_remap(blockIdx.x, gridDim.x)) * WAVES_PER_WG + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -422,6 +423,26 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
     bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
     if (!valid || p >= BR) return;
     const int64_t row = brow * BR + p;
+    if (MODE == AX_DSCALE) {
+        // row p of D'^{-1} (the output rows' own block) applied to the block row's
+        // product: the operations of a first sweep whose right-hand side is A x
+        T o[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) o[c] = T(0);
+        const T* __restrict__ dr = dinv + (brow * BR + p) * BR;
+#pragma unroll
+        for (int j = 0; j < BR; ++j) {
+            const T d = dr[j];
+#pragma unroll
+            for (int c = 0; c < M; ++c) o[c] += d * acc[j][c];
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            y[row * ld + c] = omega * o[c];
+            y2[row * ld + c] = o[c];
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < BR; ++i) {
         if (i != p) continue;
@@ -454,15 +475,16 @@ static hipError_t bsweep_mb(int mode, const Bcsr<T>& A, const T* dinv, const T* 
 
 template <typename T, int M, int BR>
 static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st,
-                           T omega) {
+                           T omega, const T* dinv, T* y2) {
     const int64_t waves = (A.n_brow + (64 / A.P) - 1) / (64 / A.P);
     if (waves == 0) return hipSuccess;
     dim3 grid(grid_for(waves, WAVES_PER_WG)), block(WG);
     switch (mode) {
-        case AX: hipLaunchKernelGGL((k_bspmv<T, M, AX, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
-        case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
-        case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
-        case S_SWEEP: hipLaunchKernelGGL((k_bspmv<T, M, S_SWEEP, BR>), grid, block, 0, st, A, x, b, y, ld, omega); break;
+        case AX: hipLaunchKernelGGL((k_bspmv<T, M, AX, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
+        case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
+        case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
+        case S_SWEEP: hipLaunchKernelGGL((k_bspmv<T, M, S_SWEEP, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
+        case AX_DSCALE: hipLaunchKernelGGL((k_bspmv<T, M, AX_DSCALE, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -482,12 +504,12 @@ static hipError_t bsweep_m(int mode, const Bcsr<T>& A, const T* dinv, const T* x
 
 template <typename T, int M>
 static hipError_t bspmv_m(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st,
-                          T omega) {
+                          T omega, const T* dinv, T* y2) {
     switch (A.br) {
-        case 1: return bspmv_mb<T, M, 1>(mode, A, x, b, y, ld, st, omega);
-        case 2: return bspmv_mb<T, M, 2>(mode, A, x, b, y, ld, st, omega);
-        case 3: return bspmv_mb<T, M, 3>(mode, A, x, b, y, ld, st, omega);
-        case 4: return bspmv_mb<T, M, 4>(mode, A, x, b, y, ld, st, omega);
+        case 1: return bspmv_mb<T, M, 1>(mode, A, x, b, y, ld, st, omega, dinv, y2);
+        case 2: return bspmv_mb<T, M, 2>(mode, A, x, b, y, ld, st, omega, dinv, y2);
+        case 3: return bspmv_mb<T, M, 3>(mode, A, x, b, y, ld, st, omega, dinv, y2);
+        case 4: return bspmv_mb<T, M, 4>(mode, A, x, b, y, ld, st, omega, dinv, y2);
         default: return hipErrorInvalidValue;
     }
 }
@@ -528,19 +550,19 @@ hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, 
 
 template <typename T>
 hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
-                        T omega) {
+                        T omega, const T* dinv, T* y2) {
     int c0 = 0;
     while (c0 < m) {
         const int w = bcsr_chunk(m - c0, cap);
         const T* bc = b ? b + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 16: e = bspmv_m<T, 16>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
-            case 8: e = bspmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
-            case 4: e = bspmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
-            case 3: e = bspmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
-            case 2: e = bspmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
-            default: e = bspmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, st, omega); break;
+            case 16: e = bspmv_m<T, 16>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2 ? y2 + c0 : nullptr); break;
+            case 8: e = bspmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2 ? y2 + c0 : nullptr); break;
+            case 4: e = bspmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2 ? y2 + c0 : nullptr); break;
+            case 3: e = bspmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2 ? y2 + c0 : nullptr); break;
+            case 2: e = bspmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2 ? y2 + c0 : nullptr); break;
+            default: e = bspmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2 ? y2 + c0 : nullptr); break;
         }
         if (e != hipSuccess) return e;
         c0 += w;
@@ -553,9 +575,9 @@ template hipError_t launch_bsweep<double>(int, const Bcsr<double>&, const double
 template hipError_t launch_bsweep<float>(int, const Bcsr<float>&, const float*, const float*, const float*, float*,
                                          float, int, const int32_t*, hipStream_t, int, float*);
 template hipError_t launch_bspmv<double>(int, const Bcsr<double>&, const double*, const double*, double*, int,
-                                         hipStream_t, int, double);
+                                         hipStream_t, int, double, const double*, double*);
 template hipError_t launch_bspmv<float>(int, const Bcsr<float>&, const float*, const float*, float*, int,
-                                        hipStream_t, int, float);
+                                        hipStream_t, int, float, const float*, float*);
 
 // ============================================================ MFMA tiles
 // Lane layout of the 16x16x4 matrix instructions (wave64), as measured on
@@ -600,14 +622,14 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
     const int br = A.br, bc = A.bc;
     const int64_t col0 = int64_t(blockIdx.y) * MFMA_COLS + i;
     const int64_t r0 = int64_t(brow) * br;
-    constexpr bool SW = (MODE == MF_SWEEP || MODE == MF_SWEEP0);
+    constexpr bool SW = (MODE == MF_SWEEP || MODE == MF_SWEEP0 || MODE == MF_RDINV);
     // epilogue operands first
     T bpre[4], xpre[4], dpre[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = Mma<T>::row(g, v);
         const int64_t e = (r0 + row) * ld + col0;
-        bpre[v] = (MODE != MF_AX && row < br) ? b[e] : T(0);
+        bpre[v] = (MODE != MF_AX && MODE != MF_RDINV && row < br) ? b[e] : T(0);
         xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP) && row < br) ? x[e] : T(0);
     }
     if (SW) {
@@ -665,7 +687,7 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int row = Mma<T>::row(g, v);
-        tl[row][i] = (row < br) ? ((MODE == MF_SWEEP) ? bpre[v] - acc[v] : bpre[v]) : T(0);
+        tl[row][i] = (row < br) ? ((MODE == MF_SWEEP) ? bpre[v] - acc[v] : (MODE == MF_RDINV) ? acc[v] : bpre[v]) : T(0);
     }
     wave_lds_sync();
     typename Mma<T>::acc acc2 = {T(0), T(0), T(0), T(0)};
@@ -678,7 +700,7 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
         const int row = Mma<T>::row(g, v);
         if (row < br) {
             y[(r0 + row) * ld + col0] = xpre[v] + omega * acc2[v];
-            if (MODE == MF_SWEEP0 && y2) y2[(r0 + row) * ld + col0] = acc2[v];
+            if ((MODE == MF_SWEEP0 || MODE == MF_RDINV) && y2) y2[(r0 + row) * ld + col0] = acc2[v];
         }
     }
 }
@@ -694,6 +716,7 @@ static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, 
         case MF_SWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
         case MF_SWEEP0: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP0, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
         case MF_SSWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SSWEEP, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
+        case MF_RDINV: hipLaunchKernelGGL((k_mfma<T, MF_RDINV, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
