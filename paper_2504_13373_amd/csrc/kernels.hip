@@ -177,6 +177,18 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
     const bool own = live && lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
     T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * A.tpad * M;
+    // the epilogue's own-row operands are loaded first, so their latency
+    // overlaps the row's product instead of following it
+    constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP);
+    constexpr bool PX = (MODE == S_SWEEP || MODE == AX_DOT);
+    T bo[PB ? M : 1], xo[PX ? M : 1];
+    if (PB || PX) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            if (PB) bo[c] = own ? b[row * ldy + c] : T(0);
+            if (PX) xo[c] = own ? x[row * ldx + c] : T(0);
+        }
+    }
     T acc[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = T(0);
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
         __shared__ T red[WAVES_PER_WG][M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            T v = own ? x[row * ldx + c] * acc[c] : T(0);
+            T v = own ? xo[PX ? c : 0] * acc[c] : T(0);
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
             if (lane == 0) red[wave][c] = v;
@@ -201,9 +213,9 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         T v = acc[c];
-        if (MODE == B_MINUS) v = b[row * ldy + c] - v;
-        else if (MODE == B_PLUS) v = b[row * ldy + c] + v;
-        else if (MODE == S_SWEEP) v = x[row * ldx + c] + omega * (b[row * ldy + c] - v);
+        if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
+        else if (MODE == B_PLUS) v = bo[PB ? c : 0] + v;
+        else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
         y[row * ldy + c] = v;
     }
 }
@@ -419,10 +431,23 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
     const int g = lane / A.P, p = lane - (lane / A.P) * A.P;
     const int64_t brow = wv * gpw + g;
     const bool valid = brow < A.n_brow;
+    const int64_t row = brow * BR + p;
+    // the epilogue's own-row operands are loaded first, so their latency
+    // overlaps the block loop instead of following the reduction
+    constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP);
+    constexpr bool PX = (MODE == S_SWEEP);
+    T bo[PB ? M : 1], xo[PX ? M : 1];
+    if (PB || PX) {
+        const bool mine = valid && p < BR;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            if (PB) bo[c] = mine ? b[row * ld + c] : T(0);
+            if (PX) xo[c] = mine ? x[row * ld + c] : T(0);
+        }
+    }
     T acc[BR][M];
     bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
     if (!valid || p >= BR) return;
-    const int64_t row = brow * BR + p;
     if (MODE == AX_DSCALE) {
         // row p of D'^{-1} (the output rows' own block) applied to the block row's
         // product: the operations of a first sweep whose right-hand side is A x
@@ -449,9 +474,9 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             T v = acc[i][c];
-            if (MODE == B_MINUS) v = b[row * ld + c] - v;
-            else if (MODE == B_PLUS) v = b[row * ld + c] + v;
-            else if (MODE == S_SWEEP) v = x[row * ld + c] + omega * (b[row * ld + c] - v);
+            if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
+            else if (MODE == B_PLUS) v = bo[PB ? c : 0] + v;
+            else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
             y[row * ld + c] = v;
         }
     }
