@@ -1218,7 +1218,9 @@ struct CgBatch : Engine {
         if (mixed) vcycle_run<float>(*C, *W, W->kr32, W->kz32, m, st, W->use_graph);
         else if (!flexible) vcycle_run<double>(*C, *W, r, W->kz, m, st, W->use_graph);  // r, z fixed buffers
         else precond_fp64(*C, *W, r, W->kz, m, st);
-        HIPCHK(launch_zdots(mixed ? W->kz32 : nullptr, W->kz, r, r_old, n, m, W->kpart, rz_out, zro, st));
+        // mixed: the FP64 z is never stored; the direction update reads z32 itself
+        HIPCHK(launch_zdots(mixed ? W->kz32 : nullptr, mixed ? nullptr : W->kz, r, r_old, n, m, W->kpart, rz_out, zro,
+                            st));
     }
 
     // uploads mask region `off` from the pinned mirror if it differs from `last`
@@ -1390,7 +1392,8 @@ struct CgBatch : Engine {
             const int64_t n = C->lv[0].n;
             for (int c = 0; c < m; ++c) W->mask_h[MASK_DIR + c] = (col[c].state == RUNNING && col[c].upd) ? 1 : 0;
             upload_mask(MASK_DIR, last_dir);
-            HIPCHK(launch_cg_dir(W->kp, W->kz, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz, W->mask + MASK_DIR, st));
+            HIPCHK(launch_cg_dir(W->kp, mixed ? nullptr : W->kz, n, m, d_rz2, flexible ? d_zro : nullptr, d_rz,
+                                 W->mask + MASK_DIR, st, mixed ? W->kz32 : nullptr));
             std::swap(d_rz, d_rz2);
             const MatStore& A0 = C->lv[0].A;
             if (!A0.vec && !use_mfma<double>(A0, m)) {

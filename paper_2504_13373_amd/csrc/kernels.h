@@ -185,12 +185,14 @@ hipError_t launch_cg_update(double* x, const double* r_in, double* r_out, const 
                             float* r32, int64_t n, int m, const double* rz, const double* pq,
                             const int32_t* active, double* part, double* rr, int32_t* flag, hipStream_t st,
                             const double* stat = nullptr, double* stat_host = nullptr, int stat_len = 0);
-// z = double(z32) if z32 != NULL; rz[c] = r.z ; zro[c] = z.r_old if r_old != NULL
+// z = double(z32) if z32 != NULL (z is then only written, and may be NULL);
+// rz[c] = r.z ; zro[c] = z.r_old if r_old != NULL
 hipError_t launch_zdots(const float* z32, double* z, const double* r, const double* r_old, int64_t n, int m,
                         double* part, double* rz, double* zro, hipStream_t st);
-// p = z + beta p, beta = active ? (rz_new - zro) / rz_old : 0  (zro may be NULL)
+// p = z + beta p, beta = active ? (rz_new - zro) / rz_old : 0  (zro may be NULL);
+// with z32 != NULL, z is double(z32) and the z argument is not read
 hipError_t launch_cg_dir(double* p, const double* z, int64_t n, int m, const double* rz_new, const double* zro,
-                         const double* rz_old, const int32_t* active, hipStream_t st);
+                         const double* rz_old, const int32_t* active, hipStream_t st, const float* z32 = nullptr);
 
 // Column c of a batch (row-major n x ld arrays kb, kx, r, p, q) takes a new
 // right-hand side: kb = r = b (caller column, stride ldb, rows reordered by perm

@@ -1691,7 +1691,7 @@ __global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, dou
             zv[c] = z32 ? double(z32[e0 + c]) : z[e0 + c];
             rv[c] = r[e0 + c];
         }
-        if (z32) {
+        if (z32 && z) {
 #pragma unroll
             for (int c = 0; c < M; ++c) z[e0 + c] = zv[c];
         }
@@ -1708,7 +1708,8 @@ __global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, dou
 template <int M>
 __global__ __launch_bounds__(WG) void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, int64_t n, int ld,
                                                const double* __restrict__ rzn, const double* __restrict__ zro,
-                                               const double* __restrict__ rzo, const int32_t* __restrict__ active) {
+                                               const double* __restrict__ rzo, const int32_t* __restrict__ active,
+                                               const float* __restrict__ z32) {
     double be[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) be[c] = active[c] ? (rzn[c] - (zro ? zro[c] : 0.0)) / rzo[c] : 0.0;
@@ -1716,7 +1717,7 @@ __global__ __launch_bounds__(WG) void k_cg_dir(double* __restrict__ p, const dou
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             const int64_t e = i * ld + c;
-            p[e] = z[e] + be[c] * p[e];
+            p[e] = (z32 ? double(z32[e]) : z[e]) + be[c] * p[e];
         }
 }
 
@@ -1856,7 +1857,7 @@ __device__ __forceinline__ void zdots_co_body(const float* __restrict__ z32, dou
                 if (Z32) zv[j] = double(fz[j]);
                 const int el = j * 64 + lane;
                 if (el < lim) {
-                    if (Z32) z[base + el] = zv[j];
+                    if (Z32 && z) z[base + el] = zv[j];
                     buf[wv][0][el / M][el % M] = zv[j];
                     buf[wv][1][el / M][el % M] = rv[j];
                     buf[wv][2][el / M][el % M] = ov[j];
@@ -1938,12 +1939,13 @@ template <int M>
 __global__ __launch_bounds__(WG) void k_cg_dir_co(double* __restrict__ p, const double* __restrict__ z, int64_t n,
                                                   const double* __restrict__ rzn, const double* __restrict__ zro,
                                                   const double* __restrict__ rzo,
-                                                  const int32_t* __restrict__ active) {
+                                                  const int32_t* __restrict__ active,
+                                                  const float* __restrict__ z32) {
     const int cl = (threadIdx.x & 63) % M;
     const double be = active[cl] ? (rzn[cl] - (zro ? zro[cl] : 0.0)) / rzo[cl] : 0.0;
     const int64_t tot = n * M;
     for (int64_t e = int64_t(blockIdx.x) * WG + threadIdx.x; e < tot; e += int64_t(gridDim.x) * WG)
-        p[e] = z[e] + be * p[e];
+        p[e] = (z32 ? double(z32[e]) : z[e]) + be * p[e];
 }
 
 #define CO_DISPATCH(w, KERNEL, ...)                                                                    \
@@ -2057,7 +2059,7 @@ hipError_t launch_zdots(const float* z32, double* z, const double* r, const doub
             else if (r_old) CO_DISPATCH(w, k_zdots_co_ft, dim3(g), dim3(WG), 0, st, z32, z, r, r_old, n, part)
             else CO_DISPATCH(w, k_zdots_co_ff, dim3(g), dim3(WG), 0, st, z32, z, r, r_old, n, part)
         } else {
-            KRY_DISPATCH(w, k_zdots, dim3(g), dim3(WG), 0, st, z32 ? z32 + c0 : nullptr, z + c0, r + c0,
+            KRY_DISPATCH(w, k_zdots, dim3(g), dim3(WG), 0, st, z32 ? z32 + c0 : nullptr, z ? z + c0 : nullptr, r + c0,
                          r_old ? r_old + c0 : nullptr, n, m, part)
         }
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part, int(g), r_old ? 2 * w : w, rz + c0, w,
@@ -2067,14 +2069,14 @@ hipError_t launch_zdots(const float* z32, double* z, const double* r, const doub
 }
 
 hipError_t launch_cg_dir(double* p, const double* z, int64_t n, int m, const double* rz_new, const double* zro,
-                         const double* rz_old, const int32_t* active, hipStream_t st) {
+                         const double* rz_old, const int32_t* active, hipStream_t st, const float* z32) {
     const unsigned g = kry_grid(n);
     return for_chunks(m, [&](int c0, int w) {
         if (co_ok(m, w)) {
-            CO_DISPATCH(w, k_cg_dir_co, dim3(g), dim3(WG), 0, st, p, z, n, rz_new, zro, rz_old, active)
+            CO_DISPATCH(w, k_cg_dir_co, dim3(g), dim3(WG), 0, st, p, z, n, rz_new, zro, rz_old, active, z32)
         } else {
-            KRY_DISPATCH(w, k_cg_dir, dim3(g), dim3(WG), 0, st, p + c0, z + c0, n, m, rz_new + c0,
-                         zro ? zro + c0 : nullptr, rz_old + c0, active + c0)
+            KRY_DISPATCH(w, k_cg_dir, dim3(g), dim3(WG), 0, st, p + c0, z ? z + c0 : nullptr, n, m, rz_new + c0,
+                         zro ? zro + c0 : nullptr, rz_old + c0, active + c0, z32 ? z32 + c0 : nullptr)
         }
         return hipGetLastError();
     });
