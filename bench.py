@@ -405,6 +405,8 @@ def bench_convdiff(args, am, torch, dev):
             res[name] = {"iterations": st.iterations[0], "converged": rc == am.AMGDG_OK, "seconds": t,
                          "solves_per_s": 1.0 / t if rc == am.AMGDG_OK else None, "true_rel_residual": tr}
             log(f"convdiff Pe {pe:g} {name}: rc {rc}, {st.iterations[0]} iterations, {t:.2f} s, true rel {tr:.2e}")
+        if pe == 1e2:
+            res["kernels"] = _level0_rates(am, torch, h, infos, dev, 3)
         sweep[f"{pe:g}"] = res
         h.close()
     mid = sweep["100"]
@@ -412,6 +414,46 @@ def bench_convdiff(args, am, torch, dev):
               f"2D convection-diffusion, LDG + upwind p=2 on the Delaunay triangulation of {side}^2 jittered points, "
               f"6-level RCB hierarchy, r=4, V(3,3), FGMRES(30) to 1e-8; value: FP64 at Peclet 100",
               {"peclet_sweep": sweep, "max_it": maxit})
+
+
+def _level0_rates(am, torch, h, infos, dev, nu, m=1, reps=20):
+    """HIP-event times of the V-cycle and of the level-0 sweep on D^-1 A (FP32
+    and FP64, m columns, internal order) with their algorithmic GB/s."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    n = infos[0].n
+    for name, (prec, wb, dt) in {"fp32": (am.AMGDG_MIXED, 4, torch.float32),
+                                 "fp64": (am.AMGDG_FP64, 8, torch.float64)}.items():
+        shape = (n,) if m == 1 else (n, m)
+        r = torch.randn(shape, dtype=dt, device=dev)
+        z = torch.zeros_like(r)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            am.amgdg_vcycle(h, r, z, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e0.record(stream)
+        for _ in range(reps):
+            am.amgdg_vcycle(h, r, z, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tv = e0.elapsed_time(e1) / reps * 1e-3
+        nN = infos[-1].n
+        bv = sum(level_bytes(i, wb, m, nu) for i in infos[:-1]) + nN * nN * 8 + 2 * nN * m * 8
+        xx, bb, yy = torch.randn_like(r), torch.randn_like(r), torch.zeros_like(r)
+        for _ in range(3):
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP_SCALED, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e0.record(stream)
+        for _ in range(reps):
+            am.amgdg_apply(h, 0, am.AMGDG_OP_SWEEP_SCALED, xx, bb, yy, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts = e0.elapsed_time(e1) / reps * 1e-3
+        sb = sweep_bytes(infos[0], wb, m)
+        out[name] = {"vcycle_ms": tv * 1e3, "vcycle_GBps": bv / tv / 1e9, "sweep_us": ts * 1e6,
+                     "sweep_GBps": sb / ts / 1e9, "sweep_frac": sb / ts / 1e9 / HBM_PEAK_GBS, "sweep_bytes": sb}
+        log(f"level-0 sweep {name}: {ts * 1e6:.1f} us ({sb / ts / 1e9:.0f} GB/s, {sb / 1e6:.1f} MB); "
+            f"V-cycle {tv * 1e3:.3f} ms ({bv / tv / 1e9:.0f} GB/s)")
+        del r, z, xx, bb, yy
+    return out
 
 
 def bench_poisson3d(args, am, torch, dev):
