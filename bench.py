@@ -256,12 +256,12 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "level-0 FP32 block-Jacobi sweep on D^-1 A (k_spmv<float,1,S_SWEEP>)",
+            "kernel": "level-0 FP32 block-Jacobi sweep on D^-1 A (k_spmv<float,1,S_SWEEP,false>)",
             "achieved": k["gbps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": k["gbps"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_spmv<float, 1, 3>"),
+            "traffic": measured_traffic("k_spmv<float, 1, 3, false>"),
             "bytes_per_launch": k["bytes"],
             "us_per_launch": k["us"],
             "copy_GBps": copy_gbps,

@@ -86,6 +86,7 @@ struct SellStore {
     Sell<double> d;
     Sell<float> f;
     int64_t n_vals = 0;
+    const int32_t* pos = nullptr;  // slice position of each block row when the rows are reordered
 };
 
 // An operator of the hierarchy in the layout its block shape calls for: the
@@ -270,20 +271,44 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
     if (br < 1 || br > 64) throw Error(AMGDG_EUNSUPPORTED, "block size must be 1..64");
     const int G = 64 / br, L = G * br;
     const int64_t ns = (n_brow + G - 1) / G;
+    auto len = [&](int64_t row) { return row < n_brow ? rp[row + 1] - rp[row] : 0; };
+    // Slot counts with the rows in order, and with the rows sorted by length
+    // (longest first, stable) within windows of 8 slices; the sorted order is
+    // kept for the square-block level operators when it cuts the padded slots
+    // by more than 5% (rows of varying length, such as LDG's neighbours of
+    // neighbours).  The prolongation's short rows stay in order: there the
+    // scattered row writes cost more than the padding.
+    std::vector<int32_t> order(static_cast<size_t>(ns * G));
+    for (int64_t q = 0; q < ns * G; ++q) order[q] = int32_t(std::min<int64_t>(q, n_brow));
+    auto slots = [&](const std::vector<int32_t>& ord) {
+        int64_t tot = 0;
+        for (int64_t s = 0; s < ns; ++s) {
+            int32_t kmax = 0;
+            for (int g = 0; g < G; ++g) kmax = std::max(kmax, len(ord[s * G + g]));
+            tot += int64_t(kmax) * G;
+        }
+        return tot;
+    };
+    const int64_t plain = slots(order);
+    std::vector<int32_t> sorted = order;
+    const int64_t win = int64_t(8) * G;
+    for (int64_t w0 = 0; w0 < ns * G; w0 += win) {
+        const auto b = sorted.begin() + w0, e = sorted.begin() + std::min(w0 + win, ns * G);
+        std::stable_sort(b, e, [&](int32_t x, int32_t y) { return len(x) > len(y); });
+    }
+    const bool use_sorted = br == bc && slots(sorted) * 20 < plain * 19;
+    if (use_sorted) order.swap(sorted);
     std::vector<int32_t> coff(ns + 1), K(ns), cols, slot_k, slot_g, slot_s;
     std::vector<int64_t> slot_src;
     int32_t c = 0;
     for (int64_t s = 0; s < ns; ++s) {
         int32_t kmax = 0;
-        for (int g = 0; g < G; ++g) {
-            const int64_t row = s * G + g;
-            if (row < n_brow) kmax = std::max(kmax, rp[row + 1] - rp[row]);
-        }
+        for (int g = 0; g < G; ++g) kmax = std::max(kmax, len(order[s * G + g]));
         K[s] = kmax;
         coff[s] = c;
         for (int kk = 0; kk < kmax; ++kk)
             for (int g = 0; g < G; ++g) {
-                const int64_t row = s * G + g;
+                const int64_t row = order[s * G + g];
                 int64_t blk = -1;
                 int32_t col = 0;
                 if (row < n_brow && kk < rp[row + 1] - rp[row]) {
@@ -310,6 +335,13 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
     d.coff = upload(C.mem, coff, st);
     d.K = upload(C.mem, K, st);
     d.cols = upload(C.mem, cols, st);
+    if (use_sorted) {
+        d.rows = upload(C.mem, order, st);
+        std::vector<int32_t> pos(static_cast<size_t>(n_brow));
+        for (int64_t q = 0; q < ns * G; ++q)
+            if (order[q] < n_brow) pos[order[q]] = int32_t(q);
+        S.pos = upload(C.mem, pos, st);
+    }
     Sell<float> f;
     f.n_brow = d.n_brow;
     f.br = br;
@@ -320,6 +352,7 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
     f.coff = d.coff;
     f.K = d.K;
     f.cols = d.cols;
+    f.rows = d.rows;
     sell_values<double>(C, d, ns, K, slot_src, slot_k, slot_g, slot_s, nat_d, st);
     if (f32) sell_values<float>(C, f, ns, K, slot_src, slot_k, slot_g, slot_s, nat_d, st);
     S.d = d;
@@ -330,11 +363,11 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
 }
 
 template <typename T>
-static T* sell_dinv(Ctx& C, const Sell<T>& A, const double* dinv_nat, hipStream_t st) {
+static T* sell_dinv(Ctx& C, const Sell<T>& A, const int32_t* pos, const double* dinv_nat, hipStream_t st) {
     const int64_t cnt = int64_t(A.n_slices) * A.brpad * A.L;
     T* out = C.mem.alloc<T>(cnt);
     HIPCHK(hipMemsetAsync(out, 0, sizeof(T) * size_t(std::max<int64_t>(cnt, 1)), st));
-    HIPCHK(launch_dinv_to_sell<T>(dinv_nat, A.n_brow, A.br, A.G, A.L, A.brpad, out, st));
+    HIPCHK(launch_dinv_to_sell<T>(dinv_nat, A.n_brow, A.br, A.G, A.L, A.brpad, out, st, pos));
     return out;
 }
 
@@ -672,8 +705,8 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         }
         build_mat(C, L.S, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.S_nat, C.mixed, st);
         if (!L.A.vec) {
-            L.Dinv_sell = sell_dinv<double>(C, L.A.s.d, L.Dinv_nat, st);
-            if (C.mixed) L.Dinv_sell32 = sell_dinv<float>(C, L.A.s.f, L.Dinv_nat, st);
+            L.Dinv_sell = sell_dinv<double>(C, L.A.s.d, L.A.s.pos, L.Dinv_nat, st);
+            if (C.mixed) L.Dinv_sell32 = sell_dinv<float>(C, L.A.s.f, L.A.s.pos, L.Dinv_nat, st);
         }
         if (C.mixed) {
             L.Dinv_nat32 = C.mem.alloc<float>(L.n_units * L.nb * L.nb);

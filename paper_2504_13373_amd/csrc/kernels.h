@@ -19,6 +19,9 @@ namespace amgdg {
 // contiguous run of 16 * L bytes.  The column of slot k of block row g of the
 // slice is cols[coff[s] + k * G + g].  tpad is the largest K*bc of any slice
 // rounded up to VW (the per-row length of the x staging buffer in LDS).
+// Block row g of slice s is block row s * G + g, or rows[s * G + g] when rows
+// is set (rows sorted by length within windows of slices, so that a slice's
+// rows have similar lengths; n_brow marks an empty position).
 template <typename T>
 struct Sell {
     int32_t n_brow = 0, br = 0, bc = 0, G = 0, L = 0, n_slices = 0, tpad = 0, brpad = 0;
@@ -27,6 +30,7 @@ struct Sell {
     const int32_t* K = nullptr;
     const int32_t* cols = nullptr;
     const T* vals = nullptr;
+    const int32_t* rows = nullptr;
 };
 
 // Block-CSR matrix with small br x bc blocks (br <= 4), for coarse levels and
@@ -124,9 +128,10 @@ template <typename T>
 hipError_t launch_to_sell_vals(const double* nat, const int64_t* slot_src, const int64_t* slot_base,
                                const int32_t* slot_k, const int32_t* slot_g, int64_t n_slots, int L, int br, int bc,
                                T* vals, hipStream_t st);
+// pos[e] (may be null: e) is the slice position s * G + g of block row e
 template <typename T>
 hipError_t launch_dinv_to_sell(const double* dinv_nat, int64_t n_brow, int br, int G, int L, int brpad, T* dinv_sell,
-                               hipStream_t st);
+                               hipStream_t st, const int32_t* pos = nullptr);
 hipError_t launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st);
 hipError_t launch_block_inverse(const double* Avals, const int32_t* diag_pos, int64_t n_brow, int nb, double* dinv,
                                 int32_t* flag, hipStream_t st);

@@ -95,7 +95,7 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     }
 }
 
-template <typename T, int M, int MODE>
+template <typename T, int M, int MODE, bool ROWS>
 __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ y, T omega,
                                                const int32_t* __restrict__ colmask, int ld, T* __restrict__ y2) {
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
     const int lc = lane < L ? lane : L - 1;
     const int g = lc / br;
     const int i = lc - g * br;
-    const int64_t brow = int64_t(slice) * G + g;
+    const int64_t brow = ROWS ? int64_t(A.rows[int64_t(slice) * G + g]) : int64_t(slice) * G + g;
     const bool own = lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
     T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (A.tpad + BP) * M;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
     }
 }
 
-template <typename T, int M, int MODE>
+template <typename T, int M, int MODE, bool ROWS>
 __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, int ldx, int ldy, T omega, T* __restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -173,7 +173,8 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
     const int lc = lane < L ? lane : L - 1;
     const int g = lc / br;
     const int i = lc - g * br;
-    const int64_t brow = int64_t(slice) * G + g;
+    const int64_t brow = !live ? int64_t(A.n_brow)
+                                 : ROWS ? int64_t(A.rows[int64_t(slice) * G + g]) : int64_t(slice) * G + g;
     const bool own = live && lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
     T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * A.tpad * M;
@@ -220,6 +221,11 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
     }
 }
 
+// the row-mapped instance only for slices whose rows were reordered
+#define SELL_LAUNCH(KERNEL, MD, ...)                                                              \
+    if (A.rows) hipLaunchKernelGGL((KERNEL<T, M, MD, true>), grid, block, lds, st, __VA_ARGS__);   \
+    else hipLaunchKernelGGL((KERNEL<T, M, MD, false>), grid, block, lds, st, __VA_ARGS__)
+
 template <typename T, int M>
 static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
                           const int32_t* mask, int ld, hipStream_t st, T* y2) {
@@ -227,10 +233,10 @@ static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x,
     if (A.n_slices == 0) return hipSuccess;
     const size_t lds = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * M * sizeof(T);
     switch (mode) {
-        case SWEEP: hipLaunchKernelGGL((k_sweep<T, M, SWEEP>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
-        case SWEEP0: hipLaunchKernelGGL((k_sweep<T, M, SWEEP0>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
-        case RELAX: hipLaunchKernelGGL((k_sweep<T, M, RELAX>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
-        case DINVA: hipLaunchKernelGGL((k_sweep<T, M, DINVA>), grid, block, lds, st, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case SWEEP: SELL_LAUNCH(k_sweep, SWEEP, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case SWEEP0: SELL_LAUNCH(k_sweep, SWEEP0, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case RELAX: SELL_LAUNCH(k_sweep, RELAX, A, dinv, x, b, y, omega, mask, ld, y2); break;
+        case DINVA: SELL_LAUNCH(k_sweep, DINVA, A, dinv, x, b, y, omega, mask, ld, y2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -243,11 +249,11 @@ static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* 
     if (A.n_slices == 0) return hipSuccess;
     const size_t lds = size_t(WAVES_PER_WG) * A.G * A.tpad * M * sizeof(T);
     switch (mode) {
-        case AX: hipLaunchKernelGGL((k_spmv<T, M, AX>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
-        case B_MINUS: hipLaunchKernelGGL((k_spmv<T, M, B_MINUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
-        case B_PLUS: hipLaunchKernelGGL((k_spmv<T, M, B_PLUS>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
-        case S_SWEEP: hipLaunchKernelGGL((k_spmv<T, M, S_SWEEP>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
-        case AX_DOT: hipLaunchKernelGGL((k_spmv<T, M, AX_DOT>), grid, block, lds, st, A, x, b, y, ldx, ldy, omega, part); break;
+        case AX: SELL_LAUNCH(k_spmv, AX, A, x, b, y, ldx, ldy, omega, part); break;
+        case B_MINUS: SELL_LAUNCH(k_spmv, B_MINUS, A, x, b, y, ldx, ldy, omega, part); break;
+        case B_PLUS: SELL_LAUNCH(k_spmv, B_PLUS, A, x, b, y, ldx, ldy, omega, part); break;
+        case S_SWEEP: SELL_LAUNCH(k_spmv, S_SWEEP, A, x, b, y, ldx, ldy, omega, part); break;
+        case AX_DOT: SELL_LAUNCH(k_spmv, AX_DOT, A, x, b, y, ldx, ldy, omega, part); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -801,7 +807,7 @@ template hipError_t launch_to_sell_vals<float>(const double*, const int64_t*, co
 
 template <typename T>
 __global__ void k_dinv_to_sell(const double* __restrict__ dn, int64_t n_brow, int br, int G, int L, int BP,
-                               T* __restrict__ ds) {
+                               T* __restrict__ ds, const int32_t* __restrict__ pos) {
     constexpr int VW = 16 / int(sizeof(T));
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per = int64_t(br) * br;
@@ -809,20 +815,24 @@ __global__ void k_dinv_to_sell(const double* __restrict__ dn, int64_t n_brow, in
     const int64_t e = t / per;
     const int rem = int(t - e * per);
     const int i = rem / br, j = rem - (rem / br) * br;
-    const int64_t s = e / G;
-    const int g = int(e - s * G);
+    const int64_t q = pos ? int64_t(pos[e]) : e;
+    const int64_t s = q / G;
+    const int g = int(q - s * G);
     ds[s * BP * L + int64_t(j / VW) * L * VW + int64_t(g * br + i) * VW + j % VW] = T(dn[t]);
 }
 
 template <typename T>
-hipError_t launch_dinv_to_sell(const double* dn, int64_t n_brow, int br, int G, int L, int BP, T* ds, hipStream_t st) {
+hipError_t launch_dinv_to_sell(const double* dn, int64_t n_brow, int br, int G, int L, int BP, T* ds, hipStream_t st,
+                               const int32_t* pos) {
     const int64_t tot = n_brow * br * br;
     if (tot == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_dinv_to_sell<T>), dim3(grid_for(tot)), dim3(WG), 0, st, dn, n_brow, br, G, L, BP, ds);
+    hipLaunchKernelGGL((k_dinv_to_sell<T>), dim3(grid_for(tot)), dim3(WG), 0, st, dn, n_brow, br, G, L, BP, ds, pos);
     return hipGetLastError();
 }
-template hipError_t launch_dinv_to_sell<double>(const double*, int64_t, int, int, int, int, double*, hipStream_t);
-template hipError_t launch_dinv_to_sell<float>(const double*, int64_t, int, int, int, int, float*, hipStream_t);
+template hipError_t launch_dinv_to_sell<double>(const double*, int64_t, int, int, int, int, double*, hipStream_t,
+                                                const int32_t*);
+template hipError_t launch_dinv_to_sell<float>(const double*, int64_t, int, int, int, int, float*, hipStream_t,
+                                               const int32_t*);
 
 template <typename Ti, typename To>
 __global__ void k_convert(const Ti* __restrict__ a, To* __restrict__ b, int64_t n) {
