@@ -351,6 +351,8 @@ __device__ __forceinline__ void bcsr_row(const Bcsr<T>& A, int64_t brow, bool va
         for (int blk = A.rp[brow] + p; blk < e; blk += A.P) {
             const int64_t cb = int64_t(A.ci[blk]) * bc;
             const T* __restrict__ a = A.vals + int64_t(blk) * BR * bc;
+            // unrolled so that several columns' loads are in flight at once
+#pragma unroll 4
             for (int j = 0; j < bc; ++j) {
                 T xv[M];
                 const T* __restrict__ xr = x + (cb + j) * ld;
