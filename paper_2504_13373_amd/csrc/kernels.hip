@@ -66,6 +66,8 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     const bool vx = M % VW == 0 && ld % VW == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     if (lane < L) {
         if (i < bc) {
+            // unrolled so that several blocks' column and x loads are in flight at once
+#pragma unroll 4
             for (int kk = 0; kk < K; ++kk) {
                 const T* __restrict__ src = x + (int64_t(cp[kk * G]) * bc + i) * ld;
                 T* dst = xr + (kk * bc + i) * M;
