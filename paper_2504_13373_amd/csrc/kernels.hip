@@ -1619,6 +1619,7 @@ __global__ __launch_bounds__(WG) void k_dot_part2(const double* __restrict__ a, 
     double s[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) s[c] = 0.0;
+#pragma unroll 2
     for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG)
 #pragma unroll
         for (int c = 0; c < M; ++c) s[c] += a[i * ld + c] * b[i * ld + c];
@@ -1651,6 +1652,7 @@ __device__ __forceinline__ void cg_update_body(double* __restrict__ x, const dou
             if (!isfinite(al[c])) al[c] = 0.0;
         }
     }
+#pragma unroll 2
     for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) {
         const int64_t e0 = i * ld;
         double xv[M], pv[M], rv[M], qv[M];
@@ -1697,6 +1699,7 @@ __global__ __launch_bounds__(WG) void k_zdots(const float* __restrict__ z32, dou
     double s[M2];
 #pragma unroll
     for (int c = 0; c < M2; ++c) s[c] = 0.0;
+#pragma unroll 2
     for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG) {
         const int64_t e0 = i * ld;
         double zv[M], rv[M];
@@ -1727,6 +1730,7 @@ __global__ __launch_bounds__(WG) void k_cg_dir(double* __restrict__ p, const dou
     double be[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) be[c] = active[c] ? (rzn[c] - (zro ? zro[c] : 0.0)) / rzo[c] : 0.0;
+#pragma unroll 2
     for (int64_t i = int64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += int64_t(gridDim.x) * WG)
 #pragma unroll
         for (int c = 0; c < M; ++c) {
@@ -1971,8 +1975,9 @@ __global__ __launch_bounds__(WG) void k_cg_dir_co(double* __restrict__ p, const 
         default: hipLaunchKernelGGL((KERNEL<1>), __VA_ARGS__); break;                                 \
     }
 
-// the coalesced forms apply when one chunk covers all m columns and m divides 64
-static inline bool co_ok(int m, int w) { return w == m && 64 % m == 0; }
+// the coalesced forms apply when one chunk covers all m > 1 columns and m divides 64
+// (at one column the per-row forms are coalesced already)
+static inline bool co_ok(int m, int w) { return w == m && m > 1 && 64 % m == 0; }
 
 template <typename F>
 static hipError_t for_chunks(int m, F&& f) {
