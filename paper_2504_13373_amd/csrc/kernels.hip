@@ -141,6 +141,7 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
 #pragma unroll
     for (int c = 0; c < M; ++c) o[c] = T(0);
     const V* __restrict__ dp = reinterpret_cast<const V*>(dinv + int64_t(slice) * BP * L) + lc;
+#pragma unroll 4
     for (int jq = 0; jq < BP / VW; ++jq) {
         T d[VW];
         *reinterpret_cast<V*>(d) = dp[jq * L];
