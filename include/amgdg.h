@@ -214,7 +214,9 @@ int amgdg_solve(amgdg_handle h, int32_t m, const double* b_dev, double* x_dev, i
  * and keeps c = D^{-1} b_k; every later sweep is u + omega (c - S_k u) with
  * S_k = D^{-1} A_k precomputed at setup, and the restricted residual is
  * (R_k D)(c - S_k u), the same operator as Algorithm 1's sweep and
- * R_k (b_k - A_k u) with one matrix read per sweep instead of A_k and D^{-1}. */
+ * R_k (b_k - A_k u) with one matrix read per sweep instead of A_k and D^{-1}.
+ * Into a non-coarsest coarse level the restriction also applies that level's
+ * D^{-1} (its first sweep's operations), so b_{k+1} is not stored. */
 int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int32_t precision,
                  int32_t flags, void* stream);
 
