@@ -62,6 +62,14 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     const int TQ = (Tn + VW - 1) / VW;
     const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
     T* xr = xs + g * TP * M;
+    const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + lc;
+    // the first PRE value vectors do not depend on the staging: load them first
+    // (one or two columns only, to keep the register count down)
+    constexpr int PRE = M <= 2 ? 4 : 0;
+    V pre[PRE > 0 ? PRE : 1];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q)
+        if (q < TQ) pre[q] = vp[q * L];
     // rows of M values move as 16-byte vectors when the stride and the base allow
     const bool vx = M % VW == 0 && ld % VW == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     if (lane < L) {
@@ -85,9 +93,19 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
             for (int c = 0; c < M; ++c) xr[t * M + c] = T(0);
     }
     wave_lds_sync();
-    const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + lc;
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+        if (q < TQ) {
+            T a[VW];
+            *reinterpret_cast<V*>(a) = pre[q];
+#pragma unroll
+            for (int u = 0; u < VW; ++u)
+#pragma unroll
+                for (int c = 0; c < M; ++c) r[c] += sign * a[u] * xr[(q * VW + u) * M + c];
+        }
+    }
 #pragma unroll 4
-    for (int q = 0; q < TQ; ++q) {
+    for (int q = PRE; q < TQ; ++q) {
         T a[VW];
         *reinterpret_cast<V*>(a) = vp[q * L];
 #pragma unroll
