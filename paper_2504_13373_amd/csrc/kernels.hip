@@ -137,6 +137,14 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
     T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (A.tpad + BP) * M;
     T* rs = xs + G * A.tpad * M;
 
+    // the first DPRE vectors of this lane's D^{-1} row do not depend on the
+    // residual: load them first (one or two columns only)
+    const V* __restrict__ dp = reinterpret_cast<const V*>(dinv + int64_t(slice) * BP * L) + lc;
+    constexpr int DPRE = M <= 2 ? 4 : 0;
+    V dpre[DPRE > 0 ? DPRE : 1];
+#pragma unroll
+    for (int q = 0; q < DPRE; ++q)
+        if (q < BP / VW) dpre[q] = dp[q * L];
     T r[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) r[c] = T(0);
@@ -158,9 +166,19 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
     T o[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) o[c] = T(0);
-    const V* __restrict__ dp = reinterpret_cast<const V*>(dinv + int64_t(slice) * BP * L) + lc;
+#pragma unroll
+    for (int jq = 0; jq < DPRE; ++jq) {
+        if (jq < BP / VW) {
+            T d[VW];
+            *reinterpret_cast<V*>(d) = dpre[jq];
+#pragma unroll
+            for (int u = 0; u < VW; ++u)
+#pragma unroll
+                for (int c = 0; c < M; ++c) o[c] += d[u] * rr[(jq * VW + u) * M + c];
+        }
+    }
 #pragma unroll 4
-    for (int jq = 0; jq < BP / VW; ++jq) {
+    for (int jq = DPRE; jq < BP / VW; ++jq) {
         T d[VW];
         *reinterpret_cast<V*>(d) = dp[jq * L];
 #pragma unroll
