@@ -51,7 +51,7 @@ extern "C" {
 /* --------------------------------------------------------------- parameters */
 typedef struct {
     int32_t  n_levels;     /* levels L_0..L_{n_levels-1}; L_{n_levels-1} is solved directly */
-    int32_t  r;            /* adaptive candidates per level (columns of B^k) */
+    int32_t  r;            /* adaptive candidates per level (columns of B^k), 1..16 */
     int32_t  t_pre;        /* pre-smoothing sweeps (Algorithm 2) */
     int32_t  t_post;       /* post-smoothing sweeps */
     int32_t  q_power;      /* power-iteration steps of Algorithm 4 */
@@ -128,7 +128,7 @@ typedef struct amgdg_ctx* amgdg_handle;
  * (eq:splitB_dg, eq:sik), T = (I - omega D^{-1} A) P~ and R = T^T (eq:TR0),
  * A_{k+1} = R A_k T and B^{k+1} = R B^k; then the inverse of the coarsest
  * matrix.  Every arithmetic step runs in the library's HIP kernels.
- *   n_elem, nb       : element count and dofs per element (1..64)
+ *   n_elem, nb       : element count and dofs per element (1..16)
  *   row_ptr, col_idx : host BSR pattern, int32, columns sorted, diagonal present
  *   vals             : host, nnzb * nb * nb doubles
  *   adj_ptr, adj_idx : host face graph of the elements (CSR) or NULL; only checked
@@ -138,7 +138,8 @@ typedef struct amgdg_ctx* amgdg_handle;
  *   B1               : host, n x r row-major in caller order, or NULL
  *   p                : parameters (NULL: defaults)
  * The coarse block size s = min(ceil(|A_J| / n_cut), |A_J|, r) must be the same
- * for every aggregate of a level (EUNSUPPORTED otherwise). */
+ * for every aggregate of a level, r must be 1..16 and an aggregate may hold at
+ * most 128 dofs (EUNSUPPORTED otherwise). */
 int amgdg_setup(amgdg_handle* out, int64_t n_elem, int32_t nb, const int32_t* row_ptr,
                 const int32_t* col_idx, const double* vals, int64_t nnzb, const int32_t* adj_ptr,
                 const int32_t* adj_idx, const int32_t* agg_of_elem, const amgdg_params* p,

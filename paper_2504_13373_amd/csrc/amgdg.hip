@@ -269,9 +269,13 @@ static void sell_values(Ctx& C, Sell<T>& d, int64_t ns, const std::vector<int32_
 static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, const std::vector<int32_t>& rp,
                        const std::vector<int32_t>& ci, const double* nat_d, bool f32, hipStream_t st) {
     if (br < 1 || br > 64) throw Error(AMGDG_EUNSUPPORTED, "block size must be 1..64");
-    const int G = 64 / br, L = G * br;
-    const int64_t ns = (n_brow + G - 1) / G;
     auto len = [&](int64_t row) { return row < n_brow ? rp[row + 1] - rp[row] : 0; };
+    int32_t longest = 0;
+    for (int64_t row = 0; row < n_brow; ++row) longest = std::max(longest, len(row));
+    // floor(64 / br) block rows per wavefront, fewer for long rows (the x
+    // staging of a slice must fit LDS)
+    const int G = sell_rows_per_wave(br, bc, longest), L = G * br;
+    const int64_t ns = (n_brow + G - 1) / G;
     // Slot counts with the rows in order, and with the rows sorted by length
     // (longest first, stable) within windows of 8 slices; the sorted order is
     // kept for the square-block level operators when it cuts the padded slots
@@ -607,7 +611,7 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
     const amgdg_params& p = C.prm;
     if (nb < 1 || nb > 16) throw Error(AMGDG_EUNSUPPORTED, "nb must be 1..16");
     if (p.n_levels < 1) throw Error(AMGDG_EINVAL, "n_levels must be >= 1");
-    if (p.n_levels > 1 && (p.r < 1 || p.r > 8)) throw Error(AMGDG_EUNSUPPORTED, "r must be 1..8");
+    if (p.n_levels > 1 && (p.r < 1 || p.r > 16)) throw Error(AMGDG_EUNSUPPORTED, "r must be 1..16");
     if (p.t_pre < 0 || p.t_post < 0 || p.q_power < 0 || p.relax_max < 1 || !(p.n_cut > 0))
         throw Error(AMGDG_EINVAL, "bad smoothing or coarsening parameters");
     if (p.b_update != 0) throw Error(AMGDG_EUNSUPPORTED, "only B^{k+1} = R B^k is implemented");

@@ -9,8 +9,8 @@ namespace amgdg {
 
 // Sliced, row-interleaved block-sparse matrix with br x bc blocks (br > 4).
 //
-// Block rows are grouped in slices of G = floor(64 / br) rows; one wavefront
-// owns a slice and each of its first L = G * br lanes owns one scalar row.  A
+// Block rows are grouped in slices of G rows (floor(64 / br), fewer for long
+// rows: see sell_rows_per_wave); one wavefront owns a slice and each of its first L = G * br lanes owns one scalar row.  A
 // slice stores K (its longest block row) block slots per row, padded with zero
 // blocks whose column is 0.  The K*bc values of a lane's row are flattened as
 // t = k*bc + j and stored in vectors of VW = 16 / sizeof(T) values:
@@ -89,6 +89,10 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap = 0,
                        T omega = T(0));
+// Block rows per wavefront of the sliced layout: floor(64 / br), lowered until
+// one column of FP64 x staging plus D^{-1} (rows of up to max_row_blocks blocks
+// of bc columns) fits the 64 KB of LDS a workgroup may take; at least 1.
+int sell_rows_per_wave(int br, int bc, int max_row_blocks);
 // y = A x and xy[c] = x[:,c] . y[:,c] (FP64, sliced layout): each workgroup of
 // the product writes one partial sum per column (its four slices in order) to
 // part (n_slices * 8 doubles suffice), which a one-workgroup kernel adds in a

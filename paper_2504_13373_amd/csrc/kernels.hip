@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cfloat>
 #include <cmath>
 
@@ -50,7 +51,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // r[c] -= sum_t vals[t] * x(t)[c] over the flattened (slot, column) values of
 // this lane's row; the x blocks of the slice are first staged in LDS (xs, one
-// row of tpad * M values per block row of the slice) by the lanes i < bc.
+// row of tpad * M values per block row of the slice) by the br lanes of the
+// block row, lane i taking the block columns i, i + br, ...
 template <typename T, int M>
 __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, int lc, int g, int i,
                                          const T* __restrict__ x, int ld, T* xs, T (&r)[M], T sign) {
@@ -73,12 +75,13 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     // rows of M values move as 16-byte vectors when the stride and the base allow
     const bool vx = M % VW == 0 && ld % VW == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     if (lane < L) {
-        if (i < bc) {
+        // lane i stages columns i, i + br, ... of every block (one pass when bc <= br)
+        for (int j = i; j < bc; j += A.br) {
             // unrolled so that several blocks' column and x loads are in flight at once
 #pragma unroll 4
             for (int kk = 0; kk < K; ++kk) {
-                const T* __restrict__ src = x + (int64_t(cp[kk * G]) * bc + i) * ld;
-                T* dst = xr + (kk * bc + i) * M;
+                const T* __restrict__ src = x + (int64_t(cp[kk * G]) * bc + j) * ld;
+                T* dst = xr + (kk * bc + j) * M;
                 if (vx) {
 #pragma unroll
                     for (int q = 0; q < M / VW; ++q) reinterpret_cast<V*>(dst)[q] = reinterpret_cast<const V*>(src)[q];
@@ -298,6 +301,26 @@ static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* 
     return hipGetLastError();
 }
 
+// LDS one workgroup may allocate on the current device (160 KB on gfx950),
+// read once per device.  Launch shapes are chosen within 64 KB, which keeps
+// several workgroups resident per CU; only a launch that cannot fit 64 KB even
+// at one block row per wavefront and one column (coarse operators whose rows
+// span most of the level) uses more, up to this limit.
+static size_t lds_limit() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int a = 0;
+        if (hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || a < 65536)
+            a = 65536;
+        cache[dev].store(a, std::memory_order_relaxed);
+        v = a;
+    }
+    return size_t(v);
+}
+
 // Columns are processed in chunks (each a separate launch): the LDS staging
 // buffers grow with the chunk width, so it is capped at 4 (FP64) / 8 (FP32).
 // and kept within 64 KB of LDS per workgroup.
@@ -312,13 +335,21 @@ static int sell_chunk(int rem, const Sell<T>& A, bool with_dinv, int want) {
     return w <= cap ? w : (cap >= 4 ? 4 : cap >= 2 ? 2 : 1);
 }
 
+int sell_rows_per_wave(int br, int bc, int max_row_blocks) {
+    const size_t need = size_t((int64_t(max_row_blocks) * bc + 1) / 2 * 2 + (br + 1) / 2 * 2) * sizeof(double);
+    int G = 64 / br;
+    while (G > 1 && size_t(WAVES_PER_WG) * G * need > 65536) --G;
+    return G;
+}
+
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                         const int32_t* colmask, hipStream_t st, int cap, T* y2) {
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, true, cap);
-        if (size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * w * sizeof(T) > 65536) return hipErrorInvalidConfiguration;
+        if (size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * w * sizeof(T) > lds_limit())
+            return hipErrorInvalidConfiguration;
         const T* xc = x ? x + c0 : nullptr;
         const T* bc = b ? b + c0 : nullptr;
         const int32_t* mc = colmask ? colmask + c0 : nullptr;
@@ -343,7 +374,7 @@ hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y,
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, false, cap);
-        if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(T) > 65536) return hipErrorInvalidConfiguration;
+        if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(T) > lds_limit()) return hipErrorInvalidConfiguration;
         const T* bc = b ? b + c0 : nullptr;
         hipError_t e;
         switch (w) {
@@ -989,13 +1020,13 @@ hipError_t launch_block_inverse(const double* Av, const int32_t* dpos, int64_t n
 // ============================================================ SVD (one-sided Jacobi)
 // One wavefront per aggregate J.  The rows of J are the contiguous dofs
 // [first_child[J] * nb, first_child[J+1] * nb) of B (row-major, r columns).
-// Lanes hold rows lane and lane + 64 (<= 128 rows), r <= 8 columns.  Hestenes'
+// Lanes hold rows lane and lane + 64 (<= 128 rows), r <= 16 columns.  Hestenes'
 // one-sided Jacobi rotates column pairs until they are orthogonal to working
 // precision; the singular values are the column norms and the left singular
 // vectors the normalised columns.  Output: the leading s columns (descending
 // singular values), each flipped so its largest-magnitude entry (lowest row on
 // ties) is positive, written to Pu (row-major n x s), and all r singular values.
-constexpr int SVD_MAXR = 8;
+constexpr int SVD_MAXR = 16;
 constexpr int SVD_MAXROWS = 128;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -2059,7 +2090,8 @@ hipError_t launch_spmv_dot(const Sell<double>& A, const double* x, double* y, in
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<double>(m - c0, A, false, cap);
-        if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(double) > 65536) return hipErrorInvalidConfiguration;
+        if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(double) > lds_limit())
+            return hipErrorInvalidConfiguration;
         hipError_t e;
         switch (w) {
             case 8: e = spmv_m<double, 8>(AX_DOT, A, x + c0, nullptr, y + c0, m, m, st, 0.0, part); break;
