@@ -83,10 +83,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rhs", type=int, default=1, help="right-hand sides per solve")
-    ap.add_argument("--workload", choices=["poisson2d", "convdiff", "poisson3d", "serving"], default="poisson2d",
+    ap.add_argument("--workload", choices=["poisson2d", "convdiff", "poisson3d", "serving", "hex"],
+                    default="poisson2d",
                     help="poisson2d: the headline workload; convdiff: LDG convection-diffusion Peclet sweep "
                          "with FGMRES(30); poisson3d: 3D tetrahedra, 16 right-hand sides; serving: a Poisson "
-                         "stream of solve requests over a catalogue of operators")
+                         "stream of solve requests over a catalogue of operators; hex: the structured "
+                         "hexahedral Poisson problem (Q1, IP and LDG, 2^M cubes per direction, M = 3, 4, 5)")
     ap.add_argument("--catalogue", type=int, default=32, help="serving: operator instances")
     ap.add_argument("--t-max", type=float, default=2e5, help="serving: largest triangle count")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="serving: seconds of arrivals counted")
@@ -130,6 +132,8 @@ def main():
         return bench_poisson3d(args, am, torch, dev)
     if args.workload == "serving":
         return bench_serving_stream(args, am, torch, dev)
+    if args.workload == "hex":
+        return bench_hex(args, am, torch, dev)
     args.side = args.side or 256
     log(f"generating workload (side {args.side})")
     t0 = time.perf_counter()
@@ -356,14 +360,14 @@ def _contract(args, metric_value, ms, dtype, workload, extra):
     print(json.dumps(line), flush=True)
 
 
-def _timed_solves(am, torch, h, b, x, method, prec, maxit, steps, restart=30):
+def _timed_solves(am, torch, h, b, x, method, prec, maxit, steps, restart=30, rtol=1e-8):
     """A two-iteration warm-up solve (captures the V-cycle graphs), then
     max(steps, 1) timed solves; returns the last status and the median time."""
     def one(it):
         x.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, st = am.amgdg_solve(h, b, x, method, prec, 1e-8, it, restart=restart)
+        rc, st = am.amgdg_solve(h, b, x, method, prec, rtol, it, restart=restart)
         torch.cuda.synchronize()
         return rc, st, time.perf_counter() - t0
     one(2)
@@ -414,6 +418,59 @@ def bench_convdiff(args, am, torch, dev):
               f"2D convection-diffusion, LDG + upwind p=2 on the Delaunay triangulation of {side}^2 jittered points, "
               f"6-level RCB hierarchy, r=4, V(3,3), FGMRES(30) to 1e-8; value: FP64 at Peclet 100",
               {"peclet_sweep": sweep, "max_it": maxit})
+
+
+# Iteration counts printed in Section 5.1 for this problem (solver / pCG, IP / LDG).
+PAPER_HEX_ITERATIONS = {3: {"ip": 7, "ldg": 7, "ip_pcg": 6, "ldg_pcg": 6},
+                        4: {"ip": 7, "ldg": 8, "ip_pcg": 6, "ldg_pcg": 7},
+                        5: {"ip": 7, "ldg": 9, "ip_pcg": 6, "ldg_pcg": 7}}
+
+
+def bench_hex(args, am, torch, dev):
+    """The structured Poisson problem of Section 5.1: 2^M cubes per direction of
+    [-1, 1]^3, Q1, IP (penalty M (p+1)^2 / 2) and minimal-dissipation LDG,
+    Dirichlet on x = -1 and Neumann elsewhere, right-hand side of the paper's
+    manufactured solution; ceil(log_8 |T_h|) levels of 8-way RCB aggregates,
+    r = 8 and r = 16 (coarse blocks min(ceil(|A_J| / 6), r)), V(3,3);
+    multigrid as the solver and as the CG preconditioner, to the paper's 1e-7,
+    in FP64, and flexible CG with the FP32 V-cycle."""
+    from workloads import configs
+    maxit = min(args.max_it, 2000)
+    table = {}
+    for r in (8, 16):
+        for M in (3, 4, 5):
+            for flux in ("ip", "ldg"):
+                w = configs.poisson3d_hex(M, flux=flux, r=r)
+                A = w.A.to_scipy()
+                t0 = time.perf_counter()
+                h, _ = am.setup_from_workload(w, mixed=True)
+                torch.cuda.synchronize()
+                setup_s = time.perf_counter() - t0
+                infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
+                b = torch.as_tensor(w.b).to(dev).contiguous()
+                x = torch.zeros_like(b)
+                res = {"dofs": w.A.n, "levels_n": [i.n for i in infos], "setup_s": setup_s,
+                       "levels_nnz": [int(i.nnzb) * i.nb * i.nb for i in infos]}
+                for name, meth, prec in (("solver", am.AMGDG_STATIONARY, am.AMGDG_FP64),
+                                         ("pcg", am.AMGDG_PCG, am.AMGDG_FP64),
+                                         ("fcg_mixed", am.AMGDG_FCG, am.AMGDG_MIXED)):
+                    rc, st, t = _timed_solves(am, torch, h, b, x, meth, prec, maxit, args.steps, rtol=1e-7)
+                    tr = float(np.linalg.norm(w.b - A @ x.cpu().numpy()) / np.linalg.norm(w.b))
+                    res[name] = {"iterations": st.iterations[0], "converged": rc == am.AMGDG_OK, "seconds": t,
+                                 "true_rel_residual": tr}
+                    log(f"hex M={M} {flux} r={r} {name}: rc {rc}, {st.iterations[0]} iterations, {t * 1e3:.1f} ms, "
+                        f"true rel {tr:.2e}")
+                paper = PAPER_HEX_ITERATIONS[M]
+                res["paper_iterations"] = {"solver": paper[flux], "pcg": paper[flux + "_pcg"]}
+                res["coarse_block_sizes"] = [i.s for i in infos[:-1]]
+                table[f"M{M}_{flux}_r{r}"] = res
+                h.close()
+    top = table["M5_ip_r16"]["pcg"]
+    _contract(args, 1.0 / top["seconds"], top["seconds"] * 1e3, "f64 (and f32 V-cycle + f64 Krylov)",
+              "3D Poisson on 2^M hexahedra per direction of [-1,1]^3, Q1, IP and LDG, Dirichlet x=-1, "
+              "Neumann elsewhere, paper's manufactured solution, ceil(log_8 |T_h|) levels, r=8 and 16, V(3,3), "
+              "to 1e-7; value: FP64 multigrid-preconditioned CG at M=5 (262,144 dofs), IP, r=16",
+              {"hex_table": table, "max_it": maxit})
 
 
 def _level0_rates(am, torch, h, infos, dev, nu, m=1, reps=20):

@@ -12,6 +12,12 @@ right-hand side 1, B^1 2.  Sizes follow the benchmark configurations:
 * ``poisson3d_p2_64``  : 64^3 jittered Kuhn cube, SIPG p=2
                          (1,572,864 tetrahedra, 15,728,640 dofs)
 
+* ``poisson3d_hex``    : the structured test problem of Section 5.1: 2^M hexahedra
+                         per direction on [-1, 1]^3, Q1 (nb = 8), IP or LDG,
+                         Dirichlet on x = -1, Neumann elsewhere, right-hand
+                         side of the paper's manufactured solution
+                         (M = 4: 4,096 hexahedra, 32,768 dofs)
+
 * ``serving_catalogue``: the operator instances of the serving stream (2D
                          jittered Delaunay meshes of 1k-200k triangles, p = 1..4,
                          SIPG-Poisson or LDG + upwind convection-diffusion)
@@ -23,7 +29,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import dg, mesh as meshes
+from . import dg, hexdg, mesh as meshes
 
 
 @dataclass
@@ -110,6 +116,23 @@ def poisson3d_kuhn(n=64, p=2, n_levels=5, bisections=3, r=4, nu=2, n_rhs=1, log=
     A = dg.assemble_sipg(m, p, log=log)
     prm = Params(n_levels, bisections, r, nu, nu, n_cut=n_cut_default(3))
     return _finish(f"poisson3d_p{p}_kuhn{n}", m, p, A, prm, "pcg", n_rhs=n_rhs)
+
+
+def poisson3d_hex(M=4, p=1, flux="ip", r=8, nu=3, n_levels=None, rhs="paper", relax_max=100):
+    """Section 5.1's structured Poisson problem.  Levels: ceil(log_8 |T_h|), so
+    that the coarsest level holds 8 aggregates, with 8-way aggregation per
+    level; rhs "paper" is the load vector of the manufactured solution, else
+    seeded N(0, 1) like the other workloads."""
+    m = hexdg.HexMesh(M)
+    A = hexdg.assemble_hex(M, p, flux)
+    if n_levels is None:
+        n_levels = max(2, M)
+    prm = Params(n_levels, 3, r, nu, nu, relax_max=relax_max, n_cut=n_cut_default(3))
+    w = _finish(f"poisson3d_hex{M}_q{p}_{flux}", m, p, A, prm, "pcg", extra={"flux": flux, "M": M})
+    if rhs == "paper":
+        w.b = np.ascontiguousarray(hexdg.paper_rhs(M, p))
+        w.tol = 1e-7
+    return w
 
 
 def levels_for_coarsest(n_elem, bisections=2, r=3, max_coarse=2048):
