@@ -470,13 +470,47 @@ def bench_hex(args, am, torch, dev):
                     res["kernels"] = _level0_rates(am, torch, h, infos, dev, 3)
                 table[f"M{M}_{flux}_r{r}"] = res
                 h.close()
+    extra = {"hex_table": table, "max_it": maxit}
+    if not args.no_cpu_baseline:
+        extra["cpu_baseline"] = _hex_cpu_baseline(configs, table)
     key = "M5_ip_r16" if "M5_ip_r16" in table else next(iter(table))
     top = table[key]["pcg"]
     _contract(args, 1.0 / top["seconds"], top["seconds"] * 1e3, "f64 (and f32 V-cycle + f64 Krylov)",
               "3D Poisson on 2^M hexahedra per direction of [-1,1]^3, Q1, IP and LDG, Dirichlet x=-1, "
               "Neumann elsewhere, paper's manufactured solution, ceil(log_8 |T_h|) levels, r=8 and 16, V(3,3), "
-              f"to 1e-7; value: FP64 multigrid-preconditioned CG, {key}",
-              {"hex_table": table, "max_it": maxit})
+              f"to 1e-7; value: FP64 multigrid-preconditioned CG, {key}", extra)
+
+
+def _hex_cpu_baseline(configs, table, M=4, flux="ldg", r=16):
+    """The FP64 oracle on the host cores, one whole pCG solve to 1e-7 of the hex
+    problem at M = 4 (LDG, r = 16), beside the GPU's time for the same solve."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import amg, krylov, rcb
+    w = configs.poisson3d_hex(M, flux=flux, r=r)
+    log(f"cpu baseline (hex M={M} {flux} r={r}): oracle setup")
+    t0 = time.perf_counter()
+    aggs, _ = rcb.rcb_hierarchy(w.centroids, w.params.n_levels, w.params.bisections)
+    A = w.A.to_scipy()
+    H = amg.setup(A, w.A.nb, aggs, w.params, w.B1)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, its, _ = krylov.pcg(A, w.b, lambda v: amg.vcycle(H, v), 1e-7, 500)[:3]
+    t_solve = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    gpu = table.get(f"M{M}_{flux}_r{r}", {}).get("pcg")
+    log(f"cpu baseline (hex): setup {t_setup:.1f} s, pCG {its} iterations in {t_solve:.2f} s")
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"FP64 oracle (NumPy/SciPy): one whole pCG solve to 1e-7 of the hex problem at M={M}, {flux}, "
+                  f"r={r} ({its} iterations, {t_solve:.2f} s; setup {t_setup:.1f} s not counted); sparse products "
+                  f"single-threaded, dense LAPACK on {threads} threads",
+        "gpu_seconds_same_solve": gpu["seconds"] if gpu else None,
+        "gpu_iterations_same_solve": gpu["iterations"] if gpu else None,
+    }
 
 
 def _level0_rates(am, torch, h, infos, dev, nu, m=1, reps=20):
