@@ -289,6 +289,8 @@ def project(M, p, u, nq=None):
 
 
 def _volume(M, p, f, nq=None, chunk=4096):
+    """int_K f phi_i for every element K and local function i (tensor Gauss
+    rule with nq points per direction), flattened in element-block order."""
     mesh = HexMesh(M)
     h, k, ne = mesh.h, p + 1, mesh.n_elem
     nq = nq or p + 4
@@ -335,4 +337,5 @@ def paper_f(x):
 
 
 def paper_rhs(M, p):
+    """Load vector of the manufactured solution: volume term and Neumann data."""
     return load_vector(M, p, paper_f, paper_grad_u)
