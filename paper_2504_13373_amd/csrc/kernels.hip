@@ -368,9 +368,98 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
     return hipSuccess;
 }
 
+// Long rows at one block row per wavefront (G = 1 with br <= 16, where the
+// row's x staging does not fit more): the sliced kernel would walk the row's
+// values with br lanes and leave the rest idle.  Here the four groups of 16
+// lanes take every fourth value vector of the row, so a wavefront still reads
+// one contiguous run per step, and two xor-shuffles add the groups' partial
+// sums.  One column per launch; every batch width takes this kernel, so a
+// column's rounding does not depend on the width.
+template <typename T, int MODE, bool ROWS>
+__global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int ldx, int ldy, T omega) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int VW = 16 / int(sizeof(T));
+    using V = typename Vec16<T>::type;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
+    if (slice >= A.n_slices) return;  // the whole wavefront
+    const int br = A.br, bc = A.bc, L = A.L;  // G == 1, so L == br
+    const int q = lane >> 4, i = lane & 15;
+    const int64_t brow = ROWS ? int64_t(A.rows[slice]) : int64_t(slice);
+    const bool own = q == 0 && i < br && brow < A.n_brow;
+    const int64_t row = brow * br + i;
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * A.tpad;
+    const int K = A.K[slice];
+    const int Tn = K * bc, TQ = (Tn + VW - 1) / VW;
+    const int32_t* __restrict__ cp = A.cols + A.coff[slice];
+    for (int t = lane; t < TQ * VW; t += 64) {
+        T v = T(0);
+        if (t < Tn) {
+            const int kk = t / bc;
+            v = x[(int64_t(cp[kk]) * bc + (t - kk * bc)) * ldx];
+        }
+        xs[t] = v;
+    }
+    wave_lds_sync();
+    T acc = T(0);
+    if (i < L) {
+        const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + i;
+#pragma unroll 4
+        for (int v = q; v < TQ; v += 4) {
+            T a[VW];
+            *reinterpret_cast<V*>(a) = vp[int64_t(v) * L];
+#pragma unroll
+            for (int u = 0; u < VW; ++u) acc += a[u] * xs[v * VW + u];
+        }
+    }
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    if (!own) return;
+    T val = acc;
+    if (MODE == B_MINUS) val = b[row * ldy] - acc;
+    else if (MODE == B_PLUS) val = b[row * ldy] + acc;
+    else if (MODE == S_SWEEP) val = x[row * ldx] + omega * (b[row * ldy] - acc);
+    y[row * ldy] = val;
+}
+
+template <typename T>
+static bool spmv_split_ok(int mode, const Sell<T>& A) {
+    return A.G == 1 && A.br <= 16 && (mode == AX || mode == B_MINUS || mode == B_PLUS || mode == S_SWEEP);
+}
+
+template <typename T>
+static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st,
+                             T omega) {
+    const size_t lds = size_t(WAVES_PER_WG) * A.tpad * sizeof(T);
+    if (lds > lds_limit()) return hipErrorInvalidConfiguration;
+    if (A.n_slices == 0) return hipSuccess;
+    const dim3 grid{unsigned(grid_for(A.n_slices, WAVES_PER_WG)), 1u, 1u}, block{unsigned(WG), 1u, 1u};
+    for (int c = 0; c < m; ++c) {
+        const T* xc = x + c;
+        const T* bcol = b ? b + c : nullptr;
+        T* yc = y + c;
+#define SPLIT_LAUNCH(MD)                                                                                       \
+    if (A.rows) hipLaunchKernelGGL((k_spmv_split<T, MD, true>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega); \
+    else hipLaunchKernelGGL((k_spmv_split<T, MD, false>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega)
+        switch (mode) {
+            case AX: SPLIT_LAUNCH(AX); break;
+            case B_MINUS: SPLIT_LAUNCH(B_MINUS); break;
+            case B_PLUS: SPLIT_LAUNCH(B_PLUS); break;
+            case S_SWEEP: SPLIT_LAUNCH(S_SWEEP); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef SPLIT_LAUNCH
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
                        T omega) {
+    if (spmv_split_ok(mode, A)) return spmv_split(mode, A, x, b, y, m, st, omega);
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, false, cap);

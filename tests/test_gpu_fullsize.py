@@ -180,7 +180,9 @@ def test_fullsize_hex_m5_ldg_r16():
     The oracle is set up at full size.  Levels 0 and 1 truncate well-conditioned
     candidate blocks (16 columns to 11 and 15; smallest relative gap at the cut
     5e-6), so their damping, relaxation sweeps, D^{-1} and the coarse operators
-    A_1 and A_2 are held to the full bar.  Level 2 keeps all 16 columns of
+    A_1 and A_2 are held to the full bar.  Every single step on every level is
+    compared with the host product of the exported operators, in both
+    precisions, one and three columns.  Level 2 keeps all 16 columns of
     nearly collapsed blocks (condition 1e10), so below it only the solve is
     checked for validity: pCG to the paper's 1e-7 in true residual, in an
     iteration count near the oracle's."""
@@ -205,6 +207,33 @@ def test_fullsize_hex_m5_ldg_r16():
             A1 = sp.bsr_matrix((v, ci, rp), shape=(n1, n1)).tocsr()
             ref = H.levels[k + 1].A
             assert sp.linalg.norm(A1 - ref) <= 1e-9 * sp.linalg.norm(ref), k
+        # every single step on every level against the host product of the exported
+        # operators (level 2's long rows take the split-row kernel), and a column
+        # of a 3-column launch equal to the same column alone
+        from test_gpu_parity import OPS, host_op
+        g = np.random.default_rng(29)
+        for prec, dt in ((am.AMGDG_FP64, torch.float64), (am.AMGDG_MIXED, torch.float32)):
+            for k in range(h.n_levels - 1):
+                info = am.amgdg_level_info_get(h, k)
+                n, n1 = info.n, info.n_agg * info.s
+                for op in OPS:
+                    nx = n1 if op == "prolong" else n
+                    ny = n1 if op.startswith("restrict") else n
+                    xs = g.standard_normal((nx, 3))
+                    bs = g.standard_normal((ny, 3))
+                    if prec == am.AMGDG_MIXED:
+                        xs, bs = (v.astype(np.float32).astype(np.float64) for v in (xs, bs))
+                    code = getattr(am, "AMGDG_OP_" + op.upper())
+                    y3 = torch.zeros((ny, 3), dtype=dt, device=DEV)
+                    am.amgdg_apply(h, k, code, to_dev(xs, dt), to_dev(bs, dt), y3, precision=prec)
+                    y1 = torch.zeros(ny, dtype=dt, device=DEV)
+                    am.amgdg_apply(h, k, code, to_dev(xs[:, 0], dt), to_dev(bs[:, 0], dt), y1, precision=prec)
+                    torch.cuda.synchronize()
+                    assert torch.equal(y3[:, 0], y1), (prec, k, op)
+                    want, scale = host_op(op, k, h, w, xs, bs, prec)
+                    err = np.abs(y3.double().cpu().numpy() - want).max(axis=0) / np.abs(scale).max(axis=0)
+                    tol = 1e-13 if prec == am.AMGDG_FP64 else 64 * 2.0 ** -24 * 4
+                    assert np.all(err <= tol), (prec, k, op, err)
         _, ito = krylov.pcg(A, w.b, lambda r: amg.vcycle(H, r), 1e-7, 200)[:2]
         x = torch.zeros(w.A.n, dtype=torch.float64, device=DEV)
         rc, st = am.amgdg_solve(h, to_dev(w.b), x, am.AMGDG_PCG, am.AMGDG_FP64, 1e-7, 200)
