@@ -342,9 +342,122 @@ int sell_rows_per_wave(int br, int bc, int max_row_blocks) {
     return G;
 }
 
+// The sweeps with D^{-1} (sliced layout) at one block row per wavefront, the
+// row's product split over four groups of 16 lanes as in k_spmv_split; the
+// block row's residual then goes through LDS to the br lanes that apply their
+// row of D^{-1}.  One column per launch at every batch width.
+template <typename T, int MODE, bool ROWS>
+__global__ __launch_bounds__(WG) void k_sweep_split(Sell<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
+                                                     const T* __restrict__ b, T* __restrict__ y, T omega,
+                                                     const int32_t* __restrict__ colmask, int ld,
+                                                     T* __restrict__ y2) {
+    constexpr bool HAS_B = (MODE == SWEEP || MODE == SWEEP0);
+    constexpr bool HAS_A = (MODE != SWEEP0);
+    constexpr int VW = 16 / int(sizeof(T));
+    using V = typename Vec16<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
+    if (slice >= A.n_slices) return;  // the whole wavefront
+    const int br = A.br, bc = A.bc, L = A.L, BP = A.brpad;  // G == 1, so L == br
+    const int q = lane >> 4, i = lane & 15;
+    const int64_t brow = ROWS ? int64_t(A.rows[slice]) : int64_t(slice);
+    const bool mine = q == 0 && i < br;
+    const bool own = mine && brow < A.n_brow;
+    const int64_t row = brow * br + i;
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * (A.tpad + BP);
+    T* rr = xs + A.tpad;
+    T acc = T(0);
+    if (HAS_A) {
+        const int K = A.K[slice];
+        const int Tn = K * bc, TQ = (Tn + VW - 1) / VW;
+        const int32_t* __restrict__ cp = A.cols + A.coff[slice];
+        for (int t = lane; t < TQ * VW; t += 64) {
+            T v = T(0);
+            if (t < Tn) {
+                const int kk = t / bc;
+                v = x[(int64_t(cp[kk]) * bc + (t - kk * bc)) * ld];
+            }
+            xs[t] = v;
+        }
+        wave_lds_sync();
+        if (i < L) {
+            const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + i;
+#pragma unroll 4
+            for (int v = q; v < TQ; v += 4) {
+                T a[VW];
+                *reinterpret_cast<V*>(a) = vp[int64_t(v) * L];
+#pragma unroll
+                for (int u = 0; u < VW; ++u) acc += a[u] * xs[v * VW + u];
+            }
+        }
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+    }
+    // residual of the block row through LDS (zero-padded to brpad), then row i of D^{-1}
+    if (q == 0 && i < BP) {
+        T r = T(0);
+        if (own) r = (HAS_B ? b[row * ld] : T(0)) - acc;
+        rr[i] = r;
+    }
+    wave_lds_sync();
+    if (!own) return;
+    const V* __restrict__ dp = reinterpret_cast<const V*>(dinv + int64_t(slice) * BP * L) + i;
+    T o = T(0);
+#pragma unroll 4
+    for (int jq = 0; jq < BP / VW; ++jq) {
+        T d[VW];
+        *reinterpret_cast<V*>(d) = dp[jq * L];
+#pragma unroll
+        for (int u = 0; u < VW; ++u) o += d[u] * rr[jq * VW + u];
+    }
+    T v;
+    if (MODE == SWEEP) v = x[row * ld] + omega * o;
+    else if (MODE == SWEEP0) v = omega * o;
+    else if (MODE == RELAX) v = colmask[0] ? x[row * ld] + omega * o : x[row * ld];
+    else v = -o;  // DINVA: r = -A x
+    y[row * ld] = v;
+    if (MODE == SWEEP0 && y2) y2[row * ld] = o;
+}
+
+template <typename T>
+static hipError_t sweep_split(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
+                              int m, const int32_t* colmask, hipStream_t st, T* y2) {
+    const size_t lds = size_t(WAVES_PER_WG) * (A.tpad + A.brpad) * sizeof(T);
+    if (lds > lds_limit()) return hipErrorInvalidConfiguration;
+    if (A.n_slices == 0) return hipSuccess;
+    const dim3 grid{unsigned(grid_for(A.n_slices, WAVES_PER_WG)), 1u, 1u}, block{unsigned(WG), 1u, 1u};
+    for (int c = 0; c < m; ++c) {
+        const T* xc = x ? x + c : nullptr;
+        const T* bcol = b ? b + c : nullptr;
+        const int32_t* mc = colmask ? colmask + c : nullptr;
+        T* yc = y + c;
+        T* y2c = y2 ? y2 + c : nullptr;
+#define SPLIT_LAUNCH(MD)                                                                                    \
+    if (A.rows)                                                                                             \
+        hipLaunchKernelGGL((k_sweep_split<T, MD, true>), grid, block, lds, st, A, dinv, xc, bcol, yc, omega, mc, m, \
+                           y2c);                                                                            \
+    else                                                                                                    \
+        hipLaunchKernelGGL((k_sweep_split<T, MD, false>), grid, block, lds, st, A, dinv, xc, bcol, yc, omega, mc, m, \
+                           y2c)
+        switch (mode) {
+            case SWEEP: SPLIT_LAUNCH(SWEEP); break;
+            case SWEEP0: SPLIT_LAUNCH(SWEEP0); break;
+            case RELAX: SPLIT_LAUNCH(RELAX); break;
+            case DINVA: SPLIT_LAUNCH(DINVA); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef SPLIT_LAUNCH
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                         const int32_t* colmask, hipStream_t st, int cap, T* y2) {
+    if (A.G == 1 && A.br <= 16) return sweep_split(mode, A, dinv, x, b, y, omega, m, colmask, st, y2);
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, true, cap);
