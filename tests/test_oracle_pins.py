@@ -345,3 +345,116 @@ def test_full_solve_against_direct():
     M32 = amg.to_fp32(H)
     x, it, _ = krylov.fgmres(A, w.b, lambda r: amg.vcycle_fp32(H, M32, r).astype(np.float64), 1e-8, 400, 2000)
     assert np.linalg.norm(w.b - A @ x) <= 1e-8 * np.linalg.norm(w.b)
+
+
+# ---------------------------------------------------------------- Algorithm 2 as a solver
+
+def test_stationary_exact_preconditioner_one_step(tiny):
+    """With M = A^{-1} the correction x + M(b - A x) is the solution after one step."""
+    A = tiny.A.to_scipy()
+    Ad = A.toarray()
+    x, it, hist = krylov.stationary(A, tiny.b, lambda r: sla.solve(Ad, r), 1e-12, 10)
+    assert it == 1 and len(hist) == 1
+    xs = sla.solve(Ad, tiny.b)
+    assert np.linalg.norm(x - xs) < 1e-12 * np.linalg.norm(xs)
+
+
+def test_stationary_iterates_are_the_neumann_partial_sums(tiny):
+    """For a fixed linear M, iterate k from x = 0 is sum_{j<k} (I - MA)^j M b
+    (formed densely), and the solver stops at the first k whose true relative
+    residual meets the tolerance, not one step earlier or later."""
+    A = tiny.A.to_scipy()
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    Mm = 0.7 * np.linalg.inv(dense_D(Ad, 3))          # a fixed linear preconditioner
+    b = tiny.b
+    E = np.eye(n) - Mm @ Ad
+    sums, term, acc = [], Mm @ b, np.zeros(n)
+    for _ in range(8):
+        acc = acc + term
+        sums.append(acc.copy())
+        term = E @ term
+    for k in (1, 2, 5, 8):
+        x, it, hist = krylov.stationary(A, b, lambda r: Mm @ r, 0.0, k)
+        assert it == k and len(hist) == k
+        assert np.linalg.norm(x - sums[k - 1]) < 1e-12 * np.linalg.norm(sums[k - 1])
+    res = [np.linalg.norm(b - Ad @ s) / np.linalg.norm(b) for s in sums]
+    assert all(res[j + 1] < res[j] for j in range(len(res) - 1))
+    kstar = 5
+    tol = math.sqrt(res[kstar - 2] * res[kstar - 1])   # between the residuals of steps 4 and 5
+    _, it, _ = krylov.stationary(A, b, lambda r: Mm @ r, tol, 100)
+    assert it == kstar
+
+
+# ---------------------------------------------------------------- eq:sik truncation (s < r)
+
+def test_coarse_size_rounding_and_caps():
+    """eq:sik h-step: |A_J| / n_cut read as the ceiling, capped by the rank
+    min(|A_J|, r) that the |A_J| x r candidate block can supply."""
+    assert amg.coarse_size(12, 5.0, 6) == 3          # ceil(2.4); the floor would give 2
+    assert amg.coarse_size(12, 3.0, 6) == 4          # exact quotient
+    assert amg.coarse_size(12, 5.0, 2) == 2          # r binds
+    assert amg.coarse_size(2, 1.0, 6) == 2           # |A_J| binds
+    assert amg.coarse_size(40, 3.0, 40) == 14        # the oversampled 2D case: ceil(13.3)
+
+
+def test_truncated_prolongator_spans_the_leading_singular_subspace(tiny):
+    """s_J < r: on each aggregate the kept columns of P~ span the dominant
+    s_J-dimensional left singular subspace of B^k[A_J, :], i.e. P~_J P~_J^T is
+    the projector onto the top s_J eigenvectors of B_J B_J^T (dense eigh)."""
+    w = tiny
+    A = w.A.to_scipy()
+    aggs, _ = rcb.rcb_hierarchy(w.centroids, 2, 2)
+    assert np.all(np.bincount(aggs[0]) == 4)               # |A_J| = 12 dofs each
+    r, n_cut = 6, 5.0
+    prm = dataclasses.replace(w.params, n_levels=2, r=r, n_cut=n_cut)
+    B1 = np.random.default_rng(2).standard_normal((A.shape[0], r))
+    H = amg.setup(A, 3, aggs, prm, B1)
+    L = H.levels[0]
+    assert L.s == 3 and L.s < r
+    P = L.P.toarray()
+    assert P.shape[1] == 3 * (aggs[0].max() + 1)
+    assert np.abs(P.T @ P - np.eye(P.shape[1])).max() < 1e-12
+    order = np.argsort(L.agg, kind="stable")
+    for J in range(int(L.agg.max()) + 1):
+        units = order[L.agg[order] == J]
+        dofs = (units[:, None] * 3 + np.arange(3)).ravel()
+        BJ = L.B[dofs]
+        lam, Q = np.linalg.eigh(BJ @ BJ.T)
+        assert lam[-3] > 1e-6 * lam[-1] and lam[-4] < (1 - 1e-3) * lam[-3]   # a gap to truncate at
+        proj = Q[:, -3:] @ Q[:, -3:].T
+        PJ = P[dofs][:, 3 * J:3 * J + 3]
+        assert np.abs(PJ @ PJ.T - proj).max() < 1e-10
+        # every other column of P~ is zero on these rows
+        assert np.abs(np.delete(P[dofs], np.s_[3 * J:3 * J + 3], axis=1)).max() == 0.0
+        # singular values: the square roots of the Gram eigenvalues, descending
+        assert np.allclose(L.sv[J], np.sqrt(np.clip(lam[::-1][:r], 0, None)), rtol=1e-8, atol=1e-12 * np.sqrt(lam[-1]))
+
+
+# ---------------------------------------------------------------- convergence under refinement
+
+@pytest.mark.slow
+def test_convergence_factor_near_constant_under_refinement():
+    """The paper's own problem and setup (Section 5.1: Q1 LDG on 2^M hexahedra
+    per direction, V(3,3), r = the median dofs per level-1 aggregate = 64,
+    n_cut = 6, tolerance 1e-7 from zero): the average convergence factor of
+    multigrid as a solver and as the CG preconditioner stays near-constant as
+    the mesh is refined (bound: factor <= 0.35, growth <= 0.1 per refinement),
+    and the pCG counts are the paper's (6 at M = 3, 7 at M = 4) within one."""
+    fac_cg, fac_st, its_cg = [], [], []
+    for M in (2, 3, 4):
+        w = configs.poisson3d_hex(M=M, p=1, flux="ldg", r=64)
+        A = w.A.to_scipy()
+        aggs, _ = rcb.rcb_hierarchy(w.centroids, w.params.n_levels, w.params.bisections)
+        H = amg.setup(A, w.A.nb, aggs, w.params, w.B1)
+        V = lambda v: amg.vcycle(H, v)
+        _, it, hist = krylov.pcg(A, w.b, V, 1e-7, 200)
+        _, its, hs = krylov.stationary(A, w.b, V, 1e-7, 200)
+        assert hist[-1] <= 1e-7 and hs[-1] <= 1e-7
+        fac_cg.append(hist[-1] ** (1.0 / it))
+        fac_st.append(hs[-1] ** (1.0 / its))
+        its_cg.append(it)
+    for fac in (fac_cg, fac_st):
+        assert max(fac) <= 0.35, fac
+        assert all(fac[j + 1] - fac[j] <= 0.1 for j in range(len(fac) - 1)), fac
+    assert abs(its_cg[1] - 6) <= 1 and abs(its_cg[2] - 7) <= 1, its_cg
