@@ -4,7 +4,8 @@ Follows Algorithm 5 (Section 4.5) with the index garbles of its listing read as
 k = 0..N-1, T^k_{k+1} and A_{k+1} = R A_k T, and the V-cycle of Algorithm 2.
 Plain NumPy/SciPy: sparse matrices at dof level, dense diagonal blocks, LAPACK
 SVD and LU.  Level k has ``nunits`` units (elements at level 0, aggregates at
-k >= 1); unit u owns the dofs [u*nb, (u+1)*nb) of that level.
+k >= 1); unit u owns the dofs [offs[u], offs[u+1]) of that level, nb dofs each
+at level 0 and s_J (eq:sik, chosen per aggregate) on coarse levels.
 """
 import math
 from dataclasses import dataclass, field
@@ -19,16 +20,19 @@ from .rng import uniform_pm1
 @dataclass
 class Level:
     A: sp.csr_matrix
-    nb: int
+    nb: int                       # dofs per unit when all units have the same size, else 0
     nunits: int
-    Dinv: np.ndarray = None
+    sizes: np.ndarray = None      # dofs of each unit
+    Dinv: np.ndarray = None       # (nunits, nb, nb) when the sizes are uniform
+    Dinv_bd: "BlockDiag" = None   # D_k^{-1} for any sizes
     omega: float = float("nan")
     rho: float = float("nan")
     B_in: np.ndarray = None       # candidates before relaxation
     B: np.ndarray = None          # relaxed candidates
     sweeps: np.ndarray = None
     agg: np.ndarray = None        # unit -> level-(k+1) aggregate
-    s: int = 0                    # coarse block size
+    s: int = 0                    # largest coarse block size s_J of the level
+    s_agg: np.ndarray = None      # s_J of every level-(k+1) aggregate
     sv: list = field(default_factory=list)
     P: sp.csr_matrix = None
     T: sp.csr_matrix = None
@@ -72,6 +76,84 @@ def apply_blockdiag(Binv, x, nb):
     return np.einsum("uij,ujm->uim", Binv, x.reshape(nun, nb, m)).reshape(-1, m)
 
 
+class BlockDiag:
+    """A block-diagonal matrix with one dense square block per unit, unit u
+    owning the dofs [offs[u], offs[u+1]) (D_k of block Jacobi, Section 4.4;
+    after eq:sik the units of a coarse level may differ in size).  Units of
+    equal size are held together as one (count, s, s) array."""
+
+    def __init__(self, sizes, groups):
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.offs = np.concatenate([[0], np.cumsum(self.sizes)])
+        self.groups = groups          # list of (s, units, dof index (count, s), blocks (count, s, s))
+
+    @staticmethod
+    def index_groups(sizes):
+        sizes = np.asarray(sizes, dtype=np.int64)
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        out = []
+        for sz in np.unique(sizes):
+            units = np.nonzero(sizes == sz)[0]
+            out.append((int(sz), units, offs[units][:, None] + np.arange(sz)[None, :]))
+        return out
+
+    @classmethod
+    def from_matrix(cls, A, sizes):
+        """The diagonal blocks of A."""
+        A = A.tocsr()
+        groups = []
+        offs = np.concatenate([[0], np.cumsum(np.asarray(sizes, dtype=np.int64))])
+        for sz, units, idx in cls.index_groups(sizes):
+            sub = A[idx.ravel(), :].tocoo()
+            u_loc = sub.row // sz
+            i_loc = sub.row % sz
+            j_loc = sub.col - offs[units[u_loc]]
+            keep = (j_loc >= 0) & (j_loc < sz)
+            D = np.zeros((len(units), sz, sz))
+            np.add.at(D, (u_loc[keep], i_loc[keep], j_loc[keep]), sub.data[keep])
+            groups.append((sz, units, idx, D))
+        return cls(sizes, groups)
+
+    def inverse(self):
+        """Block by block (LAPACK LU with partial pivoting)."""
+        return BlockDiag(self.sizes, [(sz, u, idx, np.linalg.inv(D)) for sz, u, idx, D in self.groups])
+
+    def astype(self, dt):
+        return BlockDiag(self.sizes, [(sz, u, idx, D.astype(dt)) for sz, u, idx, D in self.groups])
+
+    def apply(self, x):
+        """y = blockdiag(D_u) x for x of shape (n,) or (n, m)."""
+        if len(self.groups) == 1:                   # equal sizes: units in order
+            D = self.groups[0][3]
+            return apply_blockdiag(D, x, D.shape[1])
+        y = np.zeros(x.shape, dtype=np.result_type(x.dtype, self.groups[0][3].dtype))
+        for sz, units, idx, D in self.groups:
+            if x.ndim == 1:
+                y[idx] = np.einsum("uij,uj->ui", D, x[idx])
+            else:
+                y[idx] = np.einsum("uij,ujm->uim", D, x[idx])
+        return y
+
+    def to_csr(self):
+        rows, cols, vals = [], [], []
+        for sz, units, idx, D in self.groups:
+            rows.append(np.repeat(idx, sz, axis=1).ravel())
+            cols.append(np.tile(idx, (1, sz)).ravel())
+            vals.append(D.ravel())
+        n = int(self.offs[-1])
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+    def uniform_array(self):
+        """(nunits, nb, nb) when every unit has the same size, else None."""
+        if len(self.groups) != 1:
+            return None
+        return self.groups[0][3]
+
+
+def _apply_dinv(Dinv, x, nb):
+    return Dinv.apply(x) if isinstance(Dinv, BlockDiag) else apply_blockdiag(Dinv, x, nb)
+
+
 def power_rho(A, Dinv, nb, q, x0):
     """Algorithm 4: estimate rho(D^{-1} A) with q power steps from a unit vector.
 
@@ -79,9 +161,9 @@ def power_rho(A, Dinv, nb, q, x0):
     x = x0 / np.linalg.norm(x0)
     for _ in range(q):
         x = A @ x
-        x = apply_blockdiag(Dinv, x, nb)
+        x = _apply_dinv(Dinv, x, nb)
         x = x / np.linalg.norm(x)
-    return float(np.linalg.norm(apply_blockdiag(Dinv, A @ x, nb)))
+    return float(np.linalg.norm(_apply_dinv(Dinv, A @ x, nb)))
 
 
 def omega_from_rho(rho):
@@ -97,7 +179,7 @@ def relax_candidate(A, Dinv, nb, omega, x, gamma, relax_max):
     that passes the test is returned (no normalisation).  Returns (x, sweeps)."""
     m = 0
     while True:
-        y = x - omega * apply_blockdiag(Dinv, A @ x, nb)
+        y = x - omega * _apply_dinv(Dinv, A @ x, nb)
         m += 1
         stop = np.linalg.norm(x) / np.linalg.norm(y) < 1.0 + gamma
         x = y
@@ -119,40 +201,64 @@ def coarse_size(n_rows, n_cut, r):
     return min(math.ceil(n_rows / n_cut), n_rows, r)
 
 
-def tentative_prolongator(B, agg, nunits, nb, n_cut):
-    """eq:splitB_dg + eq:sik: per aggregate J, SVD of B[rows of J, :] (rows in
-    child order) and P_J = the leading s_J left singular vectors.
+def hstar_size(svals, delta):
+    """eq:sik, h*-step (an aggregate that equals its only child): the number of
+    singular values above delta times the largest."""
+    sv = np.asarray(svals)
+    return int(np.count_nonzero(sv > delta * sv[0])) if len(sv) and sv[0] > 0 else 0
 
-    Returns (P as csr, s, singular values per aggregate)."""
+
+def tentative_prolongator(B, agg, sizes, n_cut, delta=1e-3):
+    """eq:splitB_dg + eq:sik: per aggregate J, SVD of B[rows of J, :] (the dofs
+    of J's children, children in increasing unit id) and P_J = the leading s_J
+    left singular vectors (canonical sign).  s_J follows eq:sik per aggregate:
+    the h-step count (coarse_size) when J has several children, the h*-step
+    count (hstar_size, threshold delta) when J equals its only child.
+
+    sizes: dofs of every unit of this level (an int for equal sizes).
+    Returns (P as csr, s_J per aggregate, singular values per aggregate padded
+    with zeros to r)."""
     r = B.shape[1]
+    agg = np.asarray(agg, dtype=np.int64)
+    nunits = len(agg)
+    sizes = np.full(nunits, sizes, dtype=np.int64) if np.isscalar(sizes) else np.asarray(sizes, dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
     nagg = int(agg.max()) + 1
     order = np.argsort(agg, kind="stable")      # children of each J in increasing unit id
     counts = np.bincount(agg, minlength=nagg)
-    sizes = {coarse_size(int(c) * nb, n_cut, r) for c in counts}
-    if len(sizes) != 1:
-        raise ValueError("coarse block size must be uniform across aggregates")
-    s = sizes.pop()
-    starts = np.concatenate([[0], np.cumsum(counts)])
-    rows_P, cols_P, vals_P = [], [], []
+    su = sizes[order]
+    dof_order = np.repeat(offs[order], su) + (np.arange(su.sum()) - np.repeat(np.cumsum(su) - su, su))
+    nrows = np.bincount(agg, weights=sizes, minlength=nagg).astype(np.int64)
+    dstart = np.concatenate([[0], np.cumsum(nrows)])
+    s_agg = np.zeros(nagg, dtype=np.int64)
     svals = [None] * nagg
-    for c in np.unique(counts):
-        Js = np.nonzero(counts == c)[0]
-        units = np.stack([order[starts[J]:starts[J] + c] for J in Js])        # (G, c)
-        dofs = (units[:, :, None] * nb + np.arange(nb)[None, None, :]).reshape(len(Js), c * nb)
-        M = B[dofs]                                                          # (G, c*nb, r)
-        U, S, _ = np.linalg.svd(M, full_matrices=False)
-        U = canonical_sign(U[:, :, :s])
-        rows_P.append(np.repeat(dofs, s, axis=1).ravel())
-        cols_P.append((Js[:, None, None] * s + np.arange(s)[None, None, :]).repeat(c * nb, 1).ravel())
-        vals_P.append(U.ravel())
+    Us = []
+    for c in np.unique(nrows):
+        Js = np.nonzero(nrows == c)[0]
+        dofs = dof_order[dstart[Js][:, None] + np.arange(c)[None, :]]          # (G, c)
+        U, S, _ = np.linalg.svd(B[dofs], full_matrices=False)
+        U = canonical_sign(U)
         for g, J in enumerate(Js):
-            svals[J] = S[g]
+            s_agg[J] = hstar_size(S[g], delta) if counts[J] == 1 else coarse_size(int(c), n_cut, r)
+            svals[J] = np.concatenate([S[g], np.zeros(r - len(S[g]))])
+        Us.append((Js, dofs, U))
+    coffs = np.concatenate([[0], np.cumsum(s_agg)])
+    rows_P, cols_P, vals_P = [], [], []
+    for Js, dofs, U in Us:
+        sj = s_agg[Js]
+        for l in range(int(sj.max())):
+            sel = sj > l
+            rows_P.append(dofs[sel].ravel())
+            cols_P.append(np.repeat(coffs[Js[sel]] + l, dofs.shape[1]))
+            vals_P.append(U[sel, :, l].ravel())
     P = sp.csr_matrix((np.concatenate(vals_P), (np.concatenate(rows_P), np.concatenate(cols_P))),
-                      shape=(nunits * nb, nagg * s))
-    return P, s, svals
+                      shape=(int(offs[-1]), int(coffs[-1])))
+    return P, s_agg, svals
 
 
 def blockdiag_csr(Binv):
+    if isinstance(Binv, BlockDiag):
+        return Binv.to_csr()
     nun, nb, _ = Binv.shape
     return sp.block_diag(list(Binv), format="csr") if nun < 64 else sp.bsr_matrix(
         (Binv, np.arange(nun), np.arange(nun + 1)), shape=(nun * nb, nun * nb)).tocsr()
@@ -175,42 +281,51 @@ def galerkin(R, A, T):
 
 def setup(A0, nb, aggs, params, B1, b_update="R"):
     """Algorithm 5.  A0: scipy sparse (n x n); aggs: per-level unit->aggregate
-    maps (from rcb.rcb_hierarchy); B1: n x r initial candidates.
+    maps (from rcb.rcb_hierarchy; a map that is the identity replicates a level,
+    the h*-step of Algorithm 5's intra-element coarsening); B1: n x r initial
+    candidates.  params.delta (default 1e-3, Section 4.3) is the h*-threshold.
 
     b_update 'R' initialises B^{k+1} = R B^k (Algorithm 5); 'P' uses P^T B^k
     (eq:SA_Bk)."""
     N = len(aggs)
     A = A0.tocsr().astype(np.float64)
     nunits = A.shape[0] // nb
+    sizes = np.full(nunits, nb, dtype=np.int64)
+    delta = float(getattr(params, "delta", 1e-3))
     B = np.array(B1, dtype=np.float64, copy=True)
     if B.ndim == 1:
         B = B[:, None]
     levels = []
     for k in range(N):
-        L = Level(A=A, nb=nb, nunits=nunits)
-        L.Dinv = block_inverse(diag_blocks(A, nunits, nb))
+        uniform = bool(np.all(sizes == sizes[0]))
+        L = Level(A=A, nb=int(sizes[0]) if uniform else 0, nunits=nunits, sizes=sizes)
+        L.Dinv_bd = BlockDiag.from_matrix(A, sizes).inverse()
+        if uniform:
+            L.Dinv = L.Dinv_bd.uniform_array()
         if params.omega_fixed > 0:
             L.omega = float(params.omega_fixed)
         else:
             x0 = uniform_pm1(params.pow_seed + k, A.shape[0])
-            L.rho = power_rho(A, L.Dinv, nb, params.q_power, x0)
+            L.rho = power_rho(A, L.Dinv_bd, 0, params.q_power, x0)
             L.omega = omega_from_rho(L.rho)
         L.B_in = B.copy()
         cols, sw = [], []
         for j in range(B.shape[1]):
-            xj, mj = relax_candidate(A, L.Dinv, nb, L.omega, B[:, j].copy(), params.gamma, params.relax_max)
+            xj, mj = relax_candidate(A, L.Dinv_bd, 0, L.omega, B[:, j].copy(), params.gamma, params.relax_max)
             cols.append(xj)
             sw.append(mj)
         L.B = np.stack(cols, axis=1)
         L.sweeps = np.array(sw)
         L.agg = np.asarray(aggs[k], dtype=np.int64)
-        L.P, L.s, L.sv = tentative_prolongator(L.B, L.agg, nunits, nb, params.n_cut)
-        L.T, L.R = smoothed_prolongator(A, L.Dinv, L.omega, L.P)
+        L.P, L.s_agg, L.sv = tentative_prolongator(L.B, L.agg, sizes, params.n_cut, delta)
+        L.s = int(L.s_agg.max())
+        L.T, L.R = smoothed_prolongator(A, L.Dinv_bd, L.omega, L.P)
         Anext = galerkin(L.R, A, L.T)
         B = (L.R @ L.B) if b_update == "R" else (L.P.T @ L.B)
         levels.append(L)
-        A, nb, nunits = Anext, L.s, int(L.agg.max()) + 1
-    levels.append(Level(A=A, nb=nb, nunits=nunits))
+        A, sizes, nunits = Anext, L.s_agg.copy(), int(L.agg.max()) + 1
+    uniform = bool(np.all(sizes == sizes[0]))
+    levels.append(Level(A=A, nb=int(sizes[0]) if uniform else 0, nunits=nunits, sizes=sizes))
     lu = sla.lu_factor(A.toarray())
     return Hierarchy(levels, lu, params.t_pre, params.t_post)
 
@@ -223,7 +338,7 @@ def smooth(A, Dinv, nb, omega, b, u, sweeps):
     """Algorithm 1 with the block Jacobi smoother A~ = D / omega (eq:smoother_choice):
     u <- u + omega D^{-1} (b - A u), a fixed number of sweeps."""
     for _ in range(sweeps):
-        u = u + omega * apply_blockdiag(Dinv, b - A @ u, nb)
+        u = u + omega * _apply_dinv(Dinv, b - A @ u, nb)
     return u
 
 
@@ -240,15 +355,15 @@ def vcycle(H, b):
     bs[0] = b
     for k in range(N):
         L = Ls[k]
-        u = L.omega * apply_blockdiag(L.Dinv, bs[k], L.nb)          # first sweep from zero
-        u = smooth(L.A, L.Dinv, L.nb, L.omega, bs[k], u, H.t_pre - 1)
+        u = L.omega * L.Dinv_bd.apply(bs[k])                          # first sweep from zero
+        u = smooth(L.A, L.Dinv_bd, 0, L.omega, bs[k], u, H.t_pre - 1)
         us[k] = u
         bs[k + 1] = L.R @ (bs[k] - L.A @ u)
     us[N] = sla.lu_solve(H.lu, bs[N])
     for k in range(N - 1, -1, -1):
         L = Ls[k]
         u = us[k] + L.T @ us[k + 1]
-        us[k] = smooth(L.A, L.Dinv, L.nb, L.omega, bs[k], u, H.t_post)
+        us[k] = smooth(L.A, L.Dinv_bd, 0, L.omega, bs[k], u, H.t_post)
     return us[0]
 
 
@@ -257,7 +372,7 @@ def to_fp32(H):
     kept in FP64 (mixed-precision V-cycle)."""
     L32 = []
     for L in H.levels[:-1]:
-        L32.append(dict(A=L.A.astype(np.float32), Dinv=L.Dinv.astype(np.float32), nb=L.nb,
+        L32.append(dict(A=L.A.astype(np.float32), Dinv=L.Dinv_bd.astype(np.float32),
                         omega=np.float32(L.omega), T=L.T.astype(np.float32), R=L.R.astype(np.float32)))
     return L32
 
@@ -270,9 +385,9 @@ def vcycle_fp32(H, L32, b):
     bs[0] = np.asarray(b, dtype=np.float32)
     for k in range(N):
         L = L32[k]
-        u = L["omega"] * apply_blockdiag(L["Dinv"], bs[k], L["nb"])
+        u = L["omega"] * L["Dinv"].apply(bs[k])
         for _ in range(H.t_pre - 1):
-            u = u + L["omega"] * apply_blockdiag(L["Dinv"], bs[k] - L["A"] @ u, L["nb"])
+            u = u + L["omega"] * L["Dinv"].apply(bs[k] - L["A"] @ u)
         us[k] = u
         bs[k + 1] = (L["R"] @ (bs[k] - L["A"] @ u)).astype(np.float32)
     us[N] = sla.lu_solve(H.lu, bs[N].astype(np.float64)).astype(np.float32)
@@ -280,7 +395,7 @@ def vcycle_fp32(H, L32, b):
         L = L32[k]
         u = us[k] + L["T"] @ us[k + 1]
         for _ in range(H.t_post):
-            u = u + L["omega"] * apply_blockdiag(L["Dinv"], bs[k] - L["A"] @ u, L["nb"])
+            u = u + L["omega"] * L["Dinv"].apply(bs[k] - L["A"] @ u)
         us[k] = u
     return us[0].astype(np.float32)
 

@@ -3,7 +3,9 @@
 Sizes: the 16x16 split-square SIPG p=1 case (1,536 dofs), a 33^2-point
 Delaunay SIPG p=3 case (20,480 dofs, 4 levels: several slices per level and a
 ragged last slice) and a 17^2-point LDG+upwind p=2 convection-diffusion case
-(3,072 dofs), and the structured hexahedral Poisson problem with 8^3 Q1
+(3,072 dofs), the 3D recipe at 8^3 x 6 jittered Kuhn tetrahedra (SIPG p=2,
+nb = 10, 8-way aggregation, r = 4; 30,720 dofs, 3 levels), a 17^2-point SIPG
+p=4 case (nb = 15: four block rows and 60 lanes per wavefront), and the structured hexahedral Poisson problem with 8^3 Q1
 elements under both fluxes (IP and LDG; 4,096 dofs, nb = 8, r = 8, 3 levels;
 candidate relaxation capped at 20 sweeps, which keeps every aggregate's
 candidate block well conditioned: see test_hex_collapsed_candidates for the
@@ -34,6 +36,8 @@ def _cases():
         "hex_ip": lambda: configs.poisson3d_hex(3, flux="ip", relax_max=20),
         "hex_ldg": lambda: configs.poisson3d_hex(3, flux="ldg", relax_max=20),
         "hex_r16": lambda: configs.poisson3d_hex(3, flux="ip", r=16, relax_max=20),
+        "kuhn3d": lambda: configs.poisson3d_kuhn(n=8, p=2, n_levels=3, r=4),
+        "sipg4": lambda: configs.poisson2d_delaunay(side=17, p=4, n_levels=3, r=3),
     }
 
 
@@ -71,7 +75,7 @@ def bsr_export(h, k, which, shape):
 
 # ------------------------------------------------------------------ setup parity
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 def test_setup_parity(name):
     w, H, h = case(name)
     N = len(H.levels) - 1
@@ -161,7 +165,7 @@ def host_op(op, k, h, w, x, b, prec):
         return RD @ x, absRD @ abs(x)
 
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 @pytest.mark.parametrize("prec", [am.AMGDG_FP64, am.AMGDG_MIXED])
 @pytest.mark.parametrize("m", [1, 3, 5, 16, 32])
 def test_single_kernels(name, prec, m):
@@ -219,7 +223,7 @@ def test_internal_order_matches_caller_order():
 
 # ------------------------------------------------------------------ V-cycle
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 def test_vcycle_parity_fp64(name):
     w, H, h = case(name)
     b = np.random.default_rng(8).standard_normal(w.A.n)
@@ -230,7 +234,7 @@ def test_vcycle_parity_fp64(name):
     assert rel(z.cpu().numpy(), zo) <= 1e-10, rel(z.cpu().numpy(), zo)
 
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 def test_vcycle_linear_symmetric(name):
     w, H, h = case(name)
     g = np.random.default_rng(11)
@@ -244,7 +248,7 @@ def test_vcycle_linear_symmetric(name):
     assert abs(out[0] @ b2 - b1 @ out[1]) <= 1e-11 * abs(out[0] @ b2)
 
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 def test_vcycle_mixed_close_to_fp64(name):
     w, H, h = case(name)
     b = np.random.default_rng(8).standard_normal(w.A.n)
@@ -257,7 +261,7 @@ def test_vcycle_mixed_close_to_fp64(name):
 
 # ------------------------------------------------------------------ solves
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 def test_pcg_parity(name):
     w, H, h = case(name)
     A = w.A.to_scipy()
@@ -271,7 +275,7 @@ def test_pcg_parity(name):
     assert np.linalg.norm(w.b - A @ xg) <= 1e-8 * np.linalg.norm(w.b)
 
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 def test_mixed_fcg_against_direct_reference(name):
     """Mixed path (FP32 V-cycle, FP64 flexible CG with residual replacement):
     run to 1e-11 (attainable on these matrices; CG in FP64 stalls near 4e-12 on

@@ -277,11 +277,13 @@ def test_vcycle_linear_and_symmetric(tiny_h):
 
 def test_vcycle_exact_when_coarse_space_is_everything(tiny):
     """Singleton aggregates and s = nb: T is square and invertible, so the coarse
-    correction T (T^T A T)^{-1} T^T is A^{-1} and one cycle solves exactly."""
+    correction T (T^T A T)^{-1} T^T is A^{-1} and one cycle solves exactly.
+    Singleton aggregates are h*-steps (eq:sik): delta = 0 keeps every nonzero
+    singular value, i.e. s = nb."""
     w = tiny
     A = w.A.to_scipy()
     ne = A.shape[0] // 3
-    prm = dataclasses.replace(w.params, n_levels=2, r=3, n_cut=1.0)
+    prm = dataclasses.replace(w.params, n_levels=2, r=3, n_cut=1.0, delta=0.0)
     H = amg.setup(A, 3, [np.arange(ne, dtype=np.int32)], prm,
                   np.random.default_rng(2).standard_normal((A.shape[0], 3)))
     b = np.random.default_rng(4).standard_normal(A.shape[0])

@@ -45,6 +45,7 @@ class Params:
     relax_max: int = 100
     n_cut: float = 3.0
     pow_seed: int = 3
+    delta: float = 1e-3           # h*-step threshold of eq:sik (Section 4.3)
 
 
 @dataclass
