@@ -460,3 +460,140 @@ def test_convergence_factor_near_constant_under_refinement():
         assert max(fac) <= 0.35, fac
         assert all(fac[j + 1] - fac[j] <= 0.1 for j in range(len(fac) - 1)), fac
     assert abs(its_cg[1] - 6) <= 1 and abs(its_cg[2] - 7) <= 1, its_cg
+
+
+# ---------------------------------------------------------------- units of unequal size (eq:sik per aggregate)
+
+def test_block_diagonal_of_unequal_units():
+    """D_k of a level whose units differ in size: the diagonal blocks equal a
+    dense extraction, their inverses invert them, and applying them equals the
+    dense block-diagonal product."""
+    g = np.random.default_rng(12)
+    sizes = np.array([3, 4, 3, 5, 4, 4, 2, 3])
+    n = sizes.sum()
+    X = g.standard_normal((n, n))
+    Ad = X @ X.T + n * np.eye(n)
+    import scipy.sparse as sp
+    D = amg.BlockDiag.from_matrix(sp.csr_matrix(Ad), sizes)
+    Dinv = D.inverse()
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    Dd = np.zeros_like(Ad)
+    for u in range(len(sizes)):
+        s = slice(offs[u], offs[u + 1])
+        Dd[s, s] = Ad[s, s]
+    assert np.array_equal(D.to_csr().toarray(), Dd)
+    assert np.abs(Dinv.to_csr().toarray() @ Dd - np.eye(n)).max() < 1e-13
+    x = g.standard_normal((n, 3))
+    assert np.abs(Dinv.apply(x) - np.linalg.inv(Dd) @ x).max() < 1e-13
+    assert np.abs(Dinv.apply(x[:, 0]) - np.linalg.inv(Dd) @ x[:, 0]).max() < 1e-13
+
+
+@pytest.fixture(scope="module")
+def mixed_sizes():
+    """2D SIPG p=1 on 7x7 split squares (98 triangles): 4-way RCB gives level-1
+    aggregates of 3 and 4 elements (9 and 12 dofs), so eq:sik with n_cut = 3
+    and r = 6 keeps s_J = 3 or 4 coarse dofs per aggregate."""
+    w = configs.poisson2d_split(nx=7, p=1, n_levels=3, bisections=2, r=6, nu=2)
+    A = w.A.to_scipy()
+    aggs, _ = rcb.rcb_hierarchy(w.centroids, 3, 2)
+    H = amg.setup(A, 3, aggs, w.params, w.B1)
+    return w, A, aggs, H
+
+
+def test_unequal_coarse_blocks_follow_eq_sik(mixed_sizes):
+    w, A, aggs, H = mixed_sizes
+    L = H.levels[0]
+    counts = np.bincount(aggs[0])
+    assert set(counts) == {3, 4}
+    want = np.array([amg.coarse_size(3 * c, 3.0, 6) for c in counts])
+    assert np.array_equal(L.s_agg, want) and set(want) == {3, 4}
+    assert np.array_equal(H.levels[1].sizes, want)
+    P = L.P.toarray()
+    assert np.abs(P.T @ P - np.eye(P.shape[1])).max() < 1e-12
+    coffs = np.concatenate([[0], np.cumsum(L.s_agg)])
+    order = np.argsort(L.agg, kind="stable")
+    for J in range(len(counts)):
+        units = order[L.agg[order] == J]
+        dofs = (units[:, None] * 3 + np.arange(3)).ravel()
+        BJ = L.B[dofs]
+        sJ = int(L.s_agg[J])
+        lam, Q = np.linalg.eigh(BJ @ BJ.T)
+        proj = Q[:, -sJ:] @ Q[:, -sJ:].T
+        cols = slice(coffs[J], coffs[J + 1])
+        assert np.abs(P[dofs][:, cols] @ P[dofs][:, cols].T - proj).max() < 1e-10
+        others = np.ones(P.shape[1], bool)
+        others[cols] = False
+        assert np.abs(P[dofs][:, others]).max() == 0.0
+
+
+def test_unequal_coarse_blocks_operators_dense(mixed_sizes):
+    """T, R and A_1 over coarse units of unequal size against dense algebra,
+    level 1's block-Jacobi diagonal taken per unit size, and the two-grid error
+    propagator S^nu (I - T A_c^{-1} T^T A) S^nu of the cycle."""
+    w, A, aggs, H = mixed_sizes
+    Ad = A.toarray()
+    L0, L1 = H.levels[0], H.levels[1]
+    Dinv_d = np.linalg.inv(dense_D(Ad, 3))
+    T = (np.eye(Ad.shape[0]) - L0.omega * Dinv_d @ Ad) @ L0.P.toarray()
+    assert np.abs(L0.T.toarray() - T).max() < 1e-12 * np.abs(T).max()
+    assert np.array_equal(L0.R.toarray(), L0.T.toarray().T)
+    A1 = T.T @ Ad @ T
+    assert np.abs(L1.A.toarray() - A1).max() < 1e-12 * np.abs(A1).max()
+    offs = np.concatenate([[0], np.cumsum(L1.sizes)])
+    D1 = np.zeros_like(A1)
+    for u in range(len(L1.sizes)):
+        s = slice(offs[u], offs[u + 1])
+        D1[s, s] = A1[s, s]
+    assert np.abs(L1.Dinv_bd.to_csr().toarray() - np.linalg.inv(D1)).max() < 1e-10 * np.abs(np.linalg.inv(D1)).max()
+    # a two-level cycle on these operators
+    H2 = amg.setup(A, 3, aggs[:1], dataclasses.replace(w.params, n_levels=2), w.B1)
+    n = Ad.shape[0]
+    V = np.stack([amg.vcycle(H2, e) for e in np.eye(n)], axis=1)
+    S = np.eye(n) - H2.levels[0].omega * Dinv_d @ Ad
+    T2 = H2.levels[0].T.toarray()
+    CG = np.eye(n) - T2 @ np.linalg.solve(T2.T @ Ad @ T2, T2.T @ Ad)
+    nu = w.params.t_pre
+    E = np.linalg.matrix_power(S, nu) @ CG @ np.linalg.matrix_power(S, nu)
+    assert np.abs((np.eye(n) - V @ Ad) - E).max() < 1e-10
+    # the three-level cycle stays linear and symmetric
+    g = np.random.default_rng(9)
+    b1, b2 = g.standard_normal(n), g.standard_normal(n)
+    v = amg.vcycle(H, 2.5 * b1 + b2)
+    assert np.linalg.norm(v - (2.5 * amg.vcycle(H, b1) + amg.vcycle(H, b2))) < 1e-12 * np.linalg.norm(v)
+    assert abs(amg.vcycle(H, b1) @ b2 - b1 @ amg.vcycle(H, b2)) < 1e-12 * abs(amg.vcycle(H, b1) @ b2)
+
+
+# ---------------------------------------------------------------- h*-step (eq:sik, second case)
+
+def test_hstar_step_keeps_singular_values_above_delta(tiny):
+    """A level whose aggregates are its own units (Algorithm 5's replicated
+    level): each element keeps the left singular vectors of its candidate
+    block whose singular values exceed delta times the largest, counted here
+    from the eigenvalues of M M^T, and P~ is block diagonal per element."""
+    w = tiny
+    A = w.A.to_scipy()
+    ne = A.shape[0] // 3
+    r = 8
+    B1 = np.random.default_rng(2).standard_normal((A.shape[0], r))
+    prm0 = dataclasses.replace(w.params, n_levels=2, r=r)
+    H0 = amg.setup(A, 3, [np.arange(ne, dtype=np.int32)], dataclasses.replace(prm0, delta=0.0), B1)
+    B = H0.levels[0].B
+    ratios = []
+    for e in range(ne):
+        ev = np.sqrt(np.clip(np.linalg.eigvalsh(B[3 * e:3 * e + 3] @ B[3 * e:3 * e + 3].T)[::-1], 0, None))
+        ratios.append(ev / ev[0])
+    delta = float(np.median([rr[1] for rr in ratios]))          # splits the elements between s = 1 and s >= 2
+    H = amg.setup(A, 3, [np.arange(ne, dtype=np.int32)], dataclasses.replace(prm0, delta=delta), B1)
+    L = H.levels[0]
+    want = np.array([int(np.count_nonzero(rr > delta)) for rr in ratios])
+    assert np.array_equal(L.s_agg, want) and len(set(want)) >= 2
+    P = L.P.toarray()
+    coffs = np.concatenate([[0], np.cumsum(L.s_agg)])
+    for e in range(ne):
+        rows = slice(3 * e, 3 * e + 3)
+        Pe = P[rows, coffs[e]:coffs[e + 1]]
+        M = B[rows]
+        lam, Q = np.linalg.eigh(M @ M.T)
+        s = int(want[e])
+        assert np.abs(Pe @ Pe.T - Q[:, -s:] @ Q[:, -s:].T).max() < 1e-10
+        assert np.abs(np.delete(P[rows], np.s_[coffs[e]:coffs[e + 1]], axis=1)).max() == 0.0
