@@ -68,15 +68,25 @@ def sliced_kernels_sha256():
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    """L2-miss bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, if it was taken on the current sliced kernels (else None)."""
     f = os.path.join(ROOT, "profiles", "sweep_level0_poisson2d_p3_256_traffic.txt")
     if not os.path.exists(f):
         return None
-    kv = dict(l.strip().split("=", 1) for l in open(f) if "=" in l)
-    if kv.get("kernel") != kernel or kv.get("sliced_kernels_sha256") != sliced_kernels_sha256():
+    head, rows = {}, {}
+    for line in open(f):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("kernel="):
+            kv = dict(x.split("=", 1) for x in line.split(";"))
+            rows[kv["kernel"]] = float(kv["hbm_bytes"])
+        elif "=" in line:
+            k, v = line.split("=", 1)
+            head[k] = v
+    if head.get("sliced_kernels_sha256") != sliced_kernels_sha256():
         return None
-    return float(kv["hbm_bytes"])
+    return rows.get(kernel)
 
 
 def main():
