@@ -221,6 +221,22 @@ int amgdg_solve(amgdg_handle h, int32_t m, const double* b_dev, double* x_dev, i
 int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int32_t precision,
                  int32_t flags, void* stream);
 
+/* The V-cycle of amgdg_vcycle, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It allocates nothing: its level vectors (and, for caller-order
+ * vectors, the two permuted copies of level 0) live in one static workspace
+ * of 128 MiB per GPU, part of the library's code object and held by each GPU
+ * the library runs on until the process ends.  The kernels are those of
+ * amgdg_vcycle, launched one by one on `stream` (no graph), so z is
+ * bit-identical to amgdg_vcycle's.  Arguments as for amgdg_vcycle
+ * (AMGDG_EAGER is implied).  AMGDG_EUNSUPPORTED, before any work is queued, if
+ * the vectors need more than the workspace holds (about
+ * (4 n_0 + 5 sum_{0<k<N} n_k + 2 n_N + 2 n_0) m words).  Every call on a GPU
+ * shares that GPU's workspace: calls whose work overlaps on one GPU (other
+ * streams, other host threads) race and must be ordered by the caller. */
+int amgdg_vcycle_static(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int32_t precision,
+                        int32_t flags, void* stream);
+
 /* Single steps of the hot path on level k (one kernel launch each, for tests
  * and timing).  x, b, y: device arrays of the sizes below, double (FP64) or
  * float (MIXED), m columns.  An argument the operation does not read (b for

@@ -82,6 +82,7 @@ _SIGS = {
     "amgdg_solve": (_I32, [_P, _I32, _P, _P, _I32, _I32, _D, _I32, _I32, _I32,
                            ctypes.POINTER(amgdg_solve_stats), _P]),
     "amgdg_vcycle": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P]),
+    "amgdg_vcycle_static": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P]),
     "amgdg_apply": (_I32, [_P, _I32, _I32, _I32, _I32, _P, _P, _P, _I32, _P]),
     "amgdg_batch_bytes": (_I32, [_P, _I32, _I32, ctypes.POINTER(_I64)]),
     "amgdg_server_create": (_I32, [ctypes.POINTER(_P), _I32, _I64]),
@@ -293,6 +294,11 @@ def amgdg_solve(handle, b, x, method=AMGDG_PCG, precision=AMGDG_FP64, rtol=1e-8,
 def amgdg_vcycle(handle, r, z, precision=AMGDG_FP64, flags=0, stream=None):
     m = 1 if r.dim() == 1 else r.shape[1]
     _check(lib().amgdg_vcycle(handle.h, m, _dptr(r), _dptr(z), precision, flags, _stream(stream)))
+
+
+def amgdg_vcycle_static(handle, r, z, precision=AMGDG_FP64, flags=0, stream=None):
+    m = 1 if r.dim() == 1 else r.shape[1]
+    _check(lib().amgdg_vcycle_static(handle.h, m, _dptr(r), _dptr(z), precision, flags, _stream(stream)))
 
 
 def amgdg_apply(handle, k, op, x, b, y, precision=AMGDG_FP64, flags=0, stream=None):

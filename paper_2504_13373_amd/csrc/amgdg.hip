@@ -11,6 +11,7 @@
 #include <deque>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -919,29 +920,30 @@ template <>
 VBuf<float>& vbuf<float>(Work& W, int k) { return W.v32[k]; }
 
 template <typename T>
-static void coarse_solve(Ctx& C, Work& W, const T* b, T* u, int m, hipStream_t st);
-template <>
-void coarse_solve<double>(Ctx& C, Work&, const double* b, double* u, int m, hipStream_t st) {
-    HIPCHK(launch_gemv(C.Ainv, b, u, C.nN, m, st));
+static VBuf<T>* vbufs(Work& W) {
+    return &vbuf<T>(W, 0);
 }
-template <>
-void coarse_solve<float>(Ctx& C, Work&, const float* b, float* u, int m, hipStream_t st) {
-    HIPCHK(launch_gemv<float>(C.Ainv, b, u, C.nN, m, st));
+
+template <typename T>
+static void coarse_solve(Ctx& C, const T* b, T* u, int m, hipStream_t st) {
+    HIPCHK(launch_gemv<T>(C.Ainv, b, u, C.nN, m, st));
 }
 
 // z0 = V(b0), internal order, m columns (Algorithm 2, one pass from u = 0).
+// VB holds the level vectors of levels 0..N (the V-cycle's only workspace).
 template <typename T>
-static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t st) {
+static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStream_t st) {
     const int N = C.N;
     const int tpre = C.prm.t_pre, tpost = C.prm.t_post;
+    auto vb = [&](int k) -> VBuf<T>& { return VB[k]; };
     if (N == 0) {
-        coarse_solve<T>(C, W, b0, z0, m, st);
+        coarse_solve<T>(C, b0, z0, m, st);
         return;
     }
     bool started = false;  // level k's first sweep was done by the restriction into it
     for (int k = 0; k < N; ++k) {
         Level& L = C.lv[k];
-        VBuf<T>& V = vbuf<T>(W, k);
+        VBuf<T>& V = vb(k);
         const T* bk = (k == 0) ? b0 : V.b;
         T* cur = V.u;
         T* oth = V.w;
@@ -966,24 +968,24 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
         // sweep: it writes omega D^{-1} b_{k+1} and c_{k+1} = D^{-1} b_{k+1} (the
         // same operations as the first sweep on the stored b_{k+1}); b_{k+1}
         // itself is not needed then.
-        VBuf<T>& Vn = vbuf<T>(W, k + 1);
+        VBuf<T>& Vn = vb(k + 1);
         started = k + 1 < N && tpre > 0 &&
                   restrict_start<T>(L.RD, C.lv[k + 1], V.r, Vn.u, Vn.c, m, st);
         if (!started) mat_spmv<T>(AX, L.RD, V.r, nullptr, Vn.b, m, st);
     }
     {
-        VBuf<T>& V = vbuf<T>(W, N);
-        coarse_solve<T>(C, W, V.b, V.u, m, st);
+        VBuf<T>& V = vb(N);
+        coarse_solve<T>(C, V.b, V.u, m, st);
         V.cur = V.u;
     }
     for (int k = N - 1; k >= 0; --k) {
         Level& L = C.lv[k];
-        VBuf<T>& V = vbuf<T>(W, k);
+        VBuf<T>& V = vb(k);
         const T om = T(L.omega);
         T* cur = V.cur;
         auto other = [&](T* c) { return c == V.u ? V.w : V.u; };
         T* dst = (k == 0 && tpost == 0) ? z0 : other(cur);
-        mat_spmv<T>(B_PLUS, L.T, vbuf<T>(W, k + 1).cur, cur, dst, m, st);
+        mat_spmv<T>(B_PLUS, L.T, vb(k + 1).cur, cur, dst, m, st);
         cur = dst;
         for (int t = 0; t < tpost; ++t) {
             dst = (k == 0 && t == tpost - 1) ? z0 : other(cur);
@@ -1003,7 +1005,7 @@ static void vcycle_impl(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t 
 template <typename T>
 static void vcycle_run(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t st, bool allow_graph) {
     if (!allow_graph || C.prm.t_pre == 0 || C.N == 0) {
-        vcycle_impl<T>(C, W, b0, z0, m, st);
+        vcycle_impl<T>(C, vbufs<T>(W), b0, z0, m, st);
         return;
     }
     const int prec = int(sizeof(T));
@@ -1019,7 +1021,7 @@ static void vcycle_run(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t s
     if (!W.cap) HIPCHK(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal));
     try {
-        vcycle_impl<T>(C, W, b0, z0, m, W.cap);
+        vcycle_impl<T>(C, vbufs<T>(W), b0, z0, m, W.cap);
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(W.cap, &g);
@@ -1049,7 +1051,7 @@ struct KrylovState {
 // z = V(r) in FP64 for arbitrary r, z: through the graph's fixed buffers.
 static void precond_fp64(Ctx& C, Work& W, const double* r, double* z, int m, hipStream_t st) {
     if (!W.use_graph) {
-        vcycle_impl<double>(C, W, r, z, m, st);
+        vcycle_impl<double>(C, vbufs<double>(W), r, z, m, st);
         return;
     }
     const size_t bytes = sizeof(double) * size_t(C.lv[0].n) * m;
@@ -2057,7 +2059,7 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
         case AMGDG_OP_SWEEP0: mat_sweep<T>(SWEEP0, L, nullptr, bi, out, T(L.omega), m, nullptr, st); break;
         case AMGDG_OP_RESTRICT: mat_spmv<T>(AX, L.R, xi, nullptr, out, m, st); break;
         case AMGDG_OP_PROLONG: mat_spmv<T>(B_PLUS, L.T, xi, bi, out, m, st); break;
-        case AMGDG_OP_COARSE: coarse_solve<T>(C, W, xi, out, m, st); break;
+        case AMGDG_OP_COARSE: coarse_solve<T>(C, xi, out, m, st); break;
         case AMGDG_OP_SWEEP_SCALED: mat_spmv<T>(S_SWEEP, L.S, xi, bi, out, m, st, T(L.omega)); break;
         case AMGDG_OP_RESTRICT_SCALED: mat_spmv<T>(AX, L.RD, xi, nullptr, out, m, st); break;
         default: throw Error(AMGDG_EINVAL, "bad op");
@@ -2235,6 +2237,90 @@ static void plan_item(const Plan& P, int k, int what, std::vector<int32_t>& out3
         throw Error(AMGDG_EINVAL, "unknown plan item");
     }
     out32 = (what == AMGDG_A_ROWPTR || what == AMGDG_T_ROWPTR || what == AMGDG_R_ROWPTR) ? orp : oci;
+}
+
+// ------------------------------------------------------------ allocation-free V-cycle
+// The workspace of amgdg_vcycle_static: one array in device memory per GPU,
+// part of the library's code object, held until the process ends.  On the
+// host its name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is handed to kernels.
+constexpr size_t STATIC_WS_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
+static std::mutex g_ws_mu;
+static unsigned char* g_ws_ptr[64];
+
+static unsigned char* static_workspace() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw Error(AMGDG_EUNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (!g_ws_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error(AMGDG_EHIP, "hipGetSymbolAddress returned NULL for the static workspace");
+        g_ws_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    return g_ws_ptr[dev];
+}
+
+// Carves the V-cycle's level vectors (and, for caller-order vectors, the two
+// permuted copies of level 0) out of `base`; returns the bytes needed.  With
+// base == nullptr only the size is formed.  Level 0: u, w, r, c; levels
+// 1..N-1: b, u, w, r, c; level N: b, u (what vcycle_impl reads and writes).
+template <typename T>
+static int64_t static_layout(const Ctx& C, int m, bool caller_order, unsigned char* base, VBuf<T>* V, T** kr,
+                             T** kz) {
+    int64_t off = 0;
+    auto get = [&](int64_t n) -> T* {
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += (int64_t(sizeof(T)) * std::max<int64_t>(n, 1) + 255) / 256 * 256;
+        return p;
+    };
+    const int N = C.N;
+    for (int k = 0; k <= N; ++k) {
+        const int64_t cnt = C.lv[k].n * m;
+        VBuf<T> v;
+        if (k > 0) v.b = get(cnt);
+        v.u = get(cnt);
+        if (k < N) {
+            v.w = get(cnt);
+            v.r = get(cnt);
+            v.c = get(cnt);
+        }
+        if (V) V[k] = v;
+    }
+    if (caller_order) {
+        T* a = get(C.lv[0].n * m);
+        T* b = get(C.lv[0].n * m);
+        if (kr) *kr = a;
+        if (kz) *kz = b;
+    }
+    return off;
+}
+
+constexpr int STATIC_MAX_LEVELS = 64;
+
+template <typename T>
+static void vcycle_static_impl(Ctx& C, int m, const T* r, T* z, bool internal, hipStream_t st) {
+    if (C.N + 1 > STATIC_MAX_LEVELS) throw Error(AMGDG_EUNSUPPORTED, "more than 64 levels");
+    const int64_t need = static_layout<T>(C, m, !internal, nullptr, nullptr, nullptr, nullptr);
+    if (need > int64_t(STATIC_WS_BYTES))
+        throw Error(AMGDG_EUNSUPPORTED, "this V-cycle needs " + std::to_string(need) + " bytes of workspace; the "
+                                            "static workspace holds " + std::to_string(STATIC_WS_BYTES));
+    unsigned char* base = static_workspace();
+    VBuf<T> V[STATIC_MAX_LEVELS];
+    T *kr = nullptr, *kz = nullptr;
+    static_layout<T>(C, m, !internal, base, V, &kr, &kz);
+    const Level& L = C.lv[0];
+    if (internal) {
+        vcycle_impl<T>(C, V, r, z, m, st);
+    } else {
+        HIPCHK((launch_permute<T, T>(r, kr, C.perm_d, L.n_units, L.nb, m, 1, st)));
+        vcycle_impl<T>(C, V, kr, kz, m, st);
+        HIPCHK((launch_permute<T, T>(kz, z, C.perm_d, L.n_units, L.nb, m, 0, st)));
+    }
 }
 
 }  // namespace amgdg
@@ -2452,6 +2538,25 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
     } else {
         throw Error(AMGDG_EINVAL, "bad precision");
     }
+    return AMGDG_OK;
+    ABI_END
+}
+
+int amgdg_vcycle_static(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int32_t precision, int32_t flags,
+                        void* stream) {
+    ABI_BEGIN
+    if (!h || !r_dev || !z_dev) throw Error(AMGDG_EINVAL, "NULL argument");
+    Ctx& C = h->c;
+    if (m < 1 || m > 64) throw Error(AMGDG_EUNSUPPORTED, "m must be 1..64");
+    if (precision == AMGDG_MIXED && !C.mixed) throw Error(AMGDG_EINVAL, "mixed precision needs params.mixed = 1");
+    const bool internal = flags & AMGDG_INTERNAL_ORDER;
+    hipStream_t st = hipStream_t(stream);
+    if (precision == AMGDG_FP64)
+        vcycle_static_impl<double>(C, m, static_cast<const double*>(r_dev), static_cast<double*>(z_dev), internal, st);
+    else if (precision == AMGDG_MIXED)
+        vcycle_static_impl<float>(C, m, static_cast<const float*>(r_dev), static_cast<float*>(z_dev), internal, st);
+    else
+        throw Error(AMGDG_EINVAL, "bad precision");
     return AMGDG_OK;
     ABI_END
 }
