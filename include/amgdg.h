@@ -51,7 +51,7 @@ extern "C" {
 /* --------------------------------------------------------------- parameters */
 typedef struct {
     int32_t  n_levels;     /* levels L_0..L_{n_levels-1}; L_{n_levels-1} is solved directly */
-    int32_t  r;            /* adaptive candidates per level (columns of B^k), 1..16 */
+    int32_t  r;            /* adaptive candidates per level (columns of B^k), 1..64 */
     int32_t  t_pre;        /* pre-smoothing sweeps (Algorithm 2) */
     int32_t  t_post;       /* post-smoothing sweeps */
     int32_t  q_power;      /* power-iteration steps of Algorithm 4 */
@@ -64,11 +64,18 @@ typedef struct {
     uint64_t pow_seed;     /* level k's power-iteration start vector: SplitMix64 stream
                               pow_seed + k, entries 2u-1, in caller dof order */
     uint64_t b1_seed;      /* B^1 stream when no B^1 is given (Box-Muller normals) */
+    double   delta;        /* h*-step threshold of eq:sik: an aggregate that equals its only
+                              child keeps the singular vectors above delta * sigma_1 */
+    int32_t  hstar_smooth; /* a replicated level (every aggregate one unit: the h*-step of
+                              Algorithm 5): 0 takes T = P~ (its coarse operator keeps the fine
+                              stencil, as the paper's printed h*-hierarchy implies), 1 smooths
+                              P~ as in eq:TR0 */
 } amgdg_params;
 
 /* Fills the paper's defaults: gamma 0.03 (Section 4.2), q 3 (Section 4.4),
  * t_pre = t_post = 3 (Section 5), n_cut 3 (2D value 2^d - d + 1, Section 4.3),
- * relax_max 100, r 3, n_levels 2, adaptive omega, B^{k+1} = R B^k, FP64 only. */
+ * delta 1e-3 (Section 4.3), relax_max 100, r 3, n_levels 2, adaptive omega,
+ * B^{k+1} = R B^k, FP64 only. */
 void amgdg_default_params(amgdg_params* p);
 
 /* ------------------------------------------------------------ hierarchy */
@@ -90,6 +97,8 @@ int amgdg_partition_rcb(int64_t n_elem, int32_t dim, const double* centroids, in
  * and per level the block patterns of T (eq:TR0: block (e,J) iff J is the
  * aggregate of e or of a block column of row e of A_k), R = T^T and
  * A_{k+1} = R A_k T (block (I,J) iff T(a,I), A_k(a,b), T(b,J) all exist).
+ * On a replicated level (every aggregate a single unit) T = P~: row e of T holds
+ * its own aggregate only (amgdg_params.hstar_smooth = 0, the default).
  * Inputs as for amgdg_setup.  Host only; never touches the GPU. */
 typedef struct amgdg_plan_s* amgdg_plan;
 int amgdg_plan_create(amgdg_plan* out, int64_t n_elem, const int32_t* row_ptr, const int32_t* col_idx,
@@ -113,7 +122,10 @@ void amgdg_plan_destroy(amgdg_plan p);
 #define AMGDG_B_RELAXED  14   /* double[n * r]: candidates after relaxation */
 #define AMGDG_B_INPUT    15   /* double[n * r]: candidates before relaxation */
 #define AMGDG_PTILDE     16   /* double[n_units * nb * s]: the P~ rows of each unit */
-#define AMGDG_SVALS      17   /* double[n_agg * r]: singular values, descending */
+#define AMGDG_SVALS      17   /* double[n_agg * r]: singular values, descending (zeros beyond
+                                 the rank bound min(|A_J|, r)) */
+#define AMGDG_UNIT_DOFS  18   /* int32[n_units]: dofs of each unit of level k (s_J on coarse levels;
+                                 a unit's vector rows beyond them are zero padding) */
 
 /* Number of elements of `what` (in its own type) at level k. */
 int amgdg_plan_size(amgdg_plan p, int32_t k, int32_t what, int64_t* count);
@@ -128,7 +140,7 @@ typedef struct amgdg_ctx* amgdg_handle;
  * (eq:splitB_dg, eq:sik), T = (I - omega D^{-1} A) P~ and R = T^T (eq:TR0),
  * A_{k+1} = R A_k T and B^{k+1} = R B^k; then the inverse of the coarsest
  * matrix.  Every arithmetic step runs in the library's HIP kernels.
- *   n_elem, nb       : element count and dofs per element (1..16)
+ *   n_elem, nb       : element count and dofs per element (1..64)
  *   row_ptr, col_idx : host BSR pattern, int32, columns sorted, diagonal present
  *   vals             : host, nnzb * nb * nb doubles
  *   adj_ptr, adj_idx : host face graph of the elements (CSR) or NULL; only checked
@@ -137,9 +149,16 @@ typedef struct amgdg_ctx* amgdg_handle;
  *                      children of each coarser aggregate have consecutive ids
  *   B1               : host, n x r row-major in caller order, or NULL
  *   p                : parameters (NULL: defaults)
- * The coarse block size s = min(ceil(|A_J| / n_cut), |A_J|, r) must be the same
- * for every aggregate of a level, r must be 1..16 and an aggregate may hold at
- * most 128 dofs (EUNSUPPORTED otherwise). */
+ * Coarse sizes (eq:sik) are chosen per aggregate J: s_J = min(ceil(|A_J| / n_cut),
+ * |A_J|, r) when J has several children (h-step), and the number of singular
+ * values above delta times the largest when J equals its only child (h*-step:
+ * pass a level whose aggregates are the previous level's units, numbered so
+ * that the next level's children stay consecutive).  A coarse level whose
+ * units differ in size stores every unit with the level's largest s_J; the
+ * rows beyond a unit's own s_J are zero in every operator and vector (a unit
+ * diagonal keeps D invertible there), and AMGDG_UNIT_DOFS reports the sizes.
+ * r must be 1..64, an aggregate may hold at most 1024 dofs and s_J at most 64
+ * (EUNSUPPORTED otherwise). */
 int amgdg_setup(amgdg_handle* out, int64_t n_elem, int32_t nb, const int32_t* row_ptr,
                 const int32_t* col_idx, const double* vals, int64_t nnzb, const int32_t* adj_ptr,
                 const int32_t* adj_idx, const int32_t* agg_of_elem, const amgdg_params* p,
@@ -148,8 +167,8 @@ int amgdg_destroy(amgdg_handle h);
 
 typedef struct {
     int64_t n_units;     /* block rows of A_k */
-    int32_t nb;          /* block size of level k */
-    int32_t s;           /* block size of level k+1 (0 on the coarsest level) */
+    int32_t nb;          /* block size of level k (the largest unit) */
+    int32_t s;           /* block size of level k+1: the largest s_J (0 on the coarsest level) */
     int64_t n;           /* dofs of level k */
     int64_t nnzb;        /* blocks of A_k */
     int64_t nnzb_T;      /* blocks of T_k (0 on the coarsest level) */
@@ -157,8 +176,10 @@ typedef struct {
     double  omega;       /* damping omega_k */
     double  rho;         /* power-iteration estimate (NaN if omega was fixed) */
     int32_t r;           /* candidates relaxed on this level */
-    int32_t sweeps[16];  /* relaxation sweeps per candidate (first 16) */
+    int32_t sweeps[64];  /* relaxation sweeps per candidate */
     int64_t bytes_A, bytes_Dinv, bytes_T, bytes_R;   /* FP64 bytes held for level k */
+    int64_t n_dofs;      /* dofs of level k without the padding of units below nb (= n when
+                            every unit holds nb) */
 } amgdg_level_info;
 int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out);
 int amgdg_num_levels(amgdg_handle h);

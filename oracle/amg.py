@@ -285,6 +285,14 @@ def setup(A0, nb, aggs, params, B1, b_update="R"):
     the h*-step of Algorithm 5's intra-element coarsening); B1: n x r initial
     candidates.  params.delta (default 1e-3, Section 4.3) is the h*-threshold.
 
+    Reading of the h*-step (a replicated level, every aggregate one unit): the
+    text says it differs from an h-step only in its aggregates and s_J, which
+    would smooth P~ as in eq:TR0; the paper's printed h*-hierarchy (level-1
+    nonzeros equal to the elements' face stencil times s^2) fits T = P~ (no
+    smoothing, R = P~^T) instead, whose coarse operator keeps the fine face
+    stencil where the smoothed one spans three rings of neighbours.  The
+    unsmoothed form is the default; params.hstar_smooth = True takes eq:TR0.
+
     b_update 'R' initialises B^{k+1} = R B^k (Algorithm 5); 'P' uses P^T B^k
     (eq:SA_Bk)."""
     N = len(aggs)
@@ -319,7 +327,11 @@ def setup(A0, nb, aggs, params, B1, b_update="R"):
         L.agg = np.asarray(aggs[k], dtype=np.int64)
         L.P, L.s_agg, L.sv = tentative_prolongator(L.B, L.agg, sizes, params.n_cut, delta)
         L.s = int(L.s_agg.max())
-        L.T, L.R = smoothed_prolongator(A, L.Dinv_bd, L.omega, L.P)
+        replicated = len(np.unique(L.agg)) == nunits          # every aggregate is a single unit
+        if replicated and not getattr(params, "hstar_smooth", False):
+            L.T, L.R = L.P.tocsr(), L.P.T.tocsr()              # unsmoothed h*-step (see setup's docstring)
+        else:
+            L.T, L.R = smoothed_prolongator(A, L.Dinv_bd, L.omega, L.P)
         Anext = galerkin(L.R, A, L.T)
         B = (L.R @ L.B) if b_update == "R" else (L.P.T @ L.B)
         levels.append(L)
@@ -404,12 +416,14 @@ def vcycle_fp32(H, L32, b):
 # block patterns (structural, for index parity)
 # --------------------------------------------------------------------------
 
-def block_patterns(A0_row_ptr, A0_col_idx, aggs):
+def block_patterns(A0_row_ptr, A0_col_idx, aggs, hstar_smooth=False):
     """Structural block patterns per level: T (unit x aggregate), A_{k+1}.
 
     T block (e, J) exists iff J is e's aggregate or the aggregate of a block
-    column of row e of A_k (eq:TR0, no numerical dropping); A_{k+1} block (I, J)
-    exists iff T(a, I), A_k(a, b) and T(b, J) all exist."""
+    column of row e of A_k (eq:TR0, no numerical dropping); on a replicated
+    level (every aggregate one unit) T = P~ holds e's own aggregate only
+    unless hstar_smooth.  A_{k+1} block (I, J) exists iff T(a, I), A_k(a, b)
+    and T(b, J) all exist."""
     n0 = len(A0_row_ptr) - 1
     Apat = sp.csr_matrix((np.ones(len(A0_col_idx), dtype=np.int64), A0_col_idx, A0_row_ptr), shape=(n0, n0))
     out = []
@@ -417,7 +431,7 @@ def block_patterns(A0_row_ptr, A0_col_idx, aggs):
         nun = Apat.shape[0]
         nag = int(agg.max()) + 1
         G = sp.csr_matrix((np.ones(nun, dtype=np.int64), (np.arange(nun), agg)), shape=(nun, nag))
-        Tpat = (G + Apat @ G).tocsr()
+        Tpat = G.tocsr() if (nag == nun and not hstar_smooth) else (G + Apat @ G).tocsr()
         Tpat.data[:] = 1
         Tpat.sort_indices()
         Anext = (Tpat.T @ Apat @ Tpat).tocsr()

@@ -98,3 +98,19 @@ def agg_of_elem_levels(aggs):
         cur = a[cur]
         out.append(cur.astype(np.int32))
     return out
+
+
+def replicate_top(aggs, leaf_order):
+    """Algorithm 5's intra-element coarsening at the top level: level 0 is
+    replicated, so the first coarse level's aggregates are the single elements
+    (an h*-step, eq:sik).  They are numbered by depth-first leaf position, which
+    keeps the children of every geometric aggregate consecutive; the geometric
+    maps follow, the first one re-indexed by that position."""
+    ne = len(leaf_order)
+    pos = np.empty(ne, dtype=np.int32)
+    pos[leaf_order] = np.arange(ne, dtype=np.int32)
+    out = [pos]
+    if aggs:
+        out.append(np.asarray(aggs[0])[leaf_order].astype(np.int32))
+        out.extend(aggs[1:])
+    return out

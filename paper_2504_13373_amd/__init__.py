@@ -23,7 +23,7 @@ AMGDG_EHIP, AMGDG_ENAN, AMGDG_EBREAKDOWN, AMGDG_EUNSUPPORTED, AMGDG_ENOCONV = -4
 AMGDG_PERM, AMGDG_T_ROWPTR, AMGDG_T_COLIDX, AMGDG_A_ROWPTR, AMGDG_A_COLIDX = 1, 2, 3, 4, 5
 AMGDG_R_ROWPTR, AMGDG_R_COLIDX = 6, 7
 AMGDG_A_VALS, AMGDG_T_VALS, AMGDG_R_VALS, AMGDG_DINV = 10, 11, 12, 13
-AMGDG_B_RELAXED, AMGDG_B_INPUT, AMGDG_PTILDE, AMGDG_SVALS = 14, 15, 16, 17
+AMGDG_B_RELAXED, AMGDG_B_INPUT, AMGDG_PTILDE, AMGDG_SVALS, AMGDG_UNIT_DOFS = 14, 15, 16, 17, 18
 # precision, methods, flags, ops
 AMGDG_FP64, AMGDG_MIXED = 0, 1
 AMGDG_STATIONARY, AMGDG_PCG, AMGDG_FCG, AMGDG_FGMRES = 0, 1, 2, 3
@@ -38,15 +38,16 @@ class amgdg_params(ctypes.Structure):
                 ("t_post", ctypes.c_int32), ("q_power", ctypes.c_int32), ("relax_max", ctypes.c_int32),
                 ("omega_fixed", ctypes.c_double), ("gamma", ctypes.c_double), ("n_cut", ctypes.c_double),
                 ("b_update", ctypes.c_int32), ("mixed", ctypes.c_int32), ("pow_seed", ctypes.c_uint64),
-                ("b1_seed", ctypes.c_uint64)]
+                ("b1_seed", ctypes.c_uint64), ("delta", ctypes.c_double), ("hstar_smooth", ctypes.c_int32)]
 
 
 class amgdg_level_info(ctypes.Structure):
     _fields_ = [("n_units", ctypes.c_int64), ("nb", ctypes.c_int32), ("s", ctypes.c_int32),
                 ("n", ctypes.c_int64), ("nnzb", ctypes.c_int64), ("nnzb_T", ctypes.c_int64),
                 ("n_agg", ctypes.c_int64), ("omega", ctypes.c_double), ("rho", ctypes.c_double),
-                ("r", ctypes.c_int32), ("sweeps", ctypes.c_int32 * 16), ("bytes_A", ctypes.c_int64),
-                ("bytes_Dinv", ctypes.c_int64), ("bytes_T", ctypes.c_int64), ("bytes_R", ctypes.c_int64)]
+                ("r", ctypes.c_int32), ("sweeps", ctypes.c_int32 * 64), ("bytes_A", ctypes.c_int64),
+                ("bytes_Dinv", ctypes.c_int64), ("bytes_T", ctypes.c_int64), ("bytes_R", ctypes.c_int64),
+                ("n_dofs", ctypes.c_int64)]
 
 
 class amgdg_solve_stats(ctypes.Structure):
@@ -269,6 +270,7 @@ def _export_shape(info, what, n_elem):
         AMGDG_DINV: ((info.n_units, nb, nb), np.float64),
         AMGDG_B_RELAXED: ((info.n, r), np.float64), AMGDG_B_INPUT: ((info.n, r), np.float64),
         AMGDG_PTILDE: ((info.n, s), np.float64), AMGDG_SVALS: ((info.n_agg, r), np.float64),
+        AMGDG_UNIT_DOFS: (info.n_units, np.int32),
     }[what]
 
 
@@ -377,15 +379,31 @@ class Server:
             pass
 
 
+def hierarchy(centroids, n_levels, bisections, hstar_top=False):
+    """Element -> level-k aggregate maps ((n_levels-1, n_elem) int32) from
+    amgdg_partition_rcb.  With hstar_top the first coarse level replicates
+    level 0 (Algorithm 5's h*-step at the top): its aggregates are the single
+    elements, numbered in the partition's depth-first leaf order so that the
+    children of every coarser aggregate stay consecutive; the geometric levels
+    follow."""
+    if not hstar_top:
+        return amgdg_partition_rcb(centroids, n_levels, bisections)[0]
+    agg, leaf = amgdg_partition_rcb(centroids, n_levels - 1, bisections)
+    pos = np.empty(len(leaf), dtype=np.int32)
+    pos[leaf] = np.arange(len(leaf), dtype=np.int32)
+    return np.ascontiguousarray(np.vstack([pos[None, :], agg]) if n_levels > 2 else pos[None, :])
+
+
 def setup_from_workload(w, mixed=False, stream=None, **overrides):
     """Convenience: set up a handle for a ``workloads.configs.Workload``."""
     prm = w.params
     p = amgdg_default_params(n_levels=prm.n_levels, r=prm.r, t_pre=prm.t_pre, t_post=prm.t_post,
                              q_power=prm.q_power, relax_max=prm.relax_max, omega_fixed=prm.omega_fixed,
-                             gamma=prm.gamma, n_cut=prm.n_cut, mixed=int(mixed), pow_seed=prm.pow_seed)
+                             gamma=prm.gamma, n_cut=prm.n_cut, mixed=int(mixed), pow_seed=prm.pow_seed,
+                             delta=prm.delta, hstar_smooth=int(getattr(prm, "hstar_smooth", False)))
     for k, v in overrides.items():
         setattr(p, k, v)
-    agg, _ = amgdg_partition_rcb(w.centroids, prm.n_levels, prm.bisections)
+    agg = hierarchy(w.centroids, prm.n_levels, prm.bisections, getattr(prm, "hstar_top", False))
     adj_ptr, adj_idx = w.adjacency
     return amgdg_setup(w.A.n_brow, w.A.nb, w.A.row_ptr, w.A.col_idx, w.A.vals, agg, p, B1=w.B1,
                        adj_ptr=adj_ptr, adj_idx=adj_idx, stream=stream), agg

@@ -117,6 +117,15 @@ struct VBuf {
 struct Level {
     int64_t n_units = 0, n = 0, n_agg = 0, nnzb = 0, nT = 0;
     int nb = 0, s = 0, r = 0;
+    // Real dofs of each unit (eq:sik chooses them per aggregate): unit u owns
+    // the vector rows u*nb + [0, sz[u]); rows beyond sz[u] are padding that
+    // every operator keeps zero.  padded: some sz[u] < nb.
+    std::vector<int32_t> sz;
+    std::vector<int64_t> roff;  // real-dof offset of each unit (level order)
+    int32_t* sz_d = nullptr;
+    int64_t* roff_d = nullptr;
+    int64_t n_real = 0;
+    bool padded = false;
     double omega = 1.0, rho = std::numeric_limits<double>::quiet_NaN();
     std::vector<int32_t> sweeps;
     double* A_nat = nullptr;
@@ -554,7 +563,10 @@ static double power_rho(Ctx& C, Level& L, int k, hipStream_t st) {
     DevMem tmp;
     double* x = tmp.alloc<double>(L.n);
     double* y = tmp.alloc<double>(L.n);
-    HIPCHK(launch_uniform(C.prm.pow_seed + uint64_t(k), k == 0 ? C.perm_d : nullptr, L.n_units, L.nb, x, st));
+    if (L.padded)
+        HIPCHK(launch_uniform_padded(C.prm.pow_seed + uint64_t(k), L.roff_d, L.sz_d, L.n_units, L.nb, x, st));
+    else
+        HIPCHK(launch_uniform(C.prm.pow_seed + uint64_t(k), k == 0 ? C.perm_d : nullptr, L.n_units, L.nb, x, st));
     HIPCHK(launch_dot<double>(x, x, L.n, 1, C.scratch, C.scal, st));
     HIPCHK(launch_scale_by_inv_norm(x, L.n, C.scal, st));
     for (int it = 0; it < C.prm.q_power; ++it) {
@@ -610,16 +622,17 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
                        const double* vals, int64_t nnzb, const int32_t* agg_of_elem, const double* B1,
                        hipStream_t st) {
     const amgdg_params& p = C.prm;
-    if (nb < 1 || nb > 16) throw Error(AMGDG_EUNSUPPORTED, "nb must be 1..16");
+    if (nb < 1 || nb > 64) throw Error(AMGDG_EUNSUPPORTED, "nb must be 1..64");
     if (p.n_levels < 1) throw Error(AMGDG_EINVAL, "n_levels must be >= 1");
-    if (p.n_levels > 1 && (p.r < 1 || p.r > 16)) throw Error(AMGDG_EUNSUPPORTED, "r must be 1..16");
+    if (p.n_levels > 1 && (p.r < 1 || p.r > 64)) throw Error(AMGDG_EUNSUPPORTED, "r must be 1..64");
+    if (!(p.delta >= 0.0)) throw Error(AMGDG_EINVAL, "delta must be >= 0");
     if (p.t_pre < 0 || p.t_post < 0 || p.q_power < 0 || p.relax_max < 1 || !(p.n_cut > 0))
         throw Error(AMGDG_EINVAL, "bad smoothing or coarsening parameters");
     if (p.b_update != 0) throw Error(AMGDG_EUNSUPPORTED, "only B^{k+1} = R B^k is implemented");
     if (!vals) throw Error(AMGDG_EINVAL, "vals is NULL");
     check_finite_host(vals, nnzb * nb * nb, "A");
     try {
-        build_plan(C.plan, n_elem, row_ptr, col_idx, nnzb, p.n_levels, agg_of_elem);
+        build_plan(C.plan, n_elem, row_ptr, col_idx, nnzb, p.n_levels, agg_of_elem, p.hstar_smooth != 0);
     } catch (const std::invalid_argument& e) {
         throw Error(AMGDG_EINVAL, e.what());
     }
@@ -662,6 +675,7 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
     }
 
     int cur_nb = nb;
+    std::vector<int32_t> cur_sz(size_t(n_elem), nb);
     for (int k = 0; k <= C.N; ++k) {
         Level& L = C.lv[k];
         const bool coarsest = (k == C.N);
@@ -671,6 +685,13 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         L.nb = cur_nb;
         L.n = L.n_units * L.nb;
         L.nnzb = int64_t(Aci.size());
+        L.sz = cur_sz;
+        L.roff.assign(size_t(L.n_units) + 1, 0);
+        for (int64_t u = 0; u < L.n_units; ++u) L.roff[u + 1] = L.roff[u] + L.sz[u];
+        L.n_real = L.roff[L.n_units];
+        L.padded = L.n_real != L.n;
+        L.sz_d = upload(C.mem, L.sz, st);
+        L.roff_d = upload(C.mem, L.roff, st);
         if (coarsest) {
             C.nN = L.n;
             if (C.nN > 20000) throw Error(AMGDG_EUNSUPPORTED, "coarsest level too large for a dense inverse");
@@ -730,26 +751,75 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         HIPCHK(hipMemcpyAsync(L.B_in, B, sizeof(double) * L.n * r, hipMemcpyDeviceToDevice, st));
         relax_candidates(C, L, B, st);
         L.B_rel = B;
-        // coarse block size (eq:sik, h-step)
-        int s = -1;
+        // coarse sizes s_J (eq:sik): the h-step count from the aggregate's real
+        // dofs, or, for an aggregate that equals its only child (h*-step), the
+        // count of singular values above delta times the largest, decided on
+        // the device with the SVD
+        std::vector<int32_t> sJ(size_t(P.n_agg));
+        int smax_possible = 0;
+        bool all_h = true;
         for (int64_t J = 0; J < P.n_agg; ++J) {
-            const int64_t rows = int64_t(P.first_child[J + 1] - P.first_child[J]) * L.nb;
-            const int64_t sj = std::min<int64_t>({(int64_t)std::ceil(double(rows) / p.n_cut), rows, (int64_t)r});
-            if (s < 0) s = int(sj);
-            else if (s != sj) throw Error(AMGDG_EUNSUPPORTED, "coarse block size differs between aggregates");
+            int64_t rows = 0;
+            for (int32_t u = P.first_child[J]; u < P.first_child[J + 1]; ++u) rows += L.sz[u];
+            const int64_t cap = std::min<int64_t>(rows, r);
+            if (P.first_child[J + 1] - P.first_child[J] == 1) {
+                sJ[J] = -1;
+                all_h = false;
+                smax_possible = std::max<int>(smax_possible, int(cap));
+            } else {
+                sJ[J] = int32_t(std::min<int64_t>((int64_t)std::ceil(double(rows) / p.n_cut), cap));
+                smax_possible = std::max<int>(smax_possible, sJ[J]);
+            }
+            if (rows > 1024) throw Error(AMGDG_EUNSUPPORTED, "aggregate with more than 1024 dofs");
         }
-        L.s = s;
-        // P~ by SVD
+        bool uniform_s = all_h;
+        for (int64_t J = 1; J < P.n_agg && uniform_s; ++J) uniform_s = sJ[J] == sJ[0];
+        int64_t max_rows = 0;
+        for (int64_t J = 0; J < P.n_agg; ++J)
+            max_rows = std::max<int64_t>(max_rows, int64_t(P.first_child[J + 1] - P.first_child[J]) * L.nb);
         DevMem tmp;
         int32_t* fc = upload(tmp, P.first_child, st);
-        L.Pu = C.mem.alloc<double>(L.n * s);
         L.sv = C.mem.alloc<double>(P.n_agg * r);
-        HIPCHK(launch_svd(B, r, fc, P.n_agg, L.nb, s, L.Pu, L.sv, C.flag, st));
-        {
+        int s = 0;
+        if (uniform_s && !L.padded && r <= 16 && max_rows <= 128 && P.n_agg > 0) {
+            // one wavefront per aggregate, registers only (r <= 16, <= 128 rows)
+            s = sJ[0];
+            L.Pu = C.mem.alloc<double>(L.n * s);
+            HIPCHK(launch_svd(B, r, fc, P.n_agg, L.nb, s, L.Pu, L.sv, C.flag, st));
             const int32_t f = read_flag(C, st);
-            if (f & 2) throw Error(AMGDG_EUNSUPPORTED, "aggregate with more than 128 rows");
             if (f & 4) throw Error(AMGDG_ESINGULAR, "candidate block of an aggregate is rank deficient");
+        } else {
+            // general form: one workgroup per aggregate, columns in global memory
+            std::vector<int64_t> woff(size_t(P.n_agg) + 1, 0);
+            for (int64_t J = 0; J < P.n_agg; ++J) {
+                int64_t nr = 0;
+                for (int32_t u = P.first_child[J]; u < P.first_child[J + 1]; ++u) nr += L.sz[u];
+                woff[J + 1] = woff[J] + nr * r + (nr < r ? nr * nr : 0);
+            }
+            const int spad0 = std::max(smax_possible, 1);
+            double* Pw = tmp.alloc<double>(L.n * spad0);
+            HIPCHK(hipMemsetAsync(Pw, 0, sizeof(double) * size_t(L.n * spad0), st));
+            int32_t* sJ_d = upload(tmp, sJ, st);
+            const int64_t* woff_d = upload(tmp, woff, st);
+            double* work = tmp.alloc<double>(woff[P.n_agg]);
+            HIPCHK(launch_svd_gen(B, r, fc, L.sz_d, L.nb, P.n_agg, sJ_d, p.delta, spad0, work, woff_d, Pw, L.sv,
+                                  C.flag, st));
+            const int32_t f = read_flag(C, st);
+            if (f & 2) throw Error(AMGDG_EUNSUPPORTED, "aggregate SVD outside the supported sizes");
+            if (f & 4) throw Error(AMGDG_ESINGULAR, "candidate block of an aggregate is rank deficient");
+            sJ = download(sJ_d, P.n_agg, st);
+            for (int64_t J = 0; J < P.n_agg; ++J) {
+                if (sJ[J] < 1) throw Error(AMGDG_ESINGULAR, "an aggregate keeps no coarse vector");
+                s = std::max<int>(s, sJ[J]);
+            }
+            L.Pu = C.mem.alloc<double>(L.n * s);
+            HIPCHK(hipMemcpy2DAsync(L.Pu, sizeof(double) * s, Pw, sizeof(double) * spad0, sizeof(double) * s,
+                                    size_t(L.n), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
         }
+        if (s > 64) throw Error(AMGDG_EUNSUPPORTED, "coarse block size above 64");
+        L.s = s;
+        cur_sz = sJ;
         // T = P~ - omega D^{-1} A P~ ; R = T^T
         L.nT = int64_t(P.T_ci.size());
         {
@@ -795,6 +865,15 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
             int32_t* cpt = upload(t2, P.C_pt, st);
             int32_t* cpu = upload(t2, P.C_pu, st);
             HIPCHK(launch_galerkin(L.T_nat, ATv, cpp, cpt, cpu, nC, L.nb, s, Ln.A_nat, st));
+            // coarse units with s_J < s: unit diagonal on their padding rows
+            bool pad_next = false;
+            for (int32_t v : cur_sz) pad_next = pad_next || v < s;
+            if (pad_next) {
+                const std::vector<int32_t>& dg = (k + 1 < C.N) ? C.plan.lv[k + 1].A_diag : C.plan.AN_diag;
+                int32_t* dg_d = upload(t2, dg, st);
+                int32_t* sz_d = upload(t2, cur_sz, st);
+                HIPCHK(launch_pad_diag(Ln.A_nat, dg_d, P.n_agg, s, sz_d, st));
+            }
             HIPCHK(hipStreamSynchronize(st));
         }
         // B^{k+1} = R B^k
@@ -2126,6 +2205,10 @@ static int export_impl(Ctx& C, int k, int what, void* buf, int64_t bytes, hipStr
         copy_out(C.plan.perm, buf, bytes);
         return AMGDG_OK;
     }
+    if (what == AMGDG_UNIT_DOFS) {  // every level-0 unit holds nb dofs, so caller order needs no permutation
+        copy_out(L.sz, buf, bytes);
+        return AMGDG_OK;
+    }
     if (what == AMGDG_A_ROWPTR || what == AMGDG_A_COLIDX || what == AMGDG_A_VALS) {
         const std::vector<int32_t>& rp = coarsest ? C.plan.AN_rp : C.plan.lv[k].A_rp;
         const std::vector<int32_t>& ci = coarsest ? C.plan.AN_ci : C.plan.lv[k].A_ci;
@@ -2191,6 +2274,7 @@ static int export_impl(Ctx& C, int k, int what, void* buf, int64_t bytes, hipStr
             copy_out(v, buf, bytes);
             return AMGDG_OK;
         }
+
         default: throw Error(AMGDG_EINVAL, "unknown export item");
     }
 }
@@ -2377,6 +2461,8 @@ void amgdg_default_params(amgdg_params* p) {
     p->mixed = 0;
     p->pow_seed = 3;
     p->b1_seed = 2;
+    p->delta = 1e-3;
+    p->hstar_smooth = 0;
 }
 
 const char* amgdg_last_error(void) { return g_last_error.c_str(); }
@@ -2478,7 +2564,8 @@ int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out) {
     out->omega = L.omega;
     out->rho = L.rho;
     out->r = (k < C.N) ? L.r : 0;
-    for (size_t i = 0; i < L.sweeps.size() && i < 16; ++i) out->sweeps[i] = L.sweeps[i];
+    for (size_t i = 0; i < L.sweeps.size() && i < 64; ++i) out->sweeps[i] = L.sweeps[i];
+    out->n_dofs = L.n_real;
     out->bytes_A = L.A.n_vals * 8;
     out->bytes_Dinv = (k < C.N) ? L.n_units * L.nb * L.nb * 8 : 0;
     out->bytes_T = L.T.n_vals * 8;

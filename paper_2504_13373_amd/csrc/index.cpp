@@ -66,8 +66,8 @@ void rcb_partition(int64_t n, int32_t dim, const double* cent, int32_t n_levels,
 // ------------------------------------------------------------- symbolic phase
 
 // T pattern: row e holds {agg(e)} U {agg(c) : c in cols(A[e,:])}; with the A
-// blocks that feed each T block.
-static void symbolic_T(LevelPattern& L) {
+// blocks that feed each T block.  own_only: row e holds {agg(e)} alone (T = P~).
+static void symbolic_T(LevelPattern& L, bool own_only) {
     const int64_t nu = L.n_units;
     L.T_rp.assign(nu + 1, 0);
     std::vector<std::pair<int32_t, int32_t>> ent;  // (J, a) ; a = -1 for the own aggregate
@@ -76,7 +76,8 @@ static void symbolic_T(LevelPattern& L) {
     for (int64_t e = 0; e < nu; ++e) {
         ent.clear();
         ent.push_back({L.agg[e], -1});
-        for (int32_t a = L.A_rp[e]; a < L.A_rp[e + 1]; ++a) ent.push_back({L.agg[L.A_ci[a]], a});
+        if (!own_only)
+            for (int32_t a = L.A_rp[e]; a < L.A_rp[e + 1]; ++a) ent.push_back({L.agg[L.A_ci[a]], a});
         std::stable_sort(ent.begin(), ent.end(),
                          [](const auto& x, const auto& y) { return x.first < y.first || (x.first == y.first && x.second < y.second); });
         for (size_t i = 0; i < ent.size();) {
@@ -181,7 +182,7 @@ static void diag_positions(const std::vector<int32_t>& rp, const std::vector<int
 }
 
 void build_plan(Plan& P, int64_t n_elem, const int32_t* row_ptr, const int32_t* col_idx, int64_t nnzb,
-                int32_t n_levels, const int32_t* agg) {
+                int32_t n_levels, const int32_t* agg, bool hstar_smooth) {
     if (n_elem < 1 || !row_ptr || !col_idx || n_levels < 1) fail("plan: bad arguments");
     if (n_levels > 1 && !agg) fail("plan: aggregate hierarchy missing");
     if (n_elem >= (int64_t(1) << 31) || nnzb >= (int64_t(1) << 31)) fail("plan: sizes exceed int32 indexing");
@@ -271,7 +272,8 @@ void build_plan(Plan& P, int64_t n_elem, const int32_t* row_ptr, const int32_t* 
         L.A_rp.swap(rp);
         L.A_ci.swap(ci);
         diag_positions(L.A_rp, L.A_ci, L.A_diag, k == 0 ? "A_0" : "A_k");
-        symbolic_T(L);
+        L.replicated = L.n_agg == L.n_units;
+        symbolic_T(L, L.replicated && !hstar_smooth);
         symbolic_R(L);
         symbolic_AT(L);
         symbolic_C(L);

@@ -20,6 +20,7 @@ struct LevelPattern {
     std::vector<int32_t> A_rp, A_ci;
     std::vector<int32_t> A_diag;       // block index of the diagonal block of each row
 
+    bool replicated = false;           // every aggregate is a single unit (h*-step)
     // T_k = P~ - omega D^{-1} (A_k P~): block (e, J)
     std::vector<int32_t> T_rp, T_ci;
     std::vector<int32_t> T_row;        // block row of each T block
@@ -50,9 +51,12 @@ struct Plan {
     std::vector<int32_t> AN_rp, AN_ci, AN_diag;
 };
 
-// Throws std::invalid_argument with a message on invalid input.
+// Throws std::invalid_argument with a message on invalid input.  A level whose
+// aggregates are its own units (a replicated level, the h*-step) takes T = P~
+// (T row e holds its own aggregate only) unless hstar_smooth is set, which
+// applies eq:TR0's smoothing pattern there too.
 void build_plan(Plan& P, int64_t n_elem, const int32_t* row_ptr, const int32_t* col_idx, int64_t nnzb,
-                int32_t n_levels, const int32_t* agg_of_elem);
+                int32_t n_levels, const int32_t* agg_of_elem, bool hstar_smooth = false);
 
 void rcb_partition(int64_t n_elem, int32_t dim, const double* cent, int32_t n_levels, int32_t bisections,
                    int32_t* agg_out, int64_t* leaf_out);

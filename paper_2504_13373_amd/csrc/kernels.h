@@ -137,10 +137,24 @@ template <typename T>
 hipError_t launch_dinv_to_sell(const double* dinv_nat, int64_t n_brow, int br, int G, int L, int brpad, T* dinv_sell,
                                hipStream_t st, const int32_t* pos = nullptr);
 hipError_t launch_f64_to_f32(const double* a, float* b, int64_t n, hipStream_t st);
+// nb 1..64 (nb > 16: one wavefront per block, the block in LDS)
 hipError_t launch_block_inverse(const double* Avals, const int32_t* diag_pos, int64_t n_brow, int nb, double* dinv,
                                 int32_t* flag, hipStream_t st);
 hipError_t launch_svd(const double* B, int r, const int32_t* first_child, int64_t n_agg, int nb, int s,
                       double* Pu, double* svals, int32_t* flag, hipStream_t st);
+// Per-aggregate SVD for up to 64 candidates and any aggregate size (one
+// workgroup per aggregate, working columns in `work` at offsets woff[J]:
+// nr * r doubles, plus nr * nr when nr < r).  Unit u of the level owns the
+// rows u * nb + [0, sz[u]).  sJ[J] >= 0: vectors kept; sJ[J] < 0: keep those
+// with singular value above delta times the largest (written back to sJ).
+// Pu (row-major, spad columns) must be zeroed before.  flag |= 2 for more
+// than 1024 rows or a count above spad, 4 for a zero singular value kept.
+hipError_t launch_svd_gen(const double* B, int r, const int32_t* first_child, const int32_t* sz, int nb,
+                          int64_t n_agg, int32_t* sJ, double delta, int spad, double* work, const int64_t* woff,
+                          double* Pu, double* svals, int32_t* flag, hipStream_t st);
+// unit diagonal on the padding rows i >= sz[u] of every diagonal block
+hipError_t launch_pad_diag(double* Avals, const int32_t* diag_pos, int64_t n_brow, int nb, const int32_t* sz,
+                           hipStream_t st);
 hipError_t launch_T_build(const double* Avals, const int32_t* A_ci, const int32_t* T_row, const int32_t* T_ci,
                           const int32_t* Tm_ptr, const int32_t* Tm_a, const int32_t* agg, int64_t nT, int nb, int s,
                           const double* Pu, const double* dinv, double omega, double* W, double* Tvals,
@@ -167,6 +181,9 @@ hipError_t launch_gj_invert(double* a, int64_t n, int32_t* piv, int32_t* flag, c
 // out[0] = max |a_i|; out must hold 1 + DOT_PARTS doubles
 hipError_t launch_absmax(const double* a, int64_t n, double* out, hipStream_t st);
 hipError_t launch_uniform(uint64_t seed, const int64_t* perm, int64_t n_units, int nb, double* x, hipStream_t st);
+// a level whose units have sz[u] <= nb real dofs, the first at real offset roff[u]
+hipError_t launch_uniform_padded(uint64_t seed, const int64_t* roff, const int32_t* sz, int64_t n_units, int nb,
+                                 double* x, hipStream_t st);
 hipError_t launch_normal(uint64_t seed, const int64_t* perm, int64_t n_units, int nb, int r, double* x,
                          hipStream_t st);
 

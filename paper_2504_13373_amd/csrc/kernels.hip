@@ -1208,8 +1208,90 @@ __global__ __launch_bounds__(WG) void k_block_inverse(const double* __restrict__
         if (q < nb) dst[q] = v[q];
 }
 
+// Blocks of 17..64 rows: one wavefront per block, the block in LDS (row
+// stride 65), lane i owns row i.  In-place Gauss-Jordan with the same pivot
+// choice (largest magnitude, lowest row on ties): the pivot row is swapped
+// into place, scaled by the pivot's reciprocal (which takes the pivot's
+// position), every other row subtracts its multiple of it (its pivot-column
+// entry becoming -f times the reciprocal); the row swaps are undone as column
+// swaps of the inverse at the end.
+constexpr int MAXB_LDS = 64;
+
+__global__ __launch_bounds__(64) void k_block_inverse_lds(const double* __restrict__ Av,
+                                                          const int32_t* __restrict__ dpos, int64_t n_brow, int nb,
+                                                          double* __restrict__ dinv, int32_t* __restrict__ flag) {
+    __shared__ double a[MAXB_LDS][MAXB_LDS + 1];
+    __shared__ int piv[MAXB_LDS];
+    const int i = threadIdx.x;
+    const int64_t blk = blockIdx.x;
+    if (blk >= n_brow) return;
+    const double* src = Av + int64_t(dpos[blk]) * nb * nb;
+    double amax = 0.0;
+    if (i < nb)
+        for (int q = 0; q < nb; ++q) {
+            a[i][q] = src[int64_t(i) * nb + q];
+            amax = fmax(amax, fabs(a[i][q]));
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    const double tol = nb * DBL_EPSILON * amax;
+    bool singular = (amax == 0.0);
+    wave_lds_sync();
+    for (int c = 0; c < nb; ++c) {
+        // pivot row p >= c of largest |a[p][c]|, lowest p on ties
+        double v = (i >= c && i < nb) ? fabs(a[i][c]) : -1.0;
+        int p = i;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ov = __shfl_xor(v, o);
+            const int op = __shfl_xor(p, o);
+            if (ov > v || (ov == v && op < p)) { v = ov; p = op; }
+        }
+        if (i == 0) piv[c] = p;
+        if (p != c && i < nb) {
+            const double t = a[c][i];
+            a[c][i] = a[p][i];
+            a[p][i] = t;
+        }
+        wave_lds_sync();
+        const double pv = a[c][c];
+        if (!(fabs(pv) > tol)) singular = true;
+        const double inv = 1.0 / pv;
+        double f = 0.0;
+        if (i < nb && i != c) f = a[i][c];
+        wave_lds_sync();
+        if (i < nb) a[c][i] = (i == c) ? inv : a[c][i] * inv;
+        wave_lds_sync();
+        if (i < nb && i != c) {
+            for (int q = 0; q < nb; ++q)
+                a[i][q] = (q == c) ? -f * inv : a[i][q] - f * a[c][q];
+        }
+        wave_lds_sync();
+    }
+    // undo the row swaps as column swaps, last first
+    for (int c = nb - 1; c >= 0; --c) {
+        const int p = piv[c];
+        if (p != c && i < nb) {
+            const double t = a[i][c];
+            a[i][c] = a[i][p];
+            a[i][p] = t;
+        }
+    }
+    if (singular && i == 0) atomicOr(flag, 1);
+    if (i < nb) {
+        double* dst = dinv + blk * nb * nb + int64_t(i) * nb;
+        for (int q = 0; q < nb; ++q) dst[q] = a[i][q];
+    }
+}
+
 hipError_t launch_block_inverse(const double* Av, const int32_t* dpos, int64_t n_brow, int nb, double* dinv,
                                 int32_t* flag, hipStream_t st) {
+    if (nb > MAXB && nb <= MAXB_LDS) {
+        if (n_brow == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_block_inverse_lds, dim3(unsigned(n_brow)), dim3(64), 0, st, Av, dpos, n_brow, nb, dinv,
+                           flag);
+        return hipGetLastError();
+    }
     if (nb < 1 || nb > MAXB) return hipErrorInvalidValue;
     const int G = 64 / nb;
     const int64_t waves = (n_brow + G - 1) / G;
@@ -1319,9 +1401,189 @@ hipError_t launch_svd(const double* B, int r, const int32_t* fc, int64_t n_agg, 
     return hipGetLastError();
 }
 
+// General form (up to 64 candidates, any number of rows, one coarse size per
+// aggregate): one workgroup per aggregate J, the working columns in global
+// memory (work + woff[J]).  The rows of J are the real dofs of its children
+// (child u owns rows u*nb + [0, sz[u])), nr of them; with nr >= r the r
+// columns of B_J (length nr) are orthogonalised, with nr < r the nr columns of
+// B_J^T (length r) are, and the rotations are accumulated in V (nr x nr), whose
+// columns are then the left singular vectors of B_J.  Column pairs follow a
+// round-robin order, a round's disjoint pairs spread over the four
+// wavefronts; sweeps repeat until no pair needs a rotation (at most 60).
+// sJ[J] >= 0 is the number of vectors kept (eq:sik, h-step); sJ[J] < 0 asks
+// for the h*-step count, the singular values above delta times the largest,
+// which is written back to sJ[J].  Output: the leading sJ[J] left singular
+// vectors with canonical sign in Pu (row-major, spad columns; other entries
+// untouched), the r singular values of J in sv (zeros beyond the rank bound).
+constexpr int SVDG_MAXR = 64;
+constexpr int SVDG_SWEEPS = 60;
+
+__global__ __launch_bounds__(WG) void k_svd_gen(const double* __restrict__ B, int r, const int32_t* __restrict__ fc,
+                                                const int32_t* __restrict__ sz, int nb, int64_t n_agg,
+                                                int32_t* __restrict__ sJ, double delta, int spad,
+                                                double* __restrict__ work, const int64_t* __restrict__ woff,
+                                                double* __restrict__ Pu, double* __restrict__ sv,
+                                                int32_t* __restrict__ flag) {
+    __shared__ int32_t rowof[1024];
+    __shared__ double sig[SVDG_MAXR];
+    __shared__ int rank_of[SVDG_MAXR];
+    __shared__ int any_rot;
+    __shared__ int nr_sh;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t J = blockIdx.x;
+    if (J >= n_agg) return;
+    // real rows of J, in child order
+    if (threadIdx.x == 0) {
+        int nr = 0;
+        for (int32_t u = fc[J]; u < fc[J + 1]; ++u)
+            for (int i = 0; i < sz[u] && nr < 1024; ++i) rowof[nr++] = u * nb + i;
+        int tot = 0;
+        for (int32_t u = fc[J]; u < fc[J + 1]; ++u) tot += sz[u];
+        nr_sh = tot;
+    }
+    __syncthreads();
+    const int nr = nr_sh;
+    if (nr > 1024) {
+        if (threadIdx.x == 0) atomicOr(flag, 2);
+        return;
+    }
+    const bool tall = nr >= r;
+    const int ncol = tall ? r : nr;       // columns rotated
+    const int len = tall ? nr : r;        // their length
+    double* W = work + woff[J];           // ncol columns of length len
+    double* V = W + int64_t(ncol) * len;  // nr x nr (column-major) when !tall
+    for (int t = threadIdx.x; t < ncol * len; t += WG) {
+        const int col = t / len, e = t - (t / len) * len;
+        W[t] = tall ? B[int64_t(rowof[e]) * r + col] : B[int64_t(rowof[col]) * r + e];
+    }
+    if (!tall)
+        for (int t = threadIdx.x; t < nr * nr; t += WG) V[t] = (t / nr == t % nr) ? 1.0 : 0.0;
+    __syncthreads();
+    const int np = (ncol + 1) & ~1;       // players of the round-robin (one dummy when ncol is odd)
+    for (int sweep = 0; sweep < SVDG_SWEEPS; ++sweep) {
+        if (threadIdx.x == 0) any_rot = 0;
+        __syncthreads();
+        for (int round = 0; round < np - 1; ++round) {
+            for (int pi = wave; pi < np / 2; pi += WAVES_PER_WG) {
+                auto player = [&](int j) { return j == 0 ? 0 : 1 + (j - 1 + round) % (np - 1); };
+                int p = player(pi), q = player(np - 1 - pi);
+                if (p > q) { const int t = p; p = q; q = t; }
+                if (q >= ncol) continue;  // the dummy player
+                double* wp = W + int64_t(p) * len;
+                double* wq = W + int64_t(q) * len;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int e = lane; e < len; e += 64) {
+                    const double x = wp[e], y = wq[e];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                al = wave_sum(al);
+                be = wave_sum(be);
+                ga = wave_sum(ga);
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                if (lane == 0) any_rot = 1;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                for (int e = lane; e < len; e += 64) {
+                    const double x = wp[e], y = wq[e];
+                    wp[e] = cs * x - sn * y;
+                    wq[e] = sn * x + cs * y;
+                }
+                if (!tall) {
+                    double* vp = V + int64_t(p) * nr;
+                    double* vq = V + int64_t(q) * nr;
+                    for (int e = lane; e < nr; e += 64) {
+                        const double x = vp[e], y = vq[e];
+                        vp[e] = cs * x - sn * y;
+                        vq[e] = sn * x + cs * y;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (!any_rot) break;
+        __syncthreads();
+    }
+    // singular values: column norms
+    for (int c = wave; c < ncol; c += WAVES_PER_WG) {
+        double a = 0.0;
+        for (int e = lane; e < len; e += 64) a += W[int64_t(c) * len + e] * W[int64_t(c) * len + e];
+        a = wave_sum(a);
+        if (lane == 0) sig[c] = sqrt(a);
+    }
+    __syncthreads();
+    if (threadIdx.x < ncol) {
+        const int c = threadIdx.x;
+        int rk = 0;
+        for (int q = 0; q < ncol; ++q)
+            if (sig[q] > sig[c] || (sig[q] == sig[c] && q < c)) ++rk;
+        rank_of[c] = rk;
+        sv[J * r + rk] = sig[c];
+    }
+    for (int c = ncol + int(threadIdx.x); c < r; c += WG) sv[J * r + c] = 0.0;
+    __syncthreads();
+    __shared__ int s_keep;
+    if (threadIdx.x == 0) {
+        int sk = sJ[J];
+        double smax = 0.0;
+        for (int c = 0; c < ncol; ++c) smax = fmax(smax, sig[c]);
+        if (sk < 0) {
+            sk = 0;
+            for (int c = 0; c < ncol; ++c)
+                if (sig[c] > delta * smax) ++sk;
+            sJ[J] = sk;
+        }
+        if (sk > spad || sk > ncol) atomicOr(flag, 2);
+        s_keep = sk;
+    }
+    __syncthreads();
+    const int sk = s_keep;
+    if (sk > spad || sk > ncol) return;
+    for (int c = wave; c < ncol; c += WAVES_PER_WG) {
+        const int rk = rank_of[c];
+        if (rk >= sk) continue;
+        if (!(sig[c] > 0.0)) {
+            if (lane == 0) atomicOr(flag, 4);
+            continue;
+        }
+        // left singular vector: W_c / sigma_c (tall) or column c of V
+        const double inv = 1.0 / sig[c];
+        const double* src = tall ? W + int64_t(c) * len : V + int64_t(c) * nr;
+        const double scl = tall ? inv : 1.0;
+        double bv = -1.0, sg = 0.0;
+        int brw = 1 << 30;
+        for (int e = lane; e < nr; e += 64) {
+            const double u = src[e] * scl;
+            if (fabs(u) > bv) { bv = fabs(u); brw = e; sg = u; }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ov = __shfl_xor(bv, o);
+            const int orw = __shfl_xor(brw, o);
+            const double os = __shfl_xor(sg, o);
+            if (ov > bv || (ov == bv && orw < brw)) { bv = ov; brw = orw; sg = os; }
+        }
+        const double fl = sg < 0.0 ? -1.0 : 1.0;
+        for (int e = lane; e < nr; e += 64) Pu[int64_t(rowof[e]) * spad + rk] = fl * src[e] * scl;
+    }
+}
+
+hipError_t launch_svd_gen(const double* B, int r, const int32_t* fc, const int32_t* sz, int nb, int64_t n_agg,
+                          int32_t* sJ, double delta, int spad, double* work, const int64_t* woff, double* Pu,
+                          double* sv, int32_t* flag, hipStream_t st) {
+    if (r < 1 || r > SVDG_MAXR || spad < 1) return hipErrorInvalidValue;
+    if (n_agg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_svd_gen, dim3(unsigned(n_agg)), dim3(WG), 0, st, B, r, fc, sz, nb, n_agg, sJ, delta, spad,
+                       work, woff, Pu, sv, flag);
+    return hipGetLastError();
+}
+
 // ============================================================ T, R, A T, Galerkin
 // Small dense block products driven by host-built index lists (symbolic phase).
-// One thread per (output block, output row); s <= 16 accumulators per thread.
+// One thread per (output block, output row); the s columns of the output row
+// are formed in chunks of 16 accumulators.
 
 // W_t = sum_{a in Tm(t)} A_a * P~[col(a)]   (nb x s);  T_t = [J==agg(e)] P~[e] - omega D_e^{-1} W_t
 __global__ void k_T_W(const double* __restrict__ Av, const int32_t* __restrict__ A_ci, const int32_t* __restrict__ Tm_ptr,
@@ -1331,23 +1593,25 @@ __global__ void k_T_W(const double* __restrict__ Av, const int32_t* __restrict__
     if (tid >= nT * nb) return;
     const int64_t t = tid / nb;
     const int i = int(tid - t * nb);
-    double acc[MAXB];
+    for (int l0 = 0; l0 < s; l0 += MAXB) {
+        double acc[MAXB];
 #pragma unroll
-    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
-    for (int32_t q = Tm_ptr[t]; q < Tm_ptr[t + 1]; ++q) {
-        const int32_t a = Tm_a[q];
-        const double* Ar = Av + int64_t(a) * nb * nb + int64_t(i) * nb;
-        const double* Pc = Pu + int64_t(A_ci[a]) * nb * s;
-        for (int j = 0; j < nb; ++j) {
-            const double av = Ar[j];
+        for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+        for (int32_t q = Tm_ptr[t]; q < Tm_ptr[t + 1]; ++q) {
+            const int32_t a = Tm_a[q];
+            const double* Ar = Av + int64_t(a) * nb * nb + int64_t(i) * nb;
+            const double* Pc = Pu + int64_t(A_ci[a]) * nb * s + l0;
+            for (int j = 0; j < nb; ++j) {
+                const double av = Ar[j];
 #pragma unroll
-            for (int l = 0; l < MAXB; ++l)
-                if (l < s) acc[l] += av * Pc[j * s + l];
+                for (int l = 0; l < MAXB; ++l)
+                    if (l0 + l < s) acc[l] += av * Pc[j * s + l];
+            }
         }
-    }
 #pragma unroll
-    for (int l = 0; l < MAXB; ++l)
-        if (l < s) W[(t * nb + i) * s + l] = acc[l];
+        for (int l = 0; l < MAXB; ++l)
+            if (l0 + l < s) W[(t * nb + i) * s + l0 + l] = acc[l];
+    }
 }
 
 __global__ void k_T_final(const int32_t* __restrict__ T_row, const int32_t* __restrict__ T_ci,
@@ -1360,26 +1624,29 @@ __global__ void k_T_final(const int32_t* __restrict__ T_row, const int32_t* __re
     const int i = int(tid - t * nb);
     const int64_t e = T_row[t];
     const bool own = T_ci[t] == agg[e];
-    double acc[MAXB];
-#pragma unroll
-    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
     const double* Dr = dinv + e * nb * nb + int64_t(i) * nb;
     const double* Wt = W + t * nb * s;
-    for (int j = 0; j < nb; ++j) {
-        const double d = Dr[j];
+    for (int l0 = 0; l0 < s; l0 += MAXB) {
+        double acc[MAXB];
+#pragma unroll
+        for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+        for (int j = 0; j < nb; ++j) {
+            const double d = Dr[j];
+#pragma unroll
+            for (int l = 0; l < MAXB; ++l)
+                if (l0 + l < s) acc[l] += d * Wt[j * s + l0 + l];
+        }
 #pragma unroll
         for (int l = 0; l < MAXB; ++l)
-            if (l < s) acc[l] += d * Wt[j * s + l];
+            if (l0 + l < s)
+                Tv[(t * nb + i) * s + l0 + l] = (own ? Pu[(e * nb + i) * s + l0 + l] : 0.0) - omega * acc[l];
     }
-#pragma unroll
-    for (int l = 0; l < MAXB; ++l)
-        if (l < s) Tv[(t * nb + i) * s + l] = (own ? Pu[(e * nb + i) * s + l] : 0.0) - omega * acc[l];
 }
 
 hipError_t launch_T_build(const double* Av, const int32_t* A_ci, const int32_t* T_row, const int32_t* T_ci,
                           const int32_t* Tm_ptr, const int32_t* Tm_a, const int32_t* agg, int64_t nT, int nb, int s,
                           const double* Pu, const double* dinv, double omega, double* W, double* Tv, hipStream_t st) {
-    if (s > MAXB) return hipErrorInvalidValue;
+    if (s < 1) return hipErrorInvalidValue;
     if (nT == 0) return hipSuccess;
     hipLaunchKernelGGL(k_T_W, dim3(grid_for(nT * nb)), dim3(WG), 0, st, Av, A_ci, Tm_ptr, Tm_a, nT, nb, s, Pu, W);
     hipLaunchKernelGGL(k_T_final, dim3(grid_for(nT * nb)), dim3(WG), 0, st, T_row, T_ci, agg, nT, nb, s, Pu, dinv,
@@ -1467,27 +1734,29 @@ __global__ void k_AT(const double* __restrict__ Av, const double* __restrict__ T
     if (tid >= nAT * nb) return;
     const int64_t u = tid / nb;
     const int i = int(tid - u * nb);
-    double acc[MAXB];
+    for (int l0 = 0; l0 < s; l0 += MAXB) {
+        double acc[MAXB];
 #pragma unroll
-    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
-    for (int64_t q = pp[u]; q < pp[u + 1]; ++q) {
-        const double* Ar = Av + int64_t(pa[q]) * nb * nb + int64_t(i) * nb;
-        const double* Tt = Tv + int64_t(pt[q]) * nb * s;
-        for (int j = 0; j < nb; ++j) {
-            const double av = Ar[j];
+        for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+        for (int64_t q = pp[u]; q < pp[u + 1]; ++q) {
+            const double* Ar = Av + int64_t(pa[q]) * nb * nb + int64_t(i) * nb;
+            const double* Tt = Tv + int64_t(pt[q]) * nb * s + l0;
+            for (int j = 0; j < nb; ++j) {
+                const double av = Ar[j];
 #pragma unroll
-            for (int l = 0; l < MAXB; ++l)
-                if (l < s) acc[l] += av * Tt[j * s + l];
+                for (int l = 0; l < MAXB; ++l)
+                    if (l0 + l < s) acc[l] += av * Tt[j * s + l];
+            }
         }
-    }
 #pragma unroll
-    for (int l = 0; l < MAXB; ++l)
-        if (l < s) ATv[(u * nb + i) * s + l] = acc[l];
+        for (int l = 0; l < MAXB; ++l)
+            if (l0 + l < s) ATv[(u * nb + i) * s + l0 + l] = acc[l];
+    }
 }
 
 hipError_t launch_AT(const double* Av, const double* Tv, const int64_t* pp, const int32_t* pa, const int32_t* pt,
                      int64_t nAT, int nb, int s, double* ATv, hipStream_t st) {
-    if (s > MAXB) return hipErrorInvalidValue;
+    if (s < 1) return hipErrorInvalidValue;
     if (nAT == 0) return hipSuccess;
     hipLaunchKernelGGL(k_AT, dim3(grid_for(nAT * nb)), dim3(WG), 0, st, Av, Tv, pp, pa, pt, nAT, nb, s, ATv);
     return hipGetLastError();
@@ -1501,29 +1770,50 @@ __global__ void k_galerkin(const double* __restrict__ Tv, const double* __restri
     if (tid >= nC * s) return;
     const int64_t v = tid / s;
     const int i = int(tid - v * s);
-    double acc[MAXB];
+    for (int l0 = 0; l0 < s; l0 += MAXB) {
+        double acc[MAXB];
 #pragma unroll
-    for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
-    for (int64_t q = pp[v]; q < pp[v + 1]; ++q) {
-        const double* Tt = Tv + int64_t(pt[q]) * nb * s;
-        const double* Au = ATv + int64_t(pu[q]) * nb * s;
-        for (int j = 0; j < nb; ++j) {
-            const double tv = Tt[j * s + i];
+        for (int l = 0; l < MAXB; ++l) acc[l] = 0.0;
+        for (int64_t q = pp[v]; q < pp[v + 1]; ++q) {
+            const double* Tt = Tv + int64_t(pt[q]) * nb * s;
+            const double* Au = ATv + int64_t(pu[q]) * nb * s + l0;
+            for (int j = 0; j < nb; ++j) {
+                const double tv = Tt[j * s + i];
 #pragma unroll
-            for (int l = 0; l < MAXB; ++l)
-                if (l < s) acc[l] += tv * Au[j * s + l];
+                for (int l = 0; l < MAXB; ++l)
+                    if (l0 + l < s) acc[l] += tv * Au[j * s + l];
+            }
         }
-    }
 #pragma unroll
-    for (int l = 0; l < MAXB; ++l)
-        if (l < s) Cv[(v * s + i) * s + l] = acc[l];
+        for (int l = 0; l < MAXB; ++l)
+            if (l0 + l < s) Cv[(v * s + i) * s + l0 + l] = acc[l];
+    }
 }
 
 hipError_t launch_galerkin(const double* Tv, const double* ATv, const int64_t* pp, const int32_t* pt,
                            const int32_t* pu, int64_t nC, int nb, int s, double* Cv, hipStream_t st) {
-    if (s > MAXB) return hipErrorInvalidValue;
+    if (s < 1) return hipErrorInvalidValue;
     if (nC == 0) return hipSuccess;
     hipLaunchKernelGGL(k_galerkin, dim3(grid_for(nC * s)), dim3(WG), 0, st, Tv, ATv, pp, pt, pu, nC, nb, s, Cv);
+    return hipGetLastError();
+}
+
+// Units of a coarse level whose s_J is below the level's block size carry
+// zero rows and columns in their padding; a unit diagonal there keeps the
+// diagonal blocks invertible while the padding stays zero in every vector.
+__global__ void k_pad_diag(double* __restrict__ Av, const int32_t* __restrict__ diag_pos, int64_t n_brow, int nb,
+                           const int32_t* __restrict__ sz) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= n_brow * nb) return;
+    const int64_t u = tid / nb;
+    const int i = int(tid - u * nb);
+    if (i >= sz[u]) Av[int64_t(diag_pos[u]) * nb * nb + int64_t(i) * nb + i] = 1.0;
+}
+
+hipError_t launch_pad_diag(double* Av, const int32_t* diag_pos, int64_t n_brow, int nb, const int32_t* sz,
+                           hipStream_t st) {
+    if (n_brow * nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_diag, dim3(grid_for(n_brow * nb)), dim3(WG), 0, st, Av, diag_pos, n_brow, nb, sz);
     return hipGetLastError();
 }
 
@@ -1698,6 +1988,24 @@ __global__ void k_uniform(uint64_t seed, const int64_t* __restrict__ perm, int64
 hipError_t launch_uniform(uint64_t seed, const int64_t* perm, int64_t n_units, int nb, double* x, hipStream_t st) {
     if (n_units * nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_uniform, dim3(grid_for(n_units * nb)), dim3(WG), 0, st, seed, perm, n_units, nb, x);
+    return hipGetLastError();
+}
+
+// padded level: x[u*nb + i] = 2 U(seed, roff[u] + i) - 1 for i < sz[u], 0 in the padding
+__global__ void k_uniform_padded(uint64_t seed, const int64_t* __restrict__ roff, const int32_t* __restrict__ sz,
+                                 int64_t n_units, int nb, double* __restrict__ x) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_units * nb) return;
+    const int64_t u = t / nb;
+    const int i = int(t - u * nb);
+    x[t] = i < sz[u] ? 2.0 * u01(splitmix(seed, uint64_t(roff[u] + i))) - 1.0 : 0.0;
+}
+
+hipError_t launch_uniform_padded(uint64_t seed, const int64_t* roff, const int32_t* sz, int64_t n_units, int nb,
+                                 double* x, hipStream_t st) {
+    if (n_units * nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uniform_padded, dim3(grid_for(n_units * nb)), dim3(WG), 0, st, seed, roff, sz, n_units, nb,
+                       x);
     return hipGetLastError();
 }
 

@@ -89,6 +89,38 @@ def test_symbolic_patterns_bit_exact_vs_oracle(maker):
     plan.close()
 
 
+@pytest.mark.parametrize("maker", [
+    lambda: configs.poisson2d_delaunay(side=23, p=1, n_levels=4, bisections=2, r=3),
+    lambda: configs.poisson3d_hex(2, p=1, flux="ldg", hstar=True),
+])
+def test_replicated_level_patterns_bit_exact_vs_oracle(maker):
+    """The h*-step at the top: the library's hierarchy helper (its own
+    partition plus a replicated first level numbered by leaf position) equals
+    the oracle's, and the patterns (T = P~ on the replicated level, so its
+    coarse operator keeps the fine stencil) match bit for bit."""
+    w = maker()
+    nl = w.params.n_levels
+    if not w.params.hstar_top:
+        nl += 1
+    agg_lib = am.hierarchy(w.centroids, nl, w.params.bisections, hstar_top=True)
+    aggs, leaf = rcb.rcb_hierarchy(w.centroids, nl - 1, w.params.bisections)
+    aggs = rcb.replicate_top(aggs, leaf)
+    elem = rcb.agg_of_elem_levels(aggs)
+    for k in range(nl - 1):
+        assert np.array_equal(agg_lib[k], elem[k])
+    pats = amg.block_patterns(w.A.row_ptr, w.A.col_idx, aggs)
+    plan = am.amgdg_plan_create(w.A.n_brow, w.A.row_ptr, w.A.col_idx, nl, agg_lib)
+    for k in range(nl - 1):
+        assert np.array_equal(plan.export(k, am.AMGDG_T_ROWPTR), pats[k]["T_ptr"])
+        assert np.array_equal(plan.export(k, am.AMGDG_T_COLIDX), pats[k]["T_idx"])
+        assert np.array_equal(plan.export(k + 1, am.AMGDG_A_ROWPTR), pats[k]["A_ptr"])
+        assert np.array_equal(plan.export(k + 1, am.AMGDG_A_COLIDX), pats[k]["A_idx"])
+    # the replicated level: one T block per row, and level 1 keeps level 0's stencil
+    assert np.array_equal(np.diff(pats[0]["T_ptr"]), np.ones(w.A.n_brow, dtype=np.int32))
+    assert len(pats[0]["A_idx"]) == w.A.nnzb
+    plan.close()
+
+
 def test_plan_rejects_bad_input():
     w = configs.poisson2d_split(nx=4, p=1, n_levels=2, bisections=2, r=1)
     agg, _ = am.amgdg_partition_rcb(w.centroids, 2, 2)

@@ -46,6 +46,8 @@ class Params:
     n_cut: float = 3.0
     pow_seed: int = 3
     delta: float = 1e-3           # h*-step threshold of eq:sik (Section 4.3)
+    hstar_top: bool = False       # replicate level 0 (an h*-step before the geometric levels)
+    hstar_smooth: bool = False    # smooth P~ on the replicated level too (eq:TR0) instead of T = P~
 
 
 @dataclass
@@ -119,17 +121,19 @@ def poisson3d_kuhn(n=64, p=2, n_levels=5, bisections=3, r=4, nu=2, n_rhs=1, log=
     return _finish(f"poisson3d_p{p}_kuhn{n}", m, p, A, prm, "pcg", n_rhs=n_rhs)
 
 
-def poisson3d_hex(M=4, p=1, flux="ip", r=8, nu=3, n_levels=None, rhs="paper", relax_max=100):
+def poisson3d_hex(M=4, p=1, flux="ip", r=8, nu=3, n_levels=None, rhs="paper", relax_max=100, hstar=False):
     """Section 5.1's structured Poisson problem.  Levels: ceil(log_8 |T_h|), so
     that the coarsest level holds 8 aggregates, with 8-way aggregation per
-    level; rhs "paper" is the load vector of the manufactured solution, else
-    seeded N(0, 1) like the other workloads."""
+    level; with hstar, level 0 is replicated first (the h*-step of Section 4.3,
+    one more level).  rhs "paper" is the load vector of the manufactured
+    solution, else seeded N(0, 1) like the other workloads."""
     m = hexdg.HexMesh(M)
     A = hexdg.assemble_hex(M, p, flux)
     if n_levels is None:
-        n_levels = max(2, M)
-    prm = Params(n_levels, 3, r, nu, nu, relax_max=relax_max, n_cut=n_cut_default(3))
-    w = _finish(f"poisson3d_hex{M}_q{p}_{flux}", m, p, A, prm, "pcg", extra={"flux": flux, "M": M})
+        n_levels = max(2, M) + (1 if hstar else 0)
+    prm = Params(n_levels, 3, r, nu, nu, relax_max=relax_max, n_cut=n_cut_default(3), hstar_top=hstar)
+    w = _finish(f"poisson3d_hex{M}_q{p}_{flux}{'_hstar' if hstar else ''}", m, p, A, prm, "pcg",
+                extra={"flux": flux, "M": M})
     if rhs == "paper":
         w.b = np.ascontiguousarray(hexdg.paper_rhs(M, p))
         w.tol = 1e-7
