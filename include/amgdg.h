@@ -70,6 +70,10 @@ typedef struct {
                               Algorithm 5): 0 takes T = P~ (its coarse operator keeps the fine
                               stencil, as the paper's printed h*-hierarchy implies), 1 smooths
                               P~ as in eq:TR0 */
+    int32_t  matfree_levels; /* kappa of Section 4.6: levels 1..kappa (at most n_levels-2) keep
+                              no A_k after the setup; the V-cycle applies A_k as
+                              R_{k-1} A_{k-1} T_{k-1} (eq:matfree1, eq:matfree2), down to A_0.
+                              Single steps that need A_k are then EUNSUPPORTED on those levels */
 } amgdg_params;
 
 /* Fills the paper's defaults: gamma 0.03 (Section 4.2), q 3 (Section 4.4),
@@ -180,6 +184,8 @@ typedef struct {
     int64_t bytes_A, bytes_Dinv, bytes_T, bytes_R;   /* FP64 bytes held for level k */
     int64_t n_dofs;      /* dofs of level k without the padding of units below nb (= n when
                             every unit holds nb) */
+    int32_t matfree;     /* 1: A_k is applied matrix-free (not stored) */
+    int64_t bytes_handle;/* device bytes held by the whole hierarchy (every level) */
 } amgdg_level_info;
 int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out);
 int amgdg_num_levels(amgdg_handle h);

@@ -38,7 +38,8 @@ class amgdg_params(ctypes.Structure):
                 ("t_post", ctypes.c_int32), ("q_power", ctypes.c_int32), ("relax_max", ctypes.c_int32),
                 ("omega_fixed", ctypes.c_double), ("gamma", ctypes.c_double), ("n_cut", ctypes.c_double),
                 ("b_update", ctypes.c_int32), ("mixed", ctypes.c_int32), ("pow_seed", ctypes.c_uint64),
-                ("b1_seed", ctypes.c_uint64), ("delta", ctypes.c_double), ("hstar_smooth", ctypes.c_int32)]
+                ("b1_seed", ctypes.c_uint64), ("delta", ctypes.c_double), ("hstar_smooth", ctypes.c_int32),
+                ("matfree_levels", ctypes.c_int32)]
 
 
 class amgdg_level_info(ctypes.Structure):
@@ -47,7 +48,7 @@ class amgdg_level_info(ctypes.Structure):
                 ("n_agg", ctypes.c_int64), ("omega", ctypes.c_double), ("rho", ctypes.c_double),
                 ("r", ctypes.c_int32), ("sweeps", ctypes.c_int32 * 64), ("bytes_A", ctypes.c_int64),
                 ("bytes_Dinv", ctypes.c_int64), ("bytes_T", ctypes.c_int64), ("bytes_R", ctypes.c_int64),
-                ("n_dofs", ctypes.c_int64)]
+                ("n_dofs", ctypes.c_int64), ("matfree", ctypes.c_int32), ("bytes_handle", ctypes.c_int64)]
 
 
 class amgdg_solve_stats(ctypes.Structure):

@@ -60,6 +60,16 @@ struct DevMem {
     void zero_all(hipStream_t st) {
         for (size_t i = 0; i < blocks.size(); ++i) HIPCHK(hipMemsetAsync(blocks[i], 0, sizes[i], st));
     }
+    // frees one block of this DevMem (nothing if p is not one of them)
+    void free(void* p) {
+        for (size_t i = 0; i < blocks.size(); ++i)
+            if (blocks[i] == p) {
+                (void)hipFree(p);
+                blocks.erase(blocks.begin() + long(i));
+                sizes.erase(sizes.begin() + long(i));
+                return;
+            }
+    }
 };
 
 template <typename T>
@@ -126,6 +136,9 @@ struct Level {
     int64_t* roff_d = nullptr;
     int64_t n_real = 0;
     bool padded = false;
+    // matrix-free level (eq:matfree1, eq:matfree2): A_k is not kept after the
+    // setup; the V-cycle forms A_k u as R_{k-1} A_{k-1} T_{k-1} u
+    bool matfree = false;
     double omega = 1.0, rho = std::numeric_limits<double>::quiet_NaN();
     std::vector<int32_t> sweeps;
     double* A_nat = nullptr;
@@ -210,6 +223,8 @@ struct Work {
 
 struct Ctx {
     DevMem mem;
+    DevMem* build_mem = nullptr;  // where build_mat places a layout (nullptr: mem)
+    DevMem& bm() { return build_mem ? *build_mem : mem; }
     Plan plan;
     amgdg_params prm{};
     int N = 0;                  // index of the coarsest level
@@ -259,8 +274,8 @@ static void sell_values(Ctx& C, Sell<T>& d, int64_t ns, const std::vector<int32_
     for (size_t q = 0; q < slot_s.size(); ++q) base[q] = voff[slot_s[q]];
     d.tpad = std::max<int32_t>(tpad, VW);
     d.brpad = (d.br + VW - 1) / VW * VW;
-    d.voff = upload(C.mem, voff, st);
-    T* vals = C.mem.alloc<T>(v);
+    d.voff = upload(C.bm(), voff, st);
+    T* vals = C.bm().alloc<T>(v);
     HIPCHK(hipMemsetAsync(vals, 0, sizeof(T) * size_t(std::max<int64_t>(v, 1)), st));
     {
         DevMem tmp;
@@ -346,15 +361,15 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
     d.G = G;
     d.L = L;
     d.n_slices = int32_t(ns);
-    d.coff = upload(C.mem, coff, st);
-    d.K = upload(C.mem, K, st);
-    d.cols = upload(C.mem, cols, st);
+    d.coff = upload(C.bm(), coff, st);
+    d.K = upload(C.bm(), K, st);
+    d.cols = upload(C.bm(), cols, st);
     if (use_sorted) {
-        d.rows = upload(C.mem, order, st);
+        d.rows = upload(C.bm(), order, st);
         std::vector<int32_t> pos(static_cast<size_t>(n_brow));
         for (int64_t q = 0; q < ns * G; ++q)
             if (order[q] < n_brow) pos[order[q]] = int32_t(q);
-        S.pos = upload(C.mem, pos, st);
+        S.pos = upload(C.bm(), pos, st);
     }
     Sell<float> f;
     f.n_brow = d.n_brow;
@@ -379,7 +394,7 @@ static void build_sell(Ctx& C, SellStore& S, int64_t n_brow, int br, int bc, con
 template <typename T>
 static T* sell_dinv(Ctx& C, const Sell<T>& A, const int32_t* pos, const double* dinv_nat, hipStream_t st) {
     const int64_t cnt = int64_t(A.n_slices) * A.brpad * A.L;
-    T* out = C.mem.alloc<T>(cnt);
+    T* out = C.bm().alloc<T>(cnt);
     HIPCHK(hipMemsetAsync(out, 0, sizeof(T) * size_t(std::max<int64_t>(cnt, 1)), st));
     HIPCHK(launch_dinv_to_sell<T>(dinv_nat, A.n_brow, A.br, A.G, A.L, A.brpad, out, st, pos));
     return out;
@@ -398,8 +413,8 @@ static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const
         d.br = br;
         d.bc = bc;
         d.P = P;
-        d.rp = upload(C.mem, rp, st);
-        d.ci = upload(C.mem, ci, st);
+        d.rp = upload(C.bm(), rp, st);
+        d.ci = upload(C.bm(), ci, st);
         d.vals = nat_d;
         M.bd = d;
         M.bf.n_brow = d.n_brow;
@@ -410,7 +425,7 @@ static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const
         M.bf.ci = d.ci;
         M.n_vals = nnzb * br * bc;
         if (f32) {
-            float* fv = C.mem.alloc<float>(M.n_vals);
+            float* fv = C.bm().alloc<float>(M.n_vals);
             HIPCHK(launch_f64_to_f32(nat_d, fv, M.n_vals, st));
             M.bf.vals = fv;
         }
@@ -428,13 +443,13 @@ static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const
             d.n_brow = int32_t(n_brow);
             d.br = br;
             d.bc = bc;
-            d.rp = upload(C.mem, rp, st);
-            d.ci = upload(C.mem, ci, st);
+            d.rp = upload(C.bm(), rp, st);
+            d.ci = upload(C.bm(), ci, st);
             d.vals = nat_d;
             M.nd = d;
             if (f32) {
                 const int64_t nv = int64_t(ci.size()) * br * bc;
-                float* fv = C.mem.alloc<float>(nv);
+                float* fv = C.bm().alloc<float>(nv);
                 HIPCHK(launch_f64_to_f32(nat_d, fv, nv, st));
                 M.nf.n_brow = d.n_brow;
                 M.nf.br = br;
@@ -626,6 +641,8 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
     if (p.n_levels < 1) throw Error(AMGDG_EINVAL, "n_levels must be >= 1");
     if (p.n_levels > 1 && (p.r < 1 || p.r > 64)) throw Error(AMGDG_EUNSUPPORTED, "r must be 1..64");
     if (!(p.delta >= 0.0)) throw Error(AMGDG_EINVAL, "delta must be >= 0");
+    if (p.matfree_levels < 0 || (p.matfree_levels > 0 && p.matfree_levels > p.n_levels - 2))
+        throw Error(AMGDG_EINVAL, "matfree_levels must be 0..n_levels-2");
     if (p.t_pre < 0 || p.t_post < 0 || p.q_power < 0 || p.relax_max < 1 || !(p.n_cut > 0))
         throw Error(AMGDG_EINVAL, "bad smoothing or coarsening parameters");
     if (p.b_update != 0) throw Error(AMGDG_EUNSUPPORTED, "only B^{k+1} = R B^k is implemented");
@@ -712,6 +729,12 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         const LevelPattern& P = C.plan.lv[k];
         L.n_agg = P.n_agg;
         L.r = r;
+        // On a matrix-free level (1 <= k <= matfree_levels) A_k's layouts serve
+        // the setup's power iteration and relaxation only: they are built in
+        // FP64 into `setup_only` and freed with A_k's values at the end of this
+        // level; S_k = D_k^{-1} A_k is not formed.
+        L.matfree = k >= 1 && k <= p.matfree_levels;
+        DevMem setup_only;
         // D_k^{-1}
         {
             DevMem tmp;
@@ -721,19 +744,21 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
             if (read_flag(C, st))
                 throw Error(AMGDG_ESINGULAR, "diagonal block singular to working precision on level " + std::to_string(k));
         }
-        build_mat(C, L.A, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.A_nat, C.mixed, st);
-        {
+        if (L.matfree) C.build_mem = &setup_only;
+        build_mat(C, L.A, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.A_nat, C.mixed && !L.matfree, st);
+        if (!L.matfree) {
             DevMem tmp;
             int32_t* rp_d = upload(tmp, P.A_rp, st);
             L.S_nat = C.mem.alloc<double>(L.nnzb * L.nb * L.nb);
             HIPCHK(launch_row_scale(L.A_nat, rp_d, L.n_units, L.nb, L.Dinv_nat, L.S_nat, st));
             HIPCHK(hipStreamSynchronize(st));
+            build_mat(C, L.S, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.S_nat, C.mixed, st);
         }
-        build_mat(C, L.S, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.S_nat, C.mixed, st);
         if (!L.A.vec) {
             L.Dinv_sell = sell_dinv<double>(C, L.A.s.d, L.A.s.pos, L.Dinv_nat, st);
-            if (C.mixed) L.Dinv_sell32 = sell_dinv<float>(C, L.A.s.f, L.A.s.pos, L.Dinv_nat, st);
+            if (C.mixed && !L.matfree) L.Dinv_sell32 = sell_dinv<float>(C, L.A.s.f, L.A.s.pos, L.Dinv_nat, st);
         }
+        C.build_mem = nullptr;
         if (C.mixed) {
             L.Dinv_nat32 = C.mem.alloc<float>(L.n_units * L.nb * L.nb);
             HIPCHK(launch_f64_to_f32(L.Dinv_nat, L.Dinv_nat32, L.n_units * L.nb * L.nb, st));
@@ -884,6 +909,14 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         }
         cur_nb = s;
         HIPCHK(hipStreamSynchronize(st));
+        if (L.matfree) {
+            // A_k's values and layouts go; D_k^{-1} (natural, FP64 and FP32), T_k,
+            // R_k and R_k D_k stay
+            C.mem.free(L.A_nat);
+            L.A_nat = nullptr;
+            L.A = MatStore();
+            L.Dinv_sell = nullptr;
+        }
     }
     HIPCHK(hipStreamSynchronize(st));
 }
@@ -1008,6 +1041,22 @@ static void coarse_solve(Ctx& C, const T* b, T* u, int m, hipStream_t st) {
     HIPCHK(launch_gemv<T>(C.Ainv, b, u, C.nN, m, st));
 }
 
+// q = A_k u on a matrix-free level k (eq:matfree2 unrolled one level at a
+// time: A_k = R_{k-1} A_{k-1} T_{k-1}, with A_{k-1} formed the same way when it
+// is not stored either).  The products use level k-1's free vectors: the one
+// of u/w that does not hold u_{k-1}, and r (its residual has been restricted).
+template <typename T>
+static void matfree_apply(Ctx& C, VBuf<T>* VB, int k, const T* u, T* q, int m, hipStream_t st) {
+    Level& Lp = C.lv[k - 1];
+    VBuf<T>& Vp = VB[k - 1];
+    T* t = (Vp.cur == Vp.u) ? Vp.w : Vp.u;
+    T* t2 = Vp.r;
+    mat_spmv<T>(AX, Lp.T, u, nullptr, t, m, st);
+    if (Lp.matfree) matfree_apply<T>(C, VB, k - 1, t, t2, m, st);
+    else mat_spmv<T>(AX, Lp.A, t, nullptr, t2, m, st);
+    mat_spmv<T>(AX, Lp.R, t2, nullptr, q, m, st);
+}
+
 // z0 = V(b0), internal order, m columns (Algorithm 2, one pass from u = 0).
 // VB holds the level vectors of levels 0..N (the V-cycle's only workspace).
 template <typename T>
@@ -1030,6 +1079,32 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
         // Every sweep after the first runs on S = D^{-1} A with c = D^{-1} b:
         // u + omega D^{-1} (b - A u) = u + omega (c - S u), one matrix read
         // instead of A and D^{-1}.  The first sweep (from u = 0) also writes c.
+        if (L.matfree) {
+            // the same sweeps with A_k u formed by matfree_apply into V.r:
+            // u + omega (c - D^{-1} A_k u); the residual D^{-1} (b - A_k u) goes to
+            // the free one of u/w and is restricted by R D like S's residual
+            const T* dinv = dinv_nat_of<T>(L);
+            if (tpre == 0) {
+                HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * L.n * m, st));
+                HIPCHK(launch_bdiag<T>(BD_START, dinv, bk, nullptr, nullptr, oth, V.c, T(1), L.n_units, L.nb, m, st));
+            } else {
+                if (!started)
+                    HIPCHK(launch_bdiag<T>(BD_START, dinv, bk, nullptr, nullptr, cur, V.c, om, L.n_units, L.nb, m, st));
+                for (int t = 1; t < tpre; ++t) {
+                    V.cur = cur;
+                    matfree_apply<T>(C, VB, k, cur, V.r, m, st);
+                    HIPCHK(launch_bdiag<T>(BD_SWEEP, dinv, V.r, V.c, cur, oth, nullptr, om, L.n_units, L.nb, m, st));
+                    std::swap(cur, oth);
+                }
+            }
+            V.cur = cur;
+            matfree_apply<T>(C, VB, k, cur, V.r, m, st);
+            HIPCHK(launch_bdiag<T>(BD_RESID, dinv, V.r, V.c, nullptr, oth, nullptr, om, L.n_units, L.nb, m, st));
+            VBuf<T>& Vn = vb(k + 1);
+            started = k + 1 < N && tpre > 0 && restrict_start<T>(L.RD, C.lv[k + 1], oth, Vn.u, Vn.c, m, st);
+            if (!started) mat_spmv<T>(AX, L.RD, oth, nullptr, Vn.b, m, st);
+            continue;
+        }
         if (tpre == 0) {
             HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * L.n * m, st));
             mat_sweep<T>(SWEEP0, L, nullptr, bk, V.c, T(1), m, nullptr, st);
@@ -1068,7 +1143,14 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
         cur = dst;
         for (int t = 0; t < tpost; ++t) {
             dst = (k == 0 && t == tpost - 1) ? z0 : other(cur);
-            mat_spmv<T>(S_SWEEP, L.S, cur, V.c, dst, m, st, om);
+            if (L.matfree) {
+                V.cur = cur;
+                matfree_apply<T>(C, VB, k, cur, V.r, m, st);
+                HIPCHK(launch_bdiag<T>(BD_SWEEP, dinv_nat_of<T>(L), V.r, V.c, cur, dst, nullptr, om, L.n_units, L.nb,
+                                       m, st));
+            } else {
+                mat_spmv<T>(S_SWEEP, L.S, cur, V.c, dst, m, st, om);
+            }
             cur = dst;
         }
         V.cur = cur;
@@ -2039,6 +2121,7 @@ static void autotune_impl(Ctx& C, int m, bool lanes, hipStream_t st) {
             int kin, kout;
         } ops[3] = {{&L.S, &L.A, k, k}, {&L.T, nullptr, k + 1, k}, {&L.RD, &L.R, k, k + 1}};
         for (Op& o : ops) {
+            if (o.M == &L.S && L.matfree) continue;  // no S_k on a matrix-free level
             MatStore& M = *o.M;
             // S_k is timed in its block-Jacobi sweep (2 nu - 1 of them per level
             // and cycle), T_k and R_k D in their products
@@ -2126,6 +2209,9 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
                          op == AMGDG_OP_PROLONG || op == AMGDG_OP_SWEEP_SCALED);
     const bool uses_x = (op != AMGDG_OP_SWEEP0);
     if ((uses_b && !b) || (uses_x && !x)) throw Error(AMGDG_EINVAL, "missing input array");
+    if (L.matfree && (op == AMGDG_OP_SPMV || op == AMGDG_OP_RESIDUAL || op == AMGDG_OP_SWEEP ||
+                      op == AMGDG_OP_SWEEP0 || op == AMGDG_OP_SWEEP_SCALED))
+        throw Error(AMGDG_EUNSUPPORTED, "A_k is not stored on a matrix-free level");
     const bool fine_out = (op != AMGDG_OP_RESTRICT && op != AMGDG_OP_RESTRICT_SCALED);
     const bool fine_x = (op != AMGDG_OP_PROLONG);
     T* out = (perm && fine_out) ? V.u : y;
@@ -2213,6 +2299,7 @@ static int export_impl(Ctx& C, int k, int what, void* buf, int64_t bytes, hipStr
         const std::vector<int32_t>& rp = coarsest ? C.plan.AN_rp : C.plan.lv[k].A_rp;
         const std::vector<int32_t>& ci = coarsest ? C.plan.AN_ci : C.plan.lv[k].A_ci;
         const int64_t per = int64_t(L.nb) * L.nb;
+        if (what == AMGDG_A_VALS && !L.A_nat) throw Error(AMGDG_EUNSUPPORTED, "A_k is not stored on a matrix-free level");
         std::vector<double> v = download(L.A_nat, int64_t(ci.size()) * per, st);
         std::vector<int32_t> orp, oci;
         std::vector<double> ov;
@@ -2463,6 +2550,7 @@ void amgdg_default_params(amgdg_params* p) {
     p->b1_seed = 2;
     p->delta = 1e-3;
     p->hstar_smooth = 0;
+    p->matfree_levels = 0;
 }
 
 const char* amgdg_last_error(void) { return g_last_error.c_str(); }
@@ -2566,6 +2654,10 @@ int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out) {
     out->r = (k < C.N) ? L.r : 0;
     for (size_t i = 0; i < L.sweeps.size() && i < 64; ++i) out->sweeps[i] = L.sweeps[i];
     out->n_dofs = L.n_real;
+    out->matfree = L.matfree ? 1 : 0;
+    int64_t tot = 0;
+    for (size_t i = 0; i < C.mem.sizes.size(); ++i) tot += int64_t(C.mem.sizes[i]);
+    out->bytes_handle = tot;
     out->bytes_A = L.A.n_vals * 8;
     out->bytes_Dinv = (k < C.N) ? L.n_units * L.nb * L.nb * 8 : 0;
     out->bytes_T = L.T.n_vals * 8;

@@ -124,6 +124,15 @@ template <typename T>
 hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                        hipStream_t st, int u = 0, T* y2 = nullptr);
 
+// Block-Jacobi steps on a level applied matrix-free (q = A_k u from a chain of
+// products), D^{-1} natural (n_units x nb x nb), m columns row-major:
+//   BD_SWEEP y = x + omega (c - D^{-1} q), BD_RESID y = c - D^{-1} q,
+//   BD_START y = omega D^{-1} q and y2 = D^{-1} q (q = b, from zero).
+enum BdiagMode : int { BD_SWEEP = 0, BD_RESID = 1, BD_START = 2 };
+template <typename T>
+hipError_t launch_bdiag(int mode, const T* dinv, const T* q, const T* c, const T* x, T* y, T* y2, T omega,
+                        int64_t n_units, int nb, int m, hipStream_t st);
+
 // ---- setup ----
 // Fill the sliced values of type T from natural FP64 blocks: for slot q (one
 // block slot of one block row), its source block src[q] (-1: zero padding),

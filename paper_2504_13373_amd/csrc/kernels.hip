@@ -1817,6 +1817,55 @@ hipError_t launch_pad_diag(double* Av, const int32_t* diag_pos, int64_t n_brow, 
     return hipGetLastError();
 }
 
+// ============================================================ block-diagonal updates
+// The block-Jacobi steps of a level whose operator is applied matrix-free
+// (q = A_k u formed by another chain of products): one thread per (row, column)
+//   BD_SWEEP  y = x + omega (c - D^{-1} q)   (c = D^{-1} b)
+//   BD_RESID  y = c - D^{-1} q               (the residual D^{-1} (b - A u))
+//   BD_START  y = omega D^{-1} q, y2 = D^{-1} q   (the first sweep, q = b)
+// with D^{-1} natural (n_units x nb x nb); FP32 operands accumulate in FP32.
+template <typename T, int MODE>
+__global__ __launch_bounds__(WG) void k_bdiag(const T* __restrict__ dinv, const T* __restrict__ q,
+                                              const T* __restrict__ c, const T* __restrict__ x, T* __restrict__ y,
+                                              T* __restrict__ y2, T omega, int64_t n_units, int nb, int m) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = n_units * nb;
+    if (tid >= n * m) return;
+    const int64_t row = tid / m;
+    const int col = int(tid - row * m);
+    const int64_t u = row / nb;
+    const int i = int(row - u * nb);
+    const T* __restrict__ Dr = dinv + (u * nb + i) * nb;
+    const T* __restrict__ qu = q + u * nb * m + col;
+    T acc = T(0);
+    for (int j = 0; j < nb; ++j) acc += Dr[j] * qu[int64_t(j) * m];
+    if (MODE == BD_SWEEP) y[tid] = x[tid] + omega * (c[tid] - acc);
+    else if (MODE == BD_RESID) y[tid] = c[tid] - acc;
+    else {
+        y[tid] = omega * acc;
+        y2[tid] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_bdiag(int mode, const T* dinv, const T* q, const T* c, const T* x, T* y, T* y2, T omega,
+                        int64_t n_units, int nb, int m, hipStream_t st) {
+    const int64_t tot = n_units * nb * m;
+    if (tot == 0) return hipSuccess;
+    const dim3 g(grid_for(tot)), b(WG);
+    switch (mode) {
+        case BD_SWEEP: hipLaunchKernelGGL((k_bdiag<T, BD_SWEEP>), g, b, 0, st, dinv, q, c, x, y, y2, omega, n_units, nb, m); break;
+        case BD_RESID: hipLaunchKernelGGL((k_bdiag<T, BD_RESID>), g, b, 0, st, dinv, q, c, x, y, y2, omega, n_units, nb, m); break;
+        case BD_START: hipLaunchKernelGGL((k_bdiag<T, BD_START>), g, b, 0, st, dinv, q, c, x, y, y2, omega, n_units, nb, m); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_bdiag<double>(int, const double*, const double*, const double*, const double*, double*,
+                                         double*, double, int64_t, int, int, hipStream_t);
+template hipError_t launch_bdiag<float>(int, const float*, const float*, const float*, const float*, float*, float*,
+                                        float, int64_t, int, int, hipStream_t);
+
 // ============================================================ coarsest level
 __global__ void k_dense_from_bsr(const double* __restrict__ vals, const int32_t* __restrict__ rp,
                                  const int32_t* __restrict__ ci, int64_t n_brow, int nb, double* __restrict__ dense) {
