@@ -63,7 +63,7 @@ def sliced_kernels_sha256():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2504_13373_amd", "csrc", "kernels.hip")).read()
     a = src.index("// ============================================================ BSR kernels")
-    b = src.index("template <typename T, int M>\nstatic hipError_t sweep_m")
+    b = src.index("template <typename T, int M, bool CHUNKED = false>\nstatic hipError_t sweep_m")
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
@@ -122,6 +122,13 @@ def main():
     ap.add_argument("--hex-m", type=int, nargs="*", default=[3, 4, 5], help="hex: refinement levels M")
     ap.add_argument("--hex-r", type=int, nargs="*", default=[8, 16], help="hex: candidate counts r")
     ap.add_argument("--hex-flux", nargs="*", default=["ip", "ldg"], help="hex: fluxes (ip, ldg)")
+    ap.add_argument("--hex-p", type=int, nargs="*", default=[1], help="hex: polynomial degrees (Q_p)")
+    ap.add_argument("--hex-hstar", action="store_true", help="hex: also the h*-hierarchy for p >= 2")
+    ap.add_argument("--hex-matfree", type=int, nargs="*", default=[0],
+                    help="hex: matrix-free levels kappa (levels 1..kappa keep no A_k)")
+    ap.add_argument("--oversample", action="store_true",
+                    help="poisson2d: also the paper's oversampled setup (r = the median dofs of a level-1 "
+                         "aggregate, s_J per aggregate, levels until the coarsest holds at most 2,048 dofs)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (no amgdg_autotune before timing)")
     ap.add_argument("--tune-lanes", action="store_true",
@@ -266,6 +273,8 @@ def main():
     if args.serve > 0:
         serving = serve_bench(am, h, w.A.n, dev, args.serve, args.serve_width, args.serve_rate, maxit)
 
+    oversampled = bench_oversampled(args, am, torch, dev, w, maxit) if args.oversample else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, res["fp64"]["its"])
@@ -349,9 +358,93 @@ def main():
         "setup_s": setup_s,
         "autotune": tuning,
         "serving": serving,
+        "oversampled": oversampled,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def oversampled_levels(agg, nb, n_cut, r, max_coarse=2048):
+    """Level count and dof counts of the oversampled hierarchy: eq:sik's
+    h-step s_J = min(ceil(|A_J| / n_cut), |A_J|, r) per aggregate, levels added
+    until the coarsest holds at most max_coarse dofs (agg: element -> level-k
+    aggregate maps of the deepest partition)."""
+    sizes = np.full(agg.shape[1], nb, dtype=np.int64)
+    prev = np.arange(agg.shape[1])
+    dofs = [int(sizes.sum())]
+    for k in range(agg.shape[0]):
+        unit_of_elem = prev
+        cur = agg[k]
+        n_agg = int(cur.max()) + 1
+        # unit -> aggregate, then |A_J| = sum of its units' sizes
+        u2a = np.zeros(len(sizes), dtype=np.int64)
+        u2a[unit_of_elem] = cur
+        rows = np.bincount(u2a, weights=sizes, minlength=n_agg).astype(np.int64)
+        sizes = np.minimum(np.minimum(np.ceil(rows / n_cut).astype(np.int64), rows), r)
+        dofs.append(int(sizes.sum()))
+        prev = cur
+        if dofs[-1] <= max_coarse:
+            return k + 2, dofs
+    return agg.shape[0] + 1, dofs
+
+
+def bench_oversampled(args, am, torch, dev, w, maxit):
+    """The headline workload with the paper's own coarse spaces (Section 4.2):
+    r = the median dofs of a level-1 aggregate, s_J per aggregate (eq:sik,
+    n_cut = 3), as many levels as the coarsest level needs to hold at most
+    2,048 dofs; candidates N(0,1) from seed 2.  One warm-up and args.steps
+    timed solves per path, the V-cycle in both precisions, and the same with
+    levels 1 and 2 matrix-free (Section 4.6, kappa = 2)."""
+    agg1, _ = am.amgdg_partition_rcb(w.centroids, 2, w.params.bisections)
+    r = int(np.median(np.bincount(agg1[0]) * w.A.nb))
+    D = int(np.ceil(np.log2(w.mesh.n_elem)))
+    deep, _ = am.amgdg_partition_rcb(w.centroids, D // w.params.bisections + 1, w.params.bisections)
+    n_levels, dofs = oversampled_levels(deep, w.A.nb, w.params.n_cut, r)
+    B1 = np.ascontiguousarray(np.random.default_rng(2).standard_normal((w.A.n, r)))
+    out = {"r": r, "n_levels": n_levels, "levels_dofs_planned": dofs}
+    b = torch.as_tensor(w.b).to(dev).contiguous()
+    x = torch.zeros_like(b)
+    A = w.A.to_scipy()
+    for kappa in (0, 2):
+        agg, _ = am.amgdg_partition_rcb(w.centroids, n_levels, w.params.bisections)
+        p = am.amgdg_default_params(n_levels=n_levels, r=r, t_pre=3, t_post=3, n_cut=w.params.n_cut, mixed=1,
+                                    matfree_levels=kappa)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = am.amgdg_setup(w.A.n_brow, w.A.nb, w.A.row_ptr, w.A.col_idx, w.A.vals, agg, p, B1=B1)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
+        res = {"setup_s": setup_s, "levels_dofs": [int(i.n_dofs) for i in infos],
+               "levels_nnz": [int(i.nnzb) * i.nb * i.nb for i in infos],
+               "coarse_block_sizes": [i.s for i in infos[:-1]], "hierarchy_bytes": int(infos[0].bytes_handle)}
+        log(f"oversampled r={r} kappa={kappa}: setup {setup_s:.1f} s, levels {res['levels_dofs']}, "
+            f"nnz {res['levels_nnz']}, {res['hierarchy_bytes'] / 1e9:.2f} GB")
+        paths = (("mixed", am.AMGDG_FCG, am.AMGDG_MIXED), ("fp64", am.AMGDG_PCG, am.AMGDG_FP64))
+        for name, meth, prec in (paths if kappa == 0 else paths[:1]):
+            rc, st, t = _timed_solves(am, torch, h, b, x, meth, prec, maxit, max(1, min(args.steps, 2)))
+            tr = float(np.linalg.norm(w.b - A @ x.cpu().numpy()) / np.linalg.norm(w.b))
+            res[name] = {"iterations": st.iterations[0], "seconds": t, "solves_per_s": 1.0 / t,
+                         "true_rel_residual": tr, "converged": rc == am.AMGDG_OK}
+            log(f"oversampled kappa={kappa} {name}: {st.iterations[0]} iterations, {t:.2f} s, true rel {tr:.2e}")
+        stream = torch.cuda.current_stream()
+        res["vcycle_ms"] = {}
+        for pname, prec, dt in (("fp64", am.AMGDG_FP64, torch.float64), ("fp32", am.AMGDG_MIXED, torch.float32)):
+            rr = torch.randn(w.A.n, dtype=dt, device=dev)
+            zz = torch.zeros_like(rr)
+            for _ in range(3):
+                am.amgdg_vcycle(h, rr, zz, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                am.amgdg_vcycle(h, rr, zz, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res["vcycle_ms"][pname] = e0.elapsed_time(e1) / 10
+        log(f"oversampled kappa={kappa}: V-cycle {res['vcycle_ms']['fp64']:.3f} / {res['vcycle_ms']['fp32']:.3f} ms")
+        out[f"kappa{kappa}"] = res
+        h.close()
+    return out
 
 
 def _autotune(args, am, torch, h, m):
@@ -503,58 +596,102 @@ def bench_convdiff(args, am, torch, dev):
 PAPER_HEX_ITERATIONS = {3: {"ip": 7, "ldg": 7, "ip_pcg": 6, "ldg_pcg": 6},
                         4: {"ip": 7, "ldg": 8, "ip_pcg": 6, "ldg_pcg": 7},
                         5: {"ip": 7, "ldg": 9, "ip_pcg": 6, "ldg_pcg": 7}}
+# Section 5.2 (LDG, M = 4): iterations as the solver and as the CG preconditioner,
+# h*-multigrid (an intra-element step first) and h-multigrid, per degree p
+PAPER_HEX_HP = {1: {"hstar": 8, "h": 8, "hstar_pcg": 7, "h_pcg": 6},
+                2: {"hstar": 8, "h": 9, "hstar_pcg": 6, "h_pcg": 7},
+                3: {"hstar": 10, "h": 9, "hstar_pcg": 7, "h_pcg": 7}}
 
 
 def bench_hex(args, am, torch, dev):
     """The structured Poisson problem of Section 5.1: 2^M cubes per direction of
-    [-1, 1]^3, Q1, IP (penalty M (p+1)^2 / 2) and minimal-dissipation LDG,
+    [-1, 1]^3, Q_p, IP (penalty M (p+1)^2 / 2) and minimal-dissipation LDG,
     Dirichlet on x = -1 and Neumann elsewhere, right-hand side of the paper's
-    manufactured solution; ceil(log_8 |T_h|) levels of 8-way RCB aggregates,
-    r = 8 and r = 16 (coarse blocks min(ceil(|A_J| / 6), r)), V(3,3);
-    multigrid as the solver and as the CG preconditioner, to the paper's 1e-7,
-    in FP64, and flexible CG with the FP32 V-cycle."""
+    manufactured solution; ceil(log_8 |T_h|) levels of 8-way RCB aggregates
+    (one more with an h*-step first), r candidates (coarse sizes
+    min(ceil(|A_J| / 6), |A_J|, r) per aggregate), V(3,3); multigrid as the
+    solver and as the CG preconditioner, to the paper's 1e-7, in FP64, and
+    flexible CG with the FP32 V-cycle.  Every (r, M, flux, p, h*, kappa)
+    combination asked for is one row of the table: iterations beside the
+    paper's, times, the hierarchy (dofs, nonzeros, device bytes), the V-cycle's
+    time in both precisions; kappa > 0 applies levels 1..kappa matrix-free."""
     from workloads import configs
     maxit = min(args.max_it, 2000)
     table = {}
     for r in args.hex_r:
         for M in args.hex_m:
             for flux in args.hex_flux:
-                w = configs.poisson3d_hex(M, flux=flux, r=r)
-                A = w.A.to_scipy()
-                t0 = time.perf_counter()
-                h, _ = am.setup_from_workload(w, mixed=True)
-                torch.cuda.synchronize()
-                setup_s = time.perf_counter() - t0
-                infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
-                b = torch.as_tensor(w.b).to(dev).contiguous()
-                x = torch.zeros_like(b)
-                res = {"dofs": w.A.n, "levels_n": [i.n for i in infos], "setup_s": setup_s,
-                       "levels_nnz": [int(i.nnzb) * i.nb * i.nb for i in infos]}
-                for name, meth, prec in (("solver", am.AMGDG_STATIONARY, am.AMGDG_FP64),
-                                         ("pcg", am.AMGDG_PCG, am.AMGDG_FP64),
-                                         ("fcg_mixed", am.AMGDG_FCG, am.AMGDG_MIXED)):
-                    rc, st, t = _timed_solves(am, torch, h, b, x, meth, prec, maxit, args.steps, rtol=1e-7)
-                    tr = float(np.linalg.norm(w.b - A @ x.cpu().numpy()) / np.linalg.norm(w.b))
-                    res[name] = {"iterations": st.iterations[0], "converged": rc == am.AMGDG_OK, "seconds": t,
-                                 "true_rel_residual": tr}
-                    log(f"hex M={M} {flux} r={r} {name}: rc {rc}, {st.iterations[0]} iterations, {t * 1e3:.1f} ms, "
-                        f"true rel {tr:.2e}")
-                paper = PAPER_HEX_ITERATIONS[M]
-                res["paper_iterations"] = {"solver": paper[flux], "pcg": paper[flux + "_pcg"]}
-                res["coarse_block_sizes"] = [i.s for i in infos[:-1]]
-                if M == 5 and r == 16:
-                    res["kernels"] = _level0_rates(am, torch, h, infos, dev, 3)
-                table[f"M{M}_{flux}_r{r}"] = res
-                h.close()
+                for p in args.hex_p:
+                    for hstar in ([False, True] if args.hex_hstar and p >= 2 else [False]):
+                        for kappa in args.hex_matfree:
+                            w = configs.poisson3d_hex(M, p=p, flux=flux, r=r, hstar=hstar)
+                            if kappa > w.params.n_levels - 2:
+                                continue
+                            key = f"M{M}_{flux}_r{r}" + (f"_p{p}" if p != 1 else "") + ("_hstar" if hstar else "") \
+                                + (f"_mf{kappa}" if kappa else "")
+                            table[key] = _hex_row(args, am, torch, dev, w, M, flux, r, p, hstar, kappa, maxit)
     extra = {"hex_table": table, "max_it": maxit}
     if not args.no_cpu_baseline:
         extra["cpu_baseline"] = _hex_cpu_baseline(configs, table)
     key = "M5_ip_r16" if "M5_ip_r16" in table else next(iter(table))
     top = table[key]["pcg"]
     _contract(args, 1.0 / top["seconds"], top["seconds"] * 1e3, "f64 (and f32 V-cycle + f64 Krylov)",
-              "3D Poisson on 2^M hexahedra per direction of [-1,1]^3, Q1, IP and LDG, Dirichlet x=-1, "
-              "Neumann elsewhere, paper's manufactured solution, ceil(log_8 |T_h|) levels, r=8 and 16, V(3,3), "
+              "3D Poisson on 2^M hexahedra per direction of [-1,1]^3, Q_p, IP and LDG, Dirichlet x=-1, "
+              "Neumann elsewhere, paper's manufactured solution, ceil(log_8 |T_h|) levels, V(3,3), "
               f"to 1e-7; value: FP64 multigrid-preconditioned CG, {key}", extra)
+
+
+def _hex_row(args, am, torch, dev, w, M, flux, r, p, hstar, kappa, maxit):
+    A = w.A.to_scipy()
+    t0 = time.perf_counter()
+    h, _ = am.setup_from_workload(w, mixed=True, matfree_levels=kappa)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
+    b = torch.as_tensor(w.b).to(dev).contiguous()
+    x = torch.zeros_like(b)
+    tag = f"hex M={M} {flux} p={p} r={r}{' h*' if hstar else ''}{f' kappa={kappa}' if kappa else ''}"
+    res = {"dofs": w.A.n, "p": p, "hstar": hstar, "matfree_levels": kappa, "setup_s": setup_s,
+           "levels_dofs": [int(i.n_dofs) for i in infos],
+           "levels_nnz": [int(i.nnzb) * i.nb * i.nb for i in infos],
+           "levels_stored": [not i.matfree for i in infos],
+           "coarse_block_sizes": [i.s for i in infos[:-1]],
+           "hierarchy_bytes": int(infos[0].bytes_handle)}
+    for name, meth, prec in (("solver", am.AMGDG_STATIONARY, am.AMGDG_FP64),
+                             ("pcg", am.AMGDG_PCG, am.AMGDG_FP64),
+                             ("fcg_mixed", am.AMGDG_FCG, am.AMGDG_MIXED)):
+        rc, st, t = _timed_solves(am, torch, h, b, x, meth, prec, maxit, args.steps, rtol=1e-7)
+        tr = float(np.linalg.norm(w.b - A @ x.cpu().numpy()) / np.linalg.norm(w.b))
+        res[name] = {"iterations": st.iterations[0], "converged": rc == am.AMGDG_OK, "seconds": t,
+                     "true_rel_residual": tr}
+        log(f"{tag} {name}: rc {rc}, {st.iterations[0]} iterations, {t * 1e3:.1f} ms, true rel {tr:.2e}")
+    res["vcycle_ms"] = {}
+    stream = torch.cuda.current_stream()
+    for pname, prec, dt in (("fp64", am.AMGDG_FP64, torch.float64), ("fp32", am.AMGDG_MIXED, torch.float32)):
+        rr = torch.randn(w.A.n, dtype=dt, device=dev)
+        zz = torch.zeros_like(rr)
+        for _ in range(3):
+            am.amgdg_vcycle(h, rr, zz, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            am.amgdg_vcycle(h, rr, zz, precision=prec, flags=am.AMGDG_INTERNAL_ORDER)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["vcycle_ms"][pname] = e0.elapsed_time(e1) / 20
+    log(f"{tag}: levels {res['levels_dofs']}, nnz {res['levels_nnz']}, {res['hierarchy_bytes'] / 1e6:.1f} MB, "
+        f"V-cycle {res['vcycle_ms']['fp64']:.3f} / {res['vcycle_ms']['fp32']:.3f} ms (FP64 / FP32)")
+    if p == 1 and not hstar and M in PAPER_HEX_ITERATIONS:
+        paper = PAPER_HEX_ITERATIONS[M]
+        res["paper_iterations"] = {"solver": paper[flux], "pcg": paper[flux + "_pcg"]}
+    elif M == 4 and flux == "ldg" and p in PAPER_HEX_HP:
+        pp = PAPER_HEX_HP[p]
+        k = "hstar" if hstar else "h"
+        res["paper_iterations"] = {"solver": pp[k], "pcg": pp[k + "_pcg"]}
+    if M == 5 and r == 16 and p == 1 and not kappa:
+        res["kernels"] = _level0_rates(am, torch, h, infos, dev, 3)
+    h.close()
+    return res
 
 
 def _hex_cpu_baseline(configs, table, M=4, flux="ldg", r=16):

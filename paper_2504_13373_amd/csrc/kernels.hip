@@ -53,7 +53,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // this lane's row; the x blocks of the slice are first staged in LDS (xs, one
 // row of tpad * M values per block row of the slice) by the br lanes of the
 // block row, lane i taking the block columns i, i + br, ...
-template <typename T, int M>
+// CHUNKED (one column): rows too long for their x blocks to be staged in LDS
+// at once (coarse operators whose rows span much of the level) stage them
+// ROW_CHUNK values at a time; the products run in the same order, so the
+// result is the same as with one staging.
+constexpr int ROW_CHUNK = 512;
+
+template <typename T, int M, bool CHUNKED = false>
 __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, int lc, int g, int i,
                                          const T* __restrict__ x, int ld, T* xs, T (&r)[M], T sign) {
     constexpr int VW = 16 / int(sizeof(T));
@@ -63,8 +69,35 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     const int Tn = K * bc;
     const int TQ = (Tn + VW - 1) / VW;
     const int32_t* __restrict__ cp = A.cols + A.coff[slice] + g;
-    T* xr = xs + g * TP * M;
     const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + lc;
+    if (CHUNKED) {
+        static_assert(!CHUNKED || M == 1, "the chunked form takes one column");
+        T* xr = xs + g * ROW_CHUNK;
+        for (int c0 = 0; c0 < TQ * VW; c0 += ROW_CHUNK) {
+            const int cn = min(ROW_CHUNK, TQ * VW - c0);
+            if (lane < L)
+                for (int t = c0 + i; t < c0 + cn; t += A.br) {
+                    T v = T(0);
+                    if (t < Tn) {
+                        const int kk = t / bc;
+                        v = x[(int64_t(cp[kk * G]) * bc + (t - kk * bc)) * ld];
+                    }
+                    xr[t - c0] = v;
+                }
+            wave_lds_sync();
+            const int q1 = (c0 + cn) / VW;
+#pragma unroll 4
+            for (int q = c0 / VW; q < q1; ++q) {
+                T a[VW];
+                *reinterpret_cast<V*>(a) = vp[q * L];
+#pragma unroll
+                for (int u = 0; u < VW; ++u) r[0] += sign * a[u] * xr[q * VW + u - c0];
+            }
+            wave_lds_sync();
+        }
+        return;
+    }
+    T* xr = xs + g * TP * M;
     // the first PRE value vectors do not depend on the staging: load them first
     // (one or two columns only, to keep the register count down)
     constexpr int PRE = M <= 2 ? 4 : 0;
@@ -118,7 +151,7 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     }
 }
 
-template <typename T, int M, int MODE, bool ROWS>
+template <typename T, int M, int MODE, bool ROWS, bool CHUNKED = false>
 __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ y, T omega,
                                                const int32_t* __restrict__ colmask, int ld, T* __restrict__ y2) {
@@ -137,8 +170,9 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
     const int64_t brow = ROWS ? int64_t(A.rows[int64_t(slice) * G + g]) : int64_t(slice) * G + g;
     const bool own = lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
-    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (A.tpad + BP) * M;
-    T* rs = xs + G * A.tpad * M;
+    const int TPS = CHUNKED ? ROW_CHUNK : A.tpad;  // staged x per block row
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (TPS + BP) * M;
+    T* rs = xs + G * TPS * M;
 
     // the first DPRE vectors of this lane's D^{-1} row do not depend on the
     // residual: load them first (one or two columns only)
@@ -155,7 +189,7 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
 #pragma unroll
         for (int c = 0; c < M; ++c) r[c] = b[row * ld + c];
     }
-    if (HAS_A) sell_row<T, M>(A, slice, lane, lc, g, i, x, ld, xs, r, T(-1));
+    if (HAS_A) sell_row<T, M, CHUNKED>(A, slice, lane, lc, g, i, x, ld, xs, r, T(-1));
     // residual of the block row through LDS, then row i of D^{-1}
     T* rr = rs + g * BP * M;
     if (lane < L) {
@@ -202,7 +236,7 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
     }
 }
 
-template <typename T, int M, int MODE, bool ROWS>
+template <typename T, int M, int MODE, bool ROWS, bool CHUNKED = false>
 __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
                                               T* __restrict__ y, int ldx, int ldy, T omega, T* __restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -219,7 +253,7 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
                                  : ROWS ? int64_t(A.rows[int64_t(slice) * G + g]) : int64_t(slice) * G + g;
     const bool own = live && lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
-    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * A.tpad * M;
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (CHUNKED ? ROW_CHUNK : A.tpad) * M;
     // the epilogue's own-row operands are loaded first, so their latency
     // overlaps the row's product instead of following it
     constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP);
@@ -235,7 +269,7 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
     T acc[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = T(0);
-    if (live) sell_row<T, M>(A, slice, lane, lc, g, i, x, ldx, xs, acc, T(1));
+    if (live) sell_row<T, M, CHUNKED>(A, slice, lane, lc, g, i, x, ldx, xs, acc, T(1));
     if (MODE == AX_DOT) {
         // the workgroup's partial of x . y per column: lanes of each wave by an
         // xor tree, then the four waves in order
@@ -264,16 +298,16 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
 }
 
 // the row-mapped instance only for slices whose rows were reordered
-#define SELL_LAUNCH(KERNEL, MD, ...)                                                              \
-    if (A.rows) hipLaunchKernelGGL((KERNEL<T, M, MD, true>), grid, block, lds, st, __VA_ARGS__);   \
-    else hipLaunchKernelGGL((KERNEL<T, M, MD, false>), grid, block, lds, st, __VA_ARGS__)
+#define SELL_LAUNCH(KERNEL, MD, ...)                                                                   \
+    if (A.rows) hipLaunchKernelGGL((KERNEL<T, M, MD, true, CHUNKED>), grid, block, lds, st, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KERNEL<T, M, MD, false, CHUNKED>), grid, block, lds, st, __VA_ARGS__)
 
-template <typename T, int M>
+template <typename T, int M, bool CHUNKED = false>
 static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
                           const int32_t* mask, int ld, hipStream_t st, T* y2) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
-    const size_t lds = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * M * sizeof(T);
+    const size_t lds = size_t(WAVES_PER_WG) * A.G * ((CHUNKED ? ROW_CHUNK : A.tpad) + A.brpad) * M * sizeof(T);
     switch (mode) {
         case SWEEP: SELL_LAUNCH(k_sweep, SWEEP, A, dinv, x, b, y, omega, mask, ld, y2); break;
         case SWEEP0: SELL_LAUNCH(k_sweep, SWEEP0, A, dinv, x, b, y, omega, mask, ld, y2); break;
@@ -284,12 +318,12 @@ static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x,
     return hipGetLastError();
 }
 
-template <typename T, int M>
+template <typename T, int M, bool CHUNKED = false>
 static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int ldx, int ldy,
                          hipStream_t st, T omega, T* part = nullptr) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
-    const size_t lds = size_t(WAVES_PER_WG) * A.G * A.tpad * M * sizeof(T);
+    const size_t lds = size_t(WAVES_PER_WG) * A.G * (CHUNKED ? ROW_CHUNK : A.tpad) * M * sizeof(T);
     switch (mode) {
         case AX: SELL_LAUNCH(k_spmv, AX, A, x, b, y, ldx, ldy, omega, part); break;
         case B_MINUS: SELL_LAUNCH(k_spmv, B_MINUS, A, x, b, y, ldx, ldy, omega, part); break;
@@ -335,10 +369,16 @@ static int sell_chunk(int rem, const Sell<T>& A, bool with_dinv, int want) {
     return w <= cap ? w : (cap >= 4 ? 4 : cap >= 2 ? 2 : 1);
 }
 
+// LDS budget of a staged launch per workgroup (several workgroups stay resident per CU)
+constexpr size_t STAGE_LDS = 65536;
+
 int sell_rows_per_wave(int br, int bc, int max_row_blocks) {
     const size_t need = size_t((int64_t(max_row_blocks) * bc + 1) / 2 * 2 + (br + 1) / 2 * 2) * sizeof(double);
     int G = 64 / br;
-    while (G > 1 && size_t(WAVES_PER_WG) * G * need > 65536) --G;
+    while (G > 1 && size_t(WAVES_PER_WG) * G * need > STAGE_LDS) --G;
+    // rows too long for one staging even at one block row per wavefront run
+    // the chunked staging, whose LDS does not grow with the row: all lanes busy
+    if (G == 1 && size_t(WAVES_PER_WG) * need > STAGE_LDS) G = 64 / br;
     return G;
 }
 
@@ -457,7 +497,23 @@ static hipError_t sweep_split(int mode, const Sell<T>& A, const T* dinv, const T
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                         const int32_t* colmask, hipStream_t st, int cap, T* y2) {
-    if (A.G == 1 && A.br <= 16) return sweep_split(mode, A, dinv, x, b, y, omega, m, colmask, st, y2);
+    // Launches whose staging of one column exceeds 64 KB per workgroup (coarse
+    // operators with rows across much of the level) would hold most of a CU's
+    // LDS with one workgroup; they stage x in chunks instead (one column per
+    // launch), which keeps several workgroups resident.
+    const bool fits1 = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * sizeof(T) <= STAGE_LDS;
+    if (A.G == 1 && A.br <= 16 && size_t(WAVES_PER_WG) * (A.tpad + A.brpad) * sizeof(T) <= STAGE_LDS)
+        return sweep_split(mode, A, dinv, x, b, y, omega, m, colmask, st, y2);
+    if (!fits1) {
+        // x staging of one column does not fit the budget: chunked staging, one column per launch
+        for (int c = 0; c < m; ++c) {
+            const hipError_t e = sweep_m<T, 1, true>(mode, A, dinv, x ? x + c : nullptr, b ? b + c : nullptr, y + c,
+                                                     omega, colmask ? colmask + c : nullptr, m, st,
+                                                     y2 ? y2 + c : nullptr);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, true, cap);
@@ -572,7 +628,16 @@ static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b,
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
                        T omega) {
-    if (spmv_split_ok(mode, A)) return spmv_split(mode, A, x, b, y, m, st, omega);
+    if (spmv_split_ok(mode, A) && size_t(WAVES_PER_WG) * A.tpad * sizeof(T) <= STAGE_LDS)
+        return spmv_split(mode, A, x, b, y, m, st, omega);
+    if (size_t(WAVES_PER_WG) * A.G * A.tpad * sizeof(T) > STAGE_LDS) {
+        // x staging of one column does not fit the budget: chunked staging, one column per launch
+        for (int c = 0; c < m; ++c) {
+            const hipError_t e = spmv_m<T, 1, true>(mode, A, x + c, b ? b + c : nullptr, y + c, m, m, st, omega);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     int c0 = 0;
     while (c0 < m) {
         const int w = sell_chunk<T>(m - c0, A, false, cap);
