@@ -91,9 +91,10 @@ hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y,
                        T omega = T(0));
 // Block rows per wavefront of the sliced layout: floor(64 / br), lowered until
 // one column of FP64 x staging plus D^{-1} (rows of up to max_row_blocks blocks
-// of bc columns) fits the 64 KB of LDS a workgroup may take; at least 1.  Rows
-// too long even for one block row per wavefront keep floor(64 / br): their
-// launches stage x in chunks of 512 values (one column per launch).
+// of bc columns) fits the 64 KB of LDS a workgroup may take; at least 1.  A
+// launch whose staging exceeds the device's per-workgroup LDS even at one
+// block row per wavefront stages x in chunks of 512 values (one column per
+// launch).
 int sell_rows_per_wave(int br, int bc, int max_row_blocks);
 // y = A x and xy[c] = x[:,c] . y[:,c] (FP64, sliced layout): each workgroup of
 // the product writes one partial sum per column (its four slices in order) to

@@ -55,9 +55,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // block row, lane i taking the block columns i, i + br, ...
 // CHUNKED (one column): rows too long for their x blocks to be staged in LDS
 // at once (coarse operators whose rows span much of the level) stage them
-// ROW_CHUNK values at a time; the products run in the same order, so the
-// result is the same as with one staging.
-constexpr int ROW_CHUNK = 512;
+// A.tpad values at a time (the launcher sets tpad to the chunk length, a
+// multiple of VW); the products run in the same order, so the result is the
+// same as with one staging.
 
 template <typename T, int M, bool CHUNKED = false>
 __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, int lc, int g, int i,
@@ -72,9 +72,9 @@ __device__ __forceinline__ void sell_row(const Sell<T>& A, int slice, int lane, 
     const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + lc;
     if (CHUNKED) {
         static_assert(!CHUNKED || M == 1, "the chunked form takes one column");
-        T* xr = xs + g * ROW_CHUNK;
-        for (int c0 = 0; c0 < TQ * VW; c0 += ROW_CHUNK) {
-            const int cn = min(ROW_CHUNK, TQ * VW - c0);
+        T* xr = xs + g * TP;
+        for (int c0 = 0; c0 < TQ * VW; c0 += TP) {
+            const int cn = min(TP, TQ * VW - c0);
             if (lane < L)
                 for (int t = c0 + i; t < c0 + cn; t += A.br) {
                     T v = T(0);
@@ -170,9 +170,8 @@ __global__ __launch_bounds__(WG) void k_sweep(Sell<T> A, const T* __restrict__ d
     const int64_t brow = ROWS ? int64_t(A.rows[int64_t(slice) * G + g]) : int64_t(slice) * G + g;
     const bool own = lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
-    const int TPS = CHUNKED ? ROW_CHUNK : A.tpad;  // staged x per block row
-    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (TPS + BP) * M;
-    T* rs = xs + G * TPS * M;
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (A.tpad + BP) * M;
+    T* rs = xs + G * A.tpad * M;
 
     // the first DPRE vectors of this lane's D^{-1} row do not depend on the
     // residual: load them first (one or two columns only)
@@ -253,7 +252,7 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
                                  : ROWS ? int64_t(A.rows[int64_t(slice) * G + g]) : int64_t(slice) * G + g;
     const bool own = live && lane < L && brow < A.n_brow;
     const int64_t row = brow * br + i;
-    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * (CHUNKED ? ROW_CHUNK : A.tpad) * M;
+    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * A.tpad * M;
     // the epilogue's own-row operands are loaded first, so their latency
     // overlaps the row's product instead of following it
     constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP);
@@ -307,7 +306,7 @@ static hipError_t sweep_m(int mode, const Sell<T>& A, const T* dinv, const T* x,
                           const int32_t* mask, int ld, hipStream_t st, T* y2) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
-    const size_t lds = size_t(WAVES_PER_WG) * A.G * ((CHUNKED ? ROW_CHUNK : A.tpad) + A.brpad) * M * sizeof(T);
+    const size_t lds = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * M * sizeof(T);
     switch (mode) {
         case SWEEP: SELL_LAUNCH(k_sweep, SWEEP, A, dinv, x, b, y, omega, mask, ld, y2); break;
         case SWEEP0: SELL_LAUNCH(k_sweep, SWEEP0, A, dinv, x, b, y, omega, mask, ld, y2); break;
@@ -323,7 +322,7 @@ static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* 
                          hipStream_t st, T omega, T* part = nullptr) {
     dim3 grid(grid_for(A.n_slices, WAVES_PER_WG)), block(WG);
     if (A.n_slices == 0) return hipSuccess;
-    const size_t lds = size_t(WAVES_PER_WG) * A.G * (CHUNKED ? ROW_CHUNK : A.tpad) * M * sizeof(T);
+    const size_t lds = size_t(WAVES_PER_WG) * A.G * A.tpad * M * sizeof(T);
     switch (mode) {
         case AX: SELL_LAUNCH(k_spmv, AX, A, x, b, y, ldx, ldy, omega, part); break;
         case B_MINUS: SELL_LAUNCH(k_spmv, B_MINUS, A, x, b, y, ldx, ldy, omega, part); break;
@@ -372,13 +371,23 @@ static int sell_chunk(int rem, const Sell<T>& A, bool with_dinv, int want) {
 // LDS budget of a staged launch per workgroup (several workgroups stay resident per CU)
 constexpr size_t STAGE_LDS = 65536;
 
+// The sliced matrix as a chunked launch sees it: tpad becomes the chunk of x
+// staged at a time, the longest multiple of VW for which a workgroup's staging
+// (and D^{-1} residuals, with_dinv) takes at most 64 KB.
+template <typename T>
+static Sell<T> chunked_view(const Sell<T>& A, bool with_dinv) {
+    constexpr int VW = 16 / int(sizeof(T));
+    Sell<T> c = A;
+    const int64_t per_row = int64_t(STAGE_LDS) / (int64_t(WAVES_PER_WG) * std::max(A.G, 1) * int64_t(sizeof(T)));
+    const int64_t chunk = (per_row - (with_dinv ? A.brpad : 0)) / VW * VW;
+    c.tpad = int32_t(std::max<int64_t>(VW, std::min<int64_t>(chunk, A.tpad)));
+    return c;
+}
+
 int sell_rows_per_wave(int br, int bc, int max_row_blocks) {
     const size_t need = size_t((int64_t(max_row_blocks) * bc + 1) / 2 * 2 + (br + 1) / 2 * 2) * sizeof(double);
     int G = 64 / br;
     while (G > 1 && size_t(WAVES_PER_WG) * G * need > STAGE_LDS) --G;
-    // rows too long for one staging even at one block row per wavefront run
-    // the chunked staging, whose LDS does not grow with the row: all lanes busy
-    if (G == 1 && size_t(WAVES_PER_WG) * need > STAGE_LDS) G = 64 / br;
     return G;
 }
 
@@ -497,17 +506,17 @@ static hipError_t sweep_split(int mode, const Sell<T>& A, const T* dinv, const T
 template <typename T>
 hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                         const int32_t* colmask, hipStream_t st, int cap, T* y2) {
-    // Launches whose staging of one column exceeds 64 KB per workgroup (coarse
-    // operators with rows across much of the level) would hold most of a CU's
-    // LDS with one workgroup; they stage x in chunks instead (one column per
-    // launch), which keeps several workgroups resident.
-    const bool fits1 = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * sizeof(T) <= STAGE_LDS;
-    if (A.G == 1 && A.br <= 16 && size_t(WAVES_PER_WG) * (A.tpad + A.brpad) * sizeof(T) <= STAGE_LDS)
+    // Launches whose staging of one column exceeds the LDS a workgroup may
+    // take (coarse operators with rows across most of the level) stage x in
+    // chunks instead, one column per launch.
+    const bool fits1 = size_t(WAVES_PER_WG) * A.G * (A.tpad + A.brpad) * sizeof(T) <= lds_limit();
+    if (A.G == 1 && A.br <= 16 && size_t(WAVES_PER_WG) * (A.tpad + A.brpad) * sizeof(T) <= lds_limit())
         return sweep_split(mode, A, dinv, x, b, y, omega, m, colmask, st, y2);
     if (!fits1) {
-        // x staging of one column does not fit the budget: chunked staging, one column per launch
+        // x staging of one column does not fit: chunked staging, one column per launch
+        const Sell<T> Ac = chunked_view(A, true);
         for (int c = 0; c < m; ++c) {
-            const hipError_t e = sweep_m<T, 1, true>(mode, A, dinv, x ? x + c : nullptr, b ? b + c : nullptr, y + c,
+            const hipError_t e = sweep_m<T, 1, true>(mode, Ac, dinv, x ? x + c : nullptr, b ? b + c : nullptr, y + c,
                                                      omega, colmask ? colmask + c : nullptr, m, st,
                                                      y2 ? y2 + c : nullptr);
             if (e != hipSuccess) return e;
@@ -628,12 +637,13 @@ static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b,
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
                        T omega) {
-    if (spmv_split_ok(mode, A) && size_t(WAVES_PER_WG) * A.tpad * sizeof(T) <= STAGE_LDS)
+    if (spmv_split_ok(mode, A) && size_t(WAVES_PER_WG) * A.tpad * sizeof(T) <= lds_limit())
         return spmv_split(mode, A, x, b, y, m, st, omega);
-    if (size_t(WAVES_PER_WG) * A.G * A.tpad * sizeof(T) > STAGE_LDS) {
-        // x staging of one column does not fit the budget: chunked staging, one column per launch
+    if (size_t(WAVES_PER_WG) * A.G * A.tpad * sizeof(T) > lds_limit()) {
+        // x staging of one column does not fit: chunked staging, one column per launch
+        const Sell<T> Ac = chunked_view(A, false);
         for (int c = 0; c < m; ++c) {
-            const hipError_t e = spmv_m<T, 1, true>(mode, A, x + c, b ? b + c : nullptr, y + c, m, m, st, omega);
+            const hipError_t e = spmv_m<T, 1, true>(mode, Ac, x + c, b ? b + c : nullptr, y + c, m, m, st, omega);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

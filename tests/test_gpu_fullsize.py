@@ -249,3 +249,74 @@ def test_fullsize_hex_m5_ldg_r16():
         print(f"[gpu-fullsize] hex M=5: pCG {st.iterations[0]} iterations (oracle {ito})", flush=True)
     finally:
         h.close()
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_oversampled_long_rows():
+    """The headline mesh (Delaunay of 256^2 jittered points, SIPG p=3,
+    1,300,500 dofs) with the paper's oversampled coarse spaces: r = 40, s_J
+    per aggregate, 7 levels.  Levels 3 and 4 (26- and 35-dof units, rows across
+    much of the level) are too long for one x staging in FP64 and run the
+    chunked form.  The products with A_k, the sweeps with D^{-1} and on
+    S = D^{-1} A_k, and the residual are checked on 300 sampled block rows
+    against the exported operators, in both precisions, and a column of a
+    3-column launch equals the same column alone."""
+    print("[gpu-fullsize] building the oversampled 2D hierarchy", flush=True)
+    w = configs.poisson2d_delaunay(side=256, p=3, n_levels=7, r=40)
+    h, _ = am.setup_from_workload(w, mixed=True)
+    try:
+        g = np.random.default_rng(31)
+        for k in (3, 4):
+            info = am.amgdg_level_info_get(h, k)
+            n, nb = info.n, info.nb
+            rp = am.amgdg_export_level(h, k, am.AMGDG_A_ROWPTR)
+            ci = am.amgdg_export_level(h, k, am.AMGDG_A_COLIDX)
+            Av = am.amgdg_export_level(h, k, am.AMGDG_A_VALS)
+            Dinv = am.amgdg_export_level(h, k, am.AMGDG_DINV)
+            rows = np.sort(g.choice(info.n_units, size=min(300, info.n_units), replace=False))
+            print(f"[gpu-fullsize] oversampled level {k}: {info.n_units} units of {nb}, "
+                  f"{int(np.diff(rp).max())} blocks in the longest row", flush=True)
+            for prec, dt in ((am.AMGDG_FP64, torch.float64), (am.AMGDG_MIXED, torch.float32)):
+                x = g.standard_normal((n, 3))
+                b = g.standard_normal((n, 3))
+                if prec == am.AMGDG_MIXED:
+                    x, b = x.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+                A32 = Av.astype(np.float32).astype(np.float64) if prec == am.AMGDG_MIXED else Av
+                D32 = Dinv.astype(np.float32).astype(np.float64) if prec == am.AMGDG_MIXED else Dinv
+                om = info.omega if prec == am.AMGDG_FP64 else float(np.float32(info.omega))
+                X = x.reshape(info.n_units, nb, 3)
+                B = b.reshape(info.n_units, nb, 3)
+                want, scale = {}, {}
+                ax = np.stack([np.einsum("kij,kjc->ic", A32[rp[e]:rp[e + 1]], X[ci[rp[e]:rp[e + 1]]]) for e in rows])
+                aax = np.stack([np.einsum("kij,kjc->ic", np.abs(A32[rp[e]:rp[e + 1]]), np.abs(X[ci[rp[e]:rp[e + 1]]]))
+                                for e in rows])
+                # S = D^{-1} A formed in FP64 (then rounded for FP32), as the library forms it
+                S = {e: np.einsum("ij,kjl->kil", Dinv[e], Av[rp[e]:rp[e + 1]]) for e in rows}
+                if prec == am.AMGDG_MIXED:
+                    S = {e: v.astype(np.float32).astype(np.float64) for e, v in S.items()}
+                sx = np.stack([np.einsum("kij,kjc->ic", S[e], X[ci[rp[e]:rp[e + 1]]]) for e in rows])
+                asx = np.stack([np.einsum("kij,kjc->ic", np.abs(np.einsum("ij,kjl->kil", Dinv[e], Av[rp[e]:rp[e + 1]])),
+                                          np.abs(X[ci[rp[e]:rp[e + 1]]])) for e in rows])
+                Dr, Br, Xr = D32[rows], B[rows], X[rows]
+                want["spmv"], scale["spmv"] = ax, aax
+                want["residual"], scale["residual"] = Br - ax, np.abs(Br) + aax
+                want["sweep"] = Xr + om * np.einsum("uij,ujc->uic", Dr, Br - ax)
+                scale["sweep"] = np.abs(Xr) + om * np.einsum("uij,ujc->uic", np.abs(Dr), np.abs(Br) + aax)
+                want["sweep_scaled"] = Xr + om * (Br - sx)
+                scale["sweep_scaled"] = np.abs(Xr) + om * (np.abs(Br) + asx)
+                for op in ("spmv", "residual", "sweep", "sweep_scaled"):
+                    code = getattr(am, "AMGDG_OP_" + op.upper())
+                    y3 = torch.zeros((n, 3), dtype=dt, device=DEV)
+                    am.amgdg_apply(h, k, code, to_dev(x, dt), to_dev(b, dt), y3, precision=prec)
+                    y1 = torch.zeros(n, dtype=dt, device=DEV)
+                    am.amgdg_apply(h, k, code, to_dev(x[:, 0], dt), to_dev(b[:, 0], dt), y1, precision=prec)
+                    torch.cuda.synchronize()
+                    assert torch.equal(y3[:, 0], y1), (prec, k, op)
+                    got = y3.double().cpu().numpy().reshape(info.n_units, nb, 3)[rows]
+                    err = np.abs(got - want[op]).max(axis=(0, 1)) / np.abs(scale[op]).max(axis=(0, 1))
+                    tol = 1e-13 if prec == am.AMGDG_FP64 else 64 * 2.0 ** -24 * 4
+                    assert np.all(err <= tol), (prec, k, op, err)
+                    print(f"[gpu-fullsize]   level {k} {op} {'fp64' if prec == am.AMGDG_FP64 else 'fp32'} "
+                          f"error {err.max():.2e}", flush=True)
+    finally:
+        h.close()
