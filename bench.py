@@ -120,12 +120,16 @@ def main():
                     help="Poisson arrival rate in requests/s (0: all requests arrive at once)")
     ap.add_argument("--skip-fp64", action="store_true", help="poisson3d: time the mixed path only")
     ap.add_argument("--hex-m", type=int, nargs="*", default=[3, 4, 5], help="hex: refinement levels M")
-    ap.add_argument("--hex-r", type=int, nargs="*", default=[8, 16], help="hex: candidate counts r")
+    ap.add_argument("--hex-r", type=int, nargs="*", default=[16, 64], help="hex: candidate counts r (64: the median dofs of a level-1 aggregate, the paper's own choice)")
     ap.add_argument("--hex-flux", nargs="*", default=["ip", "ldg"], help="hex: fluxes (ip, ldg)")
     ap.add_argument("--hex-p", type=int, nargs="*", default=[1], help="hex: polynomial degrees (Q_p)")
     ap.add_argument("--hex-hstar", action="store_true", help="hex: also the h*-hierarchy for p >= 2")
     ap.add_argument("--hex-matfree", type=int, nargs="*", default=[0],
                     help="hex: matrix-free levels kappa (levels 1..kappa keep no A_k)")
+    ap.add_argument("--mixed-outer", choices=["fcg", "fgmres"], default="fcg",
+                    help="poisson2d: outer iteration of the mixed path: flexible CG with residual replacement, or "
+                         "restarted FGMRES from the true FP64 residual (iterative refinement)")
+    ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length")
     ap.add_argument("--oversample", action="store_true",
                     help="poisson2d: also the paper's oversampled setup (r = the median dofs of a level-1 "
                          "aggregate, s_J per aggregate, levels until the coarsest holds at most 2,048 dofs)")
@@ -177,10 +181,11 @@ def main():
 
     def solve(method, prec):
         x.zero_()
-        rc, st = am.amgdg_solve(h, b, x, method, prec, 1e-8, maxit)
+        rc, st = am.amgdg_solve(h, b, x, method, prec, 1e-8, maxit, restart=args.restart)
         return rc, st
 
-    paths = {"mixed": (am.AMGDG_FCG, am.AMGDG_MIXED), "fp64": (am.AMGDG_PCG, am.AMGDG_FP64)}
+    mixed_outer = am.AMGDG_FGMRES if args.mixed_outer == "fgmres" else am.AMGDG_FCG
+    paths = {"mixed": (mixed_outer, am.AMGDG_MIXED), "fp64": (am.AMGDG_PCG, am.AMGDG_FP64)}
     res = {}
     A = w.A.to_scipy()
     bh = w.b.reshape(w.A.n, m) if m > 1 else w.b[:, None]
@@ -300,7 +305,8 @@ def main():
                         f"({w.mesh.n_elem} triangles, {w.A.n} dofs), 5-level RCB hierarchy, r=3, V(3,3), "
                         f"tol 1e-8, {m} RHS per solve",
             "rhs_per_solve": m,
-            "outer": "flexible CG (mixed) / CG (fp64)",
+            "outer": ("flexible CG" if args.mixed_outer == "fcg" else f"FGMRES({args.restart}) iterative refinement")
+                     + " (mixed) / CG (fp64)",
         },
         "roofline": {
             "bound": "hbm",
