@@ -317,7 +317,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": k["gbps"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_spmv<double, 1, 3, false>"),
+            "traffic": measured_traffic("k_spmv<double, 1, 3, false, false>"),
             "traffic_kind": "L2-miss bytes (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size); the "
                             "memory-side cache or HBM serves them",
             "bytes_per_launch": k["bytes"],
