@@ -40,10 +40,16 @@ def level_bytes(info, w, m, nu):
     """Algorithmic bytes of one V(nu,nu) visit of a non-coarsest level: one pass
     over D_k^{-1} (the first sweep, which also forms c = D^{-1} b), 2nu passes over
     S_k = D_k^{-1} A_k (2nu - 1 sweeps and the residual), one over T_k and R_k D_k,
-    and (6nu+6) passes over level-k vectors."""
+    and (6nu+6) passes over level-k vectors.  A level that restricts through
+    M_k = R_k (D_k - omega A_k) has no residual pass: 2nu - 1 passes over S_k, one
+    over T_k and M_k, and (6nu+4) vector passes (the last pre-sweep writes its
+    residual, which M_k reads)."""
     S = info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
     D = info.n_units * info.nb * info.nb * w
     TR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_units + 1)
+    if getattr(info, "restrict_resid", 0):
+        MM = info.nnzb_M * info.nb * info.s * w + 4 * info.nnzb_M + 4 * (info.n_agg + 1)
+        return (2 * nu - 1) * S + D + (6 * nu + 4) * info.n * m * w + TR + MM
     RR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_agg + 1)
     return 2 * nu * S + D + (6 * nu + 6) * info.n * m * w + TR + RR
 

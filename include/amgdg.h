@@ -74,6 +74,13 @@ typedef struct {
                               no A_k after the setup; the V-cycle applies A_k as
                               R_{k-1} A_{k-1} T_{k-1} (eq:matfree1, eq:matfree2), down to A_0.
                               Single steps that need A_k are then EUNSUPPORTED on those levels */
+    int32_t  restrict_resid; /* 1 (default): on levels where it holds no more values than the
+                              residual pass over D_k^{-1} A_k and R_k D_k it replaces (plus 2^21),
+                              keep M_k = R_k (D_k - omega_k A_k); the V-cycle's last pre-sweep then
+                              also writes the residual it starts from, e, and the coarse right-hand
+                              side is M_k e = R_k (b_k - A_k u) (Algorithm 2, reassociated: one
+                              product over D_k^{-1} A_k fewer per level and cycle).  0: residual,
+                              then R_k D_k.  Needs t_pre >= 1; not on matrix-free levels */
 } amgdg_params;
 
 /* Fills the paper's defaults: gamma 0.03 (Section 4.2), q 3 (Section 4.4),
@@ -130,6 +137,11 @@ void amgdg_plan_destroy(amgdg_plan p);
                                  the rank bound min(|A_J|, r)) */
 #define AMGDG_UNIT_DOFS  18   /* int32[n_units]: dofs of each unit of level k (s_J on coarse levels;
                                  a unit's vector rows beyond them are zero padding) */
+#define AMGDG_M_ROWPTR   19   /* int32[n_agg + 1]: pattern of M_k = R_k (D_k - omega_k A_k), that of
+                                 R_k A_k (block (I,c) iff R_k(I,e) and A_k(e,c) for some e) */
+#define AMGDG_M_COLIDX   20   /* int32[nnzb_M] (level-k units) */
+#define AMGDG_M_VALS     21   /* double[nnzb_M * s * nb]; level export only, EUNSUPPORTED on a level
+                                 that keeps no M_k (amgdg_level_info.restrict_resid = 0) */
 
 /* Number of elements of `what` (in its own type) at level k. */
 int amgdg_plan_size(amgdg_plan p, int32_t k, int32_t what, int64_t* count);
@@ -186,6 +198,9 @@ typedef struct {
                             every unit holds nb) */
     int32_t matfree;     /* 1: A_k is applied matrix-free (not stored) */
     int64_t bytes_handle;/* device bytes held by the whole hierarchy (every level) */
+    int64_t nnzb_M;      /* blocks of the pattern of M_k = R_k (D_k - omega_k A_k) */
+    int32_t restrict_resid; /* 1: the V-cycle restricts through M_k (amgdg_params.restrict_resid) */
+    int64_t bytes_M;     /* FP64 bytes of M_k (0 when not kept) */
 } amgdg_level_info;
 int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out);
 int amgdg_num_levels(amgdg_handle h);
@@ -281,6 +296,12 @@ int amgdg_vcycle_static(amgdg_handle h, int32_t m, const void* r_dev, void* z_de
  * on the row-scaled operators; b here is the scaled right-hand side D^{-1} b_k): */
 #define AMGDG_OP_SWEEP_SCALED    7  /* y = x + omega (b - D^{-1} A_k x)               */
 #define AMGDG_OP_RESTRICT_SCALED 8  /* y = R_k D x  (x: n_k, y: n_{k+1})              */
+/* The forms of the restricted residual (amgdg_params.restrict_resid): */
+#define AMGDG_OP_RESTRICT_RESID  9  /* y = R_k (D - omega A_k) x (x: n_k, y: n_{k+1});
+                                       EUNSUPPORTED on a level that keeps no M_k  */
+#define AMGDG_OP_SWEEP_SCALED_RESID 10 /* y[0 : n_k m] = x + omega (b - D^{-1} A_k x) and
+                                       y[n_k m : 2 n_k m] = b - D^{-1} A_k x: y holds
+                                       2 n_k m values                            */
 int amgdg_apply(amgdg_handle h, int32_t k, int32_t op, int32_t m, int32_t precision, const void* x,
                 const void* b, void* y, int32_t flags, void* stream);
 
@@ -341,7 +362,7 @@ int amgdg_server_destroy(amgdg_server s);
  *   - columns per launch of the sliced and block-CSR kernels (1, 2, 4, 8, 16);
  *   - operand blocks loaded ahead in the 16-column MFMA tiles (1, 2, 4);
  *   - with AMGDG_TUNE_LANES, the lanes per block row of every block-CSR
- *     operator (4..64, timed at one column).
+ *     operator (4..64, 128, 256; timed at one column).
  * The first two never change a result.  The lane-group width changes the
  * summation order, hence rounding, of the block-CSR products: it can be tuned
  * once per handle (AMGDG_EINVAL on a second attempt), before use, and then
@@ -349,11 +370,15 @@ int amgdg_server_destroy(amgdg_server s);
  * handle's captured V-cycles; not to be called while a server uses the
  * handle.  Untuned shapes: 4 (FP64) / 8 (FP32) columns per sliced launch, 16
  * per block-CSR launch, 4 MFMA blocks ahead, and lanes per block row the power
- * of two >= the mean blocks per row (4..64). */
+ * of two >= the mean blocks per row (4..64), or, for rows of 96 or more
+ * entries, lanes over the row's entries: a wavefront per block row (128), or a
+ * workgroup of four (256) for rows of 128 or more entries on operators of
+ * fewer than 4,096 block rows. */
 #define AMGDG_TUNE_LANES 1
 int amgdg_autotune(amgdg_handle h, int32_t m, int32_t flags, void* stream);
 /* The shapes in use on level k (0..levels-2) for m columns, out[16]:
- * [0..3) lanes per block row of A_k, T_k, R_k (0: sliced layout); D^{-1} A_k
+ * [0..3) lanes per block row of A_k, T_k, R_k (0: sliced layout; 128 and 256:
+ * a wavefront or a workgroup per block row, lanes over its entries); D^{-1} A_k
  * and R_k D, the operators the V-cycle runs, share the shapes of A_k and R_k;
  * [3..6) FP64 and [6..9) FP32 columns per launch (0: default rule);
  * [9..12) FP64 and [12..15) FP32 MFMA blocks loaded ahead (0: default 4);

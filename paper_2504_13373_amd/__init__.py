@@ -24,13 +24,15 @@ AMGDG_PERM, AMGDG_T_ROWPTR, AMGDG_T_COLIDX, AMGDG_A_ROWPTR, AMGDG_A_COLIDX = 1, 
 AMGDG_R_ROWPTR, AMGDG_R_COLIDX = 6, 7
 AMGDG_A_VALS, AMGDG_T_VALS, AMGDG_R_VALS, AMGDG_DINV = 10, 11, 12, 13
 AMGDG_B_RELAXED, AMGDG_B_INPUT, AMGDG_PTILDE, AMGDG_SVALS, AMGDG_UNIT_DOFS = 14, 15, 16, 17, 18
+AMGDG_M_ROWPTR, AMGDG_M_COLIDX, AMGDG_M_VALS = 19, 20, 21
 # precision, methods, flags, ops
 AMGDG_FP64, AMGDG_MIXED = 0, 1
 AMGDG_STATIONARY, AMGDG_PCG, AMGDG_FCG, AMGDG_FGMRES = 0, 1, 2, 3
 AMGDG_X0, AMGDG_INTERNAL_ORDER, AMGDG_EAGER = 1, 2, 4
 AMGDG_TUNE_LANES = 1
 (AMGDG_OP_SPMV, AMGDG_OP_SWEEP, AMGDG_OP_SWEEP0, AMGDG_OP_RESIDUAL, AMGDG_OP_RESTRICT,
- AMGDG_OP_PROLONG, AMGDG_OP_COARSE, AMGDG_OP_SWEEP_SCALED, AMGDG_OP_RESTRICT_SCALED) = range(9)
+ AMGDG_OP_PROLONG, AMGDG_OP_COARSE, AMGDG_OP_SWEEP_SCALED, AMGDG_OP_RESTRICT_SCALED,
+ AMGDG_OP_RESTRICT_RESID, AMGDG_OP_SWEEP_SCALED_RESID) = range(11)
 
 
 class amgdg_params(ctypes.Structure):
@@ -39,7 +41,7 @@ class amgdg_params(ctypes.Structure):
                 ("omega_fixed", ctypes.c_double), ("gamma", ctypes.c_double), ("n_cut", ctypes.c_double),
                 ("b_update", ctypes.c_int32), ("mixed", ctypes.c_int32), ("pow_seed", ctypes.c_uint64),
                 ("b1_seed", ctypes.c_uint64), ("delta", ctypes.c_double), ("hstar_smooth", ctypes.c_int32),
-                ("matfree_levels", ctypes.c_int32)]
+                ("matfree_levels", ctypes.c_int32), ("restrict_resid", ctypes.c_int32)]
 
 
 class amgdg_level_info(ctypes.Structure):
@@ -48,7 +50,8 @@ class amgdg_level_info(ctypes.Structure):
                 ("n_agg", ctypes.c_int64), ("omega", ctypes.c_double), ("rho", ctypes.c_double),
                 ("r", ctypes.c_int32), ("sweeps", ctypes.c_int32 * 64), ("bytes_A", ctypes.c_int64),
                 ("bytes_Dinv", ctypes.c_int64), ("bytes_T", ctypes.c_int64), ("bytes_R", ctypes.c_int64),
-                ("n_dofs", ctypes.c_int64), ("matfree", ctypes.c_int32), ("bytes_handle", ctypes.c_int64)]
+                ("n_dofs", ctypes.c_int64), ("matfree", ctypes.c_int32), ("bytes_handle", ctypes.c_int64),
+                ("nnzb_M", ctypes.c_int64), ("restrict_resid", ctypes.c_int32), ("bytes_M", ctypes.c_int64)]
 
 
 class amgdg_solve_stats(ctypes.Structure):
@@ -272,6 +275,8 @@ def _export_shape(info, what, n_elem):
         AMGDG_B_RELAXED: ((info.n, r), np.float64), AMGDG_B_INPUT: ((info.n, r), np.float64),
         AMGDG_PTILDE: ((info.n, s), np.float64), AMGDG_SVALS: ((info.n_agg, r), np.float64),
         AMGDG_UNIT_DOFS: (info.n_units, np.int32),
+        AMGDG_M_ROWPTR: (info.n_agg + 1, np.int32), AMGDG_M_COLIDX: (info.nnzb_M, np.int32),
+        AMGDG_M_VALS: ((info.nnzb_M, s, nb), np.float64),
     }[what]
 
 

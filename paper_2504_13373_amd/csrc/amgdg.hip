@@ -151,6 +151,15 @@ struct Level {
     // and RD = R D (R's pattern), so that R (b - A u) = RD (D^{-1} b - S u)
     MatStore S, RD;
     double *S_nat = nullptr, *RD_nat = nullptr;
+    // M = R (D - omega A) (R A's pattern): the restriction of the residual after
+    // a sweep from the residual before it, R D (c - S u') = M (c - S u) for
+    // u' = u + omega (c - S u), so that the last pre-sweep's own residual
+    // replaces a residual pass over S.  Kept where it holds no more values
+    // than the S and RD reads it replaces (plus a launch's worth).
+    MatStore M;
+    double* M_nat = nullptr;
+    int64_t nM = 0;
+    bool has_M = false;
     double *B_in = nullptr, *B_rel = nullptr, *Pu = nullptr, *sv = nullptr, *T_nat = nullptr, *R_nat = nullptr;
 };
 
@@ -408,6 +417,10 @@ static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const
         const double avg = n_brow > 0 ? double(nnzb) / double(n_brow) : 1.0;
         int P = 4;
         while (P < avg && P < 64) P *= 2;
+        // rows of many entries: lanes over the entries, a wavefront per block
+        // row, or a workgroup where that leaves fewer than 16 wavefronts per CU
+        const double entries = avg * bc;
+        if (entries >= 96) P = (entries >= 128 && n_brow < 4096) ? 256 : 128;
         Bcsr<double> d;
         d.n_brow = int32_t(n_brow);
         d.br = br;
@@ -513,15 +526,20 @@ static int mfu_of(const MatStore& M, int m) {
     return m / MFMA_COLS <= 4 ? (sizeof(T) == 8 ? M.mfu64[m / MFMA_COLS] : M.mfu32[m / MFMA_COLS]) : 0;
 }
 
-// omega is read by S_SWEEP only
+// omega is read by S_SWEEP and S_SWEEP_R only; y2 (S_SWEEP_R only) receives b - A x
 template <typename T>
 static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, int m, hipStream_t st,
-                     T omega = T(0)) {
-    if (M.vec && !use_mfma<T>(M, m)) HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m), omega));
+                     T omega = T(0), T* y2 = nullptr) {
+    if (M.vec && !use_mfma<T>(M, m))
+        HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m), omega, nullptr, y2));
     else if (use_mfma<T>(M, m))
-        HIPCHK(launch_mfma<T>(mode == AX ? MF_AX : mode == B_MINUS ? MF_BMINUS : mode == B_PLUS ? MF_BPLUS : MF_SSWEEP,
-                              nsel<T>(M), nullptr, x, b, y, omega, m, st, mfu_of<T>(M, m)));
-    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st, cap_of<T>(M, m), omega));
+        HIPCHK(launch_mfma<T>(mode == AX        ? MF_AX
+                              : mode == B_MINUS ? MF_BMINUS
+                              : mode == B_PLUS  ? MF_BPLUS
+                              : mode == S_SWEEP_R ? MF_SSWEEP_R
+                                                    : MF_SSWEEP,
+                              nsel<T>(M), nullptr, x, b, y, omega, m, st, mfu_of<T>(M, m), y2));
+    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st, cap_of<T>(M, m), omega, y2));
 }
 
 // y2 (SWEEP0 only, may be null) receives D^{-1} b
@@ -874,6 +892,25 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
             HIPCHK(hipStreamSynchronize(st));
         }
         build_mat(C, L.RD, P.n_agg, s, L.nb, P.R_rp, P.R_ci, L.RD_nat, C.mixed, st);
+        // M = R (D - omega A), where it reads no more values than the residual
+        // pass over S and the RD product it replaces (plus 2^21, about a
+        // launch's latency at full bandwidth)
+        L.nM = int64_t(P.M_ci.size());
+        if (p.restrict_resid && p.t_pre >= 1 && !L.matfree &&
+            L.nM * s * L.nb <= L.nnzb * L.nb * L.nb + L.nT * s * L.nb + (int64_t(1) << 21)) {
+            DevMem t1;
+            int32_t* rci = upload(t1, P.R_ci, st);
+            int32_t* mci = upload(t1, P.M_ci, st);
+            int64_t* mpp = upload(t1, P.M_pp, st);
+            int32_t* mpr = upload(t1, P.M_pr, st);
+            int32_t* mpa = upload(t1, P.M_pa, st);
+            L.M_nat = C.mem.alloc<double>(L.nM * s * L.nb);
+            HIPCHK(launch_restrict_resid(L.R_nat, L.A_nat, rci, mci, mpp, mpr, mpa, L.nM, L.nb, s, L.omega, L.M_nat,
+                                         st));
+            HIPCHK(hipStreamSynchronize(st));
+            build_mat(C, L.M, P.n_agg, s, L.nb, P.M_rp, P.M_ci, L.M_nat, C.mixed, st);
+            L.has_M = true;
+        }
         // A_{k+1} = R (A T)
         Level& Ln = C.lv[k + 1];
         {
@@ -1105,27 +1142,40 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
             if (!started) mat_spmv<T>(AX, L.RD, oth, nullptr, Vn.b, m, st);
             continue;
         }
+        // With M = R (D - omega A) the last pre-sweep also writes the residual
+        // e = c - S u of the iterate it starts from, and R (b - A u') = M e for
+        // the iterate u' it writes; after a single sweep from zero e is c.
+        const bool via_M = L.has_M && tpre >= 1;
+        const T* e = V.c;
         if (tpre == 0) {
             HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * L.n * m, st));
             mat_sweep<T>(SWEEP0, L, nullptr, bk, V.c, T(1), m, nullptr, st);
         } else {
             if (!started) mat_sweep<T>(SWEEP0, L, nullptr, bk, cur, om, m, nullptr, st, V.c);
             for (int t = 1; t < tpre; ++t) {
-                mat_spmv<T>(S_SWEEP, L.S, cur, V.c, oth, m, st, om);
+                if (via_M && t == tpre - 1) {
+                    mat_spmv<T>(S_SWEEP_R, L.S, cur, V.c, oth, m, st, om, V.r);
+                    e = V.r;
+                } else {
+                    mat_spmv<T>(S_SWEEP, L.S, cur, V.c, oth, m, st, om);
+                }
                 std::swap(cur, oth);
             }
         }
         V.cur = cur;
-        // R (b - A u) = RD (c - S u)
-        mat_spmv<T>(B_MINUS, L.S, cur, V.c, V.r, m, st);
+        // R (b - A u) = RD (c - S u), or M e
+        const MatStore& Rk = via_M ? L.M : L.RD;
+        if (!via_M) {
+            mat_spmv<T>(B_MINUS, L.S, cur, V.c, V.r, m, st);
+            e = V.r;
+        }
         // Into a non-coarsest level the restriction also takes that level's first
         // sweep: it writes omega D^{-1} b_{k+1} and c_{k+1} = D^{-1} b_{k+1} (the
         // same operations as the first sweep on the stored b_{k+1}); b_{k+1}
         // itself is not needed then.
         VBuf<T>& Vn = vb(k + 1);
-        started = k + 1 < N && tpre > 0 &&
-                  restrict_start<T>(L.RD, C.lv[k + 1], V.r, Vn.u, Vn.c, m, st);
-        if (!started) mat_spmv<T>(AX, L.RD, V.r, nullptr, Vn.b, m, st);
+        started = k + 1 < N && tpre > 0 && restrict_start<T>(Rk, C.lv[k + 1], e, Vn.u, Vn.c, m, st);
+        if (!started) mat_spmv<T>(AX, Rk, e, nullptr, Vn.b, m, st);
     }
     {
         VBuf<T>& V = vb(N);
@@ -2119,9 +2169,10 @@ static void autotune_impl(Ctx& C, int m, bool lanes, hipStream_t st) {
             MatStore* M;
             MatStore* twin;
             int kin, kout;
-        } ops[3] = {{&L.S, &L.A, k, k}, {&L.T, nullptr, k + 1, k}, {&L.RD, &L.R, k, k + 1}};
+        } ops[4] = {{&L.S, &L.A, k, k}, {&L.T, nullptr, k + 1, k}, {&L.RD, &L.R, k, k + 1}, {&L.M, nullptr, k, k + 1}};
         for (Op& o : ops) {
             if (o.M == &L.S && L.matfree) continue;  // no S_k on a matrix-free level
+            if (o.M == &L.M && !L.has_M) continue;
             MatStore& M = *o.M;
             // S_k is timed in its block-Jacobi sweep (2 nu - 1 of them per level
             // and cycle), T_k and R_k D in their products
@@ -2161,7 +2212,7 @@ static void autotune_impl(Ctx& C, int m, bool lanes, hipStream_t st) {
             if (lanes && M.vec) {
                 int best = 0;
                 float bt = 0.f;
-                for (int P : {4, 8, 16, 32, 64}) {
+                for (int P : {4, 8, 16, 32, 64, 128, 256}) {
                     M.bd.P = M.bf.P = P;
                     const float t = C.mixed ? timed([&] { run(0.0f, 1); }) : timed([&] { run(0.0, 1); });
                     if (best == 0 || t < bt) best = P, bt = t;
@@ -2206,13 +2257,15 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
     // gathered into internal order; the coarse x of PROLONG and the coarse y of
     // RESTRICT are not level-0 arrays and are used as they are.
     const bool uses_b = (op == AMGDG_OP_SWEEP || op == AMGDG_OP_SWEEP0 || op == AMGDG_OP_RESIDUAL ||
-                         op == AMGDG_OP_PROLONG || op == AMGDG_OP_SWEEP_SCALED);
+                         op == AMGDG_OP_PROLONG || op == AMGDG_OP_SWEEP_SCALED ||
+                         op == AMGDG_OP_SWEEP_SCALED_RESID);
     const bool uses_x = (op != AMGDG_OP_SWEEP0);
     if ((uses_b && !b) || (uses_x && !x)) throw Error(AMGDG_EINVAL, "missing input array");
     if (L.matfree && (op == AMGDG_OP_SPMV || op == AMGDG_OP_RESIDUAL || op == AMGDG_OP_SWEEP ||
-                      op == AMGDG_OP_SWEEP0 || op == AMGDG_OP_SWEEP_SCALED))
+                      op == AMGDG_OP_SWEEP0 || op == AMGDG_OP_SWEEP_SCALED || op == AMGDG_OP_SWEEP_SCALED_RESID))
         throw Error(AMGDG_EUNSUPPORTED, "A_k is not stored on a matrix-free level");
-    const bool fine_out = (op != AMGDG_OP_RESTRICT && op != AMGDG_OP_RESTRICT_SCALED);
+    if (op == AMGDG_OP_RESTRICT_RESID && !L.has_M) throw Error(AMGDG_EUNSUPPORTED, "this level keeps no M_k");
+    const bool fine_out = (op != AMGDG_OP_RESTRICT && op != AMGDG_OP_RESTRICT_SCALED && op != AMGDG_OP_RESTRICT_RESID);
     const bool fine_x = (op != AMGDG_OP_PROLONG);
     T* out = (perm && fine_out) ? V.u : y;
     const T* xi = !uses_x ? nullptr : (fine_x ? in(x, V.b) : x);
@@ -2227,6 +2280,14 @@ static int apply_impl(Ctx& C, int k, int op, int m, const T* x, const T* b, T* y
         case AMGDG_OP_COARSE: coarse_solve<T>(C, xi, out, m, st); break;
         case AMGDG_OP_SWEEP_SCALED: mat_spmv<T>(S_SWEEP, L.S, xi, bi, out, m, st, T(L.omega)); break;
         case AMGDG_OP_RESTRICT_SCALED: mat_spmv<T>(AX, L.RD, xi, nullptr, out, m, st); break;
+        case AMGDG_OP_RESTRICT_RESID: mat_spmv<T>(AX, L.M, xi, nullptr, out, m, st); break;
+        case AMGDG_OP_SWEEP_SCALED_RESID: {
+            // the residual half goes through V.w (internal order) when level-0 rows are permuted
+            T* out2 = perm ? V.w : y + L.n * m;
+            mat_spmv<T>(S_SWEEP_R, L.S, xi, bi, out, m, st, T(L.omega), out2);
+            if (perm) HIPCHK((launch_permute<T, T>(out2, y + L.n * m, C.perm_d, nun, L.nb, m, 0, st)));
+            break;
+        }
         default: throw Error(AMGDG_EINVAL, "bad op");
     }
     if (perm && fine_out) HIPCHK((launch_permute<T, T>(out, y, C.perm_d, nun, L.nb, m, 0, st)));
@@ -2361,6 +2422,20 @@ static int export_impl(Ctx& C, int k, int what, void* buf, int64_t bytes, hipStr
             copy_out(v, buf, bytes);
             return AMGDG_OK;
         }
+        case AMGDG_M_ROWPTR:
+        case AMGDG_M_COLIDX:
+        case AMGDG_M_VALS: {
+            if (what == AMGDG_M_VALS && !L.has_M) throw Error(AMGDG_EUNSUPPORTED, "this level keeps no M_k");
+            std::vector<double> v = L.has_M ? download(L.M_nat, L.nM * nb * s, st)
+                                            : std::vector<double>(size_t(L.nM * nb * s), 0.0);
+            std::vector<int32_t> orp, oci;
+            std::vector<double> ov;
+            export_matrix(C, k, P.M_rp, P.M_ci, v, int64_t(nb) * s, false, true, orp, oci, ov);
+            if (what == AMGDG_M_ROWPTR) copy_out(orp, buf, bytes);
+            else if (what == AMGDG_M_COLIDX) copy_out(oci, buf, bytes);
+            else copy_out(ov, buf, bytes);
+            return AMGDG_OK;
+        }
 
         default: throw Error(AMGDG_EINVAL, "unknown export item");
     }
@@ -2404,10 +2479,14 @@ static void plan_item(const Plan& P, int k, int what, std::vector<int32_t>& out3
         rows_caller(P.lv[k].T_rp, P.lv[k].T_ci, true, false, orp, oci);
     } else if (what == AMGDG_R_ROWPTR || what == AMGDG_R_COLIDX) {
         rows_caller(P.lv[k].R_rp, P.lv[k].R_ci, false, true, orp, oci);
+    } else if (what == AMGDG_M_ROWPTR || what == AMGDG_M_COLIDX) {
+        rows_caller(P.lv[k].M_rp, P.lv[k].M_ci, false, true, orp, oci);
     } else {
         throw Error(AMGDG_EINVAL, "unknown plan item");
     }
-    out32 = (what == AMGDG_A_ROWPTR || what == AMGDG_T_ROWPTR || what == AMGDG_R_ROWPTR) ? orp : oci;
+    out32 = (what == AMGDG_A_ROWPTR || what == AMGDG_T_ROWPTR || what == AMGDG_R_ROWPTR || what == AMGDG_M_ROWPTR)
+                ? orp
+                : oci;
 }
 
 // ------------------------------------------------------------ allocation-free V-cycle
@@ -2551,6 +2630,7 @@ void amgdg_default_params(amgdg_params* p) {
     p->delta = 1e-3;
     p->hstar_smooth = 0;
     p->matfree_levels = 0;
+    p->restrict_resid = 1;
 }
 
 const char* amgdg_last_error(void) { return g_last_error.c_str(); }
@@ -2662,6 +2742,9 @@ int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out) {
     out->bytes_Dinv = (k < C.N) ? L.n_units * L.nb * L.nb * 8 : 0;
     out->bytes_T = L.T.n_vals * 8;
     out->bytes_R = L.R.n_vals * 8;
+    out->nnzb_M = (k < C.N) ? L.nM : 0;
+    out->restrict_resid = L.has_M ? 1 : 0;
+    out->bytes_M = L.has_M ? L.M.n_vals * 8 : 0;
     return AMGDG_OK;
     ABI_END
 }

@@ -169,6 +169,36 @@ static void symbolic_C(LevelPattern& L) {
     }
 }
 
+// M = R (D - omega A): row I, block c = sum over e with R(I,e), A(e,c).
+static void symbolic_M(LevelPattern& L) {
+    L.M_rp.assign(L.n_agg + 1, 0);
+    L.M_pp.assign(1, 0);
+    L.M_ci.clear();
+    L.M_pr.clear();
+    L.M_pa.clear();
+    std::vector<std::array<int32_t, 3>> ent;  // (c, r, a)
+    for (int64_t I = 0; I < L.n_agg; ++I) {
+        ent.clear();
+        for (int32_t rr = L.R_rp[I]; rr < L.R_rp[I + 1]; ++rr) {
+            const int32_t e = L.R_ci[rr];
+            for (int32_t a = L.A_rp[e]; a < L.A_rp[e + 1]; ++a) ent.push_back({L.A_ci[a], rr, a});
+        }
+        std::sort(ent.begin(), ent.end());
+        for (size_t i = 0; i < ent.size();) {
+            size_t j = i;
+            L.M_ci.push_back(ent[i][0]);
+            for (; j < ent.size() && ent[j][0] == ent[i][0]; ++j) {
+                L.M_pr.push_back(ent[j][1]);
+                L.M_pa.push_back(ent[j][2]);
+            }
+            L.M_pp.push_back(int64_t(L.M_pr.size()));
+            i = j;
+        }
+        if (L.M_ci.size() >= (size_t(1) << 31)) fail("plan: M_k exceeds int32 indexing");
+        L.M_rp[I + 1] = int32_t(L.M_ci.size());
+    }
+}
+
 static void diag_positions(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
                            std::vector<int32_t>& diag, const char* what) {
     int64_t n = int64_t(rp.size()) - 1;
@@ -277,6 +307,7 @@ void build_plan(Plan& P, int64_t n_elem, const int32_t* row_ptr, const int32_t* 
         symbolic_R(L);
         symbolic_AT(L);
         symbolic_C(L);
+        symbolic_M(L);
         rp = L.C_rp;
         ci = L.C_ci;
     }

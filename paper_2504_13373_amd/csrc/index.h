@@ -38,6 +38,15 @@ struct LevelPattern {
     std::vector<int32_t> C_rp, C_ci;
     std::vector<int64_t> C_pp;
     std::vector<int32_t> C_pt, C_pu;
+
+    // M_k = R_k (D_k - omega A_k): block (I, c) = sum over pairs (r, a) of
+    // R_r * A_a, r = (I, e) a block of R and a = (e, c) a block of A_k; A_k's
+    // diagonal blocks enter with weight 1 - omega, the others with -omega.
+    // It restricts the residual after a block-Jacobi sweep from the residual
+    // before it: R D (c - S u') = M (c - S u) for u' = u + omega (c - S u).
+    std::vector<int32_t> M_rp, M_ci;
+    std::vector<int64_t> M_pp;
+    std::vector<int32_t> M_pr, M_pa;
 };
 
 struct Plan {

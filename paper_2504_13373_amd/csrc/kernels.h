@@ -39,6 +39,10 @@ struct Sell {
 // products are summed across the group with xor-shuffles.
 template <typename T>
 struct Bcsr {
+    // P: 4..64 lanes per block row, each lane taking whole blocks; 128 one
+    // wavefront per block row and 256 one workgroup (four wavefronts) per block
+    // row, whose lanes take the row's entries (block, column) in order: for rows
+    // of many blocks, so that neighbouring lanes read neighbouring values
     int32_t n_brow = 0, br = 0, bc = 0, P = 0;
     const int32_t* rp = nullptr;
     const int32_t* ci = nullptr;
@@ -75,6 +79,7 @@ enum SpmvMode : int {
     AX_DOT = 4,  // y = A x, and one partial of x . y per workgroup and column (launch_spmv_dot)
     AX_DSCALE = 5, // y = omega D'^{-1} (A x), y2 = D'^{-1} (A x), D'^{-1} the br x br blocks of the
                    // output rows (block CSR only): a restriction that starts the coarse smoothing
+    S_SWEEP_R = 6, // S_SWEEP that also writes y2 = b - A x, the residual of the iterate it starts from
 };
 
 // D^{-1} in sliced layout: the br x br block of block row g is stored like a
@@ -88,7 +93,7 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
                         int m, const int32_t* colmask, hipStream_t st, int cap = 0, T* y2 = nullptr);
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap = 0,
-                       T omega = T(0));
+                       T omega = T(0), T* y2 = nullptr);  // y2: S_SWEEP_R only (required there)
 // Block rows per wavefront of the sliced layout: floor(64 / br), lowered until
 // one column of FP64 x staging plus D^{-1} (rows of up to max_row_blocks blocks
 // of bc columns) fits the 64 KB of LDS a workgroup may take; at least 1.  A
@@ -118,9 +123,12 @@ hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y
 //   MF_AX y = A x, MF_BMINUS y = b - A x, MF_BPLUS y = b + A x,
 //   MF_SWEEP y = x + omega D^{-1} (b - A x), MF_SWEEP0 y = omega D^{-1} b (and
 //   y2 = D^{-1} b when y2 is not null), MF_SSWEEP y = x + omega (b - A x),
-//   MF_RDINV y = omega D^{-1} (A x), y2 = D^{-1} (A x)
+//   MF_RDINV y = omega D^{-1} (A x), y2 = D^{-1} (A x),
+//   MF_SSWEEP_R y = x + omega (b - A x) and y2 = b - A x
 // with D^{-1} natural (n_brow x br x br, row-major), applied by MFMA too.
-enum MfmaMode : int { MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4, MF_SSWEEP = 5, MF_RDINV = 6 };
+enum MfmaMode : int {
+    MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4, MF_SSWEEP = 5, MF_RDINV = 6, MF_SSWEEP_R = 7
+};
 // u: blocks whose operand fragments are loaded before their products (1, 2 or 4;
 // 0: 4); it does not change the arithmetic.
 template <typename T>
@@ -184,6 +192,12 @@ hipError_t launch_AT(const double* Avals, const double* Tvals, const int64_t* pp
                      const int32_t* pt, int64_t nAT, int nb, int s, double* ATvals, hipStream_t st);
 hipError_t launch_galerkin(const double* Tvals, const double* ATvals, const int64_t* pp, const int32_t* pt,
                            const int32_t* pu, int64_t nC, int nb, int s, double* Cvals, hipStream_t st);
+// M = R (D - omega A), block v (s x nb) = sum over pairs q in [pp[v], pp[v+1]) of
+// w_q R_{pr[q]} A_{pa[q]}, w_q = 1 - omega when the A block is diagonal (the R
+// block's column R_ci[pr[q]] equals M_ci[v]), else -omega
+hipError_t launch_restrict_resid(const double* Rvals, const double* Avals, const int32_t* R_ci, const int32_t* M_ci,
+                                 const int64_t* pp, const int32_t* pr, const int32_t* pa, int64_t nM, int nb, int s,
+                                 double omega, double* Mvals, hipStream_t st);
 hipError_t launch_dense_from_bsr(const double* vals, const int32_t* rp, const int32_t* ci, int64_t n_brow, int nb,
                                  int64_t nnzb, double* dense, hipStream_t st);
 // in-place inverse of a dense row-major n x n matrix (Gauss-Jordan, row pivoting);

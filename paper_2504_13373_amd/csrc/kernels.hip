@@ -255,8 +255,8 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
     T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * G * A.tpad * M;
     // the epilogue's own-row operands are loaded first, so their latency
     // overlaps the row's product instead of following it
-    constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP);
-    constexpr bool PX = (MODE == S_SWEEP || MODE == AX_DOT);
+    constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP || MODE == S_SWEEP_R);
+    constexpr bool PX = (MODE == S_SWEEP || MODE == S_SWEEP_R || MODE == AX_DOT);
     T bo[PB ? M : 1], xo[PX ? M : 1];
     if (PB || PX) {
 #pragma unroll
@@ -292,6 +292,11 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
         if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
         else if (MODE == B_PLUS) v = bo[PB ? c : 0] + v;
         else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
+        else if (MODE == S_SWEEP_R) {
+            const T e = bo[PB ? c : 0] - v;
+            part[row * ldy + c] = e;  // y2: the residual the sweep starts from
+            v = xo[PX ? c : 0] + omega * e;
+        }
         y[row * ldy + c] = v;
     }
 }
@@ -328,6 +333,7 @@ static hipError_t spmv_m(int mode, const Sell<T>& A, const T* x, const T* b, T* 
         case B_MINUS: SELL_LAUNCH(k_spmv, B_MINUS, A, x, b, y, ldx, ldy, omega, part); break;
         case B_PLUS: SELL_LAUNCH(k_spmv, B_PLUS, A, x, b, y, ldx, ldy, omega, part); break;
         case S_SWEEP: SELL_LAUNCH(k_spmv, S_SWEEP, A, x, b, y, ldx, ldy, omega, part); break;
+        case S_SWEEP_R: SELL_LAUNCH(k_spmv, S_SWEEP_R, A, x, b, y, ldx, ldy, omega, part); break;
         case AX_DOT: SELL_LAUNCH(k_spmv, AX_DOT, A, x, b, y, ldx, ldy, omega, part); break;
         default: return hipErrorInvalidValue;
     }
@@ -555,7 +561,8 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
 // column's rounding does not depend on the width.
 template <typename T, int MODE, bool ROWS>
 __global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
-                                                    T* __restrict__ y, int ldx, int ldy, T omega) {
+                                                    T* __restrict__ y, int ldx, int ldy, T omega,
+                                                    T* __restrict__ y2) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int VW = 16 / int(sizeof(T));
     using V = typename Vec16<T>::type;
@@ -598,17 +605,23 @@ __global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restric
     if (MODE == B_MINUS) val = b[row * ldy] - acc;
     else if (MODE == B_PLUS) val = b[row * ldy] + acc;
     else if (MODE == S_SWEEP) val = x[row * ldx] + omega * (b[row * ldy] - acc);
+    else if (MODE == S_SWEEP_R) {
+        const T e = b[row * ldy] - acc;
+        y2[row * ldy] = e;
+        val = x[row * ldx] + omega * e;
+    }
     y[row * ldy] = val;
 }
 
 template <typename T>
 static bool spmv_split_ok(int mode, const Sell<T>& A) {
-    return A.G == 1 && A.br <= 16 && (mode == AX || mode == B_MINUS || mode == B_PLUS || mode == S_SWEEP);
+    return A.G == 1 && A.br <= 16 &&
+           (mode == AX || mode == B_MINUS || mode == B_PLUS || mode == S_SWEEP || mode == S_SWEEP_R);
 }
 
 template <typename T>
 static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st,
-                             T omega) {
+                             T omega, T* y2) {
     const size_t lds = size_t(WAVES_PER_WG) * A.tpad * sizeof(T);
     if (lds > lds_limit()) return hipErrorInvalidConfiguration;
     if (A.n_slices == 0) return hipSuccess;
@@ -617,14 +630,17 @@ static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b,
         const T* xc = x + c;
         const T* bcol = b ? b + c : nullptr;
         T* yc = y + c;
-#define SPLIT_LAUNCH(MD)                                                                                       \
-    if (A.rows) hipLaunchKernelGGL((k_spmv_split<T, MD, true>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega); \
-    else hipLaunchKernelGGL((k_spmv_split<T, MD, false>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega)
+        T* y2c = y2 ? y2 + c : nullptr;
+#define SPLIT_LAUNCH(MD)                                                                                      \
+    if (A.rows)                                                                                               \
+        hipLaunchKernelGGL((k_spmv_split<T, MD, true>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega, y2c); \
+    else hipLaunchKernelGGL((k_spmv_split<T, MD, false>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega, y2c)
         switch (mode) {
             case AX: SPLIT_LAUNCH(AX); break;
             case B_MINUS: SPLIT_LAUNCH(B_MINUS); break;
             case B_PLUS: SPLIT_LAUNCH(B_PLUS); break;
             case S_SWEEP: SPLIT_LAUNCH(S_SWEEP); break;
+            case S_SWEEP_R: SPLIT_LAUNCH(S_SWEEP_R); break;
             default: return hipErrorInvalidValue;
         }
 #undef SPLIT_LAUNCH
@@ -636,14 +652,16 @@ static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b,
 
 template <typename T>
 hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
-                       T omega) {
+                       T omega, T* y2) {
+    if ((mode == S_SWEEP_R) != (y2 != nullptr)) return hipErrorInvalidValue;
     if (spmv_split_ok(mode, A) && size_t(WAVES_PER_WG) * A.tpad * sizeof(T) <= lds_limit())
-        return spmv_split(mode, A, x, b, y, m, st, omega);
+        return spmv_split(mode, A, x, b, y, m, st, omega, y2);
     if (size_t(WAVES_PER_WG) * A.G * A.tpad * sizeof(T) > lds_limit()) {
         // x staging of one column does not fit: chunked staging, one column per launch
         const Sell<T> Ac = chunked_view(A, false);
         for (int c = 0; c < m; ++c) {
-            const hipError_t e = spmv_m<T, 1, true>(mode, Ac, x + c, b ? b + c : nullptr, y + c, m, m, st, omega);
+            const hipError_t e =
+                spmv_m<T, 1, true>(mode, Ac, x + c, b ? b + c : nullptr, y + c, m, m, st, omega, y2 ? y2 + c : nullptr);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
@@ -653,13 +671,14 @@ hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y,
         const int w = sell_chunk<T>(m - c0, A, false, cap);
         if (size_t(WAVES_PER_WG) * A.G * A.tpad * w * sizeof(T) > lds_limit()) return hipErrorInvalidConfiguration;
         const T* bc = b ? b + c0 : nullptr;
+        T* y2c = y2 ? y2 + c0 : nullptr;
         hipError_t e;
         switch (w) {
-            case 8: e = spmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
-            case 4: e = spmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
-            case 3: e = spmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
-            case 2: e = spmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
-            default: e = spmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, m, st, omega); break;
+            case 8: e = spmv_m<T, 8>(mode, A, x + c0, bc, y + c0, m, m, st, omega, y2c); break;
+            case 4: e = spmv_m<T, 4>(mode, A, x + c0, bc, y + c0, m, m, st, omega, y2c); break;
+            case 3: e = spmv_m<T, 3>(mode, A, x + c0, bc, y + c0, m, m, st, omega, y2c); break;
+            case 2: e = spmv_m<T, 2>(mode, A, x + c0, bc, y + c0, m, m, st, omega, y2c); break;
+            default: e = spmv_m<T, 1>(mode, A, x + c0, bc, y + c0, m, m, st, omega, y2c); break;
         }
         if (e != hipSuccess) return e;
         c0 += w;
@@ -672,9 +691,9 @@ template hipError_t launch_sweep<double>(int, const Sell<double>&, const double*
 template hipError_t launch_sweep<float>(int, const Sell<float>&, const float*, const float*, const float*, float*,
                                         float, int, const int32_t*, hipStream_t, int, float*);
 template hipError_t launch_spmv<double>(int, const Sell<double>&, const double*, const double*, double*, int,
-                                        hipStream_t, int, double);
+                                        hipStream_t, int, double, double*);
 template hipError_t launch_spmv<float>(int, const Sell<float>&, const float*, const float*, float*, int,
-                                       hipStream_t, int, float);
+                                       hipStream_t, int, float, float*);
 
 // ============================================================ block-CSR kernels (small blocks)
 
@@ -789,8 +808,8 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
     const int64_t row = brow * BR + p;
     // the epilogue's own-row operands are loaded first, so their latency
     // overlaps the block loop instead of following the reduction
-    constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP);
-    constexpr bool PX = (MODE == S_SWEEP);
+    constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP || MODE == S_SWEEP_R);
+    constexpr bool PX = (MODE == S_SWEEP || MODE == S_SWEEP_R);
     T bo[PB ? M : 1], xo[PX ? M : 1];
     if (PB || PX) {
         const bool mine = valid && p < BR;
@@ -832,8 +851,167 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
             if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
             else if (MODE == B_PLUS) v = bo[PB ? c : 0] + v;
             else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
+            else if (MODE == S_SWEEP_R) {
+                const T e = bo[PB ? c : 0] - v;
+                y2[row * ld + c] = e;
+                v = xo[PX ? c : 0] + omega * e;
+            }
             y[row * ld + c] = v;
         }
+    }
+}
+
+// Block rows of many blocks (Bcsr::P = 128 or 256): one wavefront (128) or one
+// workgroup (256) per block row; its lanes take the row's entries e = (block q,
+// column j) in order, e = t0, t0 + stride, ..., so that neighbouring lanes read
+// neighbouring values of a block row and the x entries of one block column.
+// The lanes' partial sums are added by an xor butterfly, then over the
+// workgroup's wavefronts in order; lane p < BR of the first wavefront writes
+// row p.  The summation order depends on the row's length only.
+template <typename T, int M, int MODE, int BR>
+__global__ __launch_bounds__(WG) void k_bspmv_wide(Bcsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int ld, T omega,
+                                                    const T* __restrict__ dinv, T* __restrict__ y2) {
+    __shared__ T red[WAVES_PER_WG][BR * M];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const bool whole = A.P == 256;  // one workgroup per block row
+    const int64_t brow = whole ? int64_t(wg) : int64_t(wg) * WAVES_PER_WG + wave;
+    if (brow >= A.n_brow) return;  // the whole wavefront (P = 128) or workgroup (P = 256)
+    const int bc = A.bc;
+    const int beg = A.rp[brow], end = A.rp[brow + 1];
+    const int E = (end - beg) * bc;
+    const int stride = whole ? 64 * WAVES_PER_WG : 64;
+    const int t0 = (whole ? wave * 64 : 0) + lane;
+    // the epilogue's own-row operands first
+    constexpr bool PB = (MODE == B_MINUS || MODE == S_SWEEP || MODE == S_SWEEP_R);
+    constexpr bool PX = (MODE == S_SWEEP || MODE == S_SWEEP_R);
+    const bool writer = lane < BR && (!whole || wave == 0);
+    const int64_t row = brow * BR + lane;
+    T bo[PB ? M : 1], xo[PX ? M : 1];
+    if (PB || PX) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            if (PB) bo[c] = writer ? b[row * ld + c] : T(0);
+            if (PX) xo[c] = writer ? x[row * ld + c] : T(0);
+        }
+    }
+    T acc[BR][M];
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[i][c] = T(0);
+    int q = t0 / bc, j = t0 - (t0 / bc) * bc;
+    const int dq = stride / bc, dj = stride - (stride / bc) * bc;
+    for (int e = t0; e < E; e += stride) {
+        const int blk = beg + q;
+        const T* __restrict__ xr = x + (int64_t(A.ci[blk]) * bc + j) * ld;
+        T xv[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) xv[c] = xr[c];
+        const T* __restrict__ a = A.vals + int64_t(blk) * BR * bc + j;
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            const T av = a[i * bc];
+#pragma unroll
+            for (int c = 0; c < M; ++c) acc[i][c] += av * xv[c];
+        }
+        j += dj;
+        q += dq;
+        if (j >= bc) {
+            j -= bc;
+            ++q;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) acc[i][c] += __shfl_xor(acc[i][c], o);
+    if (whole) {
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                for (int c = 0; c < M; ++c) red[wave][i * M + c] = acc[i][c];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                acc[i][c] = (red[0][i * M + c] + red[1][i * M + c]) + (red[2][i * M + c] + red[3][i * M + c]);
+    }
+    if (!writer) return;
+    const int p = lane;
+    if (MODE == AX_DSCALE) {
+        T o[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) o[c] = T(0);
+        const T* __restrict__ dr = dinv + (brow * BR + p) * BR;
+#pragma unroll
+        for (int jj = 0; jj < BR; ++jj) {
+            const T d = dr[jj];
+#pragma unroll
+            for (int c = 0; c < M; ++c) o[c] += d * acc[jj][c];
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            y[row * ld + c] = omega * o[c];
+            y2[row * ld + c] = o[c];
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < BR; ++i) {
+        if (i != p) continue;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            T v = acc[i][c];
+            if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
+            else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
+            else if (MODE == S_SWEEP_R) {
+                const T e = bo[PB ? c : 0] - v;
+                y2[row * ld + c] = e;
+                v = xo[PX ? c : 0] + omega * e;
+            }
+            y[row * ld + c] = v;
+        }
+    }
+}
+
+static bool bspmv_wide_mode(int mode) {
+    return mode == AX || mode == B_MINUS || mode == S_SWEEP || mode == S_SWEEP_R || mode == AX_DSCALE;
+}
+
+template <typename T, int M, int BR>
+static hipError_t bspmv_wide_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st,
+                                T omega, const T* dinv, T* y2) {
+    const int64_t wgs = A.P == 256 ? int64_t(A.n_brow) : (int64_t(A.n_brow) + WAVES_PER_WG - 1) / WAVES_PER_WG;
+    if (wgs == 0) return hipSuccess;
+    const dim3 grid{unsigned(wgs), 1u, 1u}, block{unsigned(WG), 1u, 1u};
+#define WIDE_LAUNCH(MD) hipLaunchKernelGGL((k_bspmv_wide<T, M, MD, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2)
+    switch (mode) {
+        case AX: WIDE_LAUNCH(AX); break;
+        case B_MINUS: WIDE_LAUNCH(B_MINUS); break;
+        case S_SWEEP: WIDE_LAUNCH(S_SWEEP); break;
+        case S_SWEEP_R: WIDE_LAUNCH(S_SWEEP_R); break;
+        case AX_DSCALE: WIDE_LAUNCH(AX_DSCALE); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef WIDE_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+static hipError_t bspmv_wide_m(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int ld, hipStream_t st,
+                               T omega, const T* dinv, T* y2) {
+    switch (A.br) {
+        case 1: return bspmv_wide_mb<T, M, 1>(mode, A, x, b, y, ld, st, omega, dinv, y2);
+        case 2: return bspmv_wide_mb<T, M, 2>(mode, A, x, b, y, ld, st, omega, dinv, y2);
+        case 3: return bspmv_wide_mb<T, M, 3>(mode, A, x, b, y, ld, st, omega, dinv, y2);
+        case 4: return bspmv_wide_mb<T, M, 4>(mode, A, x, b, y, ld, st, omega, dinv, y2);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -864,6 +1042,7 @@ static hipError_t bspmv_mb(int mode, const Bcsr<T>& A, const T* x, const T* b, T
         case B_MINUS: hipLaunchKernelGGL((k_bspmv<T, M, B_MINUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
         case B_PLUS: hipLaunchKernelGGL((k_bspmv<T, M, B_PLUS, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
         case S_SWEEP: hipLaunchKernelGGL((k_bspmv<T, M, S_SWEEP, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
+        case S_SWEEP_R: hipLaunchKernelGGL((k_bspmv<T, M, S_SWEEP_R, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
         case AX_DSCALE: hipLaunchKernelGGL((k_bspmv<T, M, AX_DSCALE, BR>), grid, block, 0, st, A, x, b, y, ld, omega, dinv, y2); break;
         default: return hipErrorInvalidValue;
     }
@@ -906,6 +1085,12 @@ static int bcsr_chunk(int rem, int cap) {
 template <typename T>
 hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                          const int32_t* colmask, hipStream_t st, int cap, T* y2) {
+    if (A.P > 64) {
+        // the sweeps with D^{-1} take whole blocks per lane (64 lanes) on any layout
+        Bcsr<T> A64 = A;
+        A64.P = 64;
+        return launch_bsweep<T>(mode, A64, dinv, x, b, y, omega, m, colmask, st, cap, y2);
+    }
     int c0 = 0;
     while (c0 < m) {
         const int w = bcsr_chunk(m - c0, cap);
@@ -931,6 +1116,33 @@ hipError_t launch_bsweep(int mode, const Bcsr<T>& A, const T* dinv, const T* x, 
 template <typename T>
 hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st, int cap,
                         T omega, const T* dinv, T* y2) {
+    if (mode == S_SWEEP_R && !y2) return hipErrorInvalidValue;
+    if (A.P > 64 && bspmv_wide_mode(mode)) {
+        // entry-wise lanes: up to 8 columns per launch
+        int c0 = 0;
+        while (c0 < m) {
+            int w = bcsr_chunk(m - c0, cap);
+            w = w >= 8 ? 8 : w >= 4 ? 4 : w >= 2 ? 2 : 1;
+            const T* bc = b ? b + c0 : nullptr;
+            T* y2c = y2 ? y2 + c0 : nullptr;
+            hipError_t e;
+            switch (w) {
+                case 8: e = bspmv_wide_m<T, 8>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2c); break;
+                case 4: e = bspmv_wide_m<T, 4>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2c); break;
+                case 2: e = bspmv_wide_m<T, 2>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2c); break;
+                default: e = bspmv_wide_m<T, 1>(mode, A, x + c0, bc, y + c0, m, st, omega, dinv, y2c); break;
+            }
+            if (e != hipSuccess) return e;
+            c0 += w;
+        }
+        return hipSuccess;
+    }
+    if (A.P > 64) {
+        // a mode the entry-wise kernel does not take: whole blocks per lane, 64 lanes
+        Bcsr<T> A64 = A;
+        A64.P = 64;
+        return launch_bspmv<T>(mode, A64, x, b, y, m, st, cap, omega, dinv, y2);
+    }
     int c0 = 0;
     while (c0 < m) {
         const int w = bcsr_chunk(m - c0, cap);
@@ -1010,7 +1222,7 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
         const int row = Mma<T>::row(g, v);
         const int64_t e = (r0 + row) * ld + col0;
         bpre[v] = (MODE != MF_AX && MODE != MF_RDINV && row < br) ? b[e] : T(0);
-        xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP) && row < br) ? x[e] : T(0);
+        xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP || MODE == MF_SSWEEP_R) && row < br) ? x[e] : T(0);
     }
     if (SW) {
         const T* __restrict__ Db = dinv + int64_t(brow) * br * br;
@@ -1057,6 +1269,11 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
                 if (MODE == MF_BMINUS) val = bpre[v] - val;
                 if (MODE == MF_BPLUS) val = bpre[v] + val;
                 if (MODE == MF_SSWEEP) val = xpre[v] + omega * (bpre[v] - val);
+                if (MODE == MF_SSWEEP_R) {
+                    const T e = bpre[v] - val;
+                    y2[(r0 + row) * ld + col0] = e;
+                    val = xpre[v] + omega * e;
+                }
                 y[(r0 + row) * ld + col0] = val;
             }
         }
@@ -1097,6 +1314,10 @@ static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, 
         case MF_SWEEP0: hipLaunchKernelGGL((k_mfma<T, MF_SWEEP0, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
         case MF_SSWEEP: hipLaunchKernelGGL((k_mfma<T, MF_SSWEEP, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
         case MF_RDINV: hipLaunchKernelGGL((k_mfma<T, MF_RDINV, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
+        case MF_SSWEEP_R:
+            if (!y2) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_mfma<T, MF_SSWEEP_R, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1870,6 +2091,49 @@ hipError_t launch_galerkin(const double* Tv, const double* ATv, const int64_t* p
     if (s < 1) return hipErrorInvalidValue;
     if (nC == 0) return hipSuccess;
     hipLaunchKernelGGL(k_galerkin, dim3(grid_for(nC * s)), dim3(WG), 0, st, Tv, ATv, pp, pt, pu, nC, nb, s, Cv);
+    return hipGetLastError();
+}
+
+// M_v = sum over pairs q of w_q R_{pr[q]} (s x nb) * A_{pa[q]} (nb x nb); one
+// thread per row i of an M block, nb outputs in chunks of MAXB
+__global__ void k_restrict_resid(const double* __restrict__ Rv, const double* __restrict__ Av,
+                                 const int32_t* __restrict__ R_ci, const int32_t* __restrict__ M_ci,
+                                 const int64_t* __restrict__ pp, const int32_t* __restrict__ pr,
+                                 const int32_t* __restrict__ pa, int64_t nM, int nb, int s, double omega,
+                                 double* __restrict__ Mv) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= nM * s) return;
+    const int64_t v = tid / s;
+    const int i = int(tid - v * s);
+    const int32_t col = M_ci[v];
+    for (int j0 = 0; j0 < nb; j0 += MAXB) {
+        double acc[MAXB];
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) acc[j] = 0.0;
+        for (int64_t q = pp[v]; q < pp[v + 1]; ++q) {
+            const double w = (R_ci[pr[q]] == col) ? 1.0 - omega : -omega;
+            const double* Rr = Rv + int64_t(pr[q]) * s * nb + int64_t(i) * nb;
+            const double* Ab = Av + int64_t(pa[q]) * nb * nb + j0;
+            for (int l = 0; l < nb; ++l) {
+                const double rv = w * Rr[l];
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j)
+                    if (j0 + j < nb) acc[j] += rv * Ab[int64_t(l) * nb + j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j)
+            if (j0 + j < nb) Mv[(v * s + i) * nb + j0 + j] = acc[j];
+    }
+}
+
+hipError_t launch_restrict_resid(const double* Rv, const double* Av, const int32_t* R_ci, const int32_t* M_ci,
+                                 const int64_t* pp, const int32_t* pr, const int32_t* pa, int64_t nM, int nb, int s,
+                                 double omega, double* Mv, hipStream_t st) {
+    if (s < 1 || nb < 1) return hipErrorInvalidValue;
+    if (nM == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict_resid, dim3(grid_for(nM * s)), dim3(WG), 0, st, Rv, Av, R_ci, M_ci, pp, pr, pa, nM,
+                       nb, s, omega, Mv);
     return hipGetLastError();
 }
 

@@ -81,6 +81,13 @@ def test_symbolic_patterns_bit_exact_vs_oracle(maker):
         Rp.sort_indices()
         assert np.array_equal(plan.export(k, am.AMGDG_R_ROWPTR), Rp.indptr)
         assert np.array_equal(plan.export(k, am.AMGDG_R_COLIDX), Rp.indices)
+        # M = R (D - omega A): the pattern of the product R A
+        a_ptr, a_idx = (w.A.row_ptr, w.A.col_idx) if k == 0 else (pats[k - 1]["A_ptr"], pats[k - 1]["A_idx"])
+        Ap = sp.csr_matrix((np.ones(len(a_idx)), a_idx, a_ptr), shape=(nun, nun))
+        Mp = (Rp @ Ap).tocsr()
+        Mp.sort_indices()
+        assert np.array_equal(plan.export(k, am.AMGDG_M_ROWPTR), Mp.indptr)
+        assert np.array_equal(plan.export(k, am.AMGDG_M_COLIDX), Mp.indices)
     perm = plan.export(0, am.AMGDG_PERM)
     assert sorted(perm) == list(range(w.A.n_brow))
     # every aggregate is a contiguous range of the internal order

@@ -66,7 +66,8 @@ def to_dev(a, dtype=torch.float64):
 def bsr_export(h, k, which, shape):
     rp_, ci_, v_ = {"A": (am.AMGDG_A_ROWPTR, am.AMGDG_A_COLIDX, am.AMGDG_A_VALS),
                     "T": (am.AMGDG_T_ROWPTR, am.AMGDG_T_COLIDX, am.AMGDG_T_VALS),
-                    "R": (am.AMGDG_R_ROWPTR, am.AMGDG_R_COLIDX, am.AMGDG_R_VALS)}[which]
+                    "R": (am.AMGDG_R_ROWPTR, am.AMGDG_R_COLIDX, am.AMGDG_R_VALS),
+                    "M": (am.AMGDG_M_ROWPTR, am.AMGDG_M_COLIDX, am.AMGDG_M_VALS)}[which]
     rp = am.amgdg_export_level(h, k, rp_)
     ci = am.amgdg_export_level(h, k, ci_)
     v = am.amgdg_export_level(h, k, v_)
@@ -114,6 +115,14 @@ def test_setup_parity(name):
         A1, (arp, aci) = bsr_export(h, k + 1, "A", (n1, n1))
         assert np.array_equal(arp, pats[k]["A_ptr"]) and np.array_equal(aci, pats[k]["A_idx"])
         assert sp.linalg.norm(A1 - H.levels[k + 1].A) <= 1e-9 * sp.linalg.norm(H.levels[k + 1].A)
+        if info.restrict_resid:
+            # M = R (D - omega A) of the oracle's level, D the diagonal blocks of A
+            Ak = L.A.tocoo()
+            on = (Ak.row // L.nb) == (Ak.col // L.nb)
+            Dk = sp.csr_matrix((Ak.data[on], (Ak.row[on], Ak.col[on])), shape=L.A.shape)
+            Mo = (L.T.T @ (Dk - L.omega * L.A)).tocsr()
+            Mg, _ = bsr_export(h, k, "M", (n1, L.A.shape[0]))
+            assert sp.linalg.norm(Mg - Mo) <= 1e-9 * sp.linalg.norm(Mo), k
 
 
 # ------------------------------------------------------------------ single kernels
@@ -141,6 +150,7 @@ def host_op(op, k, h, w, x, b, prec):
     D64 = amg.blockdiag_csr(Dinv)
     S, RD = (D64 @ A).tocsr(), (R @ Dblk).tocsr()
     absDA, absRD = abs(D64) @ abs(A), abs(R) @ abs(Dblk)
+    R64, A64, RD64 = R, A, RD
     if prec == am.AMGDG_MIXED:
         A, T, R, S, RD = (M.astype(np.float32).astype(np.float64) for M in (A, T, R, S, RD))
         Dinv = Dinv.astype(np.float32).astype(np.float64)
@@ -163,6 +173,15 @@ def host_op(op, k, h, w, x, b, prec):
         return x + om * (b - S @ x), abs(x) + om * (abs(b) + absDA @ abs(x))
     if op == "restrict_scaled":
         return RD @ x, absRD @ abs(x)
+    if op == "restrict_resid":
+        # M = R (D - omega A), formed in FP64 (then rounded for FP32)
+        M = (RD64 - info.omega * (R64 @ A64)).tocsr()
+        if prec == am.AMGDG_MIXED:
+            M = M.astype(np.float32).astype(np.float64)
+        return M @ x, (absRD + abs(info.omega) * (abs(R64) @ abs(A64))) @ abs(x)
+    if op == "sweep_scaled_resid":
+        e = b - S @ x
+        return np.vstack([x + om * e, e]), np.vstack([abs(x) + om * (abs(b) + absDA @ abs(x)), abs(b) + absDA @ abs(x)])
 
 
 @pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
@@ -178,14 +197,15 @@ def test_single_kernels(name, prec, m):
     for k in range(N):
         info = am.amgdg_level_info_get(h, k)
         n, n1 = info.n, info.n_agg * info.s
-        for op in OPS:
+        extra = ["sweep_scaled_resid"] + (["restrict_resid"] if info.restrict_resid else [])
+        for op in OPS + extra:
             nx = n1 if op == "prolong" else n
             ny = n1 if op.startswith("restrict") else n
             x = g.standard_normal((nx, m))
             b = g.standard_normal((ny, m))
             if prec == am.AMGDG_MIXED:
                 x, b = x.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
-            y = torch.zeros((ny, m), dtype=dt, device=DEV)
+            y = torch.zeros((2 * ny if op == "sweep_scaled_resid" else ny, m), dtype=dt, device=DEV)
             am.amgdg_apply(h, k, getattr(am, "AMGDG_OP_" + op.upper()), to_dev(x, dt), to_dev(b, dt), y, precision=prec)
             torch.cuda.synchronize()
             want, scale = host_op(op, k, h, w, x, b, prec)
@@ -232,6 +252,34 @@ def test_vcycle_parity_fp64(name):
     torch.cuda.synchronize()
     zo = amg.vcycle(H, b)
     assert rel(z.cpu().numpy(), zo) <= 1e-10, rel(z.cpu().numpy(), zo)
+
+
+_PLAIN = {}
+
+
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
+def test_restricted_residual_through_M(name):
+    """The V-cycle that restricts the last pre-sweep's residual through
+    M = R (D - omega A) against the one that forms the residual and applies
+    R D: the same cycle up to rounding, in both precisions, m = 1 and 16."""
+    w, H, h = case(name)
+    if name not in _PLAIN:
+        _PLAIN[name] = am.setup_from_workload(w, mixed=True, restrict_resid=0)[0]
+    h0 = _PLAIN[name]
+    kept = [am.amgdg_level_info_get(h, k).restrict_resid for k in range(h.n_levels - 1)]
+    print(f"[restrict-resid {name}] levels keeping M: {kept}", flush=True)
+    assert all(am.amgdg_level_info_get(h0, k).restrict_resid == 0 for k in range(h0.n_levels - 1))
+    g = np.random.default_rng(21)
+    for m in (1, 16):
+        b = g.standard_normal((w.A.n, m))
+        for prec, dt, tol in ((am.AMGDG_FP64, torch.float64, 1e-12), (am.AMGDG_MIXED, torch.float32, 2e-5)):
+            z1 = torch.zeros((w.A.n, m), dtype=dt, device=DEV)
+            z0 = torch.zeros((w.A.n, m), dtype=dt, device=DEV)
+            am.amgdg_vcycle(h, to_dev(b, dt), z1, precision=prec)
+            am.amgdg_vcycle(h0, to_dev(b, dt), z0, precision=prec)
+            torch.cuda.synchronize()
+            d = rel(z1.double().cpu().numpy(), z0.double().cpu().numpy())
+            assert d <= tol, (name, m, prec, d)
 
 
 @pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
@@ -548,7 +596,7 @@ def test_autotune_shapes_keep_results_and_lanes_keep_columns_independent():
     assert t["mfma32"]["A"] in (1, 2, 4) and not t["lanes_tuned"]
     am.amgdg_autotune(h, 1, am.AMGDG_TUNE_LANES)
     t = am.amgdg_tuning_get(h, 1, 1)
-    assert t["lanes_tuned"] and t["lanes"]["A"] in (4, 8, 16, 32, 64)
+    assert t["lanes_tuned"] and t["lanes"]["A"] in (4, 8, 16, 32, 64, 128, 256)
     with pytest.raises(am.AmgdgError) as e:
         am.amgdg_autotune(h, 1, am.AMGDG_TUNE_LANES)
     assert e.value.code == am.AMGDG_EINVAL
