@@ -44,7 +44,8 @@ def level_bytes(info, w, m, nu):
     M_k = R_k (D_k - omega A_k) has no residual pass: 2nu - 1 passes over S_k, one
     over T_k and M_k, and (6nu+4) vector passes (the last pre-sweep writes its
     residual, which M_k reads)."""
-    S = info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
+    nS = info.nnzb_S or info.nnzb  # D^-1 A as stored: its off-diagonal blocks
+    S = nS * info.nb * info.nb * w + 4 * nS + 4 * (info.n_units + 1)
     D = info.n_units * info.nb * info.nb * w
     TR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_units + 1)
     if getattr(info, "restrict_resid", 0):
@@ -56,9 +57,11 @@ def level_bytes(info, w, m, nu):
 
 def sweep_bytes(info, w, m):
     """Algorithmic bytes of one block-Jacobi sweep as the V-cycle runs it,
-    y = x + omega (c - S x) with S = D^-1 A and c = D^-1 b: S (values and
-    indices), x and c read once, y written once."""
-    return (info.nnzb * info.nb * info.nb * w + 4 * info.nnzb + 4 * (info.n_units + 1)
+    y = x + omega (c - S x) with S = D^-1 A and c = D^-1 b: S's off-diagonal
+    blocks (values and indices; its diagonal blocks are the identity), x and c
+    read once, y written once."""
+    nS = info.nnzb_S or info.nnzb
+    return (nS * info.nb * info.nb * w + 4 * nS + 4 * (info.n_units + 1)
             + 3 * info.n * m * w)
 
 

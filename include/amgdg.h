@@ -201,6 +201,9 @@ typedef struct {
     int64_t nnzb_M;      /* blocks of the pattern of M_k = R_k (D_k - omega_k A_k) */
     int32_t restrict_resid; /* 1: the V-cycle restricts through M_k (amgdg_params.restrict_resid) */
     int64_t bytes_M;     /* FP64 bytes of M_k (0 when not kept) */
+    int64_t nnzb_S;      /* blocks stored for D_k^{-1} A_k: its off-diagonal ones (its diagonal
+                            blocks are the identity and are applied as such; 0 on a
+                            matrix-free level) */
 } amgdg_level_info;
 int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out);
 int amgdg_num_levels(amgdg_handle h);

@@ -51,7 +51,8 @@ class amgdg_level_info(ctypes.Structure):
                 ("r", ctypes.c_int32), ("sweeps", ctypes.c_int32 * 64), ("bytes_A", ctypes.c_int64),
                 ("bytes_Dinv", ctypes.c_int64), ("bytes_T", ctypes.c_int64), ("bytes_R", ctypes.c_int64),
                 ("n_dofs", ctypes.c_int64), ("matfree", ctypes.c_int32), ("bytes_handle", ctypes.c_int64),
-                ("nnzb_M", ctypes.c_int64), ("restrict_resid", ctypes.c_int32), ("bytes_M", ctypes.c_int64)]
+                ("nnzb_M", ctypes.c_int64), ("restrict_resid", ctypes.c_int32), ("bytes_M", ctypes.c_int64),
+                ("nnzb_S", ctypes.c_int64)]
 
 
 class amgdg_solve_stats(ctypes.Structure):

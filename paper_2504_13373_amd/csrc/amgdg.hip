@@ -111,6 +111,7 @@ struct MatStore {
     Nbsr<double> nd;  // natural layout of a sliced matrix, for 16-column MFMA tiles
     Nbsr<float> nf;
     int64_t n_vals = 0;
+    bool unit = false;  // diagonal blocks implied identity (S = D^{-1} A)
     // tuned launch shapes per column count (0: the default rule): columns per
     // launch, and blocks loaded ahead in the MFMA tiles (per m / 16)
     std::array<int8_t, 65> cap64{}, cap32{};
@@ -151,6 +152,7 @@ struct Level {
     // and RD = R D (R's pattern), so that R (b - A u) = RD (D^{-1} b - S u)
     MatStore S, RD;
     double *S_nat = nullptr, *RD_nat = nullptr;
+    int64_t nnzb_S = 0;  // stored blocks of S: A's off-diagonal blocks
     // M = R (D - omega A) (R A's pattern): the restriction of the residual after
     // a sweep from the residual before it, R D (c - S u') = M (c - S u) for
     // u' = u + omega (c - S u), so that the last pre-sweep's own residual
@@ -409,8 +411,22 @@ static T* sell_dinv(Ctx& C, const Sell<T>& A, const int32_t* pos, const double* 
     return out;
 }
 
+static void build_mat_layouts(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const std::vector<int32_t>& rp,
+                              const std::vector<int32_t>& ci, const double* nat_d, bool f32, hipStream_t st);
+
+// unit: a square operator whose diagonal blocks are the identity and are not
+// among (rp, ci, nat_d); every layout's products add the row's own x entries
 static void build_mat(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const std::vector<int32_t>& rp,
-                      const std::vector<int32_t>& ci, const double* nat_d, bool f32, hipStream_t st) {
+                      const std::vector<int32_t>& ci, const double* nat_d, bool f32, hipStream_t st,
+                      bool unit = false) {
+    build_mat_layouts(C, M, n_brow, br, bc, rp, ci, nat_d, f32, st);
+    const int32_t u = unit ? 1 : 0;
+    M.bd.unit = M.bf.unit = M.nd.unit = M.nf.unit = M.s.d.unit = M.s.f.unit = u;
+    M.unit = unit;
+}
+
+static void build_mat_layouts(Ctx& C, MatStore& M, int64_t n_brow, int br, int bc, const std::vector<int32_t>& rp,
+                              const std::vector<int32_t>& ci, const double* nat_d, bool f32, hipStream_t st) {
     if (br <= BCSR_MAXBR) {
         M.vec = true;
         const int64_t nnzb = int64_t(ci.size());
@@ -765,12 +781,29 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         if (L.matfree) C.build_mem = &setup_only;
         build_mat(C, L.A, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.A_nat, C.mixed && !L.matfree, st);
         if (!L.matfree) {
+            // S = D^{-1} A without its diagonal blocks, D^{-1} A_ee = I: a sweep
+            // u + omega (c - S u) reads the off-diagonal blocks and u itself
             DevMem tmp;
             int32_t* rp_d = upload(tmp, P.A_rp, st);
-            L.S_nat = C.mem.alloc<double>(L.nnzb * L.nb * L.nb);
-            HIPCHK(launch_row_scale(L.A_nat, rp_d, L.n_units, L.nb, L.Dinv_nat, L.S_nat, st));
+            double* S_full = tmp.alloc<double>(L.nnzb * L.nb * L.nb);
+            HIPCHK(launch_row_scale(L.A_nat, rp_d, L.n_units, L.nb, L.Dinv_nat, S_full, st));
+            std::vector<int32_t> srp(size_t(L.n_units) + 1, 0), sci, src;
+            sci.reserve(size_t(L.nnzb - L.n_units));
+            src.reserve(size_t(L.nnzb - L.n_units));
+            for (int64_t e = 0; e < L.n_units; ++e) {
+                for (int32_t a = P.A_rp[e]; a < P.A_rp[e + 1]; ++a)
+                    if (a != P.A_diag[e]) {
+                        sci.push_back(P.A_ci[a]);
+                        src.push_back(a);
+                    }
+                srp[e + 1] = int32_t(sci.size());
+            }
+            L.nnzb_S = int64_t(sci.size());
+            int32_t* src_d = upload(tmp, src, st);
+            L.S_nat = C.mem.alloc<double>(L.nnzb_S * L.nb * L.nb);
+            HIPCHK(launch_gather_blocks(S_full, src_d, L.nnzb_S, L.nb * L.nb, L.S_nat, st));
             HIPCHK(hipStreamSynchronize(st));
-            build_mat(C, L.S, L.n_units, L.nb, L.nb, P.A_rp, P.A_ci, L.S_nat, C.mixed, st);
+            build_mat(C, L.S, L.n_units, L.nb, L.nb, srp, sci, L.S_nat, C.mixed, st, true);
         }
         if (!L.A.vec) {
             L.Dinv_sell = sell_dinv<double>(C, L.A.s.d, L.A.s.pos, L.Dinv_nat, st);
@@ -2743,6 +2776,7 @@ int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out) {
     out->bytes_T = L.T.n_vals * 8;
     out->bytes_R = L.R.n_vals * 8;
     out->nnzb_M = (k < C.N) ? L.nM : 0;
+    out->nnzb_S = (k < C.N) ? L.nnzb_S : 0;
     out->restrict_resid = L.has_M ? 1 : 0;
     out->bytes_M = L.has_M ? L.M.n_vals * 8 : 0;
     return AMGDG_OK;

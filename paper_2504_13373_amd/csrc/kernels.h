@@ -31,7 +31,11 @@ struct Sell {
     const int32_t* cols = nullptr;
     const T* vals = nullptr;
     const int32_t* rows = nullptr;
+    int32_t unit = 0;  // see below
 };
+// unit (Sell, Bcsr, Nbsr): 1 for a square operator whose diagonal blocks are
+// the identity and are not stored, S = D^{-1} A: every product adds the row's
+// own x entries to the stored blocks' sum
 
 // Block-CSR matrix with small br x bc blocks (br <= 4), for coarse levels and
 // restriction: a group of P lanes (P a power of two, 4..64) owns one block row,
@@ -47,6 +51,7 @@ struct Bcsr {
     const int32_t* rp = nullptr;
     const int32_t* ci = nullptr;
     const T* vals = nullptr;  // row-major blocks
+    int32_t unit = 0;
 };
 constexpr int BCSR_MAXBR = 4;
 
@@ -58,6 +63,7 @@ struct Nbsr {
     const int32_t* rp = nullptr;
     const int32_t* ci = nullptr;
     const T* vals = nullptr;
+    int32_t unit = 0;
 };
 constexpr int MFMA_COLS = 16;
 constexpr int NBSR_MAXB = 16;
@@ -181,6 +187,9 @@ hipError_t launch_T_build(const double* Avals, const int32_t* A_ci, const int32_
                           hipStream_t st);
 hipError_t launch_R_from_T(const double* Tvals, const int32_t* R_t, int64_t nR, int nb, int s, double* Rvals,
                            hipStream_t st);
+// out block b = vals block src[b] (n blocks of `per` values)
+hipError_t launch_gather_blocks(const double* vals, const int32_t* src, int64_t n, int per, double* out,
+                                hipStream_t st);
 // S = D^{-1} A block row by block row (S has A's pattern; dinv natural)
 hipError_t launch_row_scale(const double* Avals, const int32_t* rp, int64_t n_brow, int nb, const double* dinv,
                             double* Svals, hipStream_t st);

@@ -257,25 +257,27 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
     // overlaps the row's product instead of following it
     constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP || MODE == S_SWEEP_R);
     constexpr bool PX = (MODE == S_SWEEP || MODE == S_SWEEP_R || MODE == AX_DOT);
-    T bo[PB ? M : 1], xo[PX ? M : 1];
-    if (PB || PX) {
+    const bool px = PX || A.unit;  // the own x entries (unit: the implied diagonal blocks)
+    T bo[PB ? M : 1], xo[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            if (PB) bo[c] = own ? b[row * ldy + c] : T(0);
-            if (PX) xo[c] = own ? x[row * ldx + c] : T(0);
-        }
+    for (int c = 0; c < M; ++c) {
+        if (PB) bo[c] = own ? b[row * ldy + c] : T(0);
+        xo[c] = (px && own) ? x[row * ldx + c] : T(0);
     }
     T acc[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) acc[c] = T(0);
     if (live) sell_row<T, M, CHUNKED>(A, slice, lane, lc, g, i, x, ldx, xs, acc, T(1));
+    if (A.unit)
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[c] += xo[c];
     if (MODE == AX_DOT) {
         // the workgroup's partial of x . y per column: lanes of each wave by an
         // xor tree, then the four waves in order
         __shared__ T red[WAVES_PER_WG][M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            T v = own ? xo[PX ? c : 0] * acc[c] : T(0);
+            T v = own ? xo[c] * acc[c] : T(0);
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
             if (lane == 0) red[wave][c] = v;
@@ -291,11 +293,11 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
         T v = acc[c];
         if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
         else if (MODE == B_PLUS) v = bo[PB ? c : 0] + v;
-        else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
+        else if (MODE == S_SWEEP) v = xo[c] + omega * (bo[PB ? c : 0] - v);
         else if (MODE == S_SWEEP_R) {
             const T e = bo[PB ? c : 0] - v;
             part[row * ldy + c] = e;  // y2: the residual the sweep starts from
-            v = xo[PX ? c : 0] + omega * e;
+            v = xo[c] + omega * e;
         }
         y[row * ldy + c] = v;
     }
@@ -601,6 +603,7 @@ __global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restric
     acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
     if (!own) return;
+    if (A.unit) acc += x[row * ldx];
     T val = acc;
     if (MODE == B_MINUS) val = b[row * ldy] - acc;
     else if (MODE == B_PLUS) val = b[row * ldy] + acc;
@@ -810,18 +813,25 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
     // overlaps the block loop instead of following the reduction
     constexpr bool PB = (MODE == B_MINUS || MODE == B_PLUS || MODE == S_SWEEP || MODE == S_SWEEP_R);
     constexpr bool PX = (MODE == S_SWEEP || MODE == S_SWEEP_R);
-    T bo[PB ? M : 1], xo[PX ? M : 1];
-    if (PB || PX) {
+    const bool px = PX || A.unit;
+    T bo[PB ? M : 1], xo[M];
+    {
         const bool mine = valid && p < BR;
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             if (PB) bo[c] = mine ? b[row * ld + c] : T(0);
-            if (PX) xo[c] = mine ? x[row * ld + c] : T(0);
+            xo[c] = (px && mine) ? x[row * ld + c] : T(0);
         }
     }
     T acc[BR][M];
     bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
     if (!valid || p >= BR) return;
+    if (A.unit)
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+            if (i == p)
+#pragma unroll
+                for (int c = 0; c < M; ++c) acc[i][c] += xo[c];
     if (MODE == AX_DSCALE) {
         // row p of D'^{-1} (the output rows' own block) applied to the block row's
         // product: the operations of a first sweep whose right-hand side is A x
@@ -850,11 +860,11 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
             T v = acc[i][c];
             if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
             else if (MODE == B_PLUS) v = bo[PB ? c : 0] + v;
-            else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
+            else if (MODE == S_SWEEP) v = xo[c] + omega * (bo[PB ? c : 0] - v);
             else if (MODE == S_SWEEP_R) {
                 const T e = bo[PB ? c : 0] - v;
                 y2[row * ld + c] = e;
-                v = xo[PX ? c : 0] + omega * e;
+                v = xo[c] + omega * e;
             }
             y[row * ld + c] = v;
         }
@@ -888,39 +898,50 @@ __global__ __launch_bounds__(WG) void k_bspmv_wide(Bcsr<T> A, const T* __restric
     constexpr bool PX = (MODE == S_SWEEP || MODE == S_SWEEP_R);
     const bool writer = lane < BR && (!whole || wave == 0);
     const int64_t row = brow * BR + lane;
-    T bo[PB ? M : 1], xo[PX ? M : 1];
-    if (PB || PX) {
+    const bool px = PX || A.unit;
+    T bo[PB ? M : 1], xo[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            if (PB) bo[c] = writer ? b[row * ld + c] : T(0);
-            if (PX) xo[c] = writer ? x[row * ld + c] : T(0);
-        }
+    for (int c = 0; c < M; ++c) {
+        if (PB) bo[c] = writer ? b[row * ld + c] : T(0);
+        xo[c] = (px && writer) ? x[row * ld + c] : T(0);
     }
     T acc[BR][M];
 #pragma unroll
     for (int i = 0; i < BR; ++i)
 #pragma unroll
         for (int c = 0; c < M; ++c) acc[i][c] = T(0);
-    int q = t0 / bc, j = t0 - (t0 / bc) * bc;
-    const int dq = stride / bc, dj = stride - (stride / bc) * bc;
-    for (int e = t0; e < E; e += stride) {
-        const int blk = beg + q;
-        const T* __restrict__ xr = x + (int64_t(A.ci[blk]) * bc + j) * ld;
-        T xv[M];
+    // U of a lane's entries per step: their index, value and x loads are all
+    // issued before the products (each lane still adds its entries in order)
+    constexpr int U = (M * BR <= 8) ? 4 : 2;
+    for (int e0 = t0; e0 < E; e0 += U * stride) {
+        int blk[U], jj[U];
 #pragma unroll
-        for (int c = 0; c < M; ++c) xv[c] = xr[c];
-        const T* __restrict__ a = A.vals + int64_t(blk) * BR * bc + j;
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            const T av = a[i * bc];
-#pragma unroll
-            for (int c = 0; c < M; ++c) acc[i][c] += av * xv[c];
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * stride;
+            const int q = e < E ? e / bc : 0;
+            blk[u] = beg + q;
+            jj[u] = e < E ? e - q * bc : 0;
         }
-        j += dj;
-        q += dq;
-        if (j >= bc) {
-            j -= bc;
-            ++q;
+        int32_t col[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) col[u] = A.ci[blk[u]];
+        T av[U][BR], xv[U][M];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T* __restrict__ a = A.vals + int64_t(blk[u]) * BR * bc + jj[u];
+#pragma unroll
+            for (int i = 0; i < BR; ++i) av[u][i] = a[i * bc];
+            const T* __restrict__ xr = x + (int64_t(col[u]) * bc + jj[u]) * ld;
+#pragma unroll
+            for (int c = 0; c < M; ++c) xv[u][c] = xr[c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (e0 + u * stride >= E) break;
+#pragma unroll
+            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                for (int c = 0; c < M; ++c) acc[i][c] += av[u][i] * xv[u][c];
         }
     }
 #pragma unroll
@@ -944,6 +965,12 @@ __global__ __launch_bounds__(WG) void k_bspmv_wide(Bcsr<T> A, const T* __restric
     }
     if (!writer) return;
     const int p = lane;
+    if (A.unit)
+#pragma unroll
+        for (int i = 0; i < BR; ++i)
+            if (i == p)
+#pragma unroll
+                for (int c = 0; c < M; ++c) acc[i][c] += xo[c];
     if (MODE == AX_DSCALE) {
         T o[M];
 #pragma unroll
@@ -969,11 +996,11 @@ __global__ __launch_bounds__(WG) void k_bspmv_wide(Bcsr<T> A, const T* __restric
         for (int c = 0; c < M; ++c) {
             T v = acc[i][c];
             if (MODE == B_MINUS) v = bo[PB ? c : 0] - v;
-            else if (MODE == S_SWEEP) v = xo[PX ? c : 0] + omega * (bo[PB ? c : 0] - v);
+            else if (MODE == S_SWEEP) v = xo[c] + omega * (bo[PB ? c : 0] - v);
             else if (MODE == S_SWEEP_R) {
                 const T e = bo[PB ? c : 0] - v;
                 y2[row * ld + c] = e;
-                v = xo[PX ? c : 0] + omega * e;
+                v = xo[c] + omega * e;
             }
             y[row * ld + c] = v;
         }
@@ -1222,7 +1249,8 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
         const int row = Mma<T>::row(g, v);
         const int64_t e = (r0 + row) * ld + col0;
         bpre[v] = (MODE != MF_AX && MODE != MF_RDINV && row < br) ? b[e] : T(0);
-        xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP || MODE == MF_SSWEEP_R) && row < br) ? x[e] : T(0);
+        xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP || MODE == MF_SSWEEP_R || A.unit) && row < br) ? x[e]
+                                                                                                 : T(0);
     }
     if (SW) {
         const T* __restrict__ Db = dinv + int64_t(brow) * br * br;
@@ -1265,7 +1293,7 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
         for (int v = 0; v < 4; ++v) {
             const int row = Mma<T>::row(g, v);
             if (row < br) {
-                T val = acc[v];
+                T val = A.unit ? acc[v] + xpre[v] : acc[v];
                 if (MODE == MF_BMINUS) val = bpre[v] - val;
                 if (MODE == MF_BPLUS) val = bpre[v] + val;
                 if (MODE == MF_SSWEEP) val = xpre[v] + omega * (bpre[v] - val);
@@ -1993,6 +2021,21 @@ hipError_t launch_row_scale(const double* Av, const int32_t* rp, int64_t n_brow,
     const int64_t tot = n_brow * nb * nb;
     if (tot == 0) return hipSuccess;
     hipLaunchKernelGGL(k_row_scale, dim3(grid_for(tot)), dim3(WG), 0, st, Av, rp, n_brow, nb, dinv, Sv);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_blocks(const double* __restrict__ vals, const int32_t* __restrict__ src, int64_t n, int per,
+                                double* __restrict__ out) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid >= n * per) return;
+    const int64_t b = tid / per;
+    out[tid] = vals[int64_t(src[b]) * per + (tid - b * per)];
+}
+
+hipError_t launch_gather_blocks(const double* vals, const int32_t* src, int64_t n, int per, double* out,
+                                hipStream_t st) {
+    if (n * per == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_blocks, dim3(grid_for(n * per)), dim3(WG), 0, st, vals, src, n, per, out);
     return hipGetLastError();
 }
 
