@@ -1330,9 +1330,161 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
     }
 }
 
+// The products without D^{-1} (MF_AX, MF_BMINUS, MF_BPLUS, MF_SSWEEP,
+// MF_SSWEEP_R) with their operands staged through wavefront-private LDS by
+// 16-byte loads: a block row's U blocks are one contiguous run of values, and
+// each block's x rows hold the tile's 16 columns contiguously, so a wavefront
+// reads them with a few vector loads instead of one 4-byte load per lane per
+// operand and k step (the tiles' address processing, not HBM, limited the
+// 16-column sweep).  The accumulator tile returns through LDS to row-major
+// order, so the epilogue's b, x, y and y2 move 16 bytes per lane as well.  The
+// products are those of k_mfma, in the same order.  On the 16-column 3D sweep
+// it took the FP32 V-cycle from 12.59 to 12.03 ms (the sweep from 1367 to
+// 1338 us); the address unit's busy share had suggested more.
+// LDS per wavefront: U (br bc + 16 bc) + 16 * 17 values.
+template <typename T, int N>
+struct ExtVec {
+    typedef T type __attribute__((ext_vector_type(N)));
+};
+
+template <typename T, int MODE, int U>
+__global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
+                                               T* __restrict__ y, T omega, int ld, T* __restrict__ y2) {
+    constexpr int VW = 16 / int(sizeof(T));
+    using V = typename ExtVec<T, VW>::type;
+    constexpr int LPR = MFMA_COLS / VW;         // lanes per 16-column row: 4 (FP32), 8 (FP64)
+    constexpr int RPP = 64 / LPR;               // rows per epilogue pass: 16, 8
+    constexpr int NP = (MFMA_COLS + RPP - 1) / RPP;
+    constexpr int NL = U * NBSR_MAXB * NBSR_MAXB / (VW * 64);  // vector loads per lane and operand, at most
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int brow = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave);
+    if (brow >= A.n_brow) return;
+    const int br = A.br, bc = A.bc;
+    const int per = br * bc, xper = bc * MFMA_COLS;
+    T* sA = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * (U * (per + xper) + MFMA_COLS * 17);
+    T* sX = sA + U * per;
+    T* sY = sX + U * xper;
+    const int i = lane & 15, g = lane >> 4;
+    const int64_t tile0 = int64_t(blockIdx.y) * MFMA_COLS;
+    const int64_t r0 = int64_t(brow) * br;
+    // epilogue operands first, row-major: lane (er, eq) holds columns eq*VW.. of rows er + p*RPP
+    const int er = lane / LPR, eq = lane - (lane / LPR) * LPR;
+    constexpr bool NB = (MODE == MF_BMINUS || MODE == MF_BPLUS || MODE == MF_SSWEEP || MODE == MF_SSWEEP_R);
+    const bool nx = MODE == MF_SSWEEP || MODE == MF_SSWEEP_R || A.unit;
+    V bo[NP], xo[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int row = er + p * RPP;
+        const int64_t e = (r0 + row) * ld + tile0 + eq * VW;
+        bo[p] = (NB && row < br) ? *reinterpret_cast<const V*>(b + e) : V(T(0));
+        xo[p] = (nx && row < br) ? *reinterpret_cast<const V*>(x + e) : V(T(0));
+    }
+    typename Mma<T>::acc acc = {T(0), T(0), T(0), T(0)};
+    const int beg = A.rp[brow], end = A.rp[brow + 1];
+    const int kt = (bc + 3) >> 2;
+    for (int blk = beg; blk < end; blk += U) {
+        const int nbu = min(U, end - blk);
+        int32_t cu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cu[u] = A.ci[blk + (u < nbu ? u : 0)];
+        // the chunk's blocks (contiguous) and their x rows, all loads issued first
+        const V* __restrict__ ag = reinterpret_cast<const V*>(A.vals + int64_t(blk) * per);
+        const int nva = nbu * per / VW, nvx = nbu * bc * LPR;
+        V ra[NL], rx[NL];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int v = lane + 64 * j;
+            if (v < nva) ra[j] = ag[v];
+            if (v < nvx) {
+                const int u = v / (bc * LPR);
+                const int rem = v - u * (bc * LPR);
+                const int k = rem / LPR, q = rem - (rem / LPR) * LPR;
+                int32_t c = cu[0];
+#pragma unroll
+                for (int w = 1; w < U; ++w)
+                    if (u == w) c = cu[w];
+                rx[j] = *reinterpret_cast<const V*>(x + (int64_t(c) * bc + k) * ld + tile0 + q * VW);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int v = lane + 64 * j;
+            if (v < nva) reinterpret_cast<V*>(sA)[v] = ra[j];
+            if (v < nvx) reinterpret_cast<V*>(sX)[v] = rx[j];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (u >= nbu) break;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t >= kt) break;
+                const int k = 4 * t + g;
+                const T av = (i < br && k < bc) ? sA[u * per + i * bc + k] : T(0);
+                const T xv = (k < bc) ? sX[(u * bc + k) * MFMA_COLS + i] : T(0);
+                acc = Mma<T>::step(av, xv, acc);
+            }
+        }
+        wave_lds_sync();  // the next chunk overwrites sA and sX
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sY[Mma<T>::row(g, v) * 17 + i] = acc[v];
+    wave_lds_sync();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int row = er + p * RPP;
+        if (row >= br) break;
+        const V bv = bo[p], xv = xo[p];
+        V o, e2 = V(T(0));
+#pragma unroll
+        for (int w = 0; w < VW; ++w) {
+            T val = sY[row * 17 + eq * VW + w];
+            if (A.unit) val += xv[w];
+            if (MODE == MF_BMINUS) val = bv[w] - val;
+            if (MODE == MF_BPLUS) val = bv[w] + val;
+            if (MODE == MF_SSWEEP) val = xv[w] + omega * (bv[w] - val);
+            if (MODE == MF_SSWEEP_R) {
+                e2[w] = bv[w] - val;
+                val = xv[w] + omega * e2[w];
+            }
+            o[w] = val;
+        }
+        const int64_t e = (r0 + row) * ld + tile0 + eq * VW;
+        *reinterpret_cast<V*>(y + e) = o;
+        if (MODE == MF_SSWEEP_R) *reinterpret_cast<V*>(y2 + e) = e2;
+    }
+}
+
+template <typename T>
+static bool mfma_v_ok(int mode, const Nbsr<T>& A, const T* x, const T* b, const T* y, int ld) {
+    constexpr int VW = 16 / int(sizeof(T));
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    // FP32 only: in FP64 the staged form measured slower (the 16-column 3D sweep 2.61 ms against 2.40 ms)
+    return sizeof(T) == 4 &&
+           (mode == MF_AX || mode == MF_BMINUS || mode == MF_BPLUS || mode == MF_SSWEEP || mode == MF_SSWEEP_R) &&
+           (A.br * A.bc) % VW == 0 && ld % VW == 0 && al(A.vals) && al(x) && al(y) && (!b || al(b));
+}
+
 template <typename T, int U>
 static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                          hipStream_t st, T* y2) {
+    if (mfma_v_ok<T>(mode, A, x, b, y, m) && (mode != MF_SSWEEP_R || (reinterpret_cast<uintptr_t>(y2) & 15) == 0)) {
+        dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
+        const size_t lds = size_t(WAVES_PER_WG) * (U * (A.br * A.bc + A.bc * MFMA_COLS) + MFMA_COLS * 17) * sizeof(T);
+        if (lds <= lds_limit()) {
+#define MFV_LAUNCH(MD) hipLaunchKernelGGL((k_mfma_v<T, MD, U>), grid, block, lds, st, A, x, b, y, omega, m, y2)
+            switch (mode) {
+                case MF_AX: MFV_LAUNCH(MF_AX); break;
+                case MF_BMINUS: MFV_LAUNCH(MF_BMINUS); break;
+                case MF_BPLUS: MFV_LAUNCH(MF_BPLUS); break;
+                case MF_SSWEEP: MFV_LAUNCH(MF_SSWEEP); break;
+                default: MFV_LAUNCH(MF_SSWEEP_R); break;
+            }
+#undef MFV_LAUNCH
+            return hipGetLastError();
+        }
+    }
     dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
     switch (mode) {
         case MF_AX: hipLaunchKernelGGL((k_mfma<T, MF_AX, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
