@@ -1341,7 +1341,13 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
 // products are those of k_mfma, in the same order.  On the 16-column 3D sweep
 // it took the FP32 V-cycle from 12.59 to 12.03 ms (the sweep from 1367 to
 // 1338 us); the address unit's busy share had suggested more.
-// LDS per wavefront: U (br bc + 16 bc) + 16 * 17 values.
+// LDS per wavefront: mfma_v_lds values.
+// values of LDS per wavefront: U blocks, their x rows, the 16 x 17 result tile
+// and one spare vector, rounded up to whole 16-byte vectors
+__host__ __device__ constexpr int mfma_v_lds(int U, int per, int xper, int VW) {
+    return (U * (per + xper) + MFMA_COLS * 17 + VW + VW - 1) / VW * VW;
+}
+
 template <typename T, int N>
 struct ExtVec {
     typedef T type __attribute__((ext_vector_type(N)));
@@ -1362,7 +1368,7 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
     if (brow >= A.n_brow) return;
     const int br = A.br, bc = A.bc;
     const int per = br * bc, xper = bc * MFMA_COLS;
-    T* sA = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * (U * (per + xper) + MFMA_COLS * 17);
+    T* sA = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * mfma_v_lds(U, per, xper, VW);
     T* sX = sA + U * per;
     T* sY = sX + U * xper;
     const int i = lane & 15, g = lane >> 4;
@@ -1376,9 +1382,17 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int row = er + p * RPP;
-        const int64_t e = (r0 + row) * ld + tile0 + eq * VW;
-        bo[p] = (NB && row < br) ? *reinterpret_cast<const V*>(b + e) : V(T(0));
-        xo[p] = (nx && row < br) ? *reinterpret_cast<const V*>(x + e) : V(T(0));
+        const int64_t e = (r0 + (row < br ? row : br - 1)) * ld + tile0 + eq * VW;  // clamped: loads stay unconditional
+        bo[p] = V(T(0));
+        xo[p] = V(T(0));
+        if (NB) {
+            const V t = *reinterpret_cast<const V*>(b + e);
+            bo[p] = row < br ? t : V(T(0));
+        }
+        if (nx) {
+            const V t = *reinterpret_cast<const V*>(x + e);
+            xo[p] = row < br ? t : V(T(0));
+        }
     }
     typename Mma<T>::acc acc = {T(0), T(0), T(0), T(0)};
     const int beg = A.rp[brow], end = A.rp[brow + 1];
@@ -1391,27 +1405,28 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
         // the chunk's blocks (contiguous) and their x rows, all loads issued first
         const V* __restrict__ ag = reinterpret_cast<const V*>(A.vals + int64_t(blk) * per);
         const int nva = nbu * per / VW, nvx = nbu * bc * LPR;
+        // indices clamped to the last vector, so every load is unconditional;
+        // the surplus lanes write to a spare slot after the tile
         V ra[NL], rx[NL];
 #pragma unroll
         for (int j = 0; j < NL; ++j) {
             const int v = lane + 64 * j;
-            if (v < nva) ra[j] = ag[v];
-            if (v < nvx) {
-                const int u = v / (bc * LPR);
-                const int rem = v - u * (bc * LPR);
-                const int k = rem / LPR, q = rem - (rem / LPR) * LPR;
-                int32_t c = cu[0];
+            ra[j] = ag[v < nva ? v : nva - 1];
+            const int vx = v < nvx ? v : nvx - 1;
+            const int u = vx / (bc * LPR);
+            const int rem = vx - u * (bc * LPR);
+            const int k = rem / LPR, q = rem - (rem / LPR) * LPR;
+            int32_t c = cu[0];
 #pragma unroll
-                for (int w = 1; w < U; ++w)
-                    if (u == w) c = cu[w];
-                rx[j] = *reinterpret_cast<const V*>(x + (int64_t(c) * bc + k) * ld + tile0 + q * VW);
-            }
+            for (int w = 1; w < U; ++w) c = (u == w) ? cu[w] : c;
+            rx[j] = *reinterpret_cast<const V*>(x + (int64_t(c) * bc + k) * ld + tile0 + q * VW);
         }
+        V* const spare = reinterpret_cast<V*>(sY + MFMA_COLS * 17);
 #pragma unroll
         for (int j = 0; j < NL; ++j) {
             const int v = lane + 64 * j;
-            if (v < nva) reinterpret_cast<V*>(sA)[v] = ra[j];
-            if (v < nvx) reinterpret_cast<V*>(sX)[v] = rx[j];
+            *(v < nva ? reinterpret_cast<V*>(sA) + v : spare) = ra[j];
+            *(v < nvx ? reinterpret_cast<V*>(sX) + v : spare) = rx[j];
         }
         wave_lds_sync();
 #pragma unroll
@@ -1471,7 +1486,8 @@ static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, 
                          hipStream_t st, T* y2) {
     if (mfma_v_ok<T>(mode, A, x, b, y, m) && (mode != MF_SSWEEP_R || (reinterpret_cast<uintptr_t>(y2) & 15) == 0)) {
         dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
-        const size_t lds = size_t(WAVES_PER_WG) * (U * (A.br * A.bc + A.bc * MFMA_COLS) + MFMA_COLS * 17) * sizeof(T);
+        const size_t lds = size_t(WAVES_PER_WG) *
+                           mfma_v_lds(U, A.br * A.bc, A.bc * MFMA_COLS, 16 / int(sizeof(T))) * sizeof(T);
         if (lds <= lds_limit()) {
 #define MFV_LAUNCH(MD) hipLaunchKernelGGL((k_mfma_v<T, MD, U>), grid, block, lds, st, A, x, b, y, omega, m, y2)
             switch (mode) {
