@@ -1338,9 +1338,10 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
 // operand and k step (the tiles' address processing, not HBM, limited the
 // 16-column sweep).  The accumulator tile returns through LDS to row-major
 // order, so the epilogue's b, x, y and y2 move 16 bytes per lane as well.  The
-// products are those of k_mfma, in the same order.  On the 16-column 3D sweep
-// it took the FP32 V-cycle from 12.59 to 12.03 ms (the sweep from 1367 to
-// 1338 us); the address unit's busy share had suggested more.
+// products are those of k_mfma, in the same order.  On the 16-column 3D
+// workload the FP32 sweep went from 1367 us to 1306-1338 us and the V-cycle
+// from 12.6 ms to 12.0-12.4 ms (three runs); the address unit's busy share
+// (83% of the sweep's cycles with per-lane loads) had suggested more.
 // LDS per wavefront: mfma_v_lds values.
 // values of LDS per wavefront: U blocks, their x rows, the 16 x 17 result tile
 // and one spare vector, rounded up to whole 16-byte vectors
