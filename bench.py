@@ -319,8 +319,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "level-0 FP64 block-Jacobi sweep on D^-1 A (k_spmv<double,1,S_SWEEP,false>), the kernel "
-                      "with the most GPU time in this run; its 449 MB working set exceeds the 256 MB "
+            "kernel": "level-0 FP64 block-Jacobi sweep on D^-1 A (k_spmv<double,1,S_SWEEP,false,false>; the "
+                      "diagonal blocks of D^-1 A are the identity and are not stored), the kernel with the most "
+                      f"GPU time in this run; its {k['bytes'] / 1e6:.0f} MB working set exceeds the 256 MB "
                       "Infinity Cache, so back-to-back launches run as they do inside the V-cycles",
             "achieved": k["gbps"],
             "peak": HBM_PEAK_GBS,
@@ -341,8 +342,9 @@ def main():
             "GBps_cache_evicted": kern["fp32_cold"]["gbps"],
             "frac_cache_evicted": kern["fp32_cold"]["gbps"] / HBM_PEAK_GBS,
             "bytes_per_launch": kern["fp32"]["bytes"],
-            "note": "the FP32 operator (226 MB) fits the 256 MB Infinity Cache: back-to-back launches reuse it; "
-                    "the evicted figure reads 1 GiB between launches (outside the events)",
+            "note": f"the FP32 sweep's {kern['fp32']['bytes'] / 1e6:.0f} MB fit the 256 MB Infinity Cache: "
+                    "back-to-back launches reuse them; the evicted figure reads 1 GiB between launches (outside "
+                    "the events)",
         },
         "fp64": {
             "solves_per_s": m / fp64_t,
