@@ -74,9 +74,10 @@ typedef struct {
                               no A_k after the setup; the V-cycle applies A_k as
                               R_{k-1} A_{k-1} T_{k-1} (eq:matfree1, eq:matfree2), down to A_0.
                               Single steps that need A_k are then EUNSUPPORTED on those levels */
-    int32_t  restrict_resid; /* 1 (default): on levels where it holds no more values than the
-                              residual pass over D_k^{-1} A_k and R_k D_k it replaces (plus 2^21),
-                              keep M_k = R_k (D_k - omega_k A_k); the V-cycle's last pre-sweep then
+    int32_t  restrict_resid; /* 1 (default): on levels whose coarse block size is at most 4 and
+                              where it holds no more values than the residual pass over
+                              D_k^{-1} A_k and R_k D_k it replaces (plus 2^21), keep
+                              M_k = R_k (D_k - omega_k A_k); the V-cycle's last pre-sweep then
                               also writes the residual it starts from, e, and the coarse right-hand
                               side is M_k e = R_k (b_k - A_k u) (Algorithm 2, reassociated: one
                               product over D_k^{-1} A_k fewer per level and cycle).  0: residual,

@@ -927,9 +927,13 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         build_mat(C, L.RD, P.n_agg, s, L.nb, P.R_rp, P.R_ci, L.RD_nat, C.mixed, st);
         // M = R (D - omega A), where it reads no more values than the residual
         // pass over S and the RD product it replaces (plus 2^21, about a
-        // launch's latency at full bandwidth)
+        // launch's latency at full bandwidth), and where it is stored as block
+        // CSR (s <= 4), whose entry-wise kernel reads its long rows at full
+        // width; a sliced M (larger coarse blocks) would stage rows one
+        // neighbour layer longer than R D's, in chunks, which measured slower
+        // on the hexahedral hierarchies
         L.nM = int64_t(P.M_ci.size());
-        if (p.restrict_resid && p.t_pre >= 1 && !L.matfree &&
+        if (p.restrict_resid && p.t_pre >= 1 && !L.matfree && s <= BCSR_MAXBR &&
             L.nM * s * L.nb <= L.nnzb * L.nb * L.nb + L.nT * s * L.nb + (int64_t(1) << 21)) {
             DevMem t1;
             int32_t* rci = upload(t1, P.R_ci, st);

@@ -102,7 +102,9 @@ hipError_t launch_spmv(int mode, const Sell<T>& A, const T* x, const T* b, T* y,
                        T omega = T(0), T* y2 = nullptr);  // y2: S_SWEEP_R only (required there)
 // Block rows per wavefront of the sliced layout: floor(64 / br), lowered until
 // one column of FP64 x staging plus D^{-1} (rows of up to max_row_blocks blocks
-// of bc columns) fits the 64 KB of LDS a workgroup may take; at least 1.  A
+// of bc columns) fits the 64 KB of LDS a workgroup may take; at least 1, and 1
+// when lowering leaves half the lanes or more idle (br <= 16: the split-row
+// kernels then keep all 64 lanes busy).  A
 // launch whose staging exceeds the device's per-workgroup LDS even at one
 // block row per wavefront stages x in chunks of 512 values (one column per
 // launch).

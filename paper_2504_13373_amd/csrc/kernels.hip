@@ -396,6 +396,9 @@ int sell_rows_per_wave(int br, int bc, int max_row_blocks) {
     const size_t need = size_t((int64_t(max_row_blocks) * bc + 1) / 2 * 2 + (br + 1) / 2 * 2) * sizeof(double);
     int G = 64 / br;
     while (G > 1 && size_t(WAVES_PER_WG) * G * need > STAGE_LDS) --G;
+    // lowered so far that half the lanes or more would idle: one block row per
+    // wavefront, which the split-row kernels serve on all 64 lanes (br <= 16)
+    if (G < 64 / br && G * br <= 32 && br <= 16) G = 1;
     return G;
 }
 
