@@ -87,6 +87,8 @@ def test_setup_parity(name):
         L = H.levels[k]
         info = am.amgdg_level_info_get(h, k)
         assert info.n == L.A.shape[0] and info.nb == L.nb and info.s == L.s
+        # D^-1 A is stored without its diagonal blocks (the identity)
+        assert info.nnzb_S == info.nnzb - info.n_units, (k, info.nnzb_S, info.nnzb, info.n_units)
         if w.params.omega_fixed > 0:
             assert info.omega == w.params.omega_fixed
         else:
@@ -186,7 +188,7 @@ def host_op(op, k, h, w, x, b, prec):
 
 @pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
 @pytest.mark.parametrize("prec", [am.AMGDG_FP64, am.AMGDG_MIXED])
-@pytest.mark.parametrize("m", [1, 3, 5, 16, 32])
+@pytest.mark.parametrize("m", [1, 3, 5, 8, 16, 32])
 def test_single_kernels(name, prec, m):
     """Every single step on every level against the host product of the
     exported operators; m = 16 and 32 take the MFMA tiles on sliced levels."""
