@@ -141,8 +141,10 @@ void amgdg_plan_destroy(amgdg_plan p);
 #define AMGDG_M_ROWPTR   19   /* int32[n_agg + 1]: pattern of M_k = R_k (D_k - omega_k A_k), that of
                                  R_k A_k (block (I,c) iff R_k(I,e) and A_k(e,c) for some e) */
 #define AMGDG_M_COLIDX   20   /* int32[nnzb_M] (level-k units) */
-#define AMGDG_M_VALS     21   /* double[nnzb_M * s * nb]; level export only, EUNSUPPORTED on a level
-                                 that keeps no M_k (amgdg_level_info.restrict_resid = 0) */
+#define AMGDG_M_VALS     21   /* double[nnzb_M * s * nb]; level export only */
+/* The plan exports the M pattern of every level; a handle exports the three M
+ * items only on levels that keep M_k (amgdg_level_info.restrict_resid = 1), and
+ * returns EUNSUPPORTED elsewhere. */
 
 /* Number of elements of `what` (in its own type) at level k. */
 int amgdg_plan_size(amgdg_plan p, int32_t k, int32_t what, int64_t* count);
@@ -199,7 +201,7 @@ typedef struct {
                             every unit holds nb) */
     int32_t matfree;     /* 1: A_k is applied matrix-free (not stored) */
     int64_t bytes_handle;/* device bytes held by the whole hierarchy (every level) */
-    int64_t nnzb_M;      /* blocks of the pattern of M_k = R_k (D_k - omega_k A_k) */
+    int64_t nnzb_M;      /* blocks of M_k = R_k (D_k - omega_k A_k) where it is kept, else 0 */
     int32_t restrict_resid; /* 1: the V-cycle restricts through M_k (amgdg_params.restrict_resid) */
     int64_t bytes_M;     /* FP64 bytes of M_k (0 when not kept) */
     int64_t nnzb_S;      /* blocks stored for D_k^{-1} A_k: its off-diagonal ones (its diagonal

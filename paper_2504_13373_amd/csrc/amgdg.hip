@@ -932,9 +932,10 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
         // width; a sliced M (larger coarse blocks) would stage rows one
         // neighbour layer longer than R D's, in chunks, which measured slower
         // on the hexahedral hierarchies
+        const bool try_M = p.restrict_resid && p.t_pre >= 1 && !L.matfree && s <= BCSR_MAXBR;
+        if (try_M) symbolic_M(C.plan.lv[k]);
         L.nM = int64_t(P.M_ci.size());
-        if (p.restrict_resid && p.t_pre >= 1 && !L.matfree && s <= BCSR_MAXBR &&
-            L.nM * s * L.nb <= L.nnzb * L.nb * L.nb + L.nT * s * L.nb + (int64_t(1) << 21)) {
+        if (try_M && L.nM * s * L.nb <= L.nnzb * L.nb * L.nb + L.nT * s * L.nb + (int64_t(1) << 21)) {
             DevMem t1;
             int32_t* rci = upload(t1, P.R_ci, st);
             int32_t* mci = upload(t1, P.M_ci, st);
@@ -947,6 +948,12 @@ static void setup_impl(Ctx& C, int64_t n_elem, int32_t nb, const int32_t* row_pt
             HIPCHK(hipStreamSynchronize(st));
             build_mat(C, L.M, P.n_agg, s, L.nb, P.M_rp, P.M_ci, L.M_nat, C.mixed, st);
             L.has_M = true;
+        }
+        if (try_M) {  // the pairs served the numeric phase only
+            LevelPattern& Pm = C.plan.lv[k];
+            std::vector<int64_t>().swap(Pm.M_pp);
+            std::vector<int32_t>().swap(Pm.M_pr);
+            std::vector<int32_t>().swap(Pm.M_pa);
         }
         // A_{k+1} = R (A T)
         Level& Ln = C.lv[k + 1];
@@ -2462,9 +2469,8 @@ static int export_impl(Ctx& C, int k, int what, void* buf, int64_t bytes, hipStr
         case AMGDG_M_ROWPTR:
         case AMGDG_M_COLIDX:
         case AMGDG_M_VALS: {
-            if (what == AMGDG_M_VALS && !L.has_M) throw Error(AMGDG_EUNSUPPORTED, "this level keeps no M_k");
-            std::vector<double> v = L.has_M ? download(L.M_nat, L.nM * nb * s, st)
-                                            : std::vector<double>(size_t(L.nM * nb * s), 0.0);
+            if (!L.has_M) throw Error(AMGDG_EUNSUPPORTED, "this level keeps no M_k (its pattern: amgdg_plan_export)");
+            std::vector<double> v = download(L.M_nat, L.nM * nb * s, st);
             std::vector<int32_t> orp, oci;
             std::vector<double> ov;
             export_matrix(C, k, P.M_rp, P.M_ci, v, int64_t(nb) * s, false, true, orp, oci, ov);
@@ -2480,7 +2486,7 @@ static int export_impl(Ctx& C, int k, int what, void* buf, int64_t bytes, hipStr
 
 // ------------------------------------------------------------ plan queries
 
-static void plan_item(const Plan& P, int k, int what, std::vector<int32_t>& out32, std::vector<int64_t>& out64) {
+static void plan_item(Plan& P, int k, int what, std::vector<int32_t>& out32, std::vector<int64_t>& out64) {
     out32.clear();
     out64.clear();
     const int N = P.n_levels - 1;
@@ -2517,6 +2523,7 @@ static void plan_item(const Plan& P, int k, int what, std::vector<int32_t>& out3
     } else if (what == AMGDG_R_ROWPTR || what == AMGDG_R_COLIDX) {
         rows_caller(P.lv[k].R_rp, P.lv[k].R_ci, false, true, orp, oci);
     } else if (what == AMGDG_M_ROWPTR || what == AMGDG_M_COLIDX) {
+        symbolic_M(P.lv[k]);
         rows_caller(P.lv[k].M_rp, P.lv[k].M_ci, false, true, orp, oci);
     } else {
         throw Error(AMGDG_EINVAL, "unknown plan item");
@@ -2779,7 +2786,7 @@ int amgdg_level_info_get(amgdg_handle h, int32_t k, amgdg_level_info* out) {
     out->bytes_Dinv = (k < C.N) ? L.n_units * L.nb * L.nb * 8 : 0;
     out->bytes_T = L.T.n_vals * 8;
     out->bytes_R = L.R.n_vals * 8;
-    out->nnzb_M = (k < C.N) ? L.nM : 0;
+    out->nnzb_M = L.has_M ? L.nM : 0;
     out->nnzb_S = (k < C.N) ? L.nnzb_S : 0;
     out->restrict_resid = L.has_M ? 1 : 0;
     out->bytes_M = L.has_M ? L.M.n_vals * 8 : 0;

@@ -117,86 +117,82 @@ static void symbolic_R(LevelPattern& L) {
         }
 }
 
+// Rows of a product pattern with their pairs: for each output row, visit(emit)
+// calls emit(col, p1, p2) for every contributing pair in a fixed order; the
+// row's distinct columns are sorted and each column's pairs keep the visit
+// order (the order a sort of (col, p1, p2) triples gives when the visit runs
+// p1, then p2, ascending and meets each (p1, col) once).
+template <typename Visit>
+static void product_rows(int64_t n_rows, int64_t n_cols, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                         std::vector<int64_t>& pp, std::vector<int32_t>& p1, std::vector<int32_t>& p2,
+                         Visit visit) {
+    rp.assign(size_t(n_rows) + 1, 0);
+    pp.assign(1, 0);
+    ci.clear();
+    p1.clear();
+    p2.clear();
+    std::vector<int64_t> mark(size_t(n_cols), -1), start(size_t(n_cols), 0);
+    std::vector<int32_t> cnt(size_t(n_cols), 0), cols;
+    for (int64_t I = 0; I < n_rows; ++I) {
+        cols.clear();
+        visit(I, [&](int32_t c, int32_t, int32_t) {
+            if (mark[c] != I) {
+                mark[c] = I;
+                cnt[c] = 0;
+                cols.push_back(c);
+            }
+            ++cnt[c];
+        });
+        std::sort(cols.begin(), cols.end());
+        int64_t pos = int64_t(p1.size());
+        for (int32_t c : cols) {
+            start[c] = pos;
+            pos += cnt[c];
+            ci.push_back(c);
+            pp.push_back(pos);
+        }
+        p1.resize(size_t(pos));
+        p2.resize(size_t(pos));
+        visit(I, [&](int32_t c, int32_t a, int32_t b) {
+            const int64_t q = start[c]++;
+            p1[size_t(q)] = a;
+            p2[size_t(q)] = b;
+        });
+        if (ci.size() >= (size_t(1) << 31)) fail("plan: a product pattern exceeds int32 indexing");
+        rp[size_t(I) + 1] = int32_t(ci.size());
+    }
+}
+
 // AT = A T: row e, block J = sum over (a = (e,c), t = (c,J)).
 static void symbolic_AT(LevelPattern& L) {
-    L.AT_rp.assign(L.n_units + 1, 0);
-    L.AT_pp.assign(1, 0);
-    std::vector<std::array<int32_t, 3>> ent;  // (J, a, t)
-    for (int64_t e = 0; e < L.n_units; ++e) {
-        ent.clear();
+    product_rows(L.n_units, L.n_agg, L.AT_rp, L.AT_ci, L.AT_pp, L.AT_pa, L.AT_pt, [&](int64_t e, auto&& emit) {
         for (int32_t a = L.A_rp[e]; a < L.A_rp[e + 1]; ++a) {
-            int32_t c = L.A_ci[a];
-            for (int32_t t = L.T_rp[c]; t < L.T_rp[c + 1]; ++t) ent.push_back({L.T_ci[t], a, t});
+            const int32_t c = L.A_ci[a];
+            for (int32_t t = L.T_rp[c]; t < L.T_rp[c + 1]; ++t) emit(L.T_ci[t], a, t);
         }
-        std::sort(ent.begin(), ent.end());
-        for (size_t i = 0; i < ent.size();) {
-            size_t j = i;
-            L.AT_ci.push_back(ent[i][0]);
-            for (; j < ent.size() && ent[j][0] == ent[i][0]; ++j) {
-                L.AT_pa.push_back(ent[j][1]);
-                L.AT_pt.push_back(ent[j][2]);
-            }
-            L.AT_pp.push_back(int64_t(L.AT_pa.size()));
-            i = j;
-        }
-        L.AT_rp[e + 1] = int32_t(L.AT_ci.size());
-    }
+    });
 }
 
 // A_{k+1} = T^T (A T): row I, block J = sum over units e with T(e,I), AT(e,J).
 static void symbolic_C(LevelPattern& L) {
-    L.C_rp.assign(L.n_agg + 1, 0);
-    L.C_pp.assign(1, 0);
-    std::vector<std::array<int32_t, 3>> ent;  // (J, t, u)
-    for (int64_t I = 0; I < L.n_agg; ++I) {
-        ent.clear();
+    product_rows(L.n_agg, L.n_agg, L.C_rp, L.C_ci, L.C_pp, L.C_pt, L.C_pu, [&](int64_t I, auto&& emit) {
         for (int32_t rr = L.R_rp[I]; rr < L.R_rp[I + 1]; ++rr) {
-            int32_t e = L.R_ci[rr], t = L.R_t[rr];
-            for (int32_t u = L.AT_rp[e]; u < L.AT_rp[e + 1]; ++u) ent.push_back({L.AT_ci[u], t, u});
+            const int32_t e = L.R_ci[rr], t = L.R_t[rr];
+            for (int32_t u = L.AT_rp[e]; u < L.AT_rp[e + 1]; ++u) emit(L.AT_ci[u], t, u);
         }
-        std::sort(ent.begin(), ent.end());
-        for (size_t i = 0; i < ent.size();) {
-            size_t j = i;
-            L.C_ci.push_back(ent[i][0]);
-            for (; j < ent.size() && ent[j][0] == ent[i][0]; ++j) {
-                L.C_pt.push_back(ent[j][1]);
-                L.C_pu.push_back(ent[j][2]);
-            }
-            L.C_pp.push_back(int64_t(L.C_pt.size()));
-            i = j;
-        }
-        L.C_rp[I + 1] = int32_t(L.C_ci.size());
-    }
+    });
 }
 
 // M = R (D - omega A): row I, block c = sum over e with R(I,e), A(e,c).
-static void symbolic_M(LevelPattern& L) {
-    L.M_rp.assign(L.n_agg + 1, 0);
-    L.M_pp.assign(1, 0);
-    L.M_ci.clear();
-    L.M_pr.clear();
-    L.M_pa.clear();
-    std::vector<std::array<int32_t, 3>> ent;  // (c, r, a)
-    for (int64_t I = 0; I < L.n_agg; ++I) {
-        ent.clear();
+void symbolic_M(LevelPattern& L) {
+    if (L.M_done) return;
+    product_rows(L.n_agg, L.n_units, L.M_rp, L.M_ci, L.M_pp, L.M_pr, L.M_pa, [&](int64_t I, auto&& emit) {
         for (int32_t rr = L.R_rp[I]; rr < L.R_rp[I + 1]; ++rr) {
             const int32_t e = L.R_ci[rr];
-            for (int32_t a = L.A_rp[e]; a < L.A_rp[e + 1]; ++a) ent.push_back({L.A_ci[a], rr, a});
+            for (int32_t a = L.A_rp[e]; a < L.A_rp[e + 1]; ++a) emit(L.A_ci[a], rr, a);
         }
-        std::sort(ent.begin(), ent.end());
-        for (size_t i = 0; i < ent.size();) {
-            size_t j = i;
-            L.M_ci.push_back(ent[i][0]);
-            for (; j < ent.size() && ent[j][0] == ent[i][0]; ++j) {
-                L.M_pr.push_back(ent[j][1]);
-                L.M_pa.push_back(ent[j][2]);
-            }
-            L.M_pp.push_back(int64_t(L.M_pr.size()));
-            i = j;
-        }
-        if (L.M_ci.size() >= (size_t(1) << 31)) fail("plan: M_k exceeds int32 indexing");
-        L.M_rp[I + 1] = int32_t(L.M_ci.size());
-    }
+    });
+    L.M_done = true;
 }
 
 static void diag_positions(const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
@@ -307,7 +303,6 @@ void build_plan(Plan& P, int64_t n_elem, const int32_t* row_ptr, const int32_t* 
         symbolic_R(L);
         symbolic_AT(L);
         symbolic_C(L);
-        symbolic_M(L);
         rp = L.C_rp;
         ci = L.C_ci;
     }

@@ -44,6 +44,8 @@ struct LevelPattern {
     // diagonal blocks enter with weight 1 - omega, the others with -omega.
     // It restricts the residual after a block-Jacobi sweep from the residual
     // before it: R D (c - S u') = M (c - S u) for u' = u + omega (c - S u).
+    // Formed on demand (symbolic_M): only levels that keep M, and exports, need it.
+    bool M_done = false;
     std::vector<int32_t> M_rp, M_ci;
     std::vector<int64_t> M_pp;
     std::vector<int32_t> M_pr, M_pa;
@@ -66,6 +68,9 @@ struct Plan {
 // applies eq:TR0's smoothing pattern there too.
 void build_plan(Plan& P, int64_t n_elem, const int32_t* row_ptr, const int32_t* col_idx, int64_t nnzb,
                 int32_t n_levels, const int32_t* agg_of_elem, bool hstar_smooth = false);
+
+// The pattern of M_k = R_k (D_k - omega A_k) and its pairs (once per level).
+void symbolic_M(LevelPattern& L);
 
 void rcb_partition(int64_t n_elem, int32_t dim, const double* cent, int32_t n_levels, int32_t bisections,
                    int32_t* agg_out, int64_t* leaf_out);
