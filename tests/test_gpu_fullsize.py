@@ -78,6 +78,37 @@ def test_fullsize_setup_and_vcycle(name):
 
 
 @pytest.mark.timeout(600)
+def test_fullsize_restriction_through_M():
+    """The level-0 restriction through M = R (D - omega A) at full size (the
+    entry-wise block-CSR kernel, a wavefront per block row) against the
+    oracle's R (D - omega A) x, and each of five columns bit-identical to the
+    same column restricted alone."""
+    w, H, h = case("poisson2d")
+    info = am.amgdg_level_info_get(h, 0)
+    assert info.restrict_resid == 1
+    L = H.levels[0]
+    A = L.A.tocoo()
+    on = (A.row // L.nb) == (A.col // L.nb)
+    D = sp.csr_matrix((A.data[on], (A.row[on], A.col[on])), shape=L.A.shape)
+    perm = am.amgdg_export_level(h, 0, am.AMGDG_PERM)
+    dofs = (perm[:, None] * L.nb + np.arange(L.nb)).ravel()  # internal dof -> caller dof
+    n1 = info.n_agg * info.s
+    X = np.random.default_rng(63).standard_normal((w.A.n, 5))
+    Mo = (L.T.T @ (D - L.omega * L.A)).tocsr()
+    want = Mo @ X
+    Y5 = torch.zeros((n1, 5), dtype=torch.float64, device=DEV)
+    am.amgdg_apply(h, 0, am.AMGDG_OP_RESTRICT_RESID, to_dev(X[dofs]), None, Y5, flags=am.AMGDG_INTERNAL_ORDER)
+    torch.cuda.synchronize()
+    assert rel(Y5.cpu().numpy(), want) <= 1e-12, rel(Y5.cpu().numpy(), want)
+    for c in range(5):
+        y1 = torch.zeros((n1, 1), dtype=torch.float64, device=DEV)
+        am.amgdg_apply(h, 0, am.AMGDG_OP_RESTRICT_RESID, to_dev(X[dofs, c:c + 1]), None, y1,
+                       flags=am.AMGDG_INTERNAL_ORDER)
+        torch.cuda.synchronize()
+        assert torch.equal(y1[:, 0].cpu(), Y5[:, c].contiguous().cpu()), c
+
+
+@pytest.mark.timeout(600)
 def test_fullsize_pcg_prefix_matches_oracle():
     """40 PCG iterations (capped) on the 1.3M-dof case: the iterate equals the
     oracle's after the same 40 iterations."""
