@@ -316,6 +316,9 @@ def main():
             "rhs_per_solve": m,
             "outer": ("flexible CG" if args.mixed_outer == "fcg" else f"FGMRES({args.restart}) iterative refinement")
                      + " (mixed) / CG (fp64)",
+            "outer_note": "the mixed path's outer iteration is flexible CG with residual replacement: FGMRES(30) "
+                          "iterative refinement around the same FP32 V-cycle stagnates on this workload (30,000 "
+                          "iterations, relative residual 7.5e-6; --mixed-outer fgmres)",
         },
         "roofline": {
             "bound": "hbm",
