@@ -48,7 +48,8 @@ def level_bytes(info, w, m, nu):
     S = nS * info.nb * info.nb * w + 4 * nS + 4 * (info.n_units + 1)
     D = info.n_units * info.nb * info.nb * w
     TR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_units + 1)
-    if getattr(info, "restrict_resid", 0):
+    # (on the 16-column tiles the library restricts through M only on levels of 2,048 or more coarse block rows)
+    if getattr(info, "restrict_resid", 0) and not (m % 16 == 0 and info.n_agg < 2048):
         MM = info.nnzb_M * info.nb * info.s * w + 4 * info.nnzb_M + 4 * (info.n_agg + 1)
         return (2 * nu - 1) * S + D + (6 * nu + 4) * info.n * m * w + TR + MM
     RR = info.nnzb_T * info.nb * info.s * w + 4 * info.nnzb_T + 4 * (info.n_agg + 1)
@@ -142,6 +143,8 @@ def main():
     ap.add_argument("--oversample", action="store_true",
                     help="poisson2d: also the paper's oversampled setup (r = the median dofs of a level-1 "
                          "aggregate, s_J per aggregate, levels until the coarsest holds at most 2,048 dofs)")
+    ap.add_argument("--no-restrict-resid", action="store_true",
+                    help="form each level's residual and restrict it through R D instead of through M = R (D - omega A)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes (no amgdg_autotune before timing)")
     ap.add_argument("--tune-lanes", action="store_true",
@@ -176,7 +179,7 @@ def main():
     log(f"workload: {w.mesh.n_elem} elements, {w.A.n} dofs, {w.A.nnzb} blocks ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h, agg = am.setup_from_workload(w, mixed=True)
+    h, agg = am.setup_from_workload(w, mixed=True, restrict_resid=int(not args.no_restrict_resid))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
@@ -584,7 +587,7 @@ def bench_convdiff(args, am, torch, dev):
         w = configs.convdiff2d_delaunay(side=side, peclet=pe)
         A = w.A.to_scipy()
         t0 = time.perf_counter()
-        h, _ = am.setup_from_workload(w, mixed=True)
+        h, _ = am.setup_from_workload(w, mixed=True, restrict_resid=int(not args.no_restrict_resid))
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
@@ -664,7 +667,8 @@ def bench_hex(args, am, torch, dev):
 def _hex_row(args, am, torch, dev, w, M, flux, r, p, hstar, kappa, maxit):
     A = w.A.to_scipy()
     t0 = time.perf_counter()
-    h, _ = am.setup_from_workload(w, mixed=True, matfree_levels=kappa)
+    h, _ = am.setup_from_workload(w, mixed=True, matfree_levels=kappa,
+                                  restrict_resid=int(not args.no_restrict_resid))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
@@ -801,7 +805,7 @@ def bench_poisson3d(args, am, torch, dev):
     w = configs.poisson3d_kuhn(n=cells, n_rhs=m, log=log)
     log(f"poisson3d: {w.mesh.n_elem} tets, {w.A.n} dofs, {w.A.nnzb} blocks ({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
-    h, _ = am.setup_from_workload(w, mixed=True)
+    h, _ = am.setup_from_workload(w, mixed=True, restrict_resid=int(not args.no_restrict_resid))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     infos = [am.amgdg_level_info_get(h, k) for k in range(h.n_levels)]
@@ -882,7 +886,7 @@ def bench_serving_stream(args, am, torch, dev):
     for w in cat:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h, _ = am.setup_from_workload(w, mixed=True)
+        h, _ = am.setup_from_workload(w, mixed=True, restrict_resid=int(not args.no_restrict_resid))
         torch.cuda.synchronize()
         setup_s.append(time.perf_counter() - t0)
         handles.append(h)

@@ -1188,8 +1188,12 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
         }
         // With M = R (D - omega A) the last pre-sweep also writes the residual
         // e = c - S u of the iterate it starts from, and R (b - A u') = M e for
-        // the iterate u' it writes; after a single sweep from zero e is c.
-        const bool via_M = L.has_M && tpre >= 1;
+        // the iterate u' it writes; after a single sweep from zero e is c.  On
+        // the 16-column tiles (one wavefront per block row) M serves only levels
+        // with at least 2,048 coarse block rows: below that its long rows leave
+        // the tiles with too few wavefronts (the 3D hierarchy's last restriction
+        // took 722 us through M at 16 columns)
+        const bool via_M = L.has_M && tpre >= 1 && (!use_mfma<T>(L.M, m) || L.n_agg >= 2048);
         const T* e = V.c;
         if (tpre == 0) {
             HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * L.n * m, st));
