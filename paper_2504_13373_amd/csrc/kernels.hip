@@ -1334,7 +1334,9 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
 }
 
 // The products without D^{-1} (MF_AX, MF_BMINUS, MF_BPLUS, MF_SSWEEP,
-// MF_SSWEEP_R) with their operands staged through wavefront-private LDS by
+// MF_SSWEEP_R) and the restriction MF_RDINV (D'^{-1} of the output rows applied
+// to the result tile, row by row) with their operands staged through
+// wavefront-private LDS by
 // 16-byte loads: a block row's U blocks are one contiguous run of values, and
 // each block's x rows hold the tile's 16 columns contiguously, so a wavefront
 // reads them with a few vector loads instead of one 4-byte load per lane per
@@ -1358,8 +1360,9 @@ struct ExtVec {
 };
 
 template <typename T, int MODE, int U>
-__global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, T omega, int ld, T* __restrict__ y2) {
+__global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
+                                               const T* __restrict__ b, T* __restrict__ y, T omega, int ld,
+                                               T* __restrict__ y2) {
     constexpr int VW = 16 / int(sizeof(T));
     using V = typename ExtVec<T, VW>::type;
     constexpr int LPR = MFMA_COLS / VW;         // lanes per 16-column row: 4 (FP32), 8 (FP64)
@@ -1389,6 +1392,7 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
         const int64_t e = (r0 + (row < br ? row : br - 1)) * ld + tile0 + eq * VW;  // clamped: loads stay unconditional
         bo[p] = V(T(0));
         xo[p] = V(T(0));
+        (void)e;
         if (NB) {
             const V t = *reinterpret_cast<const V*>(b + e);
             bo[p] = row < br ? t : V(T(0));
@@ -1396,6 +1400,17 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
         if (nx) {
             const V t = *reinterpret_cast<const V*>(x + e);
             xo[p] = row < br ? t : V(T(0));
+        }
+    }
+    // MF_RDINV: row er (+ p RPP) of the output rows' D'^{-1} block (br <= 16)
+    T dr[MODE == MF_RDINV ? NP : 1][MODE == MF_RDINV ? NBSR_MAXB : 1];
+    if (MODE == MF_RDINV) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int row = er + p * RPP;
+            const T* __restrict__ dp = dinv + (r0 + (row < br ? row : br - 1)) * br;
+#pragma unroll
+            for (int j = 0; j < NBSR_MAXB; ++j) dr[p][j] = j < br ? dp[j] : T(0);
         }
     }
     typename Mma<T>::acc acc = {T(0), T(0), T(0), T(0)};
@@ -1456,6 +1471,22 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
         if (row >= br) break;
         const V bv = bo[p], xv = xo[p];
         V o, e2 = V(T(0));
+        if (MODE == MF_RDINV) {
+            // o = D'^{-1} (the tile's column), y = omega o, y2 = o
+#pragma unroll
+            for (int w = 0; w < VW; ++w) {
+                T v = T(0);
+#pragma unroll
+                for (int j = 0; j < NBSR_MAXB; ++j)
+                    if (j < br) v += dr[p][j] * sY[j * 17 + eq * VW + w];
+                e2[w] = v;
+                o[w] = omega * v;
+            }
+            const int64_t e = (r0 + row) * ld + tile0 + eq * VW;
+            *reinterpret_cast<V*>(y + e) = o;
+            *reinterpret_cast<V*>(y2 + e) = e2;
+            continue;
+        }
 #pragma unroll
         for (int w = 0; w < VW; ++w) {
             T val = sY[row * 17 + eq * VW + w];
@@ -1481,24 +1512,27 @@ static bool mfma_v_ok(int mode, const Nbsr<T>& A, const T* x, const T* b, const 
     auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     // FP32 only: in FP64 the staged form measured slower (the 16-column 3D sweep 2.61 ms against 2.40 ms)
     return sizeof(T) == 4 &&
-           (mode == MF_AX || mode == MF_BMINUS || mode == MF_BPLUS || mode == MF_SSWEEP || mode == MF_SSWEEP_R) &&
+           (mode == MF_AX || mode == MF_BMINUS || mode == MF_BPLUS || mode == MF_SSWEEP || mode == MF_SSWEEP_R ||
+            mode == MF_RDINV) &&
            (A.br * A.bc) % VW == 0 && ld % VW == 0 && al(A.vals) && al(x) && al(y) && (!b || al(b));
 }
 
 template <typename T, int U>
 static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                          hipStream_t st, T* y2) {
-    if (mfma_v_ok<T>(mode, A, x, b, y, m) && (mode != MF_SSWEEP_R || (reinterpret_cast<uintptr_t>(y2) & 15) == 0)) {
+    if (mfma_v_ok<T>(mode, A, x, b, y, m) &&
+        ((mode != MF_SSWEEP_R && mode != MF_RDINV) || (reinterpret_cast<uintptr_t>(y2) & 15) == 0)) {
         dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
         const size_t lds = size_t(WAVES_PER_WG) *
                            mfma_v_lds(U, A.br * A.bc, A.bc * MFMA_COLS, 16 / int(sizeof(T))) * sizeof(T);
         if (lds <= lds_limit()) {
-#define MFV_LAUNCH(MD) hipLaunchKernelGGL((k_mfma_v<T, MD, U>), grid, block, lds, st, A, x, b, y, omega, m, y2)
+#define MFV_LAUNCH(MD) hipLaunchKernelGGL((k_mfma_v<T, MD, U>), grid, block, lds, st, A, dinv, x, b, y, omega, m, y2)
             switch (mode) {
                 case MF_AX: MFV_LAUNCH(MF_AX); break;
                 case MF_BMINUS: MFV_LAUNCH(MF_BMINUS); break;
                 case MF_BPLUS: MFV_LAUNCH(MF_BPLUS); break;
                 case MF_SSWEEP: MFV_LAUNCH(MF_SSWEEP); break;
+                case MF_RDINV: MFV_LAUNCH(MF_RDINV); break;
                 default: MFV_LAUNCH(MF_SSWEEP_R); break;
             }
 #undef MFV_LAUNCH
