@@ -545,7 +545,7 @@ static int mfu_of(const MatStore& M, int m) {
 // omega is read by S_SWEEP and S_SWEEP_R only; y2 (S_SWEEP_R only) receives b - A x
 template <typename T>
 static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, int m, hipStream_t st,
-                     T omega = T(0), T* y2 = nullptr) {
+                     T omega = T(0), T* y2 = nullptr, bool rev = false) {
     if (M.vec && !use_mfma<T>(M, m))
         HIPCHK(launch_bspmv<T>(mode, bsel<T>(M), x, b, y, m, st, cap_of<T>(M, m), omega, nullptr, y2));
     else if (use_mfma<T>(M, m))
@@ -555,7 +555,11 @@ static void mat_spmv(int mode, const MatStore& M, const T* x, const T* b, T* y, 
                               : mode == S_SWEEP_R ? MF_SSWEEP_R
                                                     : MF_SSWEEP,
                               nsel<T>(M), nullptr, x, b, y, omega, m, st, mfu_of<T>(M, m), y2));
-    else HIPCHK(launch_spmv<T>(mode, sel<T>(M.s), x, b, y, m, st, cap_of<T>(M, m), omega, y2));
+    else {
+        Sell<T> A = sel<T>(M.s);
+        A.rev = rev ? 1 : 0;
+        HIPCHK(launch_spmv<T>(mode, A, x, b, y, m, st, cap_of<T>(M, m), omega, y2));
+    }
 }
 
 // y2 (SWEEP0 only, may be null) receives D^{-1} b
@@ -1150,6 +1154,9 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
         return;
     }
     bool started = false;  // level k's first sweep was done by the restriction into it
+    // Consecutive passes over a level's S go in opposite directions (Sell::rev):
+    // each starts on the part of S that the memory-side cache took in last
+    std::vector<int> s_pass(size_t(N), 0);
     for (int k = 0; k < N; ++k) {
         Level& L = C.lv[k];
         VBuf<T>& V = vb(k);
@@ -1201,11 +1208,12 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
         } else {
             if (!started) mat_sweep<T>(SWEEP0, L, nullptr, bk, cur, om, m, nullptr, st, V.c);
             for (int t = 1; t < tpre; ++t) {
+                const bool rev = (s_pass[k]++ & 1) != 0;
                 if (via_M && t == tpre - 1) {
-                    mat_spmv<T>(S_SWEEP_R, L.S, cur, V.c, oth, m, st, om, V.r);
+                    mat_spmv<T>(S_SWEEP_R, L.S, cur, V.c, oth, m, st, om, V.r, rev);
                     e = V.r;
                 } else {
-                    mat_spmv<T>(S_SWEEP, L.S, cur, V.c, oth, m, st, om);
+                    mat_spmv<T>(S_SWEEP, L.S, cur, V.c, oth, m, st, om, nullptr, rev);
                 }
                 std::swap(cur, oth);
             }
@@ -1214,7 +1222,7 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
         // R (b - A u) = RD (c - S u), or M e
         const MatStore& Rk = via_M ? L.M : L.RD;
         if (!via_M) {
-            mat_spmv<T>(B_MINUS, L.S, cur, V.c, V.r, m, st);
+            mat_spmv<T>(B_MINUS, L.S, cur, V.c, V.r, m, st, T(0), nullptr, (s_pass[k]++ & 1) != 0);
             e = V.r;
         }
         // Into a non-coarsest level the restriction also takes that level's first
@@ -1247,7 +1255,7 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
                 HIPCHK(launch_bdiag<T>(BD_SWEEP, dinv_nat_of<T>(L), V.r, V.c, cur, dst, nullptr, om, L.n_units, L.nb,
                                        m, st));
             } else {
-                mat_spmv<T>(S_SWEEP, L.S, cur, V.c, dst, m, st, om);
+                mat_spmv<T>(S_SWEEP, L.S, cur, V.c, dst, m, st, om, nullptr, (s_pass[k]++ & 1) != 0);
             }
             cur = dst;
         }

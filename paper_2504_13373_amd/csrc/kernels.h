@@ -32,6 +32,10 @@ struct Sell {
     const T* vals = nullptr;
     const int32_t* rows = nullptr;
     int32_t unit = 0;  // see below
+    // per launch (k_spmv): 1 visits each XCD's run of slices from its end, so
+    // that a pass that follows one in the other direction first reads what the
+    // memory-side cache took in last; the result does not depend on it
+    int32_t rev = 0;
 };
 // unit (Sell, Bcsr, Nbsr): 1 for a square operator whose diagonal blocks are
 // the identity and are not stored, S = D^{-1} A: every product adds the row's

@@ -27,6 +27,15 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
     return x * q + (x < rmd ? x : rmd) + j;
 }
 
+// The same runs, each walked from its end when rev is set (XCD x holds the
+// q + (x < rmd) workgroups x, x + 8, ...; j counts them).
+__device__ __forceinline__ int xcd_remap_dir(int bid, int nblk, int rev) {
+    const int q = nblk >> 3, rmd = nblk & 7;
+    const int x = bid & 7, j = bid >> 3;
+    const int len = q + (x < rmd ? 1 : 0);
+    return x * q + (x < rmd ? x : rmd) + (rev ? len - 1 - j : j);
+}
+
 static inline unsigned grid_for(int64_t n, int per = WG) { return unsigned((n + per - 1) / per); }
 
 // ============================================================ BSR kernels
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(WG) void k_spmv(Sell<T> A, const T* __restrict__ x,
                                               T* __restrict__ y, int ldx, int ldy, T omega, T* __restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int wg = xcd_remap_dir(blockIdx.x, gridDim.x, A.rev);
     const int slice = wg * WAVES_PER_WG + wave;
     const bool live = slice < A.n_slices;
     if (!live && MODE != AX_DOT) return;  // AX_DOT: every wave reaches the workgroup barrier
@@ -764,6 +773,17 @@ __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ 
     const int g = lane / A.P, p = lane - (lane / A.P) * A.P;
     const int64_t brow = wv * gpw + g;
     const bool valid = brow < A.n_brow;
+    // the epilogue's row of D^{-1} and the block row's b are loaded before the
+    // block loop, so their latency overlaps it
+    const bool mine = valid && p < BR;
+    T dv[BR], bv[HAS_B ? BR : 1][M];
+#pragma unroll
+    for (int j = 0; j < BR; ++j) {
+        dv[j] = mine ? dinv[(brow * BR + p) * BR + j] : T(0);
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            if (HAS_B) bv[j][c] = mine ? b[(brow * BR + j) * ld + c] : T(0);
+    }
     T acc[BR][M];
     if (HAS_A) {
         bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
@@ -778,14 +798,12 @@ __global__ __launch_bounds__(WG) void k_bsweep(Bcsr<T> A, const T* __restrict__ 
     T o[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) o[c] = T(0);
-    const T* __restrict__ dr = dinv + (brow * BR + p) * BR;
 #pragma unroll
     for (int j = 0; j < BR; ++j) {
-        const T d = dr[j];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            const T bj = HAS_B ? b[(brow * BR + j) * ld + c] : T(0);
-            o[c] += d * (bj - acc[j][c]);
+            const T bj = HAS_B ? bv[HAS_B ? j : 0][c] : T(0);
+            o[c] += dv[j] * (bj - acc[j][c]);
         }
     }
     const int64_t row = brow * BR + p;
@@ -818,6 +836,8 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
     constexpr bool PX = (MODE == S_SWEEP || MODE == S_SWEEP_R);
     const bool px = PX || A.unit;
     T bo[PB ? M : 1], xo[M];
+    constexpr bool PD = (MODE == AX_DSCALE);
+    T dv[PD ? BR : 1];
     {
         const bool mine = valid && p < BR;
 #pragma unroll
@@ -825,6 +845,9 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
             if (PB) bo[c] = mine ? b[row * ld + c] : T(0);
             xo[c] = (px && mine) ? x[row * ld + c] : T(0);
         }
+#pragma unroll
+        for (int j = 0; j < BR; ++j)
+            if (PD) dv[PD ? j : 0] = mine ? dinv[(brow * BR + p) * BR + j] : T(0);
     }
     T acc[BR][M];
     bcsr_row<T, M, BR>(A, brow, valid, p, x, ld, acc);
@@ -841,12 +864,10 @@ __global__ __launch_bounds__(WG) void k_bspmv(Bcsr<T> A, const T* __restrict__ x
         T o[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) o[c] = T(0);
-        const T* __restrict__ dr = dinv + (brow * BR + p) * BR;
 #pragma unroll
         for (int j = 0; j < BR; ++j) {
-            const T d = dr[j];
 #pragma unroll
-            for (int c = 0; c < M; ++c) o[c] += d * acc[j][c];
+            for (int c = 0; c < M; ++c) o[c] += dv[PD ? j : 0] * acc[j][c];
         }
 #pragma unroll
         for (int c = 0; c < M; ++c) {
@@ -908,6 +929,11 @@ __global__ __launch_bounds__(WG) void k_bspmv_wide(Bcsr<T> A, const T* __restric
         if (PB) bo[c] = writer ? b[row * ld + c] : T(0);
         xo[c] = (px && writer) ? x[row * ld + c] : T(0);
     }
+    constexpr bool PD = (MODE == AX_DSCALE);
+    T dv[PD ? BR : 1];
+#pragma unroll
+    for (int j = 0; j < BR; ++j)
+        if (PD) dv[PD ? j : 0] = writer ? dinv[(brow * BR + lane) * BR + j] : T(0);
     T acc[BR][M];
 #pragma unroll
     for (int i = 0; i < BR; ++i)
@@ -978,12 +1004,10 @@ __global__ __launch_bounds__(WG) void k_bspmv_wide(Bcsr<T> A, const T* __restric
         T o[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) o[c] = T(0);
-        const T* __restrict__ dr = dinv + (brow * BR + p) * BR;
 #pragma unroll
         for (int jj = 0; jj < BR; ++jj) {
-            const T d = dr[jj];
 #pragma unroll
-            for (int c = 0; c < M; ++c) o[c] += d * acc[jj][c];
+            for (int c = 0; c < M; ++c) o[c] += dv[PD ? jj : 0] * acc[jj][c];
         }
 #pragma unroll
         for (int c = 0; c < M; ++c) {
