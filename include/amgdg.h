@@ -252,7 +252,12 @@ typedef struct {
 #define AMGDG_X0             1
 #define AMGDG_INTERNAL_ORDER 2
 #define AMGDG_EAGER          4  /* launch the V-cycle kernel by kernel instead of replaying
-                                   its captured HIP graph (the default for solve and vcycle) */
+                                   its captured HIP graph.  Without it, solve and vcycle replay
+                                   the graph unless one pass over the level-0 operator
+                                   S_0 = D^{-1} A_0 reads 128 MB or more (in the V-cycle's
+                                   precision): there the host queues the kernels well ahead
+                                   of the device, and the graph's start and end would only
+                                   add idle time.  The results are the same either way. */
 int amgdg_solve(amgdg_handle h, int32_t m, const double* b_dev, double* x_dev, int32_t method,
                 int32_t precision, double rtol, int32_t max_it, int32_t restart, int32_t flags,
                 amgdg_solve_stats* stats, void* stream);
@@ -263,9 +268,14 @@ int amgdg_solve(amgdg_handle h, int32_t m, const double* b_dev, double* x_dev, i
  * and keeps c = D^{-1} b_k; every later sweep is u + omega (c - S_k u) with
  * S_k = D^{-1} A_k precomputed at setup, and the restricted residual is
  * (R_k D)(c - S_k u), the same operator as Algorithm 1's sweep and
- * R_k (b_k - A_k u) with one matrix read per sweep instead of A_k and D^{-1}.
- * Into a non-coarsest coarse level the restriction also applies that level's
- * D^{-1} (its first sweep's operations), so b_{k+1} is not stored. */
+ * R_k (b_k - A_k u) with one matrix read per sweep instead of A_k and D^{-1};
+ * on a level that keeps M_k = R_k (D_k - omega_k A_k) (params.restrict_resid)
+ * it is M_k e with e = c - S_k u the residual the last pre-sweep starts from,
+ * which that sweep writes.  Consecutive passes over S_k run in opposite
+ * directions (the order rows are visited in; the arithmetic of a row does not
+ * depend on it).  Into a non-coarsest coarse level the restriction also
+ * applies that level's D^{-1} (its first sweep's operations), so b_{k+1} is
+ * not stored. */
 int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int32_t precision,
                  int32_t flags, void* stream);
 

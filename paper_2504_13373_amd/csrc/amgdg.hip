@@ -1269,6 +1269,18 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
 // stream the first time a (precision, m, input, output) combination is seen and
 // replayed on the caller's stream; reallocating the Work drops the cache.  It
 // holds only kernel nodes (no memset or copy nodes).
+// Whether a call replays the captured V-cycle (flags without AMGDG_EAGER).
+// The graph's start and end leave the device idle for a few microseconds each;
+// where one pass over the level-0 operator S reads 128 MB or more, the host
+// queues the V-cycle's kernels one by one long before the device reaches them,
+// so those V-cycles are launched eagerly.
+static bool graph_for(const Ctx& C, int flags, int prec_bytes) {
+    if (flags & AMGDG_EAGER) return false;
+    const Level& L = C.lv[0];
+    const double s_bytes = double(L.nnzb_S) * L.nb * L.nb * prec_bytes;
+    return s_bytes < 128.0 * (1 << 20);
+}
+
 template <typename T>
 static void vcycle_run(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t st, bool allow_graph) {
     if (!allow_graph || C.prm.t_pre == 0 || C.N == 0) {
@@ -1955,7 +1967,7 @@ static int solve_impl(Ctx& C, int m, const double* b_dev, double* x_dev, int met
         throw Error(AMGDG_EUNSUPPORTED, "FGMRES: m = 1 and 1 <= restart <= 256");
     const auto t0 = Clock::now();
     Work& W = default_work(C, m, method == AMGDG_FGMRES ? restart : 0, st);
-    W.use_graph = !(flags & AMGDG_EAGER);
+    W.use_graph = graph_for(C, flags, precision == AMGDG_MIXED ? 4 : 8);
     Level& L = C.lv[0];
     const int64_t n = L.n;
     const bool internal = flags & AMGDG_INTERNAL_ORDER;
@@ -2833,7 +2845,7 @@ int amgdg_vcycle(amgdg_handle h, int32_t m, const void* r_dev, void* z_dev, int3
     Work& W = default_work(C, m, 0, st);
     Level& L = C.lv[0];
     const bool internal = flags & AMGDG_INTERNAL_ORDER;
-    const bool graph = !(flags & AMGDG_EAGER);
+    const bool graph = graph_for(C, flags, precision == AMGDG_MIXED ? 4 : 8);
     if (precision == AMGDG_FP64) {
         const double* r = static_cast<const double*>(r_dev);
         double* z = static_cast<double*>(z_dev);
