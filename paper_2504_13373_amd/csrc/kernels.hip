@@ -1361,8 +1361,10 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
 // MF_SSWEEP_R) and the restriction MF_RDINV (D'^{-1} of the output rows applied
 // to the result tile, row by row) with their operands staged through
 // wavefront-private LDS by
-// 16-byte loads: a block row's U blocks are one contiguous run of values, and
-// each block's x rows hold the tile's 16 columns contiguously, so a wavefront
+// 16-byte loads: a chunk of B consecutive blocks of a block row
+// (mfma_v_blocks: 6 blocks of 10 x 10 or 16 of 4 x 4 at U = 4) is one
+// contiguous run of values, and each block's x rows hold the tile's 16
+// columns contiguously, so a wavefront
 // reads them with a few vector loads instead of one 4-byte load per lane per
 // operand and k step (the tiles' address processing, not HBM, limited the
 // 16-column sweep).  The accumulator tile returns through LDS to row-major
@@ -1372,10 +1374,21 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
 // from 12.6 ms to 12.0-12.4 ms (three runs); the address unit's busy share
 // (83% of the sweep's cycles with per-lane loads) had suggested more.
 // LDS per wavefront: mfma_v_lds values.
-// values of LDS per wavefront: U blocks, their x rows, the 16 x 17 result tile
+// values of LDS per wavefront: B blocks, their x rows, the 16 x 17 result tile
 // and one spare vector, rounded up to whole 16-byte vectors
-__host__ __device__ constexpr int mfma_v_lds(int U, int per, int xper, int VW) {
-    return (U * (per + xper) + MFMA_COLS * 17 + VW + VW - 1) / VW * VW;
+__host__ __device__ constexpr int mfma_v_lds(int B, int per, int xper, int VW) {
+    return (B * (per + xper) + MFMA_COLS * 17 + VW + VW - 1) / VW * VW;
+}
+
+// Blocks staged per chunk: as many as the U * 16 * 16 values of operand and
+// of x rows a lane's registers hold at most (NL vectors per lane each), and at
+// most 64 (one column index per lane): 16 blocks of 4 x 4, 6 of 10 x 10 at U = 4.
+__host__ __device__ constexpr int mfma_v_blocks(int U, int br, int bc, int VW) {
+    const int nl64 = 64 * (U * NBSR_MAXB * NBSR_MAXB / (VW * 64));
+    const int by_a = nl64 / (br * bc / VW);
+    const int by_x = nl64 / (bc * (MFMA_COLS / VW));
+    const int b = by_a < by_x ? by_a : by_x;
+    return b < 1 ? 1 : b > 64 ? 64 : b;
 }
 
 template <typename T, int N>
@@ -1386,7 +1399,7 @@ struct ExtVec {
 template <typename T, int MODE, int U>
 __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                const T* __restrict__ b, T* __restrict__ y, T omega, int ld,
-                                               T* __restrict__ y2) {
+                                               T* __restrict__ y2, int B) {
     constexpr int VW = 16 / int(sizeof(T));
     using V = typename ExtVec<T, VW>::type;
     constexpr int LPR = MFMA_COLS / VW;         // lanes per 16-column row: 4 (FP32), 8 (FP64)
@@ -1399,9 +1412,9 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
     if (brow >= A.n_brow) return;
     const int br = A.br, bc = A.bc;
     const int per = br * bc, xper = bc * MFMA_COLS;
-    T* sA = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * mfma_v_lds(U, per, xper, VW);
-    T* sX = sA + U * per;
-    T* sY = sX + U * xper;
+    T* sA = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * mfma_v_lds(B, per, xper, VW);
+    T* sX = sA + B * per;
+    T* sY = sX + B * xper;
     const int i = lane & 15, g = lane >> 4;
     const int64_t tile0 = int64_t(blockIdx.y) * MFMA_COLS;
     const int64_t r0 = int64_t(brow) * br;
@@ -1440,11 +1453,10 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
     typename Mma<T>::acc acc = {T(0), T(0), T(0), T(0)};
     const int beg = A.rp[brow], end = A.rp[brow + 1];
     const int kt = (bc + 3) >> 2;
-    for (int blk = beg; blk < end; blk += U) {
-        const int nbu = min(U, end - blk);
-        int32_t cu[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) cu[u] = A.ci[blk + (u < nbu ? u : 0)];
+    for (int blk = beg; blk < end; blk += B) {
+        const int nbu = min(B, end - blk);
+        // lane l holds the column of the chunk's block l (B <= 64)
+        const int32_t cl = A.ci[blk + (lane < nbu ? lane : nbu - 1)];
         // the chunk's blocks (contiguous) and their x rows, all loads issued first
         const V* __restrict__ ag = reinterpret_cast<const V*>(A.vals + int64_t(blk) * per);
         const int nva = nbu * per / VW, nvx = nbu * bc * LPR;
@@ -1459,9 +1471,7 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
             const int u = vx / (bc * LPR);
             const int rem = vx - u * (bc * LPR);
             const int k = rem / LPR, q = rem - (rem / LPR) * LPR;
-            int32_t c = cu[0];
-#pragma unroll
-            for (int w = 1; w < U; ++w) c = (u == w) ? cu[w] : c;
+            const int32_t c = __shfl(cl, u);
             rx[j] = *reinterpret_cast<const V*>(x + (int64_t(c) * bc + k) * ld + tile0 + q * VW);
         }
         V* const spare = reinterpret_cast<V*>(sY + MFMA_COLS * 17);
@@ -1472,9 +1482,7 @@ __global__ __launch_bounds__(WG) void k_mfma_v(Nbsr<T> A, const T* __restrict__ 
             *(v < nvx ? reinterpret_cast<V*>(sX) + v : spare) = rx[j];
         }
         wave_lds_sync();
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (u >= nbu) break;
+        for (int u = 0; u < nbu; ++u) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (t >= kt) break;
@@ -1534,8 +1542,10 @@ template <typename T>
 static bool mfma_v_ok(int mode, const Nbsr<T>& A, const T* x, const T* b, const T* y, int ld) {
     constexpr int VW = 16 / int(sizeof(T));
     auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
-    // FP32 only: in FP64 the staged form measured slower (the 16-column 3D sweep 2.61 ms against 2.40 ms)
-    return sizeof(T) == 4 &&
+    // FP32, and FP64 for blocks of at most 16 values (coarse levels of 4 x 4 blocks, whose long rows
+    // the staged form takes 16 blocks at a time): in FP64 the staged form measured slower on
+    // 10 x 10 blocks (the 16-column 3D sweep 2.61 ms against 2.40 ms)
+    return (sizeof(T) == 4 || A.br * A.bc <= 16) &&
            (mode == MF_AX || mode == MF_BMINUS || mode == MF_BPLUS || mode == MF_SSWEEP || mode == MF_SSWEEP_R ||
             mode == MF_RDINV) &&
            (A.br * A.bc) % VW == 0 && ld % VW == 0 && al(A.vals) && al(x) && al(y) && (!b || al(b));
@@ -1547,10 +1557,11 @@ static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, 
     if (mfma_v_ok<T>(mode, A, x, b, y, m) &&
         ((mode != MF_SSWEEP_R && mode != MF_RDINV) || (reinterpret_cast<uintptr_t>(y2) & 15) == 0)) {
         dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
-        const size_t lds = size_t(WAVES_PER_WG) *
-                           mfma_v_lds(U, A.br * A.bc, A.bc * MFMA_COLS, 16 / int(sizeof(T))) * sizeof(T);
+        constexpr int VW = 16 / int(sizeof(T));
+        const int B = mfma_v_blocks(U, A.br, A.bc, VW);
+        const size_t lds = size_t(WAVES_PER_WG) * mfma_v_lds(B, A.br * A.bc, A.bc * MFMA_COLS, VW) * sizeof(T);
         if (lds <= lds_limit()) {
-#define MFV_LAUNCH(MD) hipLaunchKernelGGL((k_mfma_v<T, MD, U>), grid, block, lds, st, A, dinv, x, b, y, omega, m, y2)
+#define MFV_LAUNCH(MD) hipLaunchKernelGGL((k_mfma_v<T, MD, U>), grid, block, lds, st, A, dinv, x, b, y, omega, m, y2, B)
             switch (mode) {
                 case MF_AX: MFV_LAUNCH(MF_AX); break;
                 case MF_BMINUS: MFV_LAUNCH(MF_BMINUS); break;
