@@ -1051,7 +1051,12 @@ static int64_t work_layout(const Ctx& C, Work* W, int m, int restart) {
     double* scratch = get(d, int64_t(DOT_PARTS) * 64 + 1024);
     double* scal = get(d, 2048);
     double* kpart = get(d, 2 * 16 * (KRY_BLOCKS + 1) + 64);
-    double* kslice = get(d, (C.lv[0].A.vec ? 1 : int64_t(C.lv[0].A.s.d.n_slices)) * 8);
+    // partials of p.(A p): per sliced workgroup (8 columns at a time), or per
+    // workgroup of the FP64 tiles (16 columns at a time)
+    const MatStore& A0 = C.lv[0].A;
+    const int64_t n_sp = std::max<int64_t>(A0.vec ? 1 : int64_t(A0.s.d.n_slices) * 8,
+                                           use_mfma<double>(A0, m) ? mfma_dot_parts(int64_t(A0.nd.n_brow)) : 0);
+    double* kslice = get(d, n_sp);
     double* stat = get(d, ST_LEN);
     int32_t* mask = get(i, MASK_LEN);
     if (W) {
@@ -1717,6 +1722,10 @@ struct CgBatch : Engine {
             if (!A0.vec && !use_mfma<double>(A0, m)) {
                 // q = A p with p.q from per-slice partials of the product itself
                 HIPCHK(launch_spmv_dot(sel<double>(A0.s), W->kp, W->kq, m, W->kslice, d_pq, st, cap_of<double>(A0, m)));
+            } else if (use_mfma<double>(A0, m)) {
+                // the same on the FP64 tiles: per-workgroup partials of p.q
+                HIPCHK(launch_mfma_dot(nsel<double>(A0), W->kp, W->kq, m, W->kslice, W->kpart, d_pq, st,
+                                       mfu_of<double>(A0, m)));
             } else {
                 mat_spmv<double>(AX, A0, W->kp, nullptr, W->kq, m, st);
                 HIPCHK(launch_dot_tail(W->kp, W->kq, n, m, W->kpart, d_pq, st));

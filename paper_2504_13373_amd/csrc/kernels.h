@@ -139,13 +139,22 @@ hipError_t launch_bspmv(int mode, const Bcsr<T>& A, const T* x, const T* b, T* y
 //   MF_SSWEEP_R y = x + omega (b - A x) and y2 = b - A x
 // with D^{-1} natural (n_brow x br x br, row-major), applied by MFMA too.
 enum MfmaMode : int {
-    MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4, MF_SSWEEP = 5, MF_RDINV = 6, MF_SSWEEP_R = 7
+    MF_AX = 0, MF_BMINUS = 1, MF_BPLUS = 2, MF_SWEEP = 3, MF_SWEEP0 = 4, MF_SSWEEP = 5, MF_RDINV = 6, MF_SSWEEP_R = 7,
+    MF_AXDOT = 8  // y = A x and per-workgroup partials of x . y (launch_mfma_dot only)
 };
 // u: blocks whose operand fragments are loaded before their products (1, 2 or 4;
 // 0: 4); it does not change the arithmetic.
 template <typename T>
 hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                        hipStream_t st, int u = 0, T* y2 = nullptr);
+// y = A x and xy[c] = x[:,c] . y[:,c] on the FP64 tiles (m a multiple of 16),
+// one launch per 16-column tile: each workgroup writes one partial per column
+// (its four block rows in order, each block row's rows in order), a second
+// kernel adds every KRY_BLOCKS-th of them in a fixed order, and k_finalize
+// adds those.  part: mfma_dot_parts(A.n_brow) doubles, part2: 16 * KRY_BLOCKS.
+int64_t mfma_dot_parts(int64_t n_brow);
+hipError_t launch_mfma_dot(const Nbsr<double>& A, const double* x, double* y, int m, double* part, double* part2,
+                           double* xy, hipStream_t st, int u = 0);
 
 // Block-Jacobi steps on a level applied matrix-free (q = A_k u from a chain of
 // products), D^{-1} natural (n_units x nb x nb), m columns row-major:

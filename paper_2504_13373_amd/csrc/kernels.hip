@@ -1261,9 +1261,18 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
                                              const T* __restrict__ b, T* __restrict__ y, T omega, int ld,
                                              T* __restrict__ y2) {
     __shared__ T tile[WAVES_PER_WG][16][17];
+    __shared__ T red[WAVES_PER_WG][16];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int brow = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave);
-    if (brow >= A.n_brow) return;
+    if (brow >= A.n_brow) {
+        // MF_AXDOT: a wavefront past the last block row adds zero to its
+        // workgroup's partials (the first wavefront of a workgroup always has a row)
+        if (MODE == MF_AXDOT) {
+            if (lane < 16) red[wave][lane] = T(0);
+            __syncthreads();
+        }
+        return;
+    }
     const int i = lane & 15, g = lane >> 4;
     const int br = A.br, bc = A.bc;
     const int64_t col0 = int64_t(blockIdx.y) * MFMA_COLS + i;
@@ -1276,8 +1285,10 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
         const int row = Mma<T>::row(g, v);
         const int64_t e = (r0 + row) * ld + col0;
         bpre[v] = (MODE != MF_AX && MODE != MF_RDINV && row < br) ? b[e] : T(0);
-        xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP || MODE == MF_SSWEEP_R || A.unit) && row < br) ? x[e]
-                                                                                                 : T(0);
+        xpre[v] = ((MODE == MF_SWEEP || MODE == MF_SSWEEP || MODE == MF_SSWEEP_R || MODE == MF_AXDOT || A.unit) &&
+                   row < br)
+                      ? x[e]
+                      : T(0);
     }
     if (SW) {
         const T* __restrict__ Db = dinv + int64_t(brow) * br * br;
@@ -1331,6 +1342,20 @@ __global__ __launch_bounds__(WG) void k_mfma(Nbsr<T> A, const T* __restrict__ di
                 }
                 y[(r0 + row) * ld + col0] = val;
             }
+        }
+        if (MODE == MF_AXDOT) {
+            // x . (A x) of column i over this block row: the lane's rows, then the
+            // four lanes of column i; then the workgroup's four block rows in order
+            T s = T(0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (Mma<T>::row(g, v) < br) s += xpre[v] * (A.unit ? acc[v] + xpre[v] : acc[v]);
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            if (lane < 16) red[wave][lane] = s;
+            __syncthreads();
+            if (wave == 0 && lane < 16)
+                y2[int64_t(lane) * gridDim.x + blockIdx.x] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
         }
         return;
     }
@@ -2857,6 +2882,57 @@ __global__ __launch_bounds__(WG) void k_finalize(const double* __restrict__ part
             __hip_atomic_store(mdst + w, __hip_atomic_load(msrc + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
+}
+
+// part2[c * G2 + k] = sum over j of part[c * np + k + G2 j] (thread t takes j = t,
+// t + WG, ..., then a tree over the workgroup): the order is fixed by np and G2
+__global__ __launch_bounds__(WG) void k_part_stride(const double* __restrict__ part, int np, int ncol,
+                                                     double* __restrict__ part2) {
+    __shared__ double sh[WG];
+    const int G2 = gridDim.x;
+    for (int c = 0; c < ncol; ++c) {
+        double s = 0.0;
+        for (int64_t j = threadIdx.x; blockIdx.x + G2 * j < np; j += WG) s += part[int64_t(c) * np + blockIdx.x + G2 * j];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = WG / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part2[int64_t(c) * G2 + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+}
+
+int64_t mfma_dot_parts(int64_t n_brow) { return int64_t(grid_for(n_brow, WAVES_PER_WG)) * MFMA_COLS; }
+
+hipError_t launch_mfma_dot(const Nbsr<double>& A, const double* x, double* y, int m, double* part, double* part2,
+                           double* xy, hipStream_t st, int u) {
+    if (m % MFMA_COLS != 0 || A.br > NBSR_MAXB || A.bc > NBSR_MAXB) return hipErrorInvalidValue;
+    if (A.n_brow == 0) return hipSuccess;
+    const unsigned nwg = grid_for(A.n_brow, WAVES_PER_WG);
+    const unsigned g2 = unsigned(std::min<int64_t>(KRY_BLOCKS, nwg));
+    for (int c0 = 0; c0 < m; c0 += MFMA_COLS) {
+        const dim3 grid{nwg, 1u, 1u}, block{unsigned(WG), 1u, 1u};
+        switch (u) {
+            case 1:
+                hipLaunchKernelGGL((k_mfma<double, MF_AXDOT, 1>), grid, block, 0, st, A, nullptr, x + c0, nullptr, y + c0,
+                                   0.0, m, part);
+                break;
+            case 2:
+                hipLaunchKernelGGL((k_mfma<double, MF_AXDOT, 2>), grid, block, 0, st, A, nullptr, x + c0, nullptr, y + c0,
+                                   0.0, m, part);
+                break;
+            default:
+                hipLaunchKernelGGL((k_mfma<double, MF_AXDOT, 4>), grid, block, 0, st, A, nullptr, x + c0, nullptr, y + c0,
+                                   0.0, m, part);
+                break;
+        }
+        hipLaunchKernelGGL(k_part_stride, dim3(g2), dim3(WG), 0, st, part, int(nwg), MFMA_COLS, part2);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, part2, int(g2), MFMA_COLS, xy + c0, MFMA_COLS,
+                           static_cast<double*>(nullptr), static_cast<int32_t*>(nullptr));
+    }
+    return hipGetLastError();
 }
 
 static inline unsigned kry_grid(int64_t n) {
