@@ -571,28 +571,36 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
 // values with br lanes and leave the rest idle.  Here the four groups of 16
 // lanes take every fourth value vector of the row, so a wavefront still reads
 // one contiguous run per step, and two xor-shuffles add the groups' partial
-// sums.  One column per launch; every batch width takes this kernel, so a
-// column's rounding does not depend on the width.
-template <typename T, int MODE, bool ROWS>
+// sums.  With WGR (operators of few block rows, SPLIT_WG_SLICES or fewer, as
+// the hexahedral hierarchy's coarse levels) a whole workgroup takes one block
+// row: its 16 groups take every sixteenth vector, the staging is shared, and
+// the four wavefronts' sums are added in order through LDS, so four times as
+// many wavefronts stream the operator.  One column per launch; every batch
+// width takes this kernel, so a column's rounding does not depend on the width.
+constexpr int SPLIT_WG_SLICES = 4096;
+
+template <typename T, int MODE, bool ROWS, bool WGR>
 __global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
                                                     T* __restrict__ y, int ldx, int ldy, T omega,
                                                     T* __restrict__ y2) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T red[WGR ? WAVES_PER_WG : 1][16];
     constexpr int VW = 16 / int(sizeof(T));
+    constexpr int NG = WGR ? 4 * WAVES_PER_WG : 4;  // groups of 16 lanes per block row
     using V = typename Vec16<T>::type;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
-    if (slice >= A.n_slices) return;  // the whole wavefront
+    const int slice = WGR ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
+    if (slice >= A.n_slices) return;  // the whole wavefront (WGR: the whole workgroup)
     const int br = A.br, bc = A.bc, L = A.L;  // G == 1, so L == br
-    const int q = lane >> 4, i = lane & 15;
+    const int q = WGR ? wave * 4 + (lane >> 4) : lane >> 4, i = lane & 15;
     const int64_t brow = ROWS ? int64_t(A.rows[slice]) : int64_t(slice);
     const bool own = q == 0 && i < br && brow < A.n_brow;
     const int64_t row = brow * br + i;
-    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * A.tpad;
+    T* xs = reinterpret_cast<T*>(smem_raw) + (WGR ? 0 : int64_t(wave) * A.tpad);
     const int K = A.K[slice];
     const int Tn = K * bc, TQ = (Tn + VW - 1) / VW;
     const int32_t* __restrict__ cp = A.cols + A.coff[slice];
-    for (int t = lane; t < TQ * VW; t += 64) {
+    for (int t = WGR ? int(threadIdx.x) : lane; t < TQ * VW; t += WGR ? WG : 64) {
         T v = T(0);
         if (t < Tn) {
             const int kk = t / bc;
@@ -600,12 +608,13 @@ __global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restric
         }
         xs[t] = v;
     }
-    wave_lds_sync();
+    if (WGR) __syncthreads();
+    else wave_lds_sync();
     T acc = T(0);
     if (i < L) {
         const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + i;
 #pragma unroll 4
-        for (int v = q; v < TQ; v += 4) {
+        for (int v = q; v < TQ; v += NG) {
             T a[VW];
             *reinterpret_cast<V*>(a) = vp[int64_t(v) * L];
 #pragma unroll
@@ -614,6 +623,11 @@ __global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restric
     }
     acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
+    if (WGR) {
+        if (lane < 16) red[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0) acc = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+    }
     if (!own) return;
     if (A.unit) acc += x[row * ldx];
     T val = acc;
@@ -637,19 +651,27 @@ static bool spmv_split_ok(int mode, const Sell<T>& A) {
 template <typename T>
 static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b, T* y, int m, hipStream_t st,
                              T omega, T* y2) {
-    const size_t lds = size_t(WAVES_PER_WG) * A.tpad * sizeof(T);
+    const bool wgr = A.n_slices <= SPLIT_WG_SLICES;  // one workgroup per block row
+    const size_t lds = size_t(wgr ? 1 : WAVES_PER_WG) * A.tpad * sizeof(T);
     if (lds > lds_limit()) return hipErrorInvalidConfiguration;
     if (A.n_slices == 0) return hipSuccess;
-    const dim3 grid{unsigned(grid_for(A.n_slices, WAVES_PER_WG)), 1u, 1u}, block{unsigned(WG), 1u, 1u};
+    const dim3 grid{unsigned(wgr ? A.n_slices : grid_for(A.n_slices, WAVES_PER_WG)), 1u, 1u},
+        block{unsigned(WG), 1u, 1u};
     for (int c = 0; c < m; ++c) {
         const T* xc = x + c;
         const T* bcol = b ? b + c : nullptr;
         T* yc = y + c;
         T* y2c = y2 ? y2 + c : nullptr;
-#define SPLIT_LAUNCH(MD)                                                                                      \
-    if (A.rows)                                                                                               \
-        hipLaunchKernelGGL((k_spmv_split<T, MD, true>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega, y2c); \
-    else hipLaunchKernelGGL((k_spmv_split<T, MD, false>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega, y2c)
+#define SPLIT_LAUNCH_W(MD, W)                                                                                   \
+    if (A.rows)                                                                                                 \
+        hipLaunchKernelGGL((k_spmv_split<T, MD, true, W>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega, y2c); \
+    else hipLaunchKernelGGL((k_spmv_split<T, MD, false, W>), grid, block, lds, st, A, xc, bcol, yc, m, m, omega, y2c)
+#define SPLIT_LAUNCH(MD)           \
+    if (wgr) {                     \
+        SPLIT_LAUNCH_W(MD, true);  \
+    } else {                       \
+        SPLIT_LAUNCH_W(MD, false); \
+    }
         switch (mode) {
             case AX: SPLIT_LAUNCH(AX); break;
             case B_MINUS: SPLIT_LAUNCH(B_MINUS); break;
@@ -659,6 +681,7 @@ static hipError_t spmv_split(int mode, const Sell<T>& A, const T* x, const T* b,
             default: return hipErrorInvalidValue;
         }
 #undef SPLIT_LAUNCH
+#undef SPLIT_LAUNCH_W
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
