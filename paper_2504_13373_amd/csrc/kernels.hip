@@ -411,11 +411,16 @@ int sell_rows_per_wave(int br, int bc, int max_row_blocks) {
     return G;
 }
 
+// Operators of at most this many block rows at one block row per wavefront take
+// the split kernels' workgroup-per-row form (WGR).
+constexpr int SPLIT_WG_SLICES = 4096;
+
 // The sweeps with D^{-1} (sliced layout) at one block row per wavefront, the
-// row's product split over four groups of 16 lanes as in k_spmv_split; the
-// block row's residual then goes through LDS to the br lanes that apply their
-// row of D^{-1}.  One column per launch at every batch width.
-template <typename T, int MODE, bool ROWS>
+// row's product split over four groups of 16 lanes as in k_spmv_split (with WGR
+// over a workgroup's 16 groups, for operators of few block rows); the block
+// row's residual then goes through LDS to the br lanes that apply their row of
+// D^{-1}.  One column per launch at every batch width.
+template <typename T, int MODE, bool ROWS, bool WGR>
 __global__ __launch_bounds__(WG) void k_sweep_split(Sell<T> A, const T* __restrict__ dinv, const T* __restrict__ x,
                                                      const T* __restrict__ b, T* __restrict__ y, T omega,
                                                      const int32_t* __restrict__ colmask, int ld,
@@ -423,25 +428,27 @@ __global__ __launch_bounds__(WG) void k_sweep_split(Sell<T> A, const T* __restri
     constexpr bool HAS_B = (MODE == SWEEP || MODE == SWEEP0);
     constexpr bool HAS_A = (MODE != SWEEP0);
     constexpr int VW = 16 / int(sizeof(T));
+    constexpr int NG = WGR ? 4 * WAVES_PER_WG : 4;
     using V = typename Vec16<T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T red[WGR ? WAVES_PER_WG : 1][16];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slice = xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
-    if (slice >= A.n_slices) return;  // the whole wavefront
+    const int slice = WGR ? xcd_remap(blockIdx.x, gridDim.x) : xcd_remap(blockIdx.x, gridDim.x) * WAVES_PER_WG + wave;
+    if (slice >= A.n_slices) return;  // the whole wavefront (WGR: the whole workgroup)
     const int br = A.br, bc = A.bc, L = A.L, BP = A.brpad;  // G == 1, so L == br
-    const int q = lane >> 4, i = lane & 15;
+    const int q = WGR ? wave * 4 + (lane >> 4) : lane >> 4, i = lane & 15;
     const int64_t brow = ROWS ? int64_t(A.rows[slice]) : int64_t(slice);
     const bool mine = q == 0 && i < br;
     const bool own = mine && brow < A.n_brow;
     const int64_t row = brow * br + i;
-    T* xs = reinterpret_cast<T*>(smem_raw) + int64_t(wave) * (A.tpad + BP);
+    T* xs = reinterpret_cast<T*>(smem_raw) + (WGR ? 0 : int64_t(wave) * (A.tpad + BP));
     T* rr = xs + A.tpad;
     T acc = T(0);
     if (HAS_A) {
         const int K = A.K[slice];
         const int Tn = K * bc, TQ = (Tn + VW - 1) / VW;
         const int32_t* __restrict__ cp = A.cols + A.coff[slice];
-        for (int t = lane; t < TQ * VW; t += 64) {
+        for (int t = WGR ? int(threadIdx.x) : lane; t < TQ * VW; t += WGR ? WG : 64) {
             T v = T(0);
             if (t < Tn) {
                 const int kk = t / bc;
@@ -449,11 +456,12 @@ __global__ __launch_bounds__(WG) void k_sweep_split(Sell<T> A, const T* __restri
             }
             xs[t] = v;
         }
-        wave_lds_sync();
+        if (WGR) __syncthreads();
+        else wave_lds_sync();
         if (i < L) {
             const V* __restrict__ vp = reinterpret_cast<const V*>(A.vals + A.voff[slice]) + i;
 #pragma unroll 4
-            for (int v = q; v < TQ; v += 4) {
+            for (int v = q; v < TQ; v += NG) {
                 T a[VW];
                 *reinterpret_cast<V*>(a) = vp[int64_t(v) * L];
 #pragma unroll
@@ -462,7 +470,13 @@ __global__ __launch_bounds__(WG) void k_sweep_split(Sell<T> A, const T* __restri
         }
         acc += __shfl_xor(acc, 16);
         acc += __shfl_xor(acc, 32);
+        if (WGR) {
+            if (lane < 16) red[wave][lane] = acc;
+            __syncthreads();
+            acc = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+        }
     }
+    if (WGR && wave != 0) return;  // the D^{-1} stage runs on the first wavefront
     // residual of the block row through LDS (zero-padded to brpad), then row i of D^{-1}
     if (q == 0 && i < BP) {
         T r = T(0);
@@ -492,23 +506,31 @@ __global__ __launch_bounds__(WG) void k_sweep_split(Sell<T> A, const T* __restri
 template <typename T>
 static hipError_t sweep_split(int mode, const Sell<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega,
                               int m, const int32_t* colmask, hipStream_t st, T* y2) {
-    const size_t lds = size_t(WAVES_PER_WG) * (A.tpad + A.brpad) * sizeof(T);
+    const bool wgr = A.n_slices <= SPLIT_WG_SLICES;  // one workgroup per block row
+    const size_t lds = size_t(wgr ? 1 : WAVES_PER_WG) * (A.tpad + A.brpad) * sizeof(T);
     if (lds > lds_limit()) return hipErrorInvalidConfiguration;
     if (A.n_slices == 0) return hipSuccess;
-    const dim3 grid{unsigned(grid_for(A.n_slices, WAVES_PER_WG)), 1u, 1u}, block{unsigned(WG), 1u, 1u};
+    const dim3 grid{unsigned(wgr ? A.n_slices : grid_for(A.n_slices, WAVES_PER_WG)), 1u, 1u},
+        block{unsigned(WG), 1u, 1u};
     for (int c = 0; c < m; ++c) {
         const T* xc = x ? x + c : nullptr;
         const T* bcol = b ? b + c : nullptr;
         const int32_t* mc = colmask ? colmask + c : nullptr;
         T* yc = y + c;
         T* y2c = y2 ? y2 + c : nullptr;
-#define SPLIT_LAUNCH(MD)                                                                                    \
-    if (A.rows)                                                                                             \
-        hipLaunchKernelGGL((k_sweep_split<T, MD, true>), grid, block, lds, st, A, dinv, xc, bcol, yc, omega, mc, m, \
-                           y2c);                                                                            \
-    else                                                                                                    \
-        hipLaunchKernelGGL((k_sweep_split<T, MD, false>), grid, block, lds, st, A, dinv, xc, bcol, yc, omega, mc, m, \
-                           y2c)
+#define SPLIT_LAUNCH_W(MD, W)                                                                                 \
+    if (A.rows)                                                                                               \
+        hipLaunchKernelGGL((k_sweep_split<T, MD, true, W>), grid, block, lds, st, A, dinv, xc, bcol, yc, omega, mc, \
+                           m, y2c);                                                                           \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_sweep_split<T, MD, false, W>), grid, block, lds, st, A, dinv, xc, bcol, yc, omega,    \
+                           mc, m, y2c)
+#define SPLIT_LAUNCH(MD)           \
+    if (wgr) {                     \
+        SPLIT_LAUNCH_W(MD, true);  \
+    } else {                       \
+        SPLIT_LAUNCH_W(MD, false); \
+    }
         switch (mode) {
             case SWEEP: SPLIT_LAUNCH(SWEEP); break;
             case SWEEP0: SPLIT_LAUNCH(SWEEP0); break;
@@ -517,6 +539,7 @@ static hipError_t sweep_split(int mode, const Sell<T>& A, const T* dinv, const T
             default: return hipErrorInvalidValue;
         }
 #undef SPLIT_LAUNCH
+#undef SPLIT_LAUNCH_W
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -577,8 +600,6 @@ hipError_t launch_sweep(int mode, const Sell<T>& A, const T* dinv, const T* x, c
 // the four wavefronts' sums are added in order through LDS, so four times as
 // many wavefronts stream the operator.  One column per launch; every batch
 // width takes this kernel, so a column's rounding does not depend on the width.
-constexpr int SPLIT_WG_SLICES = 4096;
-
 template <typename T, int MODE, bool ROWS, bool WGR>
 __global__ __launch_bounds__(WG) void k_spmv_split(Sell<T> A, const T* __restrict__ x, const T* __restrict__ b,
                                                     T* __restrict__ y, int ldx, int ldy, T omega,
