@@ -376,7 +376,8 @@ int amgdg_server_destroy(amgdg_server s);
  * candidates on the operators of this hierarchy's V-cycle (HIP events on
  * `stream`):
  *   - columns per launch of the sliced and block-CSR kernels (1, 2, 4, 8, 16);
- *   - operand blocks loaded ahead in the 16-column MFMA tiles (1, 2, 4);
+ *   - operand blocks loaded ahead in the 16-column MFMA tiles (1, 2, 4; 3 as well where the tiles
+ *     stage their operands in LDS, whose chunk of blocks this sizes);
  *   - with AMGDG_TUNE_LANES, the lanes per block row of every block-CSR
  *     operator (4..64, 128, 256; timed at one column).
  * The first two never change a result.  The lane-group width changes the

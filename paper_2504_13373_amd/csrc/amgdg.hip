@@ -2268,7 +2268,7 @@ static void autotune_impl(Ctx& C, int m, bool lanes, hipStream_t st) {
                 if (use_mfma<T>(M, m)) {
                     int best = 0;
                     float bt = 0.f;
-                    for (int u : {1, 2, 4}) {
+                    for (int u : {1, 2, 3, 4}) {
                         mfu[m / MFMA_COLS] = int8_t(u);
                         const float t = timed([&] { run(tag, m); });
                         if (best == 0 || t < bt) best = u, bt = t;

@@ -143,7 +143,9 @@ enum MfmaMode : int {
     MF_AXDOT = 8  // y = A x and per-workgroup partials of x . y (launch_mfma_dot only)
 };
 // u: blocks whose operand fragments are loaded before their products (1, 2 or 4;
-// 0: 4); it does not change the arithmetic.
+// 0: 4); for the tiles that stage their operands in LDS, the register budget of
+// a chunk of blocks (16 x 16 u values of operand and of x rows; u = 3 for them
+// only, a chunk of four 10 x 10 blocks); it does not change the arithmetic.
 template <typename T>
 hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                        hipStream_t st, int u = 0, T* y2 = nullptr);

@@ -1623,6 +1623,11 @@ static bool mfma_v_ok(int mode, const Nbsr<T>& A, const T* x, const T* b, const 
 template <typename T, int U>
 static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, const T* b, T* y, T omega, int m,
                          hipStream_t st, T* y2) {
+    // U = 3 exists for the staged tiles only (a chunk of four 10 x 10 blocks, a
+    // whole level-0 row of the 3D tetrahedra); the per-lane tiles take 2 there
+    if constexpr (U == 3) {
+        if (!mfma_v_ok<T>(mode, A, x, b, y, m)) return mfma_u<T, 2>(mode, A, dinv, x, b, y, omega, m, st, y2);
+    }
     if (mfma_v_ok<T>(mode, A, x, b, y, m) &&
         ((mode != MF_SSWEEP_R && mode != MF_RDINV) || (reinterpret_cast<uintptr_t>(y2) & 15) == 0)) {
         dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
@@ -1643,6 +1648,9 @@ static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, 
             return hipGetLastError();
         }
     }
+    if constexpr (U == 3) {
+        return mfma_u<T, 2>(mode, A, dinv, x, b, y, omega, m, st, y2);
+    } else {
     dim3 grid(grid_for(A.n_brow, WAVES_PER_WG), m / MFMA_COLS), block(WG);
     switch (mode) {
         case MF_AX: hipLaunchKernelGGL((k_mfma<T, MF_AX, U>), grid, block, 0, st, A, dinv, x, b, y, omega, m, y2); break;
@@ -1659,6 +1667,7 @@ static hipError_t mfma_u(int mode, const Nbsr<T>& A, const T* dinv, const T* x, 
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+    }
 }
 
 template <typename T>
@@ -1669,6 +1678,7 @@ hipError_t launch_mfma(int mode, const Nbsr<T>& A, const T* dinv, const T* x, co
     switch (u) {
         case 1: return mfma_u<T, 1>(mode, A, dinv, x, b, y, omega, m, st, y2);
         case 2: return mfma_u<T, 2>(mode, A, dinv, x, b, y, omega, m, st, y2);
+        case 3: return mfma_u<T, 3>(mode, A, dinv, x, b, y, omega, m, st, y2);
         default: return mfma_u<T, 4>(mode, A, dinv, x, b, y, omega, m, st, y2);
     }
 }
