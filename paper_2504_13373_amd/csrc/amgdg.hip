@@ -1268,12 +1268,6 @@ static void vcycle_impl(Ctx& C, VBuf<T>* VB, const T* b0, T* z0, int m, hipStrea
     }
 }
 
-// The V-cycle as a captured HIP graph: its ~40 launches (most of them small
-// coarse-level kernels) are submitted as one graph launch, so the host no
-// longer paces the coarse levels.  The graph is captured on the Work's private
-// stream the first time a (precision, m, input, output) combination is seen and
-// replayed on the caller's stream; reallocating the Work drops the cache.  It
-// holds only kernel nodes (no memset or copy nodes).
 // Whether a call replays the captured V-cycle (flags without AMGDG_EAGER).
 // The graph's start and end leave the device idle for a few microseconds each;
 // where one pass over the level-0 operator S reads 128 MB or more, the host
@@ -1286,6 +1280,12 @@ static bool graph_for(const Ctx& C, int flags, int prec_bytes) {
     return s_bytes < 128.0 * (1 << 20);
 }
 
+// The V-cycle as a captured HIP graph: its ~40 launches (most of them small
+// coarse-level kernels) are submitted as one graph launch, so the host no
+// longer paces the coarse levels.  The graph is captured on the Work's private
+// stream the first time a (precision, m, input, output) combination is seen and
+// replayed on the caller's stream; reallocating the Work drops the cache.  It
+// holds only kernel nodes (no memset or copy nodes).
 template <typename T>
 static void vcycle_run(Ctx& C, Work& W, const T* b0, T* z0, int m, hipStream_t st, bool allow_graph) {
     if (!allow_graph || C.prm.t_pre == 0 || C.N == 0) {
