@@ -10,7 +10,10 @@ elements under both fluxes (IP and LDG; 4,096 dofs, nb = 8, r = 8, 3 levels;
 candidate relaxation capped at 20 sweeps, which keeps every aggregate's
 candidate block well conditioned: see test_hex_collapsed_candidates for the
 default cap), also with 16 candidates (coarse blocks of 11 and 15 dofs, the
-SVD truncated from 16 columns to 11).
+SVD truncated from 16 columns to 11), and at 16^3 elements with LDG and 16
+candidates (32,768 dofs, 4 levels), whose level 2 (64 block rows of 15 dofs,
+up to 63 off-diagonal blocks per row) takes the split-row kernels in their
+workgroup-per-row form.
 FP64 results are held to 1e-10 (1e-12 or 1e-13 for single steps), FP32 steps
 to a few units of 2^-24 of |A||x| + |b|.
 """
@@ -38,6 +41,7 @@ def _cases():
         "hex_r16": lambda: configs.poisson3d_hex(3, flux="ip", r=16, relax_max=20),
         "kuhn3d": lambda: configs.poisson3d_kuhn(n=8, p=2, n_levels=3, r=4),
         "sipg4": lambda: configs.poisson2d_delaunay(side=17, p=4, n_levels=3, r=3),
+        "hex4_ldg": lambda: configs.poisson3d_hex(4, flux="ldg", r=16, relax_max=20),
     }
 
 
@@ -76,7 +80,7 @@ def bsr_export(h, k, which, shape):
 
 # ------------------------------------------------------------------ setup parity
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4", "hex4_ldg"])
 def test_setup_parity(name):
     w, H, h = case(name)
     N = len(H.levels) - 1
@@ -186,7 +190,7 @@ def host_op(op, k, h, w, x, b, prec):
         return np.vstack([x + om * e, e]), np.vstack([abs(x) + om * (abs(b) + absDA @ abs(x)), abs(b) + absDA @ abs(x)])
 
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4", "hex4_ldg"])
 @pytest.mark.parametrize("prec", [am.AMGDG_FP64, am.AMGDG_MIXED])
 @pytest.mark.parametrize("m", [1, 3, 5, 8, 16, 32])
 def test_single_kernels(name, prec, m):
@@ -245,7 +249,7 @@ def test_internal_order_matches_caller_order():
 
 # ------------------------------------------------------------------ V-cycle
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4", "hex4_ldg"])
 def test_vcycle_parity_fp64(name):
     w, H, h = case(name)
     b = np.random.default_rng(8).standard_normal(w.A.n)
@@ -301,7 +305,7 @@ def test_vcycle_linear_symmetric(name):
     assert abs(out[0] @ b2 - b1 @ out[1]) <= 1e-11 * abs(out[0] @ b2)
 
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "ldg2", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4", "hex4_ldg"])
 def test_vcycle_mixed_close_to_fp64(name):
     w, H, h = case(name)
     b = np.random.default_rng(8).standard_normal(w.A.n)
@@ -314,7 +318,7 @@ def test_vcycle_mixed_close_to_fp64(name):
 
 # ------------------------------------------------------------------ solves
 
-@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4"])
+@pytest.mark.parametrize("name", ["c1", "sipg3", "hex_ip", "hex_ldg", "hex_r16", "kuhn3d", "sipg4", "hex4_ldg"])
 def test_pcg_parity(name):
     w, H, h = case(name)
     A = w.A.to_scipy()
