@@ -328,7 +328,8 @@ def main():
             "kernel": "level-0 FP64 block-Jacobi sweep on D^-1 A (k_spmv<double,1,S_SWEEP,false,false>; the "
                       "diagonal blocks of D^-1 A are the identity and are not stored), the kernel with the most "
                       f"GPU time in this run; its {k['bytes'] / 1e6:.0f} MB working set exceeds the 256 MB "
-                      "Infinity Cache, so back-to-back launches run as they do inside the V-cycles",
+                      "Infinity Cache, so back-to-back launches in one direction find none of it cached (inside "
+                      "the V-cycles consecutive passes alternate direction and find part of it cached)",
             "achieved": k["gbps"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
